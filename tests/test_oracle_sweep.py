@@ -1,0 +1,235 @@
+"""Pins of the oracle's Monte Carlo sweep against closed forms, exact
+geometry and conservation laws (not GPU)."""
+import math
+
+import numpy as np
+import pytest
+
+import closed_forms as CF
+from oracle import oracle as O
+from paper_2512_19925_amd import workloads as W
+
+
+def _sim(w, **kw):
+    return O.OracleSim(w.edges, w.sigma_t, w.sigma_s, w.speed, w.dt, w.n_steps, w.src_x, w.n_src,
+                       w.capacity(), w.seed, w.replica, w.n_batches, w.n_chunks, **kw)
+
+
+def _opts(w):
+    return O.LosmOpts(theta=w.theta, filter=w.filter, ma_k=w.ma_k, eps_min=w.eps_min, rho=w.rho)
+
+
+# ------------------------------------------------------------ streaming --
+def test_streaming_track_lengths_are_exact_geometry():
+    # No collisions (sigma_t negligible, sigma_s = 0): each particle moves
+    # on a straight line, so its track in each cell is the exact overlap of
+    # the path with the cell divided by |mu|; leaking particles score
+    # w/|mu| etc. at the face they cross.
+    I = 11
+    w = W.Workload(name="stream", x_lo=-0.55, x_hi=0.55, n_cells=I, sigma_t=np.full(I, 1e-30),
+                   sigma_s=np.zeros(I), speed=1.3, dt=0.07, n_steps=8, src_x=0.013, n_src=37,
+                   n_batches=4, n_chunks=3)
+    sim = _sim(w)
+    src = sim.bank(1)
+    mu = src["mu"]
+    edges = w.edges
+    for n in range(1, w.n_steps + 1):
+        for p in range(w.n_chunks):
+            sim.sweep(n, p)
+        cells, bnd = sim.tallies()
+        track = cells[..., O.T_PHI].sum(0)
+        tj = cells[..., O.T_J].sum(0)
+        expect = np.zeros(I)
+        expj = np.zeros(I)
+        exp_b = np.zeros((2, 3))
+        t0, t1 = (n - 1) * w.dt, n * w.dt
+        for m in mu:
+            xa = w.src_x + m * w.speed * t0
+            xb = w.src_x + m * w.speed * t1
+            if not (edges[0] < xa < edges[-1]) and t0 > 0:
+                continue  # already leaked
+            lo, hi = min(xa, xb), max(xa, xb)
+            for i in range(I):
+                ov = max(0.0, min(hi, edges[i + 1]) - max(lo, edges[i]))
+                expect[i] += ov / abs(m)
+                expj[i] += ov / abs(m) * m
+            if xb <= edges[0] or xb >= edges[-1]:
+                f = 0 if xb <= edges[0] else 1
+                am = abs(m)
+                exp_b[f] += [1 / am, (0.5 - am) / am, (1 / 3 - m * m) / am]
+        np.testing.assert_allclose(track, expect, rtol=1e-12, atol=1e-15)
+        np.testing.assert_allclose(tj, expj, rtol=1e-12, atol=1e-15)
+        np.testing.assert_allclose(bnd.sum(0), exp_b, rtol=1e-12, atol=1e-15)
+        leaks = sim.counters()["leaks"]
+        assert leaks == int(np.sum([(1 if (abs(w.src_x + m * w.speed * t1) >= 0.55 and
+                                           abs(w.src_x + m * w.speed * t0) < 0.55) else 0) for m in mu]))
+
+
+# -------------------------------------------------------------- sources --
+def test_source_sampling_isotropic():
+    w = W.plain_small().with_(n_src=40000)
+    sim = _sim(w)
+    b = sim.bank(1)
+    n = len(b["mu"])
+    assert n == 40000 and np.all(b["w"] == 1.0) and np.all(b["x"] == 0.0)
+    assert abs(b["mu"].mean()) < 4 * math.sqrt(1 / 3 / n)
+    assert abs((b["mu"] ** 2).mean() - 1 / 3) < 4 * math.sqrt(4 / 45 / n)
+    # on the central edge the particle belongs to the cell it moves into
+    assert np.all(b["cell"][b["mu"] >= 0] == 100) and np.all(b["cell"][b["mu"] < 0] == 99)
+    # chunk membership is close to uniform
+    counts = np.bincount(b["chunk"], minlength=4)
+    assert np.all(np.abs(counts - n / 4) < 5 * math.sqrt(n * 3 / 16))
+
+
+# ------------------------------------------------- uncollided closed form --
+def _zscores(cells, norm, exact_fn, I, edges, kinds):
+    z = []
+    for k in kinds:
+        per_batch = cells[..., k] / norm[None, :]
+        tot = per_batch.sum(0)
+        sig = CF.batch_sigma(per_batch)
+        for i in range(I):
+            ex = exact_fn(i)[k % 3]
+            if sig[i] > 0:
+                z.append((tot[i] - ex) / sig[i])
+            else:
+                assert abs(ex) < 1e-3 * max(abs(tot).max(), 1e-30) or tot[i] == ex
+    return np.array(z)
+
+
+@pytest.mark.parametrize("analog", [True, False])
+def test_uncollided_pulse_closed_form(analog):
+    # c = 0: the tallies estimate the uncollided pulse solution exactly.
+    # (A ballistic shell is far from the LOSM solution, so the windows split
+    # hard at the front: a larger floor eps_min and bank keep it small.)
+    w = W.homogeneous("c0", -3.0, 3.0, 60, 1.0, 0.0, dt=0.25, n_steps=8, n_src=20000, rho=2.0,
+                      eps_min=0.05, bank_capacity=2_000_000)
+    sim = _sim(w)
+    edges = w.edges
+    dx = np.diff(edges)
+    zs = []
+
+    def on_step(n, s):
+        cells, _ = s.tallies()
+        t0, t1 = (n - 1) * w.dt, n * w.dt
+        ex_t = [CF.uncollided_cell_time_avg(edges[i], edges[i + 1], t0, t1, 1.0, 1.0) for i in range(w.n_cells)]
+        ex_c = [CF.uncollided_cell_avg(edges[i], edges[i + 1], t1, 1.0, 1.0) for i in range(w.n_cells)]
+        zs.append(_zscores(cells, w.n_src * dx * w.dt, lambda i: ex_t[i], w.n_cells, edges, [0, 1, 2]))
+        zs.append(_zscores(cells, w.n_src * dx, lambda i: ex_c[i], w.n_cells, edges, [3, 4, 5]))
+
+    O.run(sim, w.n_steps, None if analog else _opts(w), on_step)
+    z = np.concatenate(zs)
+    assert len(z) > 500
+    chi2 = (z ** 2).mean()
+    assert 0.75 < chi2 < 1.4, chi2
+    assert np.abs(z).max() < 6.0
+
+
+# ---------------------------------------------------------- conservation --
+def test_pure_scattering_analog_conserves_exactly():
+    # c = 1, no windows, no leakage: every history survives every step, so
+    # the census holds N particles of weight 1 and the total track is N v dt.
+    w = W.homogeneous("c1", -20.0, 20.0, 200, 1.0, 1.0, dt=0.1, n_steps=6, n_src=5000)
+    sim = _sim(w)
+    for n in range(1, w.n_steps + 1):
+        for p in range(w.n_chunks):
+            sim.sweep(n, p)
+        cells, _ = sim.tallies()
+        c = sim.counters()
+        assert c["census"] == w.n_src and c["absorptions"] == 0 and c["leaks"] == 0
+        assert c["histories"] == w.n_src
+        assert abs(cells[..., O.T_PHI].sum() - w.n_src * w.speed * w.dt) < 1e-9
+        assert cells[..., O.C_PHI].sum() == w.n_src * w.speed
+        assert c["segments"] == c["census"] + c["crossings"] + c["collisions"]
+        assert int(sim.tracks().sum()) == c["segments"]
+
+
+def test_splitting_is_exact_and_weight_preserving():
+    # Fixed windows of centre 0.1 and width 5 split each unit-weight source
+    # particle into exactly ten particles of weight 1/10 at the first step
+    # start; nothing is rouletted afterwards (0.02 < 0.1 < 0.5).
+    w = W.homogeneous("split", -20.0, 20.0, 100, 1.0, 1.0, dt=0.1, n_steps=3, n_src=3000, rho=5.0,
+                    bank_capacity=40000)
+    sim = _sim(w)
+    for n in range(1, 4):
+        sim.set_windows(np.full(100, 0.1), 5.0)
+        for p in range(w.n_chunks):
+            sim.sweep(n, p)
+        c = sim.counters()
+        bank = sim.bank(1)
+        if n == 1:
+            assert c["splits"] == 3000 and c["daughters"] == 9 * 3000
+        else:
+            assert c["splits"] == 0
+        assert c["rr_kill"] == 0 and c["census"] == 30000
+        assert np.all(bank["w"] == 0.1)
+        assert abs(bank["w"].sum() - 3000.0) < 1e-9
+        # daughter lineages are distinct
+        keys = set(zip(bank["src"].tolist(), bank["lin"].tolist()))
+        assert len(keys) == 30000
+
+
+def test_roulette_is_unbiased_and_exact():
+    # Centre 10, width 4: unit weights fall under the floor 2.5 and survive
+    # with probability 1/10 at weight exactly 10.
+    w = W.homogeneous("rr", -20.0, 20.0, 100, 1.0, 1.0, dt=0.1, n_steps=1, n_src=200000, rho=4.0)
+    sim = _sim(w)
+    sim.set_windows(np.full(100, 10.0), 4.0)
+    for p in range(w.n_chunks):
+        sim.sweep(1, p)
+    c = sim.counters()
+    bank = sim.bank(1)
+    n = w.n_src
+    assert c["rr_kill"] + c["rr_survive"] == n
+    assert np.all(bank["w"] == 10.0) and len(bank["w"]) == c["rr_survive"]
+    assert abs(c["rr_survive"] - 0.1 * n) < 5 * math.sqrt(n * 0.09)
+
+
+@pytest.mark.parametrize("c", [0.5, 0.9])
+def test_scattering_moments_closed_form(c):
+    # Analog histories are independent: census-bank moments of x and mu
+    # estimate int phi, int K, int xJ and int x^2 phi of the pulse.
+    w = W.homogeneous("mom", -20.0, 20.0, 200, 1.0, c, dt=0.1, n_steps=15, n_src=40000)
+    sim = _sim(w)
+    for n in range(1, w.n_steps + 1):
+        for p in range(w.n_chunks):
+            sim.sweep(n, p)
+        if n % 5:
+            continue
+        b = sim.bank(1)
+        t = n * w.dt
+        N = w.n_src
+        # per source particle: each source contributes at most one census particle
+        src_vals = {}
+        for name, vals in (("m0", b["w"]), ("k", b["w"] * b["mu"] ** 2), ("xj", b["w"] * b["x"] * b["mu"]),
+                           ("x2", b["w"] * b["x"] ** 2)):
+            full = np.zeros(N)
+            full[b["src"]] = vals
+            src_vals[name] = full
+        ex = dict(zip(("m0", "k", "xj", "x2"), CF.moments(c, t)))
+        for name in ex:
+            v = src_vals[name]
+            se = v.std() / math.sqrt(N)
+            assert abs(v.mean() - ex[name]) < 4.5 * se, (name, t, v.mean(), ex[name], se)
+
+
+def test_windows_do_not_bias_tallies():
+    # HWW (full method, three window updates per step) and analog runs of the
+    # small plain problem estimate the same track-length flux.
+    w = W.plain_small().with_(n_src=20000, n_steps=20)
+    res = {}
+    for label, opts in (("analog", None), ("hww", _opts(w))):
+        sim = _sim(w.with_(seed=2 if opts is None else 3))
+        acc = []
+        O.run(sim, w.n_steps, opts, lambda n, s: acc.append(s.tallies()[0][..., O.T_PHI].copy()))
+        res[label] = acc
+    z = []
+    for a, h in zip(res["analog"], res["hww"]):
+        sa, sh = CF.batch_sigma(a), CF.batch_sigma(h)
+        s = np.sqrt(sa ** 2 + sh ** 2)
+        m = (sa > 0) & (sh > 0)
+        z.append((a.sum(0)[m] - h.sum(0)[m]) / s[m])
+    z = np.concatenate(z)
+    assert len(z) > 150
+    assert 0.7 < (z ** 2).mean() < 1.5
+    assert np.abs(z).max() < 6.5
