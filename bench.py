@@ -1,0 +1,194 @@
+"""Benchmark of the hybrid weight-window sweep on one MI355X.
+
+A step is one time step of the method on the full-scale problem (1000 cells
+on [-50, 50], sigma_t = 1, c = 0.9, 1e7 source particles, dt = 0.05,
+moving-average filtered HLOSM windows with rho = 5, eps_min = 1e-3 and three
+window updates per step): the semi-implicit solve, four chunks of particle
+histories with their daughters, and three fully implicit solves.
+
+Prints one JSON line: particle segments/s over the timed steps (inputs
+resident in HBM), the sweep kernel's HBM-roofline figures measured with HIP
+events on the library's stream, the figure-of-merit gain over the plain
+(analog) FP64 sweep of the same problem, and the CPU oracle timed on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle segments/s and FOM per time step vs plain FP64 sweep, 1 MI355X"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=95)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--c", type=float, default=0.9)
+    ap.add_argument("--rho", type=float, default=5.0)
+    ap.add_argument("--n-src", type=int, default=10_000_000)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--no-analog", action="store_true", help="skip the plain-sweep FOM comparison")
+    ap.add_argument("--sweep", action="store_true", help="also run every (c, rho) pair of the workload")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--out", default=None, help="also write per-step records (JSON) here")
+    return ap.parse_args()
+
+
+def fom_sigma(cells, n_src, dx, dt):
+    """FOM_sigma of the track-length flux (Sec. 5, Eq. FOM_sigma without the
+    runtime): 1 / mean over cells with flux of (sigma_i / phi_i)^2, with
+    sigma from the spread of the batch sums."""
+    per = cells[..., 0] / (n_src * dx[None, :] * dt)
+    B = per.shape[0]
+    tot = per.sum(0)
+    sig = np.sqrt(B / (B - 1.0) * ((per - tot / B) ** 2).sum(0))
+    m = tot > 0
+    if not np.any(m):
+        return 0.0
+    return 1.0 / np.mean((sig[m] / tot[m]) ** 2)
+
+
+def run_gpu(w, steps_total, warmup, analog, record):
+    import torch
+    from paper_2512_19925_amd import hww as H
+    h = H.Handle(H.spec_from_workload(w))
+    dx = np.diff(w.edges)
+    kw = dict(theta=w.theta, filter=w.filter, ma_k=w.ma_k, eps_min=w.eps_min, rho=w.rho,
+              closure_track=w.closure_track)
+    out = {"segments": 0, "kernel_ms": 0.0, "bytes": 0, "launches": 0, "step_ms": [], "fom_sigma": [],
+           "census": [], "wall_s": 0.0}
+    torch.cuda.synchronize()
+    t_start = None
+    for n in range(1, steps_total + 1):
+        if n == warmup + 1:
+            torch.cuda.synchronize()
+            t_start = time.perf_counter()
+        t0 = time.perf_counter()
+        if not analog:
+            h.solve_losm(implicit=False, **kw)
+        seg = 0
+        kms = 0.0
+        byt = 0
+        gens = 0
+        cen = 0
+        for p in range(w.n_chunks):
+            st = h.sweep_step(n, p)
+            seg += st["segments"]
+            kms += st["kernel_ms"]
+            byt += st["bytes_moved"]
+            gens += st["generations"]
+            cen += st["census"]
+            if not analog and p < w.n_chunks - 1:
+                h.solve_losm(implicit=True, **kw)
+        torch.cuda.synchronize()
+        step_ms = (time.perf_counter() - t0) * 1e3
+        if n > warmup:
+            out["segments"] += seg
+            out["kernel_ms"] += kms
+            out["bytes"] += byt
+            out["launches"] += gens
+            out["step_ms"].append(step_ms)
+            out["census"].append(cen)
+            if record:
+                cells = h.read_tallies(H.TALLY_CELLS)
+                out["fom_sigma"].append(fom_sigma(cells, w.n_src, dx, w.dt) / (step_ms * 1e-3))
+    torch.cuda.synchronize()
+    out["wall_s"] = time.perf_counter() - t_start
+    h.close()
+    return out
+
+
+def cpu_baseline(w, budget_s):
+    """The oracle, as it stands, on a bounded sample: the same problem with
+    fewer source particles, as many steps as fit in about budget_s."""
+    from oracle import oracle as O
+    frac = 10
+    n = max(w.n_src // frac, 1000)
+    ws = w.with_(n_src=n, bank_capacity=4 * n + 4096)
+    sim = O.OracleSim(ws.edges, ws.sigma_t, ws.sigma_s, ws.speed, ws.dt, ws.n_steps, ws.src_x, ws.n_src,
+                      ws.capacity(), ws.seed, ws.replica, ws.n_batches, ws.n_chunks)
+    opts = O.LosmOpts(theta=ws.theta, filter=ws.filter, ma_k=ws.ma_k, eps_min=ws.eps_min, rho=ws.rho)
+    seg = 0
+    t0 = time.perf_counter()
+    steps = 0
+    for step in range(1, ws.n_steps + 1):
+        sim.solve_losm(opts, implicit=False)
+        for p in range(ws.n_chunks):
+            sim.sweep(step, p)
+            if p < ws.n_chunks - 1:
+                sim.solve_losm(opts, implicit=True)
+        seg += sim.counters()["segments"]
+        steps = step
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": seg / dt, "unit": "segments/s", "cores": 1, "kind": "oracle",
+            "sample": f"{ws.name} with {n} source particles (1/{frac} of the workload), steps 1-{steps}, "
+                      f"{seg} segments in {dt:.1f} s, serial FP64 C oracle"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is not built.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2512_19925_amd import workloads as W
+
+    w = W.full_scale(c=args.c, rho=args.rho, n_src=args.n_src)
+    total = args.warmup + args.steps
+    if total > w.n_steps:
+        print(f"warmup + steps must be <= {w.n_steps} time steps of the workload", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.init()
+    hww = run_gpu(w, total, args.warmup, analog=False, record=True)
+    value = hww["segments"] / hww["wall_s"]
+    ms_per_step = hww["wall_s"] * 1e3 / args.steps
+    achieved = hww["bytes"] / (hww["kernel_ms"] * 1e-3) / 1e9 if hww["kernel_ms"] > 0 else 0.0
+    line = {
+        "metric": METRIC, "value": value, "unit": "segments/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{w.name}: 1D slab, {w.n_cells} cells on [{w.x_lo},{w.x_hi}], sigma_t=1, "
+                               f"c={args.c}, v=1, isotropic unit pulse at x=0, {w.n_src:.0e} source "
+                               f"particles, dt={w.dt}, steps {args.warmup + 1}-{total} of {w.n_steps}, "
+                               f"HWW rho={w.rho} eps_min={w.eps_min}, MA k={w.ma_k} filtered closures, "
+                               f"{w.n_chunks - 1} window updates per step",
+                   "n_src": w.n_src, "n_cells": w.n_cells, "time_steps": args.steps},
+        "kernel_segments_per_s": hww["segments"] / (hww["kernel_ms"] * 1e-3) if hww["kernel_ms"] else None,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "sweep_kernel<double>",
+                     "launches": hww["launches"], "avg_launch_ms": hww["kernel_ms"] / max(hww["launches"], 1),
+                     "bytes_per_launch": hww["bytes"] / max(hww["launches"], 1)},
+    }
+    if not args.no_analog:
+        ana = run_gpu(w.with_(analog=True), total, args.warmup, analog=True, record=True)
+        ratio = [a / b for a, b in zip(hww["fom_sigma"], ana["fom_sigma"]) if b > 0]
+        line["fom"] = {"kind": "FOM_sigma of the track-length flux, per time step",
+                       "hww_over_plain_mean": float(np.mean(ratio)) if ratio else None,
+                       "hww_over_plain_first_last": [ratio[0], ratio[-1]] if ratio else None,
+                       "plain_segments_per_s": ana["segments"] / ana["wall_s"],
+                       "plain_ms_per_step": ana["wall_s"] * 1e3 / args.steps}
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    if args.out:
+        with open(args.out, "w") as f:
+            json.dump({"hww": hww, "line": line}, f, default=float)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,163 @@
+/*
+ * hww.h -- C ABI of the MI355X (gfx950) hybrid weight-window sweep library.
+ *
+ * The library runs one time step of the hybrid weight-window (HWW) Monte
+ * Carlo method of Shaw & Anistratov (arXiv 2512.19925) on the GPU: flight,
+ * collision and census of a 1D monoenergetic slab particle bank, track-length
+ * and time-crossing tallies of the scalar flux, current and second angular
+ * moment, split/roulette against weight windows, and the hybrid low-order
+ * second-moment (HLOSM) solve that sets the window centres.
+ *
+ * Conventions shared by every entry point:
+ *  - Return value: HWW_OK (0) or a negative HWW_E_* code.  hww_last_error()
+ *    gives a text for the last failure of a handle.
+ *  - Host arrays passed in are borrowed for the duration of the call and
+ *    copied; output arrays are caller-allocated host memory.
+ *  - Device memory: the caller allocates one workspace of
+ *    hww_workspace_bytes() bytes (any device allocation, 256-byte aligned)
+ *    and keeps it alive until hww_destroy(); the library allocates no device
+ *    memory of its own.  All device work is queued on the HIP stream given
+ *    at init.  A handle is not thread-safe.
+ *  - Calls queue work asynchronously.  Errors raised on the device (bank
+ *    overflow, a non-finite or non-positive window, a zero pivot) are
+ *    reported by the next call that synchronises the stream:
+ *    hww_sweep_step() with a non-NULL stats pointer, hww_solve_losm() with a
+ *    non-NULL output, hww_read_tallies() and hww_sync().
+ *
+ * Mesh: cell i (0-based) is [edges[i], edges[i+1]].  A particle exactly on an
+ * interior edge belongs to the cell it moves into.  Boundaries are vacuum:
+ * leaving particles are scored by the face estimators and die.
+ */
+#ifndef HWW_H
+#define HWW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HWW_OK 0
+#define HWW_E_INVALID_ARG (-1) /* bad sizes, sigma_s > sigma_t, non-ascending edges, NULL pointers */
+#define HWW_E_STATE (-2)       /* step or chunk out of order                                      */
+#define HWW_E_CAPACITY (-3)    /* a bank or daughter queue overflowed; the step's tallies are void */
+#define HWW_E_DEVICE (-4)      /* a HIP call failed                                               */
+#define HWW_E_NUMERIC (-5)     /* non-finite / non-positive window, zero pivot in the LOSM solve  */
+
+#define HWW_FP64 0 /* FP64 flight arithmetic                                         */
+#define HWW_FP32 1 /* FP32 position/direction/flight arithmetic, FP64 weights/tallies */
+
+/* Problem of one replica (Sec. 3 Eqs. HO_transport, t-eq-bc, t-eq-ic with
+ * q = 0, vacuum boundaries and an isotropic unit-weight pulse at src_x, t = 0). */
+typedef struct hww_problem {
+  int32_t n_cells;        /* I >= 1                                               */
+  const double *edges;    /* I+1 ascending cell edges (host)                      */
+  const double *sigma_t;  /* I total cross sections, > 0 (host)                   */
+  const double *sigma_s;  /* I scattering cross sections, 0 <= sigma_s <= sigma_t */
+  double speed;           /* v > 0                                                */
+  double dt;              /* uniform time step > 0                                */
+  int32_t n_steps;        /* number of time steps                                 */
+  double src_x;           /* pulse position, inside [edges[0], edges[I]]          */
+  int64_t n_src;          /* source particles (weight 1 each), < 2^32             */
+  int64_t bank_capacity;  /* max particles in a census bank (>= n_src)            */
+  uint32_t seed;          /* Philox key word 0                                    */
+  uint32_t replica;       /* Philox key word 1 = (replica << 4) | slot, < 2^28    */
+  int32_t n_batches;      /* statistical batches B (history src mod B), 1..64     */
+  int32_t precision;      /* HWW_FP64 or HWW_FP32                                 */
+  int32_t n_chunks;       /* u_ww + 1 window-update chunks per step, 1..8         */
+} hww_problem;
+
+typedef struct hww_handle hww_handle;
+
+/* Counters of the most recent hww_sweep_step (all generations of daughters). */
+typedef struct hww_step_stats {
+  uint64_t segments, collisions, scatters, absorptions, crossings, leaks, census;
+  uint64_t splits, daughters, rr_kill, rr_survive, histories;
+  uint64_t generations;   /* kernel passes (1 + daughter generations)            */
+  double kernel_ms;       /* summed sweep-kernel time of the call (HIP events)   */
+  uint64_t bytes_moved;   /* algorithmic bank bytes read + written by the call   */
+} hww_step_stats;
+
+/* Options of an HLOSM solve (Sec. 3 Eqs. losm-disc / losm-disc-semi, Sec. 4). */
+typedef struct hww_losm_opts {
+  double theta;           /* 1/2 Crank-Nicolson, 1 backward Euler                 */
+  int32_t implicit;       /* 0: semi-implicit at step start (lagged closures F^{n-1}, P^{n-1});
+                             1: fully implicit inside the step with the closures of the chunks
+                                already swept, scaled by W_start / W_done          */
+  int32_t filter;         /* 0: none, 1: moving average (Eq. moving_average)      */
+  int32_t ma_k;           /* moving-average half width k                          */
+  double eps_min;         /* window floor of Eq. ww-center, 0 < eps_min <= 1      */
+  double rho;             /* window width rho >= 1 (Eq. ww-c&f)                   */
+  int32_t closure_track;  /* 0: closures from time-layer (census) tallies;
+                             1: from track-length tallies of the step            */
+  int32_t apply_windows;  /* 1: set the window centres from the solution         */
+} hww_losm_opts;
+
+/* Tally kinds for hww_read_tallies. */
+#define HWW_TALLY_CELLS 0    /* double [B][I][6]: track phi, J, K; census phi, J, K   */
+#define HWW_TALLY_BOUNDARY 1 /* double [B][2][3]: faces (left, right) x (phi, P, F)   */
+#define HWW_TALLY_TRACKS 2   /* uint64 [I]: segments per cell                          */
+#define HWW_TALLY_PREV_CELLS 3    /* HWW_TALLY_CELLS of the previous step              */
+#define HWW_TALLY_PREV_BOUNDARY 4 /* HWW_TALLY_BOUNDARY of the previous step           */
+#define HWW_TALLY_WINDOWS 5  /* double [3][I]: centre, ceiling, floor (zeros if analog) */
+#define HWW_TALLY_BANK_COUNTS 6   /* uint64 [2]: start-bank and census-bank sizes      */
+
+/* Bytes of device workspace the problem needs. Returns < 0 on invalid input. */
+int64_t hww_workspace_bytes(const hww_problem *problem);
+
+/* Validate and copy the problem, lay the workspace out, and build the source
+ * bank at t^0 (isotropic directions from Philox slot 3) with its census
+ * tallies, which are the initial condition of step 1.  dev_workspace must
+ * hold ws_bytes >= hww_workspace_bytes() bytes of device memory.
+ * hip_stream is a hipStream_t (NULL = default stream).  On success *out
+ * receives a handle owned by the caller (release with hww_destroy). */
+int hww_init_problem(const hww_problem *problem, void *dev_workspace, int64_t ws_bytes,
+                     void *hip_stream, hww_handle **out);
+
+/* Set absolute window centres ww_i (Sec. 2): ceiling = ww*rho, floor = ww/rho.
+ * centre: I positive finite host doubles, or NULL for analog (no windows).
+ * Errors: HWW_E_INVALID_ARG (rho < 1), HWW_E_NUMERIC (a centre <= 0 or not finite). */
+int hww_set_windows(hww_handle *h, const double *centre, double rho);
+
+/* Sweep chunk `chunk` of time step `step` (1-based): every particle of the
+ * start-of-step bank in that chunk gets the start-of-step window check and is
+ * transported to census, leakage, absorption or roulette death, together with
+ * all daughters split off on the way (Sec. 2, Sec. 3).  Chunks of a step run
+ * in order 0..n_chunks-1; chunk 0 of step n needs step n-1 complete and turns
+ * its census bank into the start bank.  stats may be NULL (then the call does
+ * not wait for the GPU).  Errors: HWW_E_STATE, HWW_E_CAPACITY, HWW_E_DEVICE. */
+int hww_sweep_step(hww_handle *h, int32_t step, int32_t chunk, hww_step_stats *stats);
+
+/* Solve the HLOSM equations (Sec. 3) from the tallies on the device:
+ * semi-implicit (needs the previous step complete; sets windows for the next
+ * step) or fully implicit (inside a step after chunk p < n_chunks-1).  With
+ * apply_windows the window centres become s * [(max(phi,0)/max phi)(1-eps)+eps]
+ * where s = (start-bank weight of the step) / n_src.
+ * phi_out: I+2 host doubles (phi_0, cell averages, phi_{I+1}) or NULL;
+ * J_out: I+1 host doubles (edge currents) or NULL. */
+int hww_solve_losm(hww_handle *h, const hww_losm_opts *opts, double *phi_out, double *J_out);
+
+/* Copy a tally array of the current step to host memory (raw per-batch sums,
+ * not normalised: track sums are w*l, census sums v*w, face sums w f(mu)/|mu|).
+ * out_bytes must equal the size of the kind.  Synchronises the stream. */
+int hww_read_tallies(hww_handle *h, int32_t kind, void *out, int64_t out_bytes);
+
+/* Copy one bank to host memory (for checks): which = 0 start bank of the
+ * current step, 1 census bank.  Arrays hold up to `cap` particles; *count
+ * receives the number of particles.  Any array pointer may be NULL. */
+int hww_read_bank(hww_handle *h, int32_t which, int64_t cap, int64_t *count, double *x, double *mu,
+                  double *w, uint32_t *src, uint64_t *lin, uint32_t *e, int32_t *cell, int32_t *chunk);
+
+/* Wait for the stream and report any pending device error. */
+int hww_sync(hww_handle *h);
+
+/* Text of the last error of the handle (or of the last failed init if h is NULL). */
+const char *hww_last_error(const hww_handle *h);
+
+/* Release the host state of the handle (the workspace stays the caller's). */
+void hww_destroy(hww_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

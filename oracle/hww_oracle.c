@@ -686,7 +686,12 @@ int orc_solve_losm(orc_sim *s, const orc_losm_opts *o, double *phi_out, double *
     for (int c = 0; c < s->n_chunks; ++c) nadd(&wtot, nval(&s->w_chunk_start[c]));
     nsum done = {0, 0};
     for (int c = 0; c < s->next_chunk; ++c) nadd(&done, nval(&s->w_chunk_start[c]));
-    if (!(nval(&done) > 0.0)) return -5;
+    if (!(nval(&done) > 0.0)) {
+      /* No start weight swept yet: no closures exist, the update is skipped. */
+      if (phi_out) memset(phi_out, 0, sizeof(double) * (I + 2));
+      if (J_out) memset(J_out, 0, sizeof(double) * (I + 1));
+      return 0;
+    }
     scale = nval(&wtot) / nval(&done);
   }
 
@@ -739,8 +744,9 @@ int orc_solve_losm(orc_sim *s, const orc_losm_opts *o, double *phi_out, double *
   if (rc == 0) {
     if (phi_out) memcpy(phi_out, phi_n, sizeof(double) * (I + 2));
     if (J_out) memcpy(J_out, J_n, sizeof(double) * (I + 1));
-    if (o->apply_windows) {
-      double sc = nval(&wtot) / (double)s->n_src;
+    double sc = nval(&wtot) / (double)s->n_src;
+    /* An empty bank has nothing to window: the windows stay as they are. */
+    if (o->apply_windows && sc > 0.0) {
       rc = orc_ww_centres(I, phi_n + 1, o->eps_min, sc, tmp);
       if (rc == 0) rc = orc_set_windows(s, tmp, o->rho);
     }

@@ -1,0 +1,109 @@
+// Internal definitions shared by the HIP kernels and the host runtime of the
+// hybrid weight-window sweep library.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hww {
+
+// Device error bits (ORed into one word of the workspace).
+enum : uint32_t { ERR_CAPACITY = 1u, ERR_NUMERIC = 2u, ERR_SPLIT = 4u };
+
+// Counter slots (per step, uint64).
+enum {
+  C_SEGMENTS = 0, C_COLLISIONS, C_SCATTERS, C_ABSORPTIONS, C_CROSSINGS, C_LEAKS, C_CENSUS,
+  C_SPLITS, C_DAUGHTERS, C_RR_KILL, C_RR_SURVIVE, C_HISTORIES, C_NCOUNTERS = 16
+};
+
+// Random-number slots of the keying contract: key = (seed, (replica << 4) | slot),
+// counter = (src, lineage lo, lineage hi, event index).
+enum { SLOT_FLIGHT = 0, SLOT_EVENT = 1, SLOT_START = 2, SLOT_BIRTH = 3, SLOT_LIN_EVENT = 4,
+       SLOT_LIN_START = 5 };
+
+// Structure-of-arrays particle bank: B * n_chunks regions of cap_r slots each;
+// region r = batch * n_chunks + chunk holds the particles of that batch whose
+// next step starts in that chunk.
+template <typename Real>
+struct Bank {
+  Real *x, *mu;
+  double *w;
+  uint64_t *lin;
+  uint32_t *src, *e;
+  int32_t *cell;
+  uint32_t *count;  // [B * n_chunks]
+};
+
+// Daughter queue: one region of cap_d slots per batch.
+template <typename Real>
+struct Queue {
+  Real *x, *mu;
+  double *w, *tau;
+  uint64_t *lin;
+  uint32_t *src, *e;
+  int32_t *cell;
+  uint32_t *count;  // [B]
+};
+
+template <typename Real>
+struct SweepArgs {
+  int32_t I, B, nc;
+  double v, dt;
+  uint32_t seed, key1;  // key1 = replica << 4
+  const double *edges, *sig_t, *cratio;
+  const double *centre, *wceil, *wfloor;
+  int32_t ww_on;
+  int32_t gen, chunk;
+  int64_t cap_r, cap_d;
+  Bank<Real> in_bank;
+  Queue<Real> in_q;
+  Bank<Real> census;
+  Queue<Real> out_q;
+  uint32_t *cursor;                // [B]
+  double *tal;                     // [B][I][6]
+  double *bnd;                     // [B][2][3]
+  unsigned long long *tracks;      // [I]
+  unsigned long long *counters;    // [C_NCOUNTERS]
+  double *wnext;                   // [nc]
+  uint32_t *err;
+};
+
+struct SourceArgs {
+  int32_t I, B, nc;
+  double v, dt, src_x;
+  int64_t n_src;
+  uint32_t seed, key1;
+  const double *edges;
+  int64_t cap_r;
+  double *tal;  // census part of [B][I][6]
+  double *wnext;
+  uint32_t *err;
+};
+
+struct LosmArgs {
+  int32_t I, B, nc;
+  double v, dt, n_src;
+  const double *edges, *sig_t, *sig_s;
+  const double *tal_ic, *bnd_ic;  // tally set of the initial condition (census at t^{n-1})
+  const double *tal_cl, *bnd_cl;  // tally set of the closures (same as tal_ic when semi-implicit)
+  const double *wstart, *wnext;   // [nc] chunk weights of the start bank / census bank
+  int32_t next_chunk;             // chunks already swept in the step (implicit solve)
+  double theta;
+  int32_t implicit, filter, ma_k, closure_track, apply_windows;
+  double eps_min, rho;
+  double *scratch;                // >= 16 * (2I + 4) doubles
+  double *centre, *wceil, *wfloor;
+  double *phi_out, *J_out;        // I+2, I+1 (device)
+  uint32_t *err;
+  int32_t *status;                // 0 ok, else error bits of this solve
+};
+
+// Launchers (defined in the .hip files).
+hipError_t launch_sweep_f64(const SweepArgs<double> &a, int grid, int block, size_t lds, hipStream_t s);
+hipError_t launch_source_f64(const SourceArgs &a, const Bank<double> &bank, hipStream_t s);
+hipError_t launch_losm(const LosmArgs &a, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);
+hipError_t launch_rotate_chunks(double *wstart, double *wnext, int nc, hipStream_t s);
+
+}  // namespace hww

@@ -1,0 +1,641 @@
+// Host runtime and C ABI of the hybrid weight-window sweep library (see
+// include/hww.h for the contract of every entry point).  The runtime owns no
+// device memory: it carves the caller's workspace into banks, queues, tally
+// sets and solver scratch, and queues kernels on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/hww.h"
+#include "hww_internal.h"
+
+using namespace hww;
+
+namespace {
+
+constexpr int kMaxGenerations = 64;
+constexpr double kRegionSlack = 1.5;
+
+struct Layout {
+  int64_t total = 0;
+  int64_t cap_r = 0, cap_d = 0;
+  int64_t off_edges, off_sigt, off_sigs, off_cratio, off_centre, off_ceil, off_floor;
+  int64_t off_bank[2], off_bank_counts[2], off_q[2], off_q_counts[2];
+  int64_t off_tal[2], off_bnd[2], off_tracks, off_counters, off_wstart, off_wnext;
+  int64_t off_cursor, off_err, off_status, off_scratch, off_phi_out, off_J_out;
+};
+
+int64_t align_up(int64_t v) { return (v + 255) & ~int64_t(255); }
+
+struct Carver {
+  int64_t cur = 0;
+  int64_t take(int64_t bytes) {
+    const int64_t o = cur;
+    cur = align_up(cur + bytes);
+    return o;
+  }
+};
+
+bool real_bytes(int precision, int64_t *rb) {
+  if (precision == HWW_FP64) { *rb = 8; return true; }
+  return false;
+}
+
+
+void make_layout(const hww_problem &p, Layout *L) {
+  const int64_t I = p.n_cells, B = p.n_batches, nc = p.n_chunks, R = B * nc;
+  int64_t rb = 8;
+  real_bytes(p.precision, &rb);
+  L->cap_r = (int64_t)std::ceil(kRegionSlack * (double)p.bank_capacity / (double)R) + 256;
+  L->cap_d = (p.bank_capacity + B - 1) / B + 4096;
+  Carver c;
+  L->off_edges = c.take(8 * (I + 1));
+  L->off_sigt = c.take(8 * I);
+  L->off_sigs = c.take(8 * I);
+  L->off_cratio = c.take(8 * I);
+  // centre, ceiling and floor are one contiguous [3][I] block
+  L->off_centre = c.take(8 * 3 * I);
+  L->off_ceil = L->off_centre + 8 * I;
+  L->off_floor = L->off_centre + 16 * I;
+  for (int k = 0; k < 2; ++k) {
+    L->off_bank[k] = c.take(0);
+    // x, mu, w, lin, src, e, cell arrays, each R * cap_r long
+    c.take(rb * R * L->cap_r);
+    c.take(rb * R * L->cap_r);
+    c.take(8 * R * L->cap_r);
+    c.take(8 * R * L->cap_r);
+    c.take(4 * R * L->cap_r);
+    c.take(4 * R * L->cap_r);
+    c.take(4 * R * L->cap_r);
+    L->off_bank_counts[k] = c.take(4 * R);
+  }
+  for (int k = 0; k < 2; ++k) {
+    L->off_q[k] = c.take(0);
+    c.take(rb * B * L->cap_d);
+    c.take(rb * B * L->cap_d);
+    c.take(8 * B * L->cap_d);
+    c.take(8 * B * L->cap_d);
+    c.take(8 * B * L->cap_d);
+    c.take(4 * B * L->cap_d);
+    c.take(4 * B * L->cap_d);
+    c.take(4 * B * L->cap_d);
+    L->off_q_counts[k] = c.take(4 * B);
+  }
+  for (int k = 0; k < 2; ++k) {
+    L->off_tal[k] = c.take(8 * B * I * 6);
+    L->off_bnd[k] = c.take(8 * B * 6);
+  }
+  L->off_tracks = c.take(8 * I);
+  L->off_counters = c.take(8 * C_NCOUNTERS);
+  L->off_wstart = c.take(8 * nc);
+  L->off_wnext = c.take(8 * nc);
+  L->off_cursor = c.take(4 * B);
+  L->off_err = c.take(4);
+  L->off_status = c.take(4);
+  L->off_scratch = c.take(8 * 24 * (I + 4));
+  L->off_phi_out = c.take(8 * (I + 2));
+  L->off_J_out = c.take(8 * (I + 1));
+  L->total = c.cur;
+}
+
+template <typename Real>
+Bank<Real> bank_view(char *ws, int64_t off, int64_t off_counts, int64_t slots) {
+  Bank<Real> b;
+  int64_t o = off;
+  auto take = [&](int64_t bytes) {
+    char *p = ws + o;
+    o = align_up(o + bytes);
+    return p;
+  };
+  b.x = reinterpret_cast<Real *>(take(sizeof(Real) * slots));
+  b.mu = reinterpret_cast<Real *>(take(sizeof(Real) * slots));
+  b.w = reinterpret_cast<double *>(take(8 * slots));
+  b.lin = reinterpret_cast<uint64_t *>(take(8 * slots));
+  b.src = reinterpret_cast<uint32_t *>(take(4 * slots));
+  b.e = reinterpret_cast<uint32_t *>(take(4 * slots));
+  b.cell = reinterpret_cast<int32_t *>(take(4 * slots));
+  b.count = reinterpret_cast<uint32_t *>(ws + off_counts);
+  return b;
+}
+
+template <typename Real>
+Queue<Real> queue_view(char *ws, int64_t off, int64_t off_counts, int64_t slots) {
+  Queue<Real> q;
+  int64_t o = off;
+  auto take = [&](int64_t bytes) {
+    char *p = ws + o;
+    o = align_up(o + bytes);
+    return p;
+  };
+  q.x = reinterpret_cast<Real *>(take(sizeof(Real) * slots));
+  q.mu = reinterpret_cast<Real *>(take(sizeof(Real) * slots));
+  q.w = reinterpret_cast<double *>(take(8 * slots));
+  q.tau = reinterpret_cast<double *>(take(8 * slots));
+  q.lin = reinterpret_cast<uint64_t *>(take(8 * slots));
+  q.src = reinterpret_cast<uint32_t *>(take(4 * slots));
+  q.e = reinterpret_cast<uint32_t *>(take(4 * slots));
+  q.cell = reinterpret_cast<int32_t *>(take(4 * slots));
+  q.count = reinterpret_cast<uint32_t *>(ws + off_counts);
+  return q;
+}
+
+std::string g_init_error;
+
+}  // namespace
+
+struct hww_handle {
+  hww_problem p{};
+  int I = 0, B = 0, nc = 0, R = 0;
+  Layout L;
+  hipStream_t stream = nullptr;
+  char *ws = nullptr;
+  double *edges, *sig_t, *sig_s, *cratio, *centre, *wceil, *wfloor;
+  Bank<double> bank[2];
+  Queue<double> q[2];
+  double *tal[2], *bnd[2];
+  unsigned long long *tracks, *counters;
+  double *wstart, *wnext;
+  uint32_t *cursor, *err;
+  int32_t *status;
+  double *scratch, *phi_out, *J_out;
+
+  int start_bank = 0;  // census bank = 1 - start_bank
+  int cur_tal = 0;
+  int step = 0, next_chunk = 0;
+  int ww_on = 0;
+  int fatal = 0;
+  int n_cu = 256;
+  int block = 512;
+  std::vector<uint32_t> census_counts;  // host mirror, refreshed after each sweep
+  std::vector<uint32_t> start_counts;
+  uint64_t last_counters[C_NCOUNTERS] = {};
+  hipEvent_t ev[2 * kMaxGenerations] = {};
+  std::string msg;
+};
+
+namespace {
+
+int fail(hww_handle *h, int code, const std::string &m) {
+  if (h) h->msg = m;
+  else g_init_error = m;
+  return code;
+}
+
+int check_hip(hww_handle *h, hipError_t e, const char *what) {
+  if (e == hipSuccess) return HWW_OK;
+  return fail(h, HWW_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(h, expr)                                \
+  do {                                                 \
+    int rc__ = check_hip((h), (expr), #expr);          \
+    if (rc__ != HWW_OK) return rc__;                   \
+  } while (0)
+
+int validate(const hww_problem *p, std::string *why) {
+  if (!p) { *why = "problem is NULL"; return HWW_E_INVALID_ARG; }
+  if (p->n_cells < 1 || !p->edges || !p->sigma_t || !p->sigma_s) { *why = "bad mesh or cross sections"; return HWW_E_INVALID_ARG; }
+  if (!(p->speed > 0.0) || !(p->dt > 0.0) || p->n_steps < 1) { *why = "speed, dt and n_steps must be positive"; return HWW_E_INVALID_ARG; }
+  if (p->n_src < 0 || p->n_src > 0xFFFFFFFFll) { *why = "n_src out of range"; return HWW_E_INVALID_ARG; }
+  if (p->bank_capacity < p->n_src || p->bank_capacity < 1 || p->bank_capacity > (int64_t)1 << 34) { *why = "bank_capacity out of range"; return HWW_E_INVALID_ARG; }
+  if (p->n_batches < 1 || p->n_batches > 64) { *why = "n_batches must be 1..64"; return HWW_E_INVALID_ARG; }
+  if (p->n_chunks < 1 || p->n_chunks > 8) { *why = "n_chunks must be 1..8"; return HWW_E_INVALID_ARG; }
+  if (p->replica >= (1u << 28)) { *why = "replica must be < 2^28"; return HWW_E_INVALID_ARG; }
+  int64_t rb;
+  if (!real_bytes(p->precision, &rb)) { *why = "unsupported precision"; return HWW_E_INVALID_ARG; }
+  for (int i = 0; i < p->n_cells; ++i) {
+    if (!(p->edges[i + 1] > p->edges[i])) { *why = "edges must ascend"; return HWW_E_INVALID_ARG; }
+    if (!(p->sigma_t[i] > 0.0) || !(p->sigma_s[i] >= 0.0) || p->sigma_s[i] > p->sigma_t[i] ||
+        !std::isfinite(p->sigma_t[i])) { *why = "need 0 < sigma_t, 0 <= sigma_s <= sigma_t"; return HWW_E_INVALID_ARG; }
+  }
+  if (!(p->src_x >= p->edges[0] && p->src_x <= p->edges[p->n_cells])) { *why = "src_x outside the mesh"; return HWW_E_INVALID_ARG; }
+  // LDS histogram of one work-group: [I][6] doubles + [I] u32 + small.
+  const int64_t lds = (int64_t)p->n_cells * 6 * 8 + (int64_t)(p->n_chunks + 6) * 8 + ((int64_t)p->n_cells + C_NCOUNTERS) * 4;
+  if (lds > 160 * 1024) { *why = "too many cells for the LDS histogram (I <= 3300)"; return HWW_E_INVALID_ARG; }
+  return HWW_OK;
+}
+
+size_t lds_bytes(const hww_handle *h) {
+  return (size_t)h->I * 6 * 8 + (size_t)(h->nc + 6) * 8 + ((size_t)h->I + C_NCOUNTERS) * 4;
+}
+
+// Read the device error word; map it to an ABI code (sticky).
+int poll_errors(hww_handle *h) {
+  uint32_t e = 0;
+  HIPCHK(h, hipMemcpyAsync(&e, h->err, 4, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (e & (ERR_CAPACITY | ERR_SPLIT)) {
+    h->fatal = HWW_E_CAPACITY;
+    return fail(h, HWW_E_CAPACITY, (e & ERR_SPLIT) ? "a split exceeded 1e9 daughters" : "bank or daughter queue overflow");
+  }
+  if (e & ERR_NUMERIC) {
+    h->fatal = HWW_E_NUMERIC;
+    return fail(h, HWW_E_NUMERIC, "non-finite or non-positive window, or zero pivot in the LOSM solve");
+  }
+  return HWW_OK;
+}
+
+int grid_for(const hww_handle *h, uint64_t max_per_batch) {
+  const uint64_t per_wg = (uint64_t)h->block * 2;
+  uint64_t k = (max_per_batch + per_wg - 1) / per_wg;
+  const uint64_t kmax = std::max<uint64_t>(1, (uint64_t)(2 * h->n_cu) / (uint64_t)h->B);
+  k = std::max<uint64_t>(1, std::min(k, kmax));
+  return (int)(k * (uint64_t)h->B);
+}
+
+SweepArgs<double> base_args(hww_handle *h) {
+  SweepArgs<double> a{};
+  a.I = h->I; a.B = h->B; a.nc = h->nc;
+  a.v = h->p.speed; a.dt = h->p.dt;
+  a.seed = h->p.seed; a.key1 = h->p.replica << 4;
+  a.edges = h->edges; a.sig_t = h->sig_t; a.cratio = h->cratio;
+  a.centre = h->centre; a.wceil = h->wceil; a.wfloor = h->wfloor;
+  a.ww_on = h->ww_on;
+  a.cap_r = h->L.cap_r; a.cap_d = h->L.cap_d;
+  a.in_bank = h->bank[h->start_bank];
+  a.census = h->bank[1 - h->start_bank];
+  a.cursor = h->cursor;
+  a.tal = h->tal[h->cur_tal];
+  a.bnd = h->bnd[h->cur_tal];
+  a.tracks = h->tracks;
+  a.counters = h->counters;
+  a.wnext = h->wnext;
+  a.err = h->err;
+  return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t hww_workspace_bytes(const hww_problem *problem) {
+  std::string why;
+  if (validate(problem, &why) != HWW_OK) return HWW_E_INVALID_ARG;
+  Layout L;
+  make_layout(*problem, &L);
+  return L.total;
+}
+
+int hww_init_problem(const hww_problem *problem, void *dev_workspace, int64_t ws_bytes, void *hip_stream,
+                     hww_handle **out) {
+  std::string why;
+  if (!out) return fail(nullptr, HWW_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  int rc = validate(problem, &why);
+  if (rc != HWW_OK) return fail(nullptr, rc, why);
+  Layout L;
+  make_layout(*problem, &L);
+  if (!dev_workspace || ws_bytes < L.total) return fail(nullptr, HWW_E_INVALID_ARG, "workspace too small");
+  if (reinterpret_cast<uintptr_t>(dev_workspace) % 256 != 0) return fail(nullptr, HWW_E_INVALID_ARG, "workspace not 256-byte aligned");
+
+  hww_handle *h = new hww_handle();
+  h->p = *problem;
+  h->p.edges = h->p.sigma_t = h->p.sigma_s = nullptr;
+  h->I = problem->n_cells;
+  h->B = problem->n_batches;
+  h->nc = problem->n_chunks;
+  h->R = h->B * h->nc;
+  h->L = L;
+  h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  h->ws = reinterpret_cast<char *>(dev_workspace);
+  char *ws = h->ws;
+  h->edges = reinterpret_cast<double *>(ws + L.off_edges);
+  h->sig_t = reinterpret_cast<double *>(ws + L.off_sigt);
+  h->sig_s = reinterpret_cast<double *>(ws + L.off_sigs);
+  h->cratio = reinterpret_cast<double *>(ws + L.off_cratio);
+  h->centre = reinterpret_cast<double *>(ws + L.off_centre);
+  h->wceil = reinterpret_cast<double *>(ws + L.off_ceil);
+  h->wfloor = reinterpret_cast<double *>(ws + L.off_floor);
+  for (int k = 0; k < 2; ++k) {
+    h->bank[k] = bank_view<double>(ws, L.off_bank[k], L.off_bank_counts[k], (int64_t)h->R * L.cap_r);
+    h->q[k] = queue_view<double>(ws, L.off_q[k], L.off_q_counts[k], (int64_t)h->B * L.cap_d);
+    h->tal[k] = reinterpret_cast<double *>(ws + L.off_tal[k]);
+    h->bnd[k] = reinterpret_cast<double *>(ws + L.off_bnd[k]);
+  }
+  h->tracks = reinterpret_cast<unsigned long long *>(ws + L.off_tracks);
+  h->counters = reinterpret_cast<unsigned long long *>(ws + L.off_counters);
+  h->wstart = reinterpret_cast<double *>(ws + L.off_wstart);
+  h->wnext = reinterpret_cast<double *>(ws + L.off_wnext);
+  h->cursor = reinterpret_cast<uint32_t *>(ws + L.off_cursor);
+  h->err = reinterpret_cast<uint32_t *>(ws + L.off_err);
+  h->status = reinterpret_cast<int32_t *>(ws + L.off_status);
+  h->scratch = reinterpret_cast<double *>(ws + L.off_scratch);
+  h->phi_out = reinterpret_cast<double *>(ws + L.off_phi_out);
+  h->J_out = reinterpret_cast<double *>(ws + L.off_J_out);
+  h->census_counts.assign(h->R, 0);
+  h->start_counts.assign(h->R, 0);
+
+  auto bail = [&](int code) {
+    g_init_error = h->msg;
+    for (auto &e : h->ev)
+      if (e) (void)hipEventDestroy(e);
+    delete h;
+    return code;
+  };
+#define INITCHK(expr)                                  \
+  do {                                                 \
+    int rc__ = check_hip(h, (expr), #expr);            \
+    if (rc__ != HWW_OK) return bail(rc__);             \
+  } while (0)
+
+  int dev = 0;
+  INITCHK(hipGetDevice(&dev));
+  INITCHK(hipDeviceGetAttribute(&h->n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+  for (auto &e : h->ev) INITCHK(hipEventCreate(&e));
+
+  const int I = h->I;
+  std::vector<double> cr(I);
+  for (int i = 0; i < I; ++i) cr[i] = problem->sigma_s[i] / problem->sigma_t[i];
+  INITCHK(hipMemcpyAsync(h->edges, problem->edges, 8 * (I + 1), hipMemcpyHostToDevice, h->stream));
+  INITCHK(hipMemcpyAsync(h->sig_t, problem->sigma_t, 8 * I, hipMemcpyHostToDevice, h->stream));
+  INITCHK(hipMemcpyAsync(h->sig_s, problem->sigma_s, 8 * I, hipMemcpyHostToDevice, h->stream));
+  INITCHK(hipMemcpyAsync(h->cratio, cr.data(), 8 * I, hipMemcpyHostToDevice, h->stream));
+  // Zero everything the kernels accumulate into.
+  for (int k = 0; k < 2; ++k) {
+    INITCHK(launch_fill_u32(h->bank[k].count, 0u, h->R, h->stream));
+    INITCHK(launch_fill_u32(h->q[k].count, 0u, h->B, h->stream));
+    INITCHK(launch_fill_f64(h->tal[k], 0.0, (int64_t)h->B * I * 6, h->stream));
+    INITCHK(launch_fill_f64(h->bnd[k], 0.0, (int64_t)h->B * 6, h->stream));
+  }
+  INITCHK(launch_fill_u32(reinterpret_cast<uint32_t *>(h->tracks), 0u, 2 * (int64_t)I, h->stream));
+  INITCHK(launch_fill_u32(reinterpret_cast<uint32_t *>(h->counters), 0u, 2 * C_NCOUNTERS, h->stream));
+  INITCHK(launch_fill_f64(h->wstart, 0.0, h->nc, h->stream));
+  INITCHK(launch_fill_f64(h->wnext, 0.0, h->nc, h->stream));
+  INITCHK(launch_fill_f64(h->centre, 0.0, 3 * (int64_t)I, h->stream));
+  INITCHK(launch_fill_u32(h->err, 0u, 1, h->stream));
+
+  // Source bank = census bank of step 0 (bank 1); its tallies fill set 0.
+  h->start_bank = 0;
+  h->cur_tal = 0;
+  SourceArgs sa{};
+  sa.I = I; sa.B = h->B; sa.nc = h->nc;
+  sa.v = problem->speed; sa.dt = problem->dt; sa.src_x = problem->src_x;
+  sa.n_src = problem->n_src; sa.seed = problem->seed; sa.key1 = problem->replica << 4;
+  sa.edges = h->edges; sa.cap_r = L.cap_r;
+  sa.tal = h->tal[0]; sa.wnext = h->wnext; sa.err = h->err;
+  INITCHK(launch_source_f64(sa, h->bank[1], h->stream));
+  INITCHK(hipMemcpyAsync(h->census_counts.data(), h->bank[1].count, 4 * h->R, hipMemcpyDeviceToHost, h->stream));
+  int prc = poll_errors(h);
+  if (prc != HWW_OK) return bail(prc);
+  h->step = 0;
+  h->next_chunk = h->nc;
+  *out = h;
+  return HWW_OK;
+#undef INITCHK
+}
+
+int hww_set_windows(hww_handle *h, const double *centre, double rho) {
+  if (!h) return HWW_E_INVALID_ARG;
+  if (!centre) {
+    h->ww_on = 0;
+    return HWW_OK;
+  }
+  if (!(rho >= 1.0) || !std::isfinite(rho)) return fail(h, HWW_E_INVALID_ARG, "rho must be >= 1");
+  const int I = h->I;
+  std::vector<double> w3(3 * (size_t)I);
+  for (int i = 0; i < I; ++i) {
+    if (!(centre[i] > 0.0) || !std::isfinite(centre[i])) return fail(h, HWW_E_NUMERIC, "window centres must be positive and finite");
+    w3[i] = centre[i];
+    w3[I + i] = centre[i] * rho;
+    w3[2 * I + i] = centre[i] / rho;
+  }
+  HIPCHK(h, hipMemcpyAsync(h->centre, w3.data(), 8 * 3 * (size_t)I, hipMemcpyHostToDevice, h->stream));
+  // The host vector must outlive the copy.
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  h->ww_on = 1;
+  return HWW_OK;
+}
+
+int hww_sweep_step(hww_handle *h, int32_t step, int32_t chunk, hww_step_stats *stats) {
+  if (!h) return HWW_E_INVALID_ARG;
+  if (h->fatal) return fail(h, h->fatal, "an earlier error left the problem invalid");
+  if (chunk < 0 || chunk >= h->nc) return fail(h, HWW_E_INVALID_ARG, "chunk out of range");
+  if (chunk == 0) {
+    if (h->next_chunk != h->nc || step != h->step + 1 || step > h->p.n_steps)
+      return fail(h, HWW_E_STATE, "step out of order");
+    // The census bank of the finished step becomes the start bank.
+    h->start_bank = 1 - h->start_bank;
+    h->start_counts = h->census_counts;
+    HIPCHK(h, launch_fill_u32(h->bank[1 - h->start_bank].count, 0u, h->R, h->stream));
+    h->cur_tal = 1 - h->cur_tal;
+    HIPCHK(h, launch_fill_f64(h->tal[h->cur_tal], 0.0, (int64_t)h->B * h->I * 6, h->stream));
+    HIPCHK(h, launch_fill_f64(h->bnd[h->cur_tal], 0.0, (int64_t)h->B * 6, h->stream));
+    HIPCHK(h, launch_fill_u32(reinterpret_cast<uint32_t *>(h->tracks), 0u, 2 * (int64_t)h->I, h->stream));
+    HIPCHK(h, launch_fill_u32(reinterpret_cast<uint32_t *>(h->counters), 0u, 2 * C_NCOUNTERS, h->stream));
+    HIPCHK(h, launch_rotate_chunks(h->wstart, h->wnext, h->nc, h->stream));
+    std::fill(h->census_counts.begin(), h->census_counts.end(), 0u);
+    std::memset(h->last_counters, 0, sizeof h->last_counters);
+    h->step = step;
+    h->next_chunk = 0;
+  } else if (step != h->step || chunk != h->next_chunk) {
+    return fail(h, HWW_E_STATE, "chunk out of order");
+  }
+
+  const size_t lds = lds_bytes(h);
+  SweepArgs<double> a = base_args(h);
+  a.chunk = chunk;
+  uint64_t max_in = 0;
+  for (int b = 0; b < h->B; ++b) max_in = std::max<uint64_t>(max_in, h->start_counts[b * h->nc + chunk]);
+  int gen = 0;
+  int n_ev = 0;
+  std::vector<uint32_t> qc(h->B);
+  for (;;) {
+    if (gen >= kMaxGenerations) return fail(h, HWW_E_CAPACITY, "more than 64 generations of daughters");
+    const int qo = gen & 1;  // queue written by this generation
+    a.gen = gen;
+    a.out_q = h->q[qo];
+    if (gen > 0) a.in_q = h->q[1 - qo];
+    HIPCHK(h, launch_fill_u32(h->q[qo].count, 0u, h->B, h->stream));
+    HIPCHK(h, launch_fill_u32(h->cursor, 0u, h->B, h->stream));
+    if (max_in > 0) {
+      HIPCHK(h, hipEventRecord(h->ev[2 * n_ev], h->stream));
+      HIPCHK(h, launch_sweep_f64(a, grid_for(h, max_in), h->block, lds, h->stream));
+      HIPCHK(h, hipEventRecord(h->ev[2 * n_ev + 1], h->stream));
+      ++n_ev;
+    }
+    HIPCHK(h, hipMemcpyAsync(qc.data(), h->q[qo].count, 4 * h->B, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    uint64_t tot = 0;
+    max_in = 0;
+    for (int b = 0; b < h->B; ++b) {
+      tot += qc[b];
+      max_in = std::max<uint64_t>(max_in, qc[b]);
+    }
+    ++gen;
+    if (tot == 0) break;
+    if (max_in > (uint64_t)h->L.cap_d) break;  // overflow: reported below
+  }
+  h->next_chunk = chunk + 1;
+
+  unsigned long long cnt[C_NCOUNTERS];
+  HIPCHK(h, hipMemcpyAsync(cnt, h->counters, sizeof cnt, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipMemcpyAsync(h->census_counts.data(), h->bank[1 - h->start_bank].count, 4 * h->R,
+                           hipMemcpyDeviceToHost, h->stream));
+  int rc = poll_errors(h);
+  if (rc != HWW_OK) return rc;
+  uint64_t census_total = 0;
+  for (uint32_t c : h->census_counts) census_total += c;
+  if (census_total > (uint64_t)h->p.bank_capacity) {
+    h->fatal = HWW_E_CAPACITY;
+    return fail(h, HWW_E_CAPACITY, "census bank exceeds bank_capacity");
+  }
+  if (stats) {
+    uint64_t d[C_NCOUNTERS];
+    for (int k = 0; k < C_NCOUNTERS; ++k) d[k] = cnt[k] - h->last_counters[k];
+    stats->segments = d[C_SEGMENTS];
+    stats->collisions = d[C_COLLISIONS];
+    stats->scatters = d[C_SCATTERS];
+    stats->absorptions = d[C_ABSORPTIONS];
+    stats->crossings = d[C_CROSSINGS];
+    stats->leaks = d[C_LEAKS];
+    stats->census = d[C_CENSUS];
+    stats->splits = d[C_SPLITS];
+    stats->daughters = d[C_DAUGHTERS];
+    stats->rr_kill = d[C_RR_KILL];
+    stats->rr_survive = d[C_RR_SURVIVE];
+    stats->histories = d[C_HISTORIES];
+    stats->generations = (uint64_t)gen;
+    double ms = 0.0;
+    for (int k = 0; k < n_ev; ++k) {
+      float t = 0.0f;
+      HIPCHK(h, hipEventElapsedTime(&t, h->ev[2 * k], h->ev[2 * k + 1]));
+      ms += t;
+    }
+    stats->kernel_ms = ms;
+    const uint64_t rec = 44, drec = 52;
+    stats->bytes_moved = d[C_HISTORIES] * rec + d[C_CENSUS] * rec + d[C_DAUGHTERS] * 2 * drec;
+  }
+  for (int k = 0; k < C_NCOUNTERS; ++k) h->last_counters[k] = cnt[k];
+  return HWW_OK;
+}
+
+int hww_solve_losm(hww_handle *h, const hww_losm_opts *o, double *phi_out, double *J_out) {
+  if (!h || !o) return HWW_E_INVALID_ARG;
+  if (h->fatal) return fail(h, h->fatal, "an earlier error left the problem invalid");
+  if (!(o->theta > 0.0 && o->theta <= 1.0) || o->ma_k < 0 || (o->filter != 0 && o->filter != 1))
+    return fail(h, HWW_E_INVALID_ARG, "bad LOSM options");
+  if (o->apply_windows && (!(o->rho >= 1.0) || !(o->eps_min > 0.0 && o->eps_min <= 1.0)))
+    return fail(h, HWW_E_INVALID_ARG, "bad window options");
+  LosmArgs a{};
+  a.I = h->I; a.B = h->B; a.nc = h->nc;
+  a.v = h->p.speed; a.dt = h->p.dt; a.n_src = (double)h->p.n_src;
+  a.edges = h->edges; a.sig_t = h->sig_t; a.sig_s = h->sig_s;
+  if (!o->implicit) {
+    if (h->next_chunk != h->nc || h->step >= h->p.n_steps) return fail(h, HWW_E_STATE, "semi-implicit solve needs a finished step");
+    a.tal_ic = h->tal[h->cur_tal]; a.bnd_ic = h->bnd[h->cur_tal];
+    a.tal_cl = a.tal_ic; a.bnd_cl = a.bnd_ic;
+  } else {
+    if (h->step < 1 || h->next_chunk < 1 || h->next_chunk >= h->nc) return fail(h, HWW_E_STATE, "implicit solve needs a step in progress");
+    a.tal_ic = h->tal[1 - h->cur_tal]; a.bnd_ic = h->bnd[1 - h->cur_tal];
+    a.tal_cl = h->tal[h->cur_tal]; a.bnd_cl = h->bnd[h->cur_tal];
+  }
+  a.wstart = h->wstart; a.wnext = h->wnext; a.next_chunk = h->next_chunk;
+  a.theta = o->theta; a.implicit = o->implicit; a.filter = o->filter; a.ma_k = o->ma_k;
+  a.closure_track = o->closure_track; a.apply_windows = o->apply_windows;
+  a.eps_min = o->eps_min; a.rho = o->rho;
+  a.scratch = h->scratch; a.centre = h->centre; a.wceil = h->wceil; a.wfloor = h->wfloor;
+  a.phi_out = h->phi_out; a.J_out = h->J_out; a.err = h->err; a.status = h->status;
+  HIPCHK(h, launch_losm(a, h->stream));
+  if (o->apply_windows) h->ww_on = 1;
+  if (phi_out || J_out) {
+    if (phi_out) HIPCHK(h, hipMemcpyAsync(phi_out, h->phi_out, 8 * (size_t)(h->I + 2), hipMemcpyDeviceToHost, h->stream));
+    if (J_out) HIPCHK(h, hipMemcpyAsync(J_out, h->J_out, 8 * (size_t)(h->I + 1), hipMemcpyDeviceToHost, h->stream));
+    return poll_errors(h);
+  }
+  return HWW_OK;
+}
+
+int hww_read_tallies(hww_handle *h, int32_t kind, void *out, int64_t out_bytes) {
+  if (!h || !out) return HWW_E_INVALID_ARG;
+  const int64_t I = h->I, B = h->B;
+  const void *src = nullptr;
+  int64_t bytes = 0;
+  uint64_t counts[2];
+  switch (kind) {
+    case HWW_TALLY_CELLS: src = h->tal[h->cur_tal]; bytes = 8 * B * I * 6; break;
+    case HWW_TALLY_BOUNDARY: src = h->bnd[h->cur_tal]; bytes = 8 * B * 6; break;
+    case HWW_TALLY_TRACKS: src = h->tracks; bytes = 8 * I; break;
+    case HWW_TALLY_PREV_CELLS: src = h->tal[1 - h->cur_tal]; bytes = 8 * B * I * 6; break;
+    case HWW_TALLY_PREV_BOUNDARY: src = h->bnd[1 - h->cur_tal]; bytes = 8 * B * 6; break;
+    case HWW_TALLY_WINDOWS: src = h->centre; bytes = 8 * 3 * I; break;
+    case HWW_TALLY_BANK_COUNTS: bytes = 16; break;
+    default: return fail(h, HWW_E_INVALID_ARG, "unknown tally kind");
+  }
+  if (out_bytes != bytes) return fail(h, HWW_E_INVALID_ARG, "out_bytes does not match the tally kind");
+  if (kind == HWW_TALLY_BANK_COUNTS) {
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    uint64_t s0 = 0, s1 = 0;
+    for (uint32_t c : h->start_counts) s0 += c;
+    for (uint32_t c : h->census_counts) s1 += c;
+    counts[0] = h->step == 0 ? 0 : s0;
+    counts[1] = s1;
+    std::memcpy(out, counts, 16);
+    return HWW_OK;
+  }
+  if (kind == HWW_TALLY_WINDOWS && !h->ww_on) {
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    std::memset(out, 0, bytes);
+    return poll_errors(h);
+  }
+  HIPCHK(h, hipMemcpyAsync(out, src, bytes, hipMemcpyDeviceToHost, h->stream));
+  return poll_errors(h);
+}
+
+int hww_read_bank(hww_handle *h, int32_t which, int64_t cap, int64_t *count, double *x, double *mu, double *w,
+                  uint32_t *src, uint64_t *lin, uint32_t *e, int32_t *cell, int32_t *chunk) {
+  if (!h || !count || (which != 0 && which != 1)) return HWW_E_INVALID_ARG;
+  if (which == 0 && h->step == 0) {
+    *count = 0;
+    return HWW_OK;
+  }
+  const Bank<double> &bk = h->bank[which == 0 ? h->start_bank : 1 - h->start_bank];
+  std::vector<uint32_t> cnt(h->R);
+  HIPCHK(h, hipMemcpyAsync(cnt.data(), bk.count, 4 * h->R, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  int64_t total = 0;
+  for (int r = 0; r < h->R; ++r) total += std::min<int64_t>(cnt[r], h->L.cap_r);
+  *count = total;
+  if (total > cap) return fail(h, HWW_E_INVALID_ARG, "cap smaller than the bank");
+  int64_t o = 0;
+  for (int r = 0; r < h->R; ++r) {
+    const int64_t n = std::min<int64_t>(cnt[r], h->L.cap_r);
+    if (n == 0) continue;
+    const int64_t k = (int64_t)r * h->L.cap_r;
+    if (x) HIPCHK(h, hipMemcpyAsync(x + o, bk.x + k, 8 * n, hipMemcpyDeviceToHost, h->stream));
+    if (mu) HIPCHK(h, hipMemcpyAsync(mu + o, bk.mu + k, 8 * n, hipMemcpyDeviceToHost, h->stream));
+    if (w) HIPCHK(h, hipMemcpyAsync(w + o, bk.w + k, 8 * n, hipMemcpyDeviceToHost, h->stream));
+    if (src) HIPCHK(h, hipMemcpyAsync(src + o, bk.src + k, 4 * n, hipMemcpyDeviceToHost, h->stream));
+    if (lin) HIPCHK(h, hipMemcpyAsync(lin + o, bk.lin + k, 8 * n, hipMemcpyDeviceToHost, h->stream));
+    if (e) HIPCHK(h, hipMemcpyAsync(e + o, bk.e + k, 4 * n, hipMemcpyDeviceToHost, h->stream));
+    if (cell) HIPCHK(h, hipMemcpyAsync(cell + o, bk.cell + k, 4 * n, hipMemcpyDeviceToHost, h->stream));
+    if (chunk)
+      for (int64_t j = 0; j < n; ++j) chunk[o + j] = r % h->nc;
+    o += n;
+  }
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return HWW_OK;
+}
+
+int hww_sync(hww_handle *h) {
+  if (!h) return HWW_E_INVALID_ARG;
+  return poll_errors(h);
+}
+
+const char *hww_last_error(const hww_handle *h) {
+  return h ? h->msg.c_str() : g_init_error.c_str();
+}
+
+void hww_destroy(hww_handle *h) {
+  if (!h) return;
+  (void)hipStreamSynchronize(h->stream);
+  for (auto &e : h->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete h;
+}
+
+}  // extern "C"
