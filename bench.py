@@ -77,20 +77,12 @@ def run_gpu(w, steps_total, warmup, analog, record):
         t0 = time.perf_counter()
         if not analog:
             h.solve_losm(implicit=False, **kw)
-        seg = 0
-        kms = 0.0
-        byt = 0
-        gens = 0
-        cen = 0
         for p in range(w.n_chunks):
-            st = h.sweep_step(n, p)
-            seg += st["segments"]
-            kms += st["kernel_ms"]
-            byt += st["bytes_moved"]
-            gens += st["generations"]
-            cen += st["census"]
+            st = h.sweep_step(n, p, stats=(p == w.n_chunks - 1))
             if not analog and p < w.n_chunks - 1:
                 h.solve_losm(implicit=True, **kw)
+        seg, kms, byt, cen = st["segments"], st["kernel_ms"], st["bytes_moved"], st["census"]
+        gens = st["launches"]
         torch.cuda.synchronize()
         step_ms = (time.perf_counter() - t0) * 1e3
         if n > warmup:

@@ -69,13 +69,15 @@ typedef struct hww_problem {
 
 typedef struct hww_handle hww_handle;
 
-/* Counters of the most recent hww_sweep_step (all generations of daughters). */
+/* Counters of the current time step so far (all chunks swept in the step up
+ * to and including the call that fills the struct, with their daughters). */
 typedef struct hww_step_stats {
   uint64_t segments, collisions, scatters, absorptions, crossings, leaks, census;
   uint64_t splits, daughters, rr_kill, rr_survive, histories;
-  uint64_t generations;   /* kernel passes (1 + daughter generations)            */
-  double kernel_ms;       /* summed sweep-kernel time of the call (HIP events)   */
-  uint64_t bytes_moved;   /* algorithmic bank bytes read + written by the call   */
+  uint64_t generations;   /* most daughter generations of any work-group in one launch, + 1 */
+  uint64_t launches;      /* sweep-kernel launches of the step so far                   */
+  double kernel_ms;       /* summed sweep-kernel time of those launches (HIP events)    */
+  uint64_t bytes_moved;   /* algorithmic bank bytes read + written by those launches    */
 } hww_step_stats;
 
 /* Options of an HLOSM solve (Sec. 3 Eqs. losm-disc / losm-disc-semi, Sec. 4). */
@@ -124,8 +126,9 @@ int hww_set_windows(hww_handle *h, const double *centre, double rho);
  * transported to census, leakage, absorption or roulette death, together with
  * all daughters split off on the way (Sec. 2, Sec. 3).  Chunks of a step run
  * in order 0..n_chunks-1; chunk 0 of step n needs step n-1 complete and turns
- * its census bank into the start bank.  stats may be NULL (then the call does
- * not wait for the GPU).  Errors: HWW_E_STATE, HWW_E_CAPACITY, HWW_E_DEVICE. */
+ * its census bank into the start bank.  With stats == NULL the call only
+ * queues one kernel launch; with stats it waits for the GPU and fills the
+ * step's counters so far.  Errors: HWW_E_STATE, HWW_E_CAPACITY, HWW_E_DEVICE. */
 int hww_sweep_step(hww_handle *h, int32_t step, int32_t chunk, hww_step_stats *stats);
 
 /* Solve the HLOSM equations (Sec. 3) from the tallies on the device:

@@ -8,12 +8,12 @@
 namespace hww {
 
 // Device error bits (ORed into one word of the workspace).
-enum : uint32_t { ERR_CAPACITY = 1u, ERR_NUMERIC = 2u, ERR_SPLIT = 4u };
+enum : uint32_t { ERR_CAPACITY = 1u, ERR_NUMERIC = 2u, ERR_SPLIT = 4u, ERR_GENERATIONS = 8u };
 
 // Counter slots (per step, uint64).
 enum {
   C_SEGMENTS = 0, C_COLLISIONS, C_SCATTERS, C_ABSORPTIONS, C_CROSSINGS, C_LEAKS, C_CENSUS,
-  C_SPLITS, C_DAUGHTERS, C_RR_KILL, C_RR_SURVIVE, C_HISTORIES, C_NCOUNTERS = 16
+  C_SPLITS, C_DAUGHTERS, C_RR_KILL, C_RR_SURVIVE, C_HISTORIES, C_GENERATIONS, C_NCOUNTERS = 16
 };
 
 // Random-number slots of the keying contract: key = (seed, (replica << 4) | slot),
@@ -21,9 +21,14 @@ enum {
 enum { SLOT_FLIGHT = 0, SLOT_EVENT = 1, SLOT_START = 2, SLOT_BIRTH = 3, SLOT_LIN_EVENT = 4,
        SLOT_LIN_START = 5 };
 
-// Structure-of-arrays particle bank: B * n_chunks regions of cap_r slots each;
-// region r = batch * n_chunks + chunk holds the particles of that batch whose
-// next step starts in that chunk.
+// Work-group-local daughter generations per launch before giving up.
+constexpr int kMaxGenerations = 4096;
+
+// Structure-of-arrays particle bank.  Region (batch b, chunk c) holds the
+// particles of batch b whose next step starts in chunk c.  It is cut into K
+// segments of seg_cap slots, segment j written only by work-group j of batch
+// b (so appends need only a work-group-local counter), and one overflow
+// segment of ovf_cap slots shared through a device atomic.
 template <typename Real>
 struct Bank {
   Real *x, *mu;
@@ -31,10 +36,16 @@ struct Bank {
   uint64_t *lin;
   uint32_t *src, *e;
   int32_t *cell;
-  uint32_t *count;  // [B * n_chunks]
+  uint32_t *segcnt;  // [B][nc][K]
+  uint32_t *ovfcnt;  // [B][nc]
 };
 
-// Daughter queue: one region of cap_d slots per batch.
+struct BankGeom {
+  int32_t K;
+  int64_t seg_cap, ovf_cap, stride;  // stride = K * seg_cap + ovf_cap slots per region
+};
+
+// Daughter buffers: two per work-group, dcap slots each.
 template <typename Real>
 struct Queue {
   Real *x, *mu;
@@ -42,7 +53,6 @@ struct Queue {
   uint64_t *lin;
   uint32_t *src, *e;
   int32_t *cell;
-  uint32_t *count;  // [B]
 };
 
 template <typename Real>
@@ -53,13 +63,13 @@ struct SweepArgs {
   const double *edges, *sig_t, *cratio;
   const double *centre, *wceil, *wfloor;
   int32_t ww_on;
-  int32_t gen, chunk;
-  int64_t cap_r, cap_d;
+  int32_t chunk;
+  BankGeom geom;
   Bank<Real> in_bank;
-  Queue<Real> in_q;
   Bank<Real> census;
-  Queue<Real> out_q;
-  uint32_t *cursor;                // [B]
+  Queue<Real> dq;
+  int64_t dcap;
+  uint32_t *cursor;                // [B] tile cursors of the start bank
   double *tal;                     // [B][I][6]
   double *bnd;                     // [B][2][3]
   unsigned long long *tracks;      // [I]
@@ -74,7 +84,7 @@ struct SourceArgs {
   int64_t n_src;
   uint32_t seed, key1;
   const double *edges;
-  int64_t cap_r;
+  BankGeom geom;
   double *tal;  // census part of [B][I][6]
   double *wnext;
   uint32_t *err;
@@ -91,16 +101,27 @@ struct LosmArgs {
   double theta;
   int32_t implicit, filter, ma_k, closure_track, apply_windows;
   double eps_min, rho;
-  double *scratch;                // >= 16 * (2I + 4) doubles
+  double *scratch;                // >= 24 * (I + 4) doubles
+  double *factor;                 // [3][2I+3] LU factors of the system for `theta`
+  int32_t refactor;               // 1: (re)compute the factors first
   double *centre, *wceil, *wfloor;
   double *phi_out, *J_out;        // I+2, I+1 (device)
   uint32_t *err;
   int32_t *status;                // 0 ok, else error bits of this solve
 };
 
+// Dynamic LDS of the sweep and source kernels: [I][6] + nc + 6 doubles for
+// the histogram, then 32-bit words for segment counts, counters, cursors and
+// the start-bank tile table.
+__host__ __device__ inline size_t lds_doubles(int I, int nc) { return (size_t)I * 6 + nc + 6; }
+__host__ __device__ inline size_t lds_words(int I, int K) { return (size_t)I + 16 + 8 + 2 + 1 + (K + 2) + (K + 1); }
+inline size_t sweep_lds_bytes(int I, int nc, int K) { return lds_doubles(I, nc) * 8 + lds_words(I, K) * 4; }
+
 // Launchers (defined in the .hip files).
+hipError_t sweep_occupancy_f64(int block, size_t lds, int *blocks_per_cu);
 hipError_t launch_sweep_f64(const SweepArgs<double> &a, int grid, int block, size_t lds, hipStream_t s);
-hipError_t launch_source_f64(const SourceArgs &a, const Bank<double> &bank, hipStream_t s);
+hipError_t launch_source_f64(const SourceArgs &a, const Bank<double> &bank, int grid, int block, size_t lds,
+                             hipStream_t s);
 hipError_t launch_losm(const LosmArgs &a, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);

@@ -2,21 +2,83 @@
 // Anistratov, arXiv 2512.19925, Sec. 3 Eqs. losm-disc and losm-disc-semi;
 // moving-average filter of Sec. 4; window centres of Sec. 2 Eq. ww-center).
 //
-// One work-group per system.  Phases, separated by barriers:
-//   1. sum the per-batch tallies of the initial-condition set (census at
+// The interleaved tridiagonal system of 2I+3 unknowns
+// [phi_0, J_0, phi_1, J_1, ..., J_I, phi_{I+1}] has a matrix that depends
+// only on the mesh, the cross sections, v, dt and theta, so its LU factors
+// (Gaussian elimination without pivoting, the Thomas algorithm) are computed
+// once per theta by losm_factor_kernel.  Each solve (losm_kernel, one
+// work-group) then
+//   1. sums the per-batch tallies of the initial-condition set (census at
 //      t^{n-1}, face tallies of step n-1) and of the closure set
-//   2. grid functions: phi^{n-1}, J^{n-1} at edges (linear interpolation of
+//   2. forms phi^{n-1}, J^{n-1} at edges (linear interpolation of
 //      cell-average currents), F^{n-1}, F^n, P_L, P_R
-//   3. optional moving-average filter of F^n, F^{n-1}, phi^{n-1}, J^{n-1}
-//   4. assemble the interleaved tridiagonal system of 2I+3 unknowns
-//      [phi_0, J_0, phi_1, J_1, ..., J_I, phi_{I+1}] and solve it
-//   5. window centres s * [(max(phi,0)/max phi)(1-eps) + eps], ceiling and
-//      floor (Sec. 2 Eq. ww-c&f)
+//   3. optionally moving-average filters F^n, F^{n-1}, phi^{n-1}, J^{n-1}
+//   4. assembles the right-hand side
+//   5. runs the forward and backward substitutions, each a first-order
+//      affine recurrence, as a parallel scan over the work-group
+//   6. sets the window centres s [(max(phi,0)/max phi)(1-eps) + eps],
+//      ceiling and floor (Sec. 2 Eq. ww-c&f).
 #include "hww_internal.h"
 
 namespace hww {
 
 static constexpr int LOSM_THREADS = 1024;
+
+// Row r of the matrix: sub-diagonal a, diagonal b, super-diagonal c.
+__device__ inline void losm_row(const LosmArgs &A, int r, double th, double inv_vdt, double *a, double *b,
+                                double *c) {
+  const int I = A.I, n = 2 * I + 3;
+  if (r == 0) {  // left boundary relation phi_0/2 + J_0 = 2 J_L + P_L
+    *a = 0.0; *b = 0.5; *c = 1.0;
+  } else if (r == n - 1) {  // right boundary relation J_I - phi_{I+1}/2 = 2 J_R - P_R
+    *a = 1.0; *b = -0.5; *c = 0.0;
+  } else if ((r & 1) == 0) {  // balance over cell i = r/2
+    const int i = r / 2;
+    const double dx = A.edges[i] - A.edges[i - 1];
+    const double sa = A.sig_t[i - 1] - A.sig_s[i - 1];
+    *a = -th;
+    *b = dx * inv_vdt + th * sa * dx;
+    *c = th;
+  } else {  // first moment over the half cells around edge i = (r-1)/2
+    const int i = (r - 1) / 2;
+    const double dxl = (i >= 1) ? A.edges[i] - A.edges[i - 1] : 0.0;
+    const double dxr = (i <= I - 1) ? A.edges[i + 1] - A.edges[i] : 0.0;
+    const double stl = (i >= 1) ? A.sig_t[i - 1] : 0.0;
+    const double str = (i <= I - 1) ? A.sig_t[i] : 0.0;
+    const double dxh = 0.5 * (dxr + dxl);
+    const double sh = (stl * dxl + str * dxr) / (dxl + dxr);
+    *a = -th / 3.0;
+    *b = dxh * inv_vdt + th * sh * dxh;
+    *c = th / 3.0;
+  }
+}
+
+// Thomas factors for the forward recurrence d'_i = d_i/den_i + alpha_i d'_{i-1}
+// (alpha_i = -a_i/den_i) and the backward one x_i = d'_i + gamma_i x_{i+1}
+// (gamma_i = -c_i/den_i), den_i = b_i - a_i c_{i-1}/den_{i-1}.
+// factor = [alpha | 1/den | gamma], each 2I+3 long.  One lane; runs once per theta.
+__global__ void losm_factor_kernel(LosmArgs A) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int n = 2 * A.I + 3;
+  const double th = A.theta;
+  const double inv_vdt = 1.0 / (A.v * A.dt);
+  double *alpha = A.factor, *inv = A.factor + n, *gamma = A.factor + 2 * n;
+  double cp = 0.0;
+  for (int r = 0; r < n; ++r) {
+    double a, b, c;
+    losm_row(A, r, th, inv_vdt, &a, &b, &c);
+    const double den = (r == 0) ? b : b - a * cp;
+    if (den == 0.0 || !isfinite(den)) {
+      atomicOr(A.err, ERR_NUMERIC);
+      *A.status = (int)ERR_NUMERIC;
+      return;
+    }
+    cp = (r < n - 1) ? c / den : 0.0;
+    alpha[r] = (r == 0) ? 0.0 : -a / den;
+    inv[r] = 1.0 / den;
+    gamma[r] = -cp;
+  }
+}
 
 __device__ void ma_filter_dev(const double *in, double *out, int M, int k) {
   for (int m = 1 + (int)threadIdx.x; m <= M; m += blockDim.x) {
@@ -29,11 +91,36 @@ __device__ void ma_filter_dev(const double *in, double *out, int M, int k) {
   }
 }
 
+// Inclusive scan of affine maps y -> p + q y across the work-group (thread
+// order), Hillis-Steele in LDS.  On return (P, Q) of thread t compose the
+// maps of threads 0..t (later maps applied last).
+__device__ void affine_scan(double *sp, double *sq, double &P, double &Q) {
+  const int t = threadIdx.x;
+  sp[t] = P;
+  sq[t] = Q;
+  __syncthreads();
+  for (int o = 1; o < (int)blockDim.x; o <<= 1) {
+    double pp = 0.0, qq = 1.0;
+    const bool has = t >= o;
+    if (has) { pp = sp[t - o]; qq = sq[t - o]; }
+    __syncthreads();
+    if (has) {
+      // this map after the earlier one: y -> P + Q (pp + qq y)
+      P = P + Q * pp;
+      Q = Q * qq;
+      sp[t] = P;
+      sq[t] = Q;
+    }
+    __syncthreads();
+  }
+}
+
 __global__ void __launch_bounds__(LOSM_THREADS) losm_kernel(LosmArgs A) {
   const int I = A.I;
   const int M = I + 2;
   const int n = 2 * I + 3;
   const int tid = threadIdx.x;
+  const int T = blockDim.x;
   double *S = A.scratch;
   double *phi_o = S;
   double *J_o = phi_o + M;
@@ -45,11 +132,8 @@ __global__ void __launch_bounds__(LOSM_THREADS) losm_kernel(LosmArgs A) {
   double *gi_K = gi_J + I;
   double *gc_phi = gi_K + I;
   double *gc_K = gc_phi + I;
-  double *a = gc_K + I;
-  double *bb = a + n;
-  double *c = bb + n;
-  double *d = c + n;
-  double *u = d + n;
+  extern __shared__ double u[];  // [n] right-hand side, then solution
+  __shared__ double sp[LOSM_THREADS], sq[LOSM_THREADS];
   __shared__ double face[12];  // ic: phi L/R, P L/R, F L/R; cl: same
   __shared__ double sc[4];     // scale, s, max
   __shared__ int bad;
@@ -57,7 +141,7 @@ __global__ void __launch_bounds__(LOSM_THREADS) losm_kernel(LosmArgs A) {
   __shared__ double red[LOSM_THREADS / 64];
 
   if (tid == 0) {
-    bad = 0;
+    bad = (*A.status != 0) ? 1 : 0;  // a failed factorization stays failed
     skip = 0;
     double wtot = 0.0, done = 0.0, wn = 0.0;
     for (int q = 0; q < A.nc; ++q) {
@@ -76,17 +160,17 @@ __global__ void __launch_bounds__(LOSM_THREADS) losm_kernel(LosmArgs A) {
     }
   }
   __syncthreads();
+  if (bad) return;
   if (skip) {
-    for (int i = tid; i <= I + 1; i += blockDim.x) A.phi_out[i] = 0.0;
-    for (int i = tid; i <= I; i += blockDim.x) A.J_out[i] = 0.0;
-    if (tid == 0) *A.status = 0;
+    for (int i = tid; i <= I + 1; i += T) A.phi_out[i] = 0.0;
+    for (int i = tid; i <= I; i += T) A.J_out[i] = 0.0;
     return;
   }
   const double scale = sc[0];
 
   // 1. batch sums and normalisation per source particle.
   const int kc = A.closure_track ? 0 : 3;
-  for (int i = tid; i < I; i += blockDim.x) {
+  for (int i = tid; i < I; i += T) {
     double p = 0.0, j = 0.0, k = 0.0, cp = 0.0, ck = 0.0;
     for (int b = 0; b < A.B; ++b) {
       const double *t = A.tal_ic + ((size_t)b * I + i) * 6;
@@ -117,7 +201,7 @@ __global__ void __launch_bounds__(LOSM_THREADS) losm_kernel(LosmArgs A) {
   __syncthreads();
 
   // 2. grid functions.
-  for (int i = tid; i <= I + 1; i += blockDim.x) {
+  for (int i = tid; i <= I + 1; i += T) {
     if (i == 0) {
       phi_o[0] = face[0];
       F_o[0] = face[4];
@@ -138,11 +222,11 @@ __global__ void __launch_bounds__(LOSM_THREADS) losm_kernel(LosmArgs A) {
   __syncthreads();
   double PL, PR;
   if (!A.implicit) {
-    for (int i = tid; i <= I + 1; i += blockDim.x) F_n[i] = F_o[i];
+    for (int i = tid; i <= I + 1; i += T) F_n[i] = F_o[i];
     PL = face[2];
     PR = face[3];
   } else {
-    for (int i = tid; i <= I + 1; i += blockDim.x) {
+    for (int i = tid; i <= I + 1; i += T) {
       if (i == 0) F_n[0] = face[10];
       else if (i == I + 1) F_n[I + 1] = face[11];
       else F_n[i] = gc_phi[i - 1] / 3.0 - gc_K[i - 1];
@@ -158,90 +242,91 @@ __global__ void __launch_bounds__(LOSM_THREADS) losm_kernel(LosmArgs A) {
     for (int q = 0; q < 3; ++q) {
       ma_filter_dev(arrs[q], tmp, I, A.ma_k);
       __syncthreads();
-      for (int i = tid; i < I; i += blockDim.x) arrs[q][i] = tmp[i];
+      for (int i = tid; i < I; i += T) arrs[q][i] = tmp[i];
       __syncthreads();
     }
     ma_filter_dev(J_o, tmp, I + 1, A.ma_k);
     __syncthreads();
-    for (int i = tid; i <= I; i += blockDim.x) J_o[i] = tmp[i];
+    for (int i = tid; i <= I; i += T) J_o[i] = tmp[i];
     __syncthreads();
   }
 
-  // 4. assemble.
+  // 4. right-hand side.
   const double th = A.theta;
   const double inv_vdt = 1.0 / (A.v * A.dt);
-  for (int r = tid; r < n; r += blockDim.x) {
+  for (int r = tid; r < n; r += T) {
+    double d;
     if (r == 0) {
-      a[0] = 0.0; bb[0] = 0.5; c[0] = 1.0; d[0] = PL;
+      d = PL;
     } else if (r == n - 1) {
-      a[r] = 1.0; bb[r] = -0.5; c[r] = 0.0; d[r] = -PR;
+      d = -PR;
     } else if ((r & 1) == 0) {
-      const int i = r / 2;  // balance of cell i (1..I)
+      const int i = r / 2;
       const double dx = A.edges[i] - A.edges[i - 1];
       const double sa = A.sig_t[i - 1] - A.sig_s[i - 1];
-      a[r] = -th;
-      bb[r] = dx * inv_vdt + th * sa * dx;
-      c[r] = th;
-      d[r] = dx * inv_vdt * phi_o[i] + th * 0.0 * dx
-           + (th - 1.0) * (J_o[i] - J_o[i - 1] + sa * dx * phi_o[i] - 0.0 * dx);
+      d = dx * inv_vdt * phi_o[i] + (th - 1.0) * (J_o[i] - J_o[i - 1] + sa * dx * phi_o[i]);
     } else {
-      const int i = (r - 1) / 2;  // first moment at edge i (0..I)
+      const int i = (r - 1) / 2;
       const double dxl = (i >= 1) ? A.edges[i] - A.edges[i - 1] : 0.0;
       const double dxr = (i <= I - 1) ? A.edges[i + 1] - A.edges[i] : 0.0;
       const double stl = (i >= 1) ? A.sig_t[i - 1] : 0.0;
       const double str = (i <= I - 1) ? A.sig_t[i] : 0.0;
       const double dxh = 0.5 * (dxr + dxl);
       const double sh = (stl * dxl + str * dxr) / (dxl + dxr);
-      a[r] = -th / 3.0;
-      bb[r] = dxh * inv_vdt + th * sh * dxh;
-      c[r] = th / 3.0;
-      d[r] = dxh * inv_vdt * J_o[i] + th * (F_n[i + 1] - F_n[i])
-           + (th - 1.0) * ((phi_o[i + 1] - phi_o[i]) / 3.0 + sh * dxh * J_o[i] - (F_o[i + 1] - F_o[i]));
+      d = dxh * inv_vdt * J_o[i] + th * (F_n[i + 1] - F_n[i])
+        + (th - 1.0) * ((phi_o[i + 1] - phi_o[i]) / 3.0 + sh * dxh * J_o[i] - (F_o[i + 1] - F_o[i]));
     }
+    u[r] = d;
   }
   __syncthreads();
 
-  // Thomas elimination (no pivoting), one lane.
-  if (tid == 0 && !bad) {
-    double den = bb[0];
-    if (den == 0.0 || !isfinite(den)) bad = 1;
-    double cp = c[0] / den;
-    double dp = d[0] / den;
-    a[0] = cp;  // reuse a[] for c' and d[] for d'
-    d[0] = dp;
-    for (int i = 1; i < n && !bad; ++i) {
-      den = bb[i] - a[i] * cp;
-      if (den == 0.0 || !isfinite(den)) { bad = 1; break; }
-      cp = (i < n - 1) ? c[i] / den : 0.0;
-      dp = (d[i] - a[i] * dp) / den;
-      a[i] = cp;
-      d[i] = dp;
+  // 5. substitutions as parallel scans of affine recurrences.
+  const double *alpha = A.factor, *inv = A.factor + n, *gamma = A.factor + 2 * n;
+  const int m = (n + T - 1) / T;
+  const int r0 = tid * m, r1 = min(r0 + m, n);
+  {
+    double P = 0.0, Q = 1.0;  // composite map of this thread's rows
+    for (int r = r0; r < r1; ++r) {
+      const double al = alpha[r];
+      P = u[r] * inv[r] + al * P;
+      Q = al * Q;
     }
-    if (!bad) {
-      double xn = d[n - 1];
-      u[n - 1] = xn;
-      for (int i = n - 2; i >= 0; --i) {
-        xn = d[i] - a[i] * xn;
-        u[i] = xn;
-      }
+    affine_scan(sp, sq, P, Q);
+    double y = (tid == 0) ? 0.0 : sp[tid - 1];  // d' of the row before this thread's first
+    for (int r = r0; r < r1; ++r) {
+      y = u[r] * inv[r] + alpha[r] * y;
+      u[r] = y;
     }
   }
   __syncthreads();
-  if (bad) {
-    if (tid == 0) {
-      atomicOr(A.err, ERR_NUMERIC);
-      *A.status = (int)ERR_NUMERIC;
+  {
+    // backward: thread t takes the mirrored block so that the scan runs from the end
+    const int tb = T - 1 - tid;
+    const int b0 = tb * m, b1 = min(b0 + m, n);
+    double P = 0.0, Q = 1.0;
+    for (int r = b1 - 1; r >= b0; --r) {
+      const double g = (r == n - 1) ? 0.0 : gamma[r];
+      P = u[r] + g * P;
+      Q = g * Q;
     }
-    return;
+    affine_scan(sp, sq, P, Q);
+    double y = (tid == 0) ? 0.0 : sp[tid - 1];  // x of the row after this block
+    __syncthreads();
+    for (int r = b1 - 1; r >= b0; --r) {
+      const double g = (r == n - 1) ? 0.0 : gamma[r];
+      y = u[r] + g * y;
+      u[r] = y;
+    }
   }
-  for (int i = tid; i <= I + 1; i += blockDim.x) A.phi_out[i] = u[2 * i];
-  for (int i = tid; i <= I; i += blockDim.x) A.J_out[i] = u[2 * i + 1];
+  __syncthreads();
+  for (int i = tid; i <= I + 1; i += T) A.phi_out[i] = u[2 * i];
+  for (int i = tid; i <= I; i += T) A.J_out[i] = u[2 * i + 1];
 
-  // 5. window centres (an empty bank has nothing to window: unchanged).
+  // 6. window centres (an empty bank has nothing to window: unchanged).
   if (A.apply_windows && sc[1] > 0.0) {
     double mx = -__builtin_inf();
     int nonfinite = 0;
-    for (int i = tid; i < I; i += blockDim.x) {
+    for (int i = tid; i < I; i += T) {
       const double p = u[2 * (i + 1)];
       if (!isfinite(p)) nonfinite = 1;
       if (p > mx) mx = p;
@@ -254,34 +339,43 @@ __global__ void __launch_bounds__(LOSM_THREADS) losm_kernel(LosmArgs A) {
     if (nonfinite) atomicOr(&bad, 1);
     __syncthreads();
     if (tid == 0) {
-      double m = red[0];
-      for (int q = 1; q < (int)(blockDim.x >> 6); ++q) m = red[q] > m ? red[q] : m;
-      sc[2] = m;
-      if (!(m > 0.0) || !(sc[1] > 0.0)) bad = 1;
+      double mm = red[0];
+      for (int q = 1; q < (T >> 6); ++q) mm = red[q] > mm ? red[q] : mm;
+      sc[2] = mm;
+      if (!(mm > 0.0)) bad = 1;
     }
     __syncthreads();
     if (bad) {
-      if (tid == 0) {
-        atomicOr(A.err, ERR_NUMERIC);
-        *A.status = (int)ERR_NUMERIC;
-      }
+      if (tid == 0) atomicOr(A.err, ERR_NUMERIC);
       return;
     }
-    const double m = sc[2], s = sc[1];
-    for (int i = tid; i < I; i += blockDim.x) {
+    const double mm = sc[2], s = sc[1];
+    for (int i = tid; i < I; i += T) {
       const double p = u[2 * (i + 1)];
-      const double rr = p > 0.0 ? p / m : 0.0;
+      const double rr = p > 0.0 ? p / mm : 0.0;
       const double ww = s * (rr * (1.0 - A.eps_min) + A.eps_min);
       A.centre[i] = ww;
       A.wceil[i] = ww * A.rho;
       A.wfloor[i] = ww / A.rho;
     }
   }
-  if (tid == 0) *A.status = 0;
 }
 
 hipError_t launch_losm(const LosmArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(losm_kernel, dim3(1), dim3(LOSM_THREADS), 0, s, a);
+  if (a.refactor) {
+    hipLaunchKernelGGL(losm_factor_kernel, dim3(1), dim3(64), 0, s, a);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  const size_t lds = (size_t)(2 * a.I + 3) * sizeof(double);
+  static size_t done = 0;
+  if (lds > 32 * 1024 && lds > done) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&losm_kernel),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    done = lds;
+  }
+  hipLaunchKernelGGL(losm_kernel, dim3(1), dim3(LOSM_THREADS), lds, s, a);
   return hipGetLastError();
 }
 

@@ -11,23 +11,25 @@
 #include <string>
 #include <vector>
 
-#include "../../include/hww.h"
+#include "hww.h"
 #include "hww_internal.h"
 
 using namespace hww;
 
 namespace {
 
-constexpr int kMaxGenerations = 64;
-constexpr double kRegionSlack = 1.5;
+constexpr double kSegSlack = 2.0;   // segment capacity / fair share of a work-group
+constexpr double kOvfShare = 0.5;   // overflow capacity / fair share of a region
+constexpr int kBlock = 512;         // threads per sweep work-group
 
 struct Layout {
   int64_t total = 0;
-  int64_t cap_r = 0, cap_d = 0;
+  BankGeom geom{};
+  int64_t dcap = 0;
   int64_t off_edges, off_sigt, off_sigs, off_cratio, off_centre, off_ceil, off_floor;
-  int64_t off_bank[2], off_bank_counts[2], off_q[2], off_q_counts[2];
+  int64_t off_bank[2], off_segcnt[2], off_ovfcnt[2], off_q;
   int64_t off_tal[2], off_bnd[2], off_tracks, off_counters, off_wstart, off_wnext;
-  int64_t off_cursor, off_err, off_status, off_scratch, off_phi_out, off_J_out;
+  int64_t off_cursor, off_err, off_status, off_scratch, off_factor, off_phi_out, off_J_out;
 };
 
 int64_t align_up(int64_t v) { return (v + 255) & ~int64_t(255); }
@@ -46,13 +48,31 @@ bool real_bytes(int precision, int64_t *rb) {
   return false;
 }
 
+// Work-groups per batch: the grid is B * K persistent work-groups, about two
+// per compute unit of a 256-CU MI355X when the LDS histogram allows it.
+int segments_per_batch(int I, int B, int nc) {
+  const size_t lds = sweep_lds_bytes(I, nc, 64);
+  const int target = lds <= 80 * 1024 ? 512 : 256;
+  int K = (target + B / 2) / B;
+  if (K < 1) K = 1;
+  if (K > 64) K = 64;
+  return K;
+}
 
 void make_layout(const hww_problem &p, Layout *L) {
   const int64_t I = p.n_cells, B = p.n_batches, nc = p.n_chunks, R = B * nc;
   int64_t rb = 8;
   real_bytes(p.precision, &rb);
-  L->cap_r = (int64_t)std::ceil(kRegionSlack * (double)p.bank_capacity / (double)R) + 256;
-  L->cap_d = (p.bank_capacity + B - 1) / B + 4096;
+  const int K = segments_per_batch((int)I, (int)B, (int)nc);
+  BankGeom &G = L->geom;
+  G.K = K;
+  const double share = (double)p.bank_capacity / (double)R;
+  G.seg_cap = (int64_t)std::ceil(kSegSlack * share / K) + 64;
+  G.ovf_cap = (int64_t)std::ceil(kOvfShare * share) + 1024;
+  G.stride = (int64_t)K * G.seg_cap + G.ovf_cap;
+  L->dcap = std::max<int64_t>(4096, (p.bank_capacity + B * K - 1) / (B * K));
+  const int64_t slots = R * G.stride;
+  const int64_t dslots = 2 * B * K * L->dcap;
   Carver c;
   L->off_edges = c.take(8 * (I + 1));
   L->off_sigt = c.take(8 * I);
@@ -64,28 +84,26 @@ void make_layout(const hww_problem &p, Layout *L) {
   L->off_floor = L->off_centre + 16 * I;
   for (int k = 0; k < 2; ++k) {
     L->off_bank[k] = c.take(0);
-    // x, mu, w, lin, src, e, cell arrays, each R * cap_r long
-    c.take(rb * R * L->cap_r);
-    c.take(rb * R * L->cap_r);
-    c.take(8 * R * L->cap_r);
-    c.take(8 * R * L->cap_r);
-    c.take(4 * R * L->cap_r);
-    c.take(4 * R * L->cap_r);
-    c.take(4 * R * L->cap_r);
-    L->off_bank_counts[k] = c.take(4 * R);
+    // x, mu, w, lin, src, e, cell arrays
+    c.take(rb * slots);
+    c.take(rb * slots);
+    c.take(8 * slots);
+    c.take(8 * slots);
+    c.take(4 * slots);
+    c.take(4 * slots);
+    c.take(4 * slots);
+    L->off_segcnt[k] = c.take(4 * R * K);
+    L->off_ovfcnt[k] = c.take(4 * R);
   }
-  for (int k = 0; k < 2; ++k) {
-    L->off_q[k] = c.take(0);
-    c.take(rb * B * L->cap_d);
-    c.take(rb * B * L->cap_d);
-    c.take(8 * B * L->cap_d);
-    c.take(8 * B * L->cap_d);
-    c.take(8 * B * L->cap_d);
-    c.take(4 * B * L->cap_d);
-    c.take(4 * B * L->cap_d);
-    c.take(4 * B * L->cap_d);
-    L->off_q_counts[k] = c.take(4 * B);
-  }
+  L->off_q = c.take(0);
+  c.take(rb * dslots);
+  c.take(rb * dslots);
+  c.take(8 * dslots);
+  c.take(8 * dslots);
+  c.take(8 * dslots);
+  c.take(4 * dslots);
+  c.take(4 * dslots);
+  c.take(4 * dslots);
   for (int k = 0; k < 2; ++k) {
     L->off_tal[k] = c.take(8 * B * I * 6);
     L->off_bnd[k] = c.take(8 * B * 6);
@@ -98,13 +116,14 @@ void make_layout(const hww_problem &p, Layout *L) {
   L->off_err = c.take(4);
   L->off_status = c.take(4);
   L->off_scratch = c.take(8 * 24 * (I + 4));
+  L->off_factor = c.take(8 * 3 * (2 * I + 3));
   L->off_phi_out = c.take(8 * (I + 2));
   L->off_J_out = c.take(8 * (I + 1));
   L->total = c.cur;
 }
 
 template <typename Real>
-Bank<Real> bank_view(char *ws, int64_t off, int64_t off_counts, int64_t slots) {
+Bank<Real> bank_view(char *ws, int64_t off, int64_t off_seg, int64_t off_ovf, int64_t slots) {
   Bank<Real> b;
   int64_t o = off;
   auto take = [&](int64_t bytes) {
@@ -119,12 +138,13 @@ Bank<Real> bank_view(char *ws, int64_t off, int64_t off_counts, int64_t slots) {
   b.src = reinterpret_cast<uint32_t *>(take(4 * slots));
   b.e = reinterpret_cast<uint32_t *>(take(4 * slots));
   b.cell = reinterpret_cast<int32_t *>(take(4 * slots));
-  b.count = reinterpret_cast<uint32_t *>(ws + off_counts);
+  b.segcnt = reinterpret_cast<uint32_t *>(ws + off_seg);
+  b.ovfcnt = reinterpret_cast<uint32_t *>(ws + off_ovf);
   return b;
 }
 
 template <typename Real>
-Queue<Real> queue_view(char *ws, int64_t off, int64_t off_counts, int64_t slots) {
+Queue<Real> queue_view(char *ws, int64_t off, int64_t slots) {
   Queue<Real> q;
   int64_t o = off;
   auto take = [&](int64_t bytes) {
@@ -140,7 +160,6 @@ Queue<Real> queue_view(char *ws, int64_t off, int64_t off_counts, int64_t slots)
   q.src = reinterpret_cast<uint32_t *>(take(4 * slots));
   q.e = reinterpret_cast<uint32_t *>(take(4 * slots));
   q.cell = reinterpret_cast<int32_t *>(take(4 * slots));
-  q.count = reinterpret_cast<uint32_t *>(ws + off_counts);
   return q;
 }
 
@@ -150,31 +169,29 @@ std::string g_init_error;
 
 struct hww_handle {
   hww_problem p{};
-  int I = 0, B = 0, nc = 0, R = 0;
+  int I = 0, B = 0, nc = 0, R = 0, K = 1;
   Layout L;
   hipStream_t stream = nullptr;
   char *ws = nullptr;
   double *edges, *sig_t, *sig_s, *cratio, *centre, *wceil, *wfloor;
   Bank<double> bank[2];
-  Queue<double> q[2];
+  Queue<double> dq;
   double *tal[2], *bnd[2];
   unsigned long long *tracks, *counters;
   double *wstart, *wnext;
   uint32_t *cursor, *err;
   int32_t *status;
-  double *scratch, *phi_out, *J_out;
+  double *scratch, *factor, *phi_out, *J_out;
 
   int start_bank = 0;  // census bank = 1 - start_bank
   int cur_tal = 0;
   int step = 0, next_chunk = 0;
   int ww_on = 0;
   int fatal = 0;
-  int n_cu = 256;
-  int block = 512;
-  std::vector<uint32_t> census_counts;  // host mirror, refreshed after each sweep
-  std::vector<uint32_t> start_counts;
-  uint64_t last_counters[C_NCOUNTERS] = {};
-  hipEvent_t ev[2 * kMaxGenerations] = {};
+  double factor_theta = -1.0;  // theta of the LU factors in the workspace
+  size_t lds = 0;
+  int n_launch = 0;            // sweep launches of the current step
+  hipEvent_t ev[2 * 8] = {};
   std::string msg;
 };
 
@@ -214,38 +231,46 @@ int validate(const hww_problem *p, std::string *why) {
         !std::isfinite(p->sigma_t[i])) { *why = "need 0 < sigma_t, 0 <= sigma_s <= sigma_t"; return HWW_E_INVALID_ARG; }
   }
   if (!(p->src_x >= p->edges[0] && p->src_x <= p->edges[p->n_cells])) { *why = "src_x outside the mesh"; return HWW_E_INVALID_ARG; }
-  // LDS histogram of one work-group: [I][6] doubles + [I] u32 + small.
-  const int64_t lds = (int64_t)p->n_cells * 6 * 8 + (int64_t)(p->n_chunks + 6) * 8 + ((int64_t)p->n_cells + C_NCOUNTERS) * 4;
-  if (lds > 160 * 1024) { *why = "too many cells for the LDS histogram (I <= 3300)"; return HWW_E_INVALID_ARG; }
+  if (sweep_lds_bytes(p->n_cells, p->n_chunks, 64) > 160 * 1024) { *why = "too many cells for the LDS histogram (I <= 3300)"; return HWW_E_INVALID_ARG; }
   return HWW_OK;
 }
 
-size_t lds_bytes(const hww_handle *h) {
-  return (size_t)h->I * 6 * 8 + (size_t)(h->nc + 6) * 8 + ((size_t)h->I + C_NCOUNTERS) * 4;
+// Census-bank occupancy from the device counts (synchronises).
+int census_total(hww_handle *h, int bank_idx, uint64_t *total) {
+  std::vector<uint32_t> seg((size_t)h->R * h->K), ovf(h->R);
+  HIPCHK(h, hipMemcpyAsync(seg.data(), h->bank[bank_idx].segcnt, 4 * seg.size(), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipMemcpyAsync(ovf.data(), h->bank[bank_idx].ovfcnt, 4 * ovf.size(), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  uint64_t t = 0;
+  for (uint32_t c : seg) t += std::min<uint64_t>(c, (uint64_t)h->L.geom.seg_cap);
+  for (uint32_t c : ovf) t += std::min<uint64_t>(c, (uint64_t)h->L.geom.ovf_cap);
+  *total = t;
+  return HWW_OK;
 }
 
-// Read the device error word; map it to an ABI code (sticky).
+// Read the device error word and the census occupancy; map them to an ABI
+// code.  Errors are sticky: the problem must be re-initialised.
 int poll_errors(hww_handle *h) {
   uint32_t e = 0;
   HIPCHK(h, hipMemcpyAsync(&e, h->err, 4, hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(h, hipStreamSynchronize(h->stream));
-  if (e & (ERR_CAPACITY | ERR_SPLIT)) {
+  uint64_t cen = 0;
+  int rc = census_total(h, 1 - h->start_bank, &cen);
+  if (rc != HWW_OK) return rc;
+  if (e & (ERR_CAPACITY | ERR_SPLIT | ERR_GENERATIONS)) {
     h->fatal = HWW_E_CAPACITY;
-    return fail(h, HWW_E_CAPACITY, (e & ERR_SPLIT) ? "a split exceeded 1e9 daughters" : "bank or daughter queue overflow");
+    return fail(h, HWW_E_CAPACITY, (e & ERR_SPLIT) ? "a split exceeded 1e9 daughters"
+                                   : (e & ERR_GENERATIONS) ? "too many daughter generations"
+                                                           : "bank segment or daughter buffer overflow");
+  }
+  if (cen > (uint64_t)h->p.bank_capacity) {
+    h->fatal = HWW_E_CAPACITY;
+    return fail(h, HWW_E_CAPACITY, "census bank exceeds bank_capacity");
   }
   if (e & ERR_NUMERIC) {
     h->fatal = HWW_E_NUMERIC;
     return fail(h, HWW_E_NUMERIC, "non-finite or non-positive window, or zero pivot in the LOSM solve");
   }
   return HWW_OK;
-}
-
-int grid_for(const hww_handle *h, uint64_t max_per_batch) {
-  const uint64_t per_wg = (uint64_t)h->block * 2;
-  uint64_t k = (max_per_batch + per_wg - 1) / per_wg;
-  const uint64_t kmax = std::max<uint64_t>(1, (uint64_t)(2 * h->n_cu) / (uint64_t)h->B);
-  k = std::max<uint64_t>(1, std::min(k, kmax));
-  return (int)(k * (uint64_t)h->B);
 }
 
 SweepArgs<double> base_args(hww_handle *h) {
@@ -256,9 +281,11 @@ SweepArgs<double> base_args(hww_handle *h) {
   a.edges = h->edges; a.sig_t = h->sig_t; a.cratio = h->cratio;
   a.centre = h->centre; a.wceil = h->wceil; a.wfloor = h->wfloor;
   a.ww_on = h->ww_on;
-  a.cap_r = h->L.cap_r; a.cap_d = h->L.cap_d;
+  a.geom = h->L.geom;
   a.in_bank = h->bank[h->start_bank];
   a.census = h->bank[1 - h->start_bank];
+  a.dq = h->dq;
+  a.dcap = h->L.dcap;
   a.cursor = h->cursor;
   a.tal = h->tal[h->cur_tal];
   a.bnd = h->bnd[h->cur_tal];
@@ -267,6 +294,12 @@ SweepArgs<double> base_args(hww_handle *h) {
   a.wnext = h->wnext;
   a.err = h->err;
   return a;
+}
+
+int zero_counts(hww_handle *h, int k) {
+  HIPCHK(h, launch_fill_u32(h->bank[k].segcnt, 0u, (int64_t)h->R * h->K, h->stream));
+  HIPCHK(h, launch_fill_u32(h->bank[k].ovfcnt, 0u, h->R, h->stream));
+  return HWW_OK;
 }
 
 }  // namespace
@@ -301,9 +334,12 @@ int hww_init_problem(const hww_problem *problem, void *dev_workspace, int64_t ws
   h->nc = problem->n_chunks;
   h->R = h->B * h->nc;
   h->L = L;
+  h->K = L.geom.K;
+  h->lds = sweep_lds_bytes(h->I, h->nc, h->K);
   h->stream = reinterpret_cast<hipStream_t>(hip_stream);
   h->ws = reinterpret_cast<char *>(dev_workspace);
   char *ws = h->ws;
+  const int64_t slots = (int64_t)h->R * L.geom.stride;
   h->edges = reinterpret_cast<double *>(ws + L.off_edges);
   h->sig_t = reinterpret_cast<double *>(ws + L.off_sigt);
   h->sig_s = reinterpret_cast<double *>(ws + L.off_sigs);
@@ -312,11 +348,11 @@ int hww_init_problem(const hww_problem *problem, void *dev_workspace, int64_t ws
   h->wceil = reinterpret_cast<double *>(ws + L.off_ceil);
   h->wfloor = reinterpret_cast<double *>(ws + L.off_floor);
   for (int k = 0; k < 2; ++k) {
-    h->bank[k] = bank_view<double>(ws, L.off_bank[k], L.off_bank_counts[k], (int64_t)h->R * L.cap_r);
-    h->q[k] = queue_view<double>(ws, L.off_q[k], L.off_q_counts[k], (int64_t)h->B * L.cap_d);
+    h->bank[k] = bank_view<double>(ws, L.off_bank[k], L.off_segcnt[k], L.off_ovfcnt[k], slots);
     h->tal[k] = reinterpret_cast<double *>(ws + L.off_tal[k]);
     h->bnd[k] = reinterpret_cast<double *>(ws + L.off_bnd[k]);
   }
+  h->dq = queue_view<double>(ws, L.off_q, 2 * (int64_t)h->B * h->K * L.dcap);
   h->tracks = reinterpret_cast<unsigned long long *>(ws + L.off_tracks);
   h->counters = reinterpret_cast<unsigned long long *>(ws + L.off_counters);
   h->wstart = reinterpret_cast<double *>(ws + L.off_wstart);
@@ -325,10 +361,9 @@ int hww_init_problem(const hww_problem *problem, void *dev_workspace, int64_t ws
   h->err = reinterpret_cast<uint32_t *>(ws + L.off_err);
   h->status = reinterpret_cast<int32_t *>(ws + L.off_status);
   h->scratch = reinterpret_cast<double *>(ws + L.off_scratch);
+  h->factor = reinterpret_cast<double *>(ws + L.off_factor);
   h->phi_out = reinterpret_cast<double *>(ws + L.off_phi_out);
   h->J_out = reinterpret_cast<double *>(ws + L.off_J_out);
-  h->census_counts.assign(h->R, 0);
-  h->start_counts.assign(h->R, 0);
 
   auto bail = [&](int code) {
     g_init_error = h->msg;
@@ -343,11 +378,7 @@ int hww_init_problem(const hww_problem *problem, void *dev_workspace, int64_t ws
     if (rc__ != HWW_OK) return bail(rc__);             \
   } while (0)
 
-  int dev = 0;
-  INITCHK(hipGetDevice(&dev));
-  INITCHK(hipDeviceGetAttribute(&h->n_cu, hipDeviceAttributeMultiprocessorCount, dev));
   for (auto &e : h->ev) INITCHK(hipEventCreate(&e));
-
   const int I = h->I;
   std::vector<double> cr(I);
   for (int i = 0; i < I; ++i) cr[i] = problem->sigma_s[i] / problem->sigma_t[i];
@@ -357,8 +388,7 @@ int hww_init_problem(const hww_problem *problem, void *dev_workspace, int64_t ws
   INITCHK(hipMemcpyAsync(h->cratio, cr.data(), 8 * I, hipMemcpyHostToDevice, h->stream));
   // Zero everything the kernels accumulate into.
   for (int k = 0; k < 2; ++k) {
-    INITCHK(launch_fill_u32(h->bank[k].count, 0u, h->R, h->stream));
-    INITCHK(launch_fill_u32(h->q[k].count, 0u, h->B, h->stream));
+    if (zero_counts(h, k) != HWW_OK) return bail(HWW_E_DEVICE);
     INITCHK(launch_fill_f64(h->tal[k], 0.0, (int64_t)h->B * I * 6, h->stream));
     INITCHK(launch_fill_f64(h->bnd[k], 0.0, (int64_t)h->B * 6, h->stream));
   }
@@ -368,6 +398,7 @@ int hww_init_problem(const hww_problem *problem, void *dev_workspace, int64_t ws
   INITCHK(launch_fill_f64(h->wnext, 0.0, h->nc, h->stream));
   INITCHK(launch_fill_f64(h->centre, 0.0, 3 * (int64_t)I, h->stream));
   INITCHK(launch_fill_u32(h->err, 0u, 1, h->stream));
+  INITCHK(launch_fill_u32(reinterpret_cast<uint32_t *>(h->status), 0u, 1, h->stream));
 
   // Source bank = census bank of step 0 (bank 1); its tallies fill set 0.
   h->start_bank = 0;
@@ -376,10 +407,9 @@ int hww_init_problem(const hww_problem *problem, void *dev_workspace, int64_t ws
   sa.I = I; sa.B = h->B; sa.nc = h->nc;
   sa.v = problem->speed; sa.dt = problem->dt; sa.src_x = problem->src_x;
   sa.n_src = problem->n_src; sa.seed = problem->seed; sa.key1 = problem->replica << 4;
-  sa.edges = h->edges; sa.cap_r = L.cap_r;
+  sa.edges = h->edges; sa.geom = L.geom;
   sa.tal = h->tal[0]; sa.wnext = h->wnext; sa.err = h->err;
-  INITCHK(launch_source_f64(sa, h->bank[1], h->stream));
-  INITCHK(hipMemcpyAsync(h->census_counts.data(), h->bank[1].count, 4 * h->R, hipMemcpyDeviceToHost, h->stream));
+  INITCHK(launch_source_f64(sa, h->bank[1], h->B * h->K, 256, h->lds, h->stream));
   int prc = poll_errors(h);
   if (prc != HWW_OK) return bail(prc);
   h->step = 0;
@@ -420,97 +450,58 @@ int hww_sweep_step(hww_handle *h, int32_t step, int32_t chunk, hww_step_stats *s
       return fail(h, HWW_E_STATE, "step out of order");
     // The census bank of the finished step becomes the start bank.
     h->start_bank = 1 - h->start_bank;
-    h->start_counts = h->census_counts;
-    HIPCHK(h, launch_fill_u32(h->bank[1 - h->start_bank].count, 0u, h->R, h->stream));
+    if (zero_counts(h, 1 - h->start_bank) != HWW_OK) return HWW_E_DEVICE;
     h->cur_tal = 1 - h->cur_tal;
     HIPCHK(h, launch_fill_f64(h->tal[h->cur_tal], 0.0, (int64_t)h->B * h->I * 6, h->stream));
     HIPCHK(h, launch_fill_f64(h->bnd[h->cur_tal], 0.0, (int64_t)h->B * 6, h->stream));
     HIPCHK(h, launch_fill_u32(reinterpret_cast<uint32_t *>(h->tracks), 0u, 2 * (int64_t)h->I, h->stream));
     HIPCHK(h, launch_fill_u32(reinterpret_cast<uint32_t *>(h->counters), 0u, 2 * C_NCOUNTERS, h->stream));
     HIPCHK(h, launch_rotate_chunks(h->wstart, h->wnext, h->nc, h->stream));
-    std::fill(h->census_counts.begin(), h->census_counts.end(), 0u);
-    std::memset(h->last_counters, 0, sizeof h->last_counters);
     h->step = step;
     h->next_chunk = 0;
+    h->n_launch = 0;
   } else if (step != h->step || chunk != h->next_chunk) {
     return fail(h, HWW_E_STATE, "chunk out of order");
   }
 
-  const size_t lds = lds_bytes(h);
   SweepArgs<double> a = base_args(h);
   a.chunk = chunk;
-  uint64_t max_in = 0;
-  for (int b = 0; b < h->B; ++b) max_in = std::max<uint64_t>(max_in, h->start_counts[b * h->nc + chunk]);
-  int gen = 0;
-  int n_ev = 0;
-  std::vector<uint32_t> qc(h->B);
-  for (;;) {
-    if (gen >= kMaxGenerations) return fail(h, HWW_E_CAPACITY, "more than 64 generations of daughters");
-    const int qo = gen & 1;  // queue written by this generation
-    a.gen = gen;
-    a.out_q = h->q[qo];
-    if (gen > 0) a.in_q = h->q[1 - qo];
-    HIPCHK(h, launch_fill_u32(h->q[qo].count, 0u, h->B, h->stream));
-    HIPCHK(h, launch_fill_u32(h->cursor, 0u, h->B, h->stream));
-    if (max_in > 0) {
-      HIPCHK(h, hipEventRecord(h->ev[2 * n_ev], h->stream));
-      HIPCHK(h, launch_sweep_f64(a, grid_for(h, max_in), h->block, lds, h->stream));
-      HIPCHK(h, hipEventRecord(h->ev[2 * n_ev + 1], h->stream));
-      ++n_ev;
-    }
-    HIPCHK(h, hipMemcpyAsync(qc.data(), h->q[qo].count, 4 * h->B, hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(h, hipStreamSynchronize(h->stream));
-    uint64_t tot = 0;
-    max_in = 0;
-    for (int b = 0; b < h->B; ++b) {
-      tot += qc[b];
-      max_in = std::max<uint64_t>(max_in, qc[b]);
-    }
-    ++gen;
-    if (tot == 0) break;
-    if (max_in > (uint64_t)h->L.cap_d) break;  // overflow: reported below
-  }
+  HIPCHK(h, launch_fill_u32(h->cursor, 0u, h->B, h->stream));
+  const int k = h->n_launch;
+  HIPCHK(h, hipEventRecord(h->ev[2 * k], h->stream));
+  HIPCHK(h, launch_sweep_f64(a, h->B * h->K, kBlock, h->lds, h->stream));
+  HIPCHK(h, hipEventRecord(h->ev[2 * k + 1], h->stream));
+  h->n_launch = k + 1;
   h->next_chunk = chunk + 1;
+  if (!stats) return HWW_OK;
 
   unsigned long long cnt[C_NCOUNTERS];
   HIPCHK(h, hipMemcpyAsync(cnt, h->counters, sizeof cnt, hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(h, hipMemcpyAsync(h->census_counts.data(), h->bank[1 - h->start_bank].count, 4 * h->R,
-                           hipMemcpyDeviceToHost, h->stream));
   int rc = poll_errors(h);
   if (rc != HWW_OK) return rc;
-  uint64_t census_total = 0;
-  for (uint32_t c : h->census_counts) census_total += c;
-  if (census_total > (uint64_t)h->p.bank_capacity) {
-    h->fatal = HWW_E_CAPACITY;
-    return fail(h, HWW_E_CAPACITY, "census bank exceeds bank_capacity");
+  stats->segments = cnt[C_SEGMENTS];
+  stats->collisions = cnt[C_COLLISIONS];
+  stats->scatters = cnt[C_SCATTERS];
+  stats->absorptions = cnt[C_ABSORPTIONS];
+  stats->crossings = cnt[C_CROSSINGS];
+  stats->leaks = cnt[C_LEAKS];
+  stats->census = cnt[C_CENSUS];
+  stats->splits = cnt[C_SPLITS];
+  stats->daughters = cnt[C_DAUGHTERS];
+  stats->rr_kill = cnt[C_RR_KILL];
+  stats->rr_survive = cnt[C_RR_SURVIVE];
+  stats->histories = cnt[C_HISTORIES];
+  stats->generations = cnt[C_GENERATIONS];
+  stats->launches = (uint64_t)h->n_launch;
+  double ms = 0.0;
+  for (int q = 0; q < h->n_launch; ++q) {
+    float t = 0.0f;
+    HIPCHK(h, hipEventElapsedTime(&t, h->ev[2 * q], h->ev[2 * q + 1]));
+    ms += t;
   }
-  if (stats) {
-    uint64_t d[C_NCOUNTERS];
-    for (int k = 0; k < C_NCOUNTERS; ++k) d[k] = cnt[k] - h->last_counters[k];
-    stats->segments = d[C_SEGMENTS];
-    stats->collisions = d[C_COLLISIONS];
-    stats->scatters = d[C_SCATTERS];
-    stats->absorptions = d[C_ABSORPTIONS];
-    stats->crossings = d[C_CROSSINGS];
-    stats->leaks = d[C_LEAKS];
-    stats->census = d[C_CENSUS];
-    stats->splits = d[C_SPLITS];
-    stats->daughters = d[C_DAUGHTERS];
-    stats->rr_kill = d[C_RR_KILL];
-    stats->rr_survive = d[C_RR_SURVIVE];
-    stats->histories = d[C_HISTORIES];
-    stats->generations = (uint64_t)gen;
-    double ms = 0.0;
-    for (int k = 0; k < n_ev; ++k) {
-      float t = 0.0f;
-      HIPCHK(h, hipEventElapsedTime(&t, h->ev[2 * k], h->ev[2 * k + 1]));
-      ms += t;
-    }
-    stats->kernel_ms = ms;
-    const uint64_t rec = 44, drec = 52;
-    stats->bytes_moved = d[C_HISTORIES] * rec + d[C_CENSUS] * rec + d[C_DAUGHTERS] * 2 * drec;
-  }
-  for (int k = 0; k < C_NCOUNTERS; ++k) h->last_counters[k] = cnt[k];
+  stats->kernel_ms = ms;
+  const uint64_t rec = 44, drec = 52;
+  stats->bytes_moved = cnt[C_HISTORIES] * rec + cnt[C_CENSUS] * rec + cnt[C_DAUGHTERS] * 2 * drec;
   return HWW_OK;
 }
 
@@ -538,9 +529,13 @@ int hww_solve_losm(hww_handle *h, const hww_losm_opts *o, double *phi_out, doubl
   a.theta = o->theta; a.implicit = o->implicit; a.filter = o->filter; a.ma_k = o->ma_k;
   a.closure_track = o->closure_track; a.apply_windows = o->apply_windows;
   a.eps_min = o->eps_min; a.rho = o->rho;
-  a.scratch = h->scratch; a.centre = h->centre; a.wceil = h->wceil; a.wfloor = h->wfloor;
+  a.scratch = h->scratch; a.factor = h->factor;
+  a.refactor = (o->theta != h->factor_theta) ? 1 : 0;
+  a.centre = h->centre; a.wceil = h->wceil; a.wfloor = h->wfloor;
   a.phi_out = h->phi_out; a.J_out = h->J_out; a.err = h->err; a.status = h->status;
+  if (a.refactor) HIPCHK(h, launch_fill_u32(reinterpret_cast<uint32_t *>(h->status), 0u, 1, h->stream));
   HIPCHK(h, launch_losm(a, h->stream));
+  h->factor_theta = o->theta;
   if (o->apply_windows) h->ww_on = 1;
   if (phi_out || J_out) {
     if (phi_out) HIPCHK(h, hipMemcpyAsync(phi_out, h->phi_out, 8 * (size_t)(h->I + 2), hipMemcpyDeviceToHost, h->stream));
@@ -555,7 +550,6 @@ int hww_read_tallies(hww_handle *h, int32_t kind, void *out, int64_t out_bytes) 
   const int64_t I = h->I, B = h->B;
   const void *src = nullptr;
   int64_t bytes = 0;
-  uint64_t counts[2];
   switch (kind) {
     case HWW_TALLY_CELLS: src = h->tal[h->cur_tal]; bytes = 8 * B * I * 6; break;
     case HWW_TALLY_BOUNDARY: src = h->bnd[h->cur_tal]; bytes = 8 * B * 6; break;
@@ -568,12 +562,13 @@ int hww_read_tallies(hww_handle *h, int32_t kind, void *out, int64_t out_bytes) 
   }
   if (out_bytes != bytes) return fail(h, HWW_E_INVALID_ARG, "out_bytes does not match the tally kind");
   if (kind == HWW_TALLY_BANK_COUNTS) {
-    HIPCHK(h, hipStreamSynchronize(h->stream));
-    uint64_t s0 = 0, s1 = 0;
-    for (uint32_t c : h->start_counts) s0 += c;
-    for (uint32_t c : h->census_counts) s1 += c;
-    counts[0] = h->step == 0 ? 0 : s0;
-    counts[1] = s1;
+    uint64_t counts[2] = {0, 0};
+    if (h->step > 0) {
+      int rc = census_total(h, h->start_bank, &counts[0]);
+      if (rc != HWW_OK) return rc;
+    }
+    int rc = census_total(h, 1 - h->start_bank, &counts[1]);
+    if (rc != HWW_OK) return rc;
     std::memcpy(out, counts, 16);
     return HWW_OK;
   }
@@ -593,29 +588,38 @@ int hww_read_bank(hww_handle *h, int32_t which, int64_t cap, int64_t *count, dou
     *count = 0;
     return HWW_OK;
   }
-  const Bank<double> &bk = h->bank[which == 0 ? h->start_bank : 1 - h->start_bank];
-  std::vector<uint32_t> cnt(h->R);
-  HIPCHK(h, hipMemcpyAsync(cnt.data(), bk.count, 4 * h->R, hipMemcpyDeviceToHost, h->stream));
+  const int bi = which == 0 ? h->start_bank : 1 - h->start_bank;
+  const Bank<double> &bk = h->bank[bi];
+  const BankGeom &G = h->L.geom;
+  std::vector<uint32_t> seg((size_t)h->R * h->K), ovf(h->R);
+  HIPCHK(h, hipMemcpyAsync(seg.data(), bk.segcnt, 4 * seg.size(), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipMemcpyAsync(ovf.data(), bk.ovfcnt, 4 * ovf.size(), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
   int64_t total = 0;
-  for (int r = 0; r < h->R; ++r) total += std::min<int64_t>(cnt[r], h->L.cap_r);
+  for (int r = 0; r < h->R; ++r) {
+    for (int j = 0; j < h->K; ++j) total += std::min<int64_t>(seg[(size_t)r * h->K + j], G.seg_cap);
+    total += std::min<int64_t>(ovf[r], G.ovf_cap);
+  }
   *count = total;
   if (total > cap) return fail(h, HWW_E_INVALID_ARG, "cap smaller than the bank");
   int64_t o = 0;
   for (int r = 0; r < h->R; ++r) {
-    const int64_t n = std::min<int64_t>(cnt[r], h->L.cap_r);
-    if (n == 0) continue;
-    const int64_t k = (int64_t)r * h->L.cap_r;
-    if (x) HIPCHK(h, hipMemcpyAsync(x + o, bk.x + k, 8 * n, hipMemcpyDeviceToHost, h->stream));
-    if (mu) HIPCHK(h, hipMemcpyAsync(mu + o, bk.mu + k, 8 * n, hipMemcpyDeviceToHost, h->stream));
-    if (w) HIPCHK(h, hipMemcpyAsync(w + o, bk.w + k, 8 * n, hipMemcpyDeviceToHost, h->stream));
-    if (src) HIPCHK(h, hipMemcpyAsync(src + o, bk.src + k, 4 * n, hipMemcpyDeviceToHost, h->stream));
-    if (lin) HIPCHK(h, hipMemcpyAsync(lin + o, bk.lin + k, 8 * n, hipMemcpyDeviceToHost, h->stream));
-    if (e) HIPCHK(h, hipMemcpyAsync(e + o, bk.e + k, 4 * n, hipMemcpyDeviceToHost, h->stream));
-    if (cell) HIPCHK(h, hipMemcpyAsync(cell + o, bk.cell + k, 4 * n, hipMemcpyDeviceToHost, h->stream));
-    if (chunk)
-      for (int64_t j = 0; j < n; ++j) chunk[o + j] = r % h->nc;
-    o += n;
+    for (int j = 0; j <= h->K; ++j) {
+      const int64_t n = j < h->K ? std::min<int64_t>(seg[(size_t)r * h->K + j], G.seg_cap)
+                                 : std::min<int64_t>(ovf[r], G.ovf_cap);
+      if (n == 0) continue;
+      const int64_t k = (int64_t)r * G.stride + (int64_t)j * G.seg_cap;
+      if (x) HIPCHK(h, hipMemcpyAsync(x + o, bk.x + k, 8 * n, hipMemcpyDeviceToHost, h->stream));
+      if (mu) HIPCHK(h, hipMemcpyAsync(mu + o, bk.mu + k, 8 * n, hipMemcpyDeviceToHost, h->stream));
+      if (w) HIPCHK(h, hipMemcpyAsync(w + o, bk.w + k, 8 * n, hipMemcpyDeviceToHost, h->stream));
+      if (src) HIPCHK(h, hipMemcpyAsync(src + o, bk.src + k, 4 * n, hipMemcpyDeviceToHost, h->stream));
+      if (lin) HIPCHK(h, hipMemcpyAsync(lin + o, bk.lin + k, 8 * n, hipMemcpyDeviceToHost, h->stream));
+      if (e) HIPCHK(h, hipMemcpyAsync(e + o, bk.e + k, 4 * n, hipMemcpyDeviceToHost, h->stream));
+      if (cell) HIPCHK(h, hipMemcpyAsync(cell + o, bk.cell + k, 4 * n, hipMemcpyDeviceToHost, h->stream));
+      if (chunk)
+        for (int64_t q = 0; q < n; ++q) chunk[o + q] = r % h->nc;
+      o += n;
+    }
   }
   HIPCHK(h, hipStreamSynchronize(h->stream));
   return HWW_OK;

@@ -4,15 +4,18 @@
 // track-length and time-crossing tallies (Sec. 3, Eqs. phi-mc, ct-mc),
 // and split / Russian roulette against weight windows (Sec. 2).
 //
-// Launch shape: grid = B * k work-groups.  Work-group g serves batch
-// b = g mod B; all lanes of a wave therefore belong to one batch, so a
-// work-group keeps its batch's tallies in an LDS histogram that is flushed
-// to HBM once, with FP64 atomics, and census / daughter writes compact by
-// wave ballot into batch-private regions with one atomic per wave.
-//
+// Launch shape: grid = B * K work-groups; work-group g serves batch
+// b = g mod B and owns segment j = g / B of every census region of that
+// batch.  Consequences:
+//  - all lanes of a wave belong to one batch, so the work-group keeps the
+//    batch's tallies in an LDS histogram flushed to HBM once per launch;
+//  - census appends need only a work-group-local LDS counter (a shared
+//    overflow segment takes what does not fit);
+//  - daughters split off by the work-group go to its own buffer and are
+//    transported by the same work-group in further generations, so no
+//    work-group ever waits for another and the host never waits at all.
 // Each wave keeps its 64 lanes busy: a lane whose particle ends (census,
-// leak, absorption, roulette) refills from the wave's current tile of the
-// input list; tiles are claimed from a per-batch atomic cursor.
+// leak, absorption, roulette) refills from the wave's current tile.
 #include "hww_internal.h"
 
 namespace hww {
@@ -52,9 +55,23 @@ __device__ __forceinline__ double u53(uint32_t a, uint32_t b) {
   return k * (1.0 / 9007199254740992.0);
 }
 
-__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 __device__ __forceinline__ uint32_t rank_below(uint64_t m) {
   return (uint32_t)__popcll(m & __lanemask_lt());
+}
+
+__device__ __forceinline__ int first_lane(uint64_t m) { return __ffsll((long long)m) - 1; }
+
+// Cell of x; a point on an interior edge belongs to the cell it moves into.
+__device__ __forceinline__ int32_t find_cell(const double *edges, int I, double x, double mu) {
+  if (x <= edges[0]) return 0;
+  if (x >= edges[I]) return I - 1;
+  int32_t lo = 0, hi = I;
+  while (hi - lo > 1) {
+    const int32_t mid = (lo + hi) / 2;
+    if (edges[mid] <= x) lo = mid; else hi = mid;
+  }
+  if (x == edges[lo] && mu < 0.0 && lo > 0) lo -= 1;
+  return lo;
 }
 
 struct LaneCounters {
@@ -62,40 +79,145 @@ struct LaneCounters {
   uint32_t splits, daughters, rr_kill, rr_survive, histories;
 };
 
-// Shared-memory layout of a work-group.
+// Shared-memory carve-up common to the sweep and source kernels.
 struct Lds {
-  double *hist;    // [I][6]
-  uint32_t *trk;   // [I]
-  double *wnext;   // [nc]
-  double *bnd;     // [6]
-  uint32_t *cnt;   // [C_NCOUNTERS]
+  double *hist;     // [I][6]
+  double *wnext;    // [nc]
+  double *bnd;      // [6]
+  uint32_t *trk;    // [I]
+  uint32_t *cnt;    // [16]
+  uint32_t *ccnt;   // [8]   census appends of this work-group per chunk
+  uint32_t *dcnt;   // [2]   daughters per buffer
+  uint32_t *dcur;   // [1]   daughter tile cursor
+  uint32_t *tstart; // [K+2] first tile of each start-bank segment
+  uint32_t *nseg;   // [K+1] particles of each start-bank segment
 };
 
-__device__ __forceinline__ void lds_add(double *p, double v) { atomicAdd(p, v); }
+
+__device__ inline Lds carve(double *raw, int I, int nc, int K) {
+  Lds L;
+  L.hist = raw;
+  L.wnext = raw + (size_t)I * 6;
+  L.bnd = L.wnext + nc;
+  L.trk = reinterpret_cast<uint32_t *>(L.bnd + 6);
+  L.cnt = L.trk + I;
+  L.ccnt = L.cnt + 16;
+  L.dcnt = L.ccnt + 8;
+  L.dcur = L.dcnt + 2;
+  L.tstart = L.dcur + 1;
+  L.nseg = L.tstart + (K + 2);
+  return L;
+}
+
+__device__ inline void zero_lds(double *raw, int I, int nc, int K) {
+  const size_t nd = lds_doubles(I, nc);
+  for (size_t t = threadIdx.x; t < nd; t += blockDim.x) raw[t] = 0.0;
+  uint32_t *w = reinterpret_cast<uint32_t *>(raw + nd);
+  const size_t nw = lds_words(I, K);
+  for (size_t t = threadIdx.x; t < nw; t += blockDim.x) w[t] = 0u;
+}
+
+// Flush the work-group histogram of batch b (nonzero entries only).
+__device__ inline void flush_tallies(const Lds &L, int I, int nc, int b, double *tal, double *bnd,
+                                     unsigned long long *tracks, double *wnext) {
+  double *tal_b = tal + (size_t)b * I * 6;
+  for (int j = threadIdx.x; j < I * 6; j += blockDim.x) {
+    const double val = L.hist[j];
+    if (val != 0.0) unsafeAtomicAdd(&tal_b[j], val);
+  }
+  if (tracks) {
+    for (int j = threadIdx.x; j < I; j += blockDim.x) {
+      const uint32_t t = L.trk[j];
+      if (t != 0) atomicAdd(&tracks[j], (unsigned long long)t);
+    }
+  }
+  if (bnd && threadIdx.x < 6) {
+    const double val = L.bnd[threadIdx.x];
+    if (val != 0.0) unsafeAtomicAdd(&bnd[b * 6 + threadIdx.x], val);
+  }
+  if (threadIdx.x < (unsigned)nc) {
+    const double val = L.wnext[threadIdx.x];
+    if (val != 0.0) unsafeAtomicAdd(&wnext[threadIdx.x], val);
+  }
+}
+
+template <typename Real>
+__device__ inline void store_record(const Bank<Real> &bk, int64_t k, double x, double mu, double w,
+                                    uint64_t lin, uint32_t src, uint32_t e, int32_t cell) {
+  bk.x[k] = (Real)x;
+  bk.mu[k] = (Real)mu;
+  bk.w[k] = w;
+  bk.lin[k] = lin;
+  bk.src[k] = src;
+  bk.e[k] = e;
+  bk.cell[k] = cell;
+}
+
+// Append the census particles of the wave (lanes with `mine`) to region
+// (b, c): the work-group's own segment first, the shared overflow after.
+template <typename Real>
+__device__ inline void census_append(const Bank<Real> &bk, const BankGeom &G, uint32_t *ccnt_c,
+                                     uint32_t *ovfcnt_bc, int64_t region_base, int j, bool mine, double x,
+                                     double mu, double w, uint64_t lin, uint32_t src, uint32_t e,
+                                     int32_t cell, uint32_t *err) {
+  const uint32_t lane = __lane_id();
+  const uint64_t m = __ballot(mine);
+  if (m == 0) return;
+  const int leader = first_lane(m);
+  uint32_t base = 0;
+  if ((int)lane == leader) base = atomicAdd(ccnt_c, (uint32_t)__popcll(m));
+  base = __shfl(base, leader);
+  const uint64_t slot = (uint64_t)base + rank_below(m);
+  const bool in_seg = mine && slot < (uint64_t)G.seg_cap;
+  int64_t k = -1;
+  if (in_seg) k = region_base + (int64_t)j * G.seg_cap + (int64_t)slot;
+  const uint64_t om = __ballot(mine && !in_seg);
+  if (om != 0) {
+    const int ol = first_lane(om);
+    uint32_t ob = 0;
+    if ((int)lane == ol) ob = atomicAdd(ovfcnt_bc, (uint32_t)__popcll(om));
+    ob = __shfl(ob, ol);
+    if (mine && !in_seg) {
+      const uint64_t os = (uint64_t)ob + rank_below(om);
+      if (os < (uint64_t)G.ovf_cap) k = region_base + (int64_t)G.K * G.seg_cap + (int64_t)os;
+      else atomicOr(err, ERR_CAPACITY);
+    }
+  }
+  if (k >= 0) store_record(bk, k, x, mu, w, lin, src, e, cell);
+}
 
 template <typename Real>
 __global__ void __launch_bounds__(1024) sweep_kernel(SweepArgs<Real> A) {
   extern __shared__ double lds_raw[];
-  const int I = A.I;
-  Lds L;
-  L.hist = lds_raw;
-  L.wnext = lds_raw + (size_t)I * 6;
-  L.bnd = L.wnext + A.nc;
-  L.trk = reinterpret_cast<uint32_t *>(L.bnd + 6);
-  L.cnt = L.trk + I;
-  for (int j = threadIdx.x; j < I * 6 + A.nc + 6; j += blockDim.x) lds_raw[j] = 0.0;
-  for (int j = threadIdx.x; j < I + C_NCOUNTERS; j += blockDim.x) L.trk[j] = 0u;
+  const int I = A.I, nc = A.nc;
+  const BankGeom G = A.geom;
+  const int K = G.K;
+  Lds L = carve(lds_raw, I, nc, K);
+  zero_lds(lds_raw, I, nc, K);
+  const int b = blockIdx.x % A.B;
+  const int jseg = blockIdx.x / A.B;
+  const int tid = threadIdx.x;
+  const int r_in = b * nc + A.chunk;
+  const int64_t in_region = (int64_t)r_in * G.stride;
+  __syncthreads();
+  if (tid < nc) L.ccnt[tid] = A.census.segcnt[(b * nc + tid) * K + jseg];
+  if (tid == 0) {
+    uint32_t acc = 0;
+    for (int s = 0; s <= K; ++s) {
+      uint32_t n = (s < K) ? A.in_bank.segcnt[r_in * K + s] : A.in_bank.ovfcnt[r_in];
+      const uint32_t cap = (uint32_t)((s < K) ? G.seg_cap : G.ovf_cap);
+      if (n > cap) n = cap;
+      L.nseg[s] = n;
+      L.tstart[s] = acc;
+      acc += (n + TILE - 1) / TILE;
+    }
+    L.tstart[K + 1] = acc;
+  }
   __syncthreads();
 
-  const int b = blockIdx.x % A.B;
-  const uint32_t lane = lane_id();
-  const bool from_bank = (A.gen == 0);
-  uint32_t n_in = from_bank ? A.in_bank.count[b * A.nc + A.chunk] : A.in_q.count[b];
-  // An overflowed list is already flagged; never read past its region.
-  const int64_t in_cap = from_bank ? A.cap_r : A.cap_d;
-  if ((int64_t)n_in > in_cap) n_in = (uint32_t)in_cap;
-  const int64_t in_base = from_bank ? (int64_t)(b * A.nc + A.chunk) * A.cap_r : (int64_t)b * A.cap_d;
+  const uint32_t lane = __lane_id();
   const double v = A.v;
+  const int64_t dstride = A.dcap;
 
   // Lane state.
   double x = 0.0, mu = 0.0, w = 0.0, tau = 0.0;
@@ -103,16 +225,15 @@ __global__ void __launch_bounds__(1024) sweep_kernel(SweepArgs<Real> A) {
   uint32_t src = 0, e = 0;
   uint64_t lin = 0;
   bool active = false;
-  // Pending split of this lane: daughters copy the lane state.
+  // Pending split of this lane: the daughters copy the lane state.
   uint32_t nd = 0;
   uint64_t lin_base = 0;
   uint32_t e_d = 0;
-
-  uint32_t tile_next = 0, tile_end = 0;
-  bool exhausted = false;
   LaneCounters C = {};
+  int out_buf = 0;
 
-  // Write the pending daughters of all lanes of the wave (converged call).
+  // Write the pending daughters of all lanes of the wave into the work-
+  // group's buffer `out_buf` (converged call).
   auto flush_daughters = [&]() {
     const uint32_t cntd = nd > 1 ? nd - 1 : 0;
     uint32_t incl = cntd;
@@ -124,26 +245,23 @@ __global__ void __launch_bounds__(1024) sweep_kernel(SweepArgs<Real> A) {
     const uint32_t total = __shfl(incl, 63);
     if (total != 0) {
       uint32_t base = 0;
-      if (lane == 0) base = atomicAdd(&A.out_q.count[b], total);
+      if (lane == 0) base = atomicAdd(&L.dcnt[out_buf], total);
       base = __shfl(base, 0);
-      if ((uint64_t)base + total > (uint64_t)A.cap_d) {
-        if (lane == 0) atomicOr(A.err, ERR_CAPACITY);
-      }
+      if ((uint64_t)base + total > (uint64_t)A.dcap && lane == 0) atomicOr(A.err, ERR_CAPACITY);
+      const int64_t qb = ((int64_t)out_buf * gridDim.x + blockIdx.x) * dstride;
       const uint32_t start = base + incl - cntd;
-      for (uint32_t j = 1; j <= cntd; ++j) {
-        const uint64_t slot = (uint64_t)start + (j - 1);
-        if (slot >= (uint64_t)A.cap_d) break;
-        {
-          const int64_t k = (int64_t)b * A.cap_d + (int64_t)slot;
-          A.out_q.x[k] = (Real)x;
-          A.out_q.mu[k] = (Real)mu;
-          A.out_q.w[k] = w;
-          A.out_q.tau[k] = tau;
-          A.out_q.lin[k] = lin_base + j;
-          A.out_q.src[k] = src;
-          A.out_q.e[k] = e_d;
-          A.out_q.cell[k] = cell;
-        }
+      for (uint32_t q = 1; q <= cntd; ++q) {
+        const uint64_t slot = (uint64_t)start + (q - 1);
+        if (slot >= (uint64_t)A.dcap) break;
+        const int64_t k = qb + (int64_t)slot;
+        A.dq.x[k] = (Real)x;
+        A.dq.mu[k] = (Real)mu;
+        A.dq.w[k] = w;
+        A.dq.tau[k] = tau;
+        A.dq.lin[k] = lin_base + q;
+        A.dq.src[k] = src;
+        A.dq.e[k] = e_d;
+        A.dq.cell[k] = cell;
       }
     }
     nd = 0;
@@ -151,9 +269,7 @@ __global__ void __launch_bounds__(1024) sweep_kernel(SweepArgs<Real> A) {
 
   // Weight-window check of the lane's particle in its cell (Sec. 2).
   // kind 0: after an event at index e_ev; kind 1: start of step.
-  // xi_slot: slot whose u_b is the roulette variate (drawn only if needed).
-  auto ww_check = [&](int kind, uint32_t e_ev, uint32_t e_daughter, int xi_slot, bool have_xi,
-                      double xi) {
+  auto ww_check = [&](int kind, uint32_t e_ev, uint32_t e_daughter, int xi_slot, bool have_xi, double xi) {
     if (!A.ww_on) return;
     const double ww = A.centre[cell];
     if (w > A.wceil[cell]) {
@@ -163,7 +279,7 @@ __global__ void __launch_bounds__(1024) sweep_kernel(SweepArgs<Real> A) {
         active = false;
         return;
       }
-      if (ndf - 1.0 > (double)A.cap_d) {
+      if (ndf - 1.0 > (double)A.dcap) {
         atomicOr(A.err, ERR_CAPACITY);
         active = false;
         return;
@@ -192,180 +308,210 @@ __global__ void __launch_bounds__(1024) sweep_kernel(SweepArgs<Real> A) {
     }
   };
 
+  int gen = 0;
+  uint32_t n_list = 0;  // daughters to transport in a generation >= 1
   for (;;) {
-    // ---------------------------------------------------------- refill --
-    const uint64_t need_m = __ballot(!active);
-    if (need_m != 0) {
-      if (tile_next == tile_end && !exhausted) {
-        uint32_t t0 = 0;
-        if (lane == 0) t0 = atomicAdd(&A.cursor[b], (uint32_t)TILE);
-        t0 = __shfl(t0, 0);
-        if (t0 >= n_in) {
-          exhausted = true;
-        } else {
-          tile_next = t0;
-          tile_end = min(t0 + (uint32_t)TILE, n_in);
-        }
-      }
-      const uint32_t avail = tile_end - tile_next;
-      if (avail != 0) {
-        const uint32_t take = min((uint32_t)__popcll(need_m), avail);
-        const uint32_t rk = rank_below(need_m);
-        if (!active && rk < take) {
-          const int64_t k = in_base + (int64_t)(tile_next + rk);
-          if (from_bank) {
-            x = (double)A.in_bank.x[k];
-            mu = (double)A.in_bank.mu[k];
-            w = A.in_bank.w[k];
-            lin = A.in_bank.lin[k];
-            src = A.in_bank.src[k];
-            e = A.in_bank.e[k];
-            cell = A.in_bank.cell[k];
-            tau = A.dt;
-            active = true;
-            C.histories += 1;
-            ww_check(1, e, e, SLOT_START, false, 0.0);
+    const bool from_bank = (gen == 0);
+    const int in_buf = (gen + 1) & 1;  // buffer written by the previous generation
+    out_buf = gen & 1;
+    const int64_t in_qbase = ((int64_t)in_buf * gridDim.x + blockIdx.x) * dstride;
+
+    int64_t tile_base = 0;
+    uint32_t tile_next = 0, tile_end = 0;
+    bool exhausted = false;
+    for (;;) {
+      // ---------------------------------------------------------- refill --
+      const uint64_t need_m = __ballot(!active);
+      if (need_m != 0) {
+        if (tile_next == tile_end && !exhausted) {
+          int64_t tb = -1;
+          uint32_t tl = 0;
+          if (lane == 0) {
+            if (from_bank) {
+              const uint32_t t = atomicAdd(&A.cursor[b], 1u);
+              if (t < L.tstart[K + 1]) {
+                int s = K;
+                while (L.tstart[s] > t) --s;
+                const uint32_t off = (t - L.tstart[s]) * (uint32_t)TILE;
+                tl = min((uint32_t)TILE, L.nseg[s] - off);
+                tb = in_region + (s < K ? (int64_t)s * G.seg_cap : (int64_t)K * G.seg_cap) + off;
+              }
+            } else {
+              const uint32_t t0 = atomicAdd(L.dcur, (uint32_t)TILE);
+              if (t0 < n_list) {
+                tl = min((uint32_t)TILE, n_list - t0);
+                tb = in_qbase + t0;
+              }
+            }
+          }
+          tb = __shfl(tb, 0);
+          tl = __shfl(tl, 0);
+          if (tb < 0) {
+            exhausted = true;
           } else {
-            x = (double)A.in_q.x[k];
-            mu = (double)A.in_q.mu[k];
-            w = A.in_q.w[k];
-            tau = A.in_q.tau[k];
-            lin = A.in_q.lin[k];
-            src = A.in_q.src[k];
-            e = A.in_q.e[k];
-            cell = A.in_q.cell[k];
-            active = true;
+            tile_base = tb;
+            tile_next = 0;
+            tile_end = tl;
           }
         }
-        tile_next += take;
-      }
-      flush_daughters();
-    }
-    if (__ballot(active) == 0) {
-      if (exhausted && tile_next == tile_end) break;
-      continue;
-    }
-
-    // --------------------------------------------------------- segment --
-    bool at_census = false;
-    int32_t next_chunk = 0;
-    if (active) {
-      const int i = cell;
-      uint32_t r[4];
-      draw(A.seed, A.key1, SLOT_FLIGHT, src, lin, e, r);
-      const double ua = u53(r[0], r[1]);
-      const double ub = u53(r[2], r[3]);
-      const double d_coll = -log(1.0 - ua) / A.sig_t[i];
-      const double xl = A.edges[i], xr = A.edges[i + 1];
-      double d_bnd;
-      if (mu > 0.0) d_bnd = (xr - x) / mu;
-      else if (mu < 0.0) d_bnd = (xl - x) / mu;
-      else d_bnd = __builtin_inf();
-      const double d_cen = v * tau;
-      int ev;
-      double l;
-      if (d_cen <= d_bnd && d_cen <= d_coll) { ev = 0; l = d_cen; }
-      else if (d_bnd <= d_coll) { ev = 1; l = d_bnd; }
-      else { ev = 2; l = d_coll; }
-
-      // Track-length tally of phi, J and K in cell i (Eq. phi-mc).
-      const double wl = w * l;
-      const double t1 = wl * mu;
-      lds_add(&L.hist[i * 6 + 0], wl);
-      lds_add(&L.hist[i * 6 + 1], t1);
-      lds_add(&L.hist[i * 6 + 2], t1 * mu);
-      atomicAdd(&L.trk[i], 1u);
-      C.segments += 1;
-      const uint32_t e_ev = e;
-      e = e_ev + 1;
-
-      if (ev == 0) {
-        double xn = x + mu * l;
-        if (xn < xl) xn = xl;
-        if (xn > xr) xn = xr;
-        x = xn;
-        uint32_t rc[4];
-        draw(A.seed, A.key1, SLOT_START, src, lin, e, rc);
-        next_chunk = (int32_t)(u53(rc[0], rc[1]) * (double)A.nc);
-        if (next_chunk >= A.nc) next_chunk = A.nc - 1;
-        // Time-crossing tally at t^n (Eq. ct-mc): v*w per particle.
-        const double vw = v * w;
-        const double c1 = vw * mu;
-        lds_add(&L.hist[i * 6 + 3], vw);
-        lds_add(&L.hist[i * 6 + 4], c1);
-        lds_add(&L.hist[i * 6 + 5], c1 * mu);
-        lds_add(&L.wnext[next_chunk], w);
-        C.census += 1;
-        at_census = true;
-        active = false;
-      } else {
-        tau = tau - l / v;
-        if (ev == 1) {
-          const bool out_l = (i == 0 && mu < 0.0);
-          const bool out_r = (i == I - 1 && mu > 0.0);
-          if (out_l || out_r) {
-            // Edge-crossing estimators at the domain faces (w f(mu)/|mu|).
-            const double am = fabs(mu);
-            double *f = L.bnd + (out_l ? 0 : 3);
-            lds_add(&f[0], w / am);
-            lds_add(&f[1], w * (0.5 - am) / am);
-            lds_add(&f[2], w * (1.0 / 3.0 - mu * mu) / am);
-            C.leaks += 1;
-            active = false;
-          } else {
-            if (mu > 0.0) { x = xr; cell = i + 1; }
-            else { x = xl; cell = i - 1; }
-            C.crossings += 1;
-            ww_check(0, e_ev, e, SLOT_EVENT, false, 0.0);
+        const uint32_t avail = tile_end - tile_next;
+        if (avail != 0) {
+          const uint32_t take = min((uint32_t)__popcll(need_m), avail);
+          const uint32_t rk = rank_below(need_m);
+          if (!active && rk < take) {
+            const int64_t k = tile_base + (int64_t)(tile_next + rk);
+            if (from_bank) {
+              x = (double)A.in_bank.x[k];
+              mu = (double)A.in_bank.mu[k];
+              w = A.in_bank.w[k];
+              lin = A.in_bank.lin[k];
+              src = A.in_bank.src[k];
+              e = A.in_bank.e[k];
+              cell = A.in_bank.cell[k];
+              tau = A.dt;
+              active = true;
+              C.histories += 1;
+              ww_check(1, e, e, SLOT_START, false, 0.0);
+            } else {
+              x = (double)A.dq.x[k];
+              mu = (double)A.dq.mu[k];
+              w = A.dq.w[k];
+              tau = A.dq.tau[k];
+              lin = A.dq.lin[k];
+              src = A.dq.src[k];
+              e = A.dq.e[k];
+              cell = A.dq.cell[k];
+              active = true;
+            }
           }
-        } else {
+          tile_next += take;
+        }
+        flush_daughters();
+      }
+      if (__ballot(active) == 0) {
+        if (exhausted && tile_next == tile_end) break;
+        continue;
+      }
+
+      // --------------------------------------------------------- segment --
+      bool at_census = false;
+      int32_t next_chunk = 0;
+      if (active) {
+        const int i = cell;
+        uint32_t r[4];
+        draw(A.seed, A.key1, SLOT_FLIGHT, src, lin, e, r);
+        const double ua = u53(r[0], r[1]);
+        const double ub = u53(r[2], r[3]);
+        const double d_coll = -log(1.0 - ua) / A.sig_t[i];
+        const double xl = A.edges[i], xr = A.edges[i + 1];
+        double d_bnd;
+        if (mu > 0.0) d_bnd = (xr - x) / mu;
+        else if (mu < 0.0) d_bnd = (xl - x) / mu;
+        else d_bnd = __builtin_inf();
+        const double d_cen = v * tau;
+        int ev;
+        double l;
+        if (d_cen <= d_bnd && d_cen <= d_coll) { ev = 0; l = d_cen; }
+        else if (d_bnd <= d_coll) { ev = 1; l = d_bnd; }
+        else { ev = 2; l = d_coll; }
+
+        // Track-length tally of phi, J and K in cell i (Eq. phi-mc).
+        const double wl = w * l;
+        const double t1 = wl * mu;
+        atomicAdd(&L.hist[i * 6 + 0], wl);
+        atomicAdd(&L.hist[i * 6 + 1], t1);
+        atomicAdd(&L.hist[i * 6 + 2], t1 * mu);
+        atomicAdd(&L.trk[i], 1u);
+        C.segments += 1;
+        const uint32_t e_ev = e;
+        e = e_ev + 1;
+
+        if (ev == 0) {
           double xn = x + mu * l;
           if (xn < xl) xn = xl;
           if (xn > xr) xn = xr;
           x = xn;
-          C.collisions += 1;
-          if (ub < A.cratio[i]) {
-            uint32_t r1[4];
-            draw(A.seed, A.key1, SLOT_EVENT, src, lin, e_ev, r1);
-            mu = 2.0 * u53(r1[0], r1[1]) - 1.0;
-            C.scatters += 1;
-            ww_check(0, e_ev, e, SLOT_EVENT, true, u53(r1[2], r1[3]));
+          uint32_t rc[4];
+          draw(A.seed, A.key1, SLOT_START, src, lin, e, rc);
+          next_chunk = (int32_t)(u53(rc[0], rc[1]) * (double)nc);
+          if (next_chunk >= nc) next_chunk = nc - 1;
+          // Time-crossing tally at t^n (Eq. ct-mc): v*w per particle.
+          const double vw = v * w;
+          const double c1 = vw * mu;
+          atomicAdd(&L.hist[i * 6 + 3], vw);
+          atomicAdd(&L.hist[i * 6 + 4], c1);
+          atomicAdd(&L.hist[i * 6 + 5], c1 * mu);
+          atomicAdd(&L.wnext[next_chunk], w);
+          C.census += 1;
+          at_census = true;
+          active = false;
+        } else {
+          tau = tau - l / v;
+          if (ev == 1) {
+            const bool out_l = (i == 0 && mu < 0.0);
+            const bool out_r = (i == I - 1 && mu > 0.0);
+            if (out_l || out_r) {
+              // Edge-crossing estimators at the domain faces (w f(mu)/|mu|).
+              const double am = fabs(mu);
+              double *f = L.bnd + (out_l ? 0 : 3);
+              atomicAdd(&f[0], w / am);
+              atomicAdd(&f[1], w * (0.5 - am) / am);
+              atomicAdd(&f[2], w * (1.0 / 3.0 - mu * mu) / am);
+              C.leaks += 1;
+              active = false;
+            } else {
+              if (mu > 0.0) { x = xr; cell = i + 1; }
+              else { x = xl; cell = i - 1; }
+              C.crossings += 1;
+              ww_check(0, e_ev, e, SLOT_EVENT, false, 0.0);
+            }
           } else {
-            C.absorptions += 1;
-            active = false;
+            double xn = x + mu * l;
+            if (xn < xl) xn = xl;
+            if (xn > xr) xn = xr;
+            x = xn;
+            C.collisions += 1;
+            if (ub < A.cratio[i]) {
+              uint32_t r1[4];
+              draw(A.seed, A.key1, SLOT_EVENT, src, lin, e_ev, r1);
+              mu = 2.0 * u53(r1[0], r1[1]) - 1.0;
+              C.scatters += 1;
+              ww_check(0, e_ev, e, SLOT_EVENT, true, u53(r1[2], r1[3]));
+            } else {
+              C.absorptions += 1;
+              active = false;
+            }
           }
         }
       }
+
+      // -------------------------------------------------- census appends --
+      if (__ballot(at_census) != 0) {
+        for (int c = 0; c < nc; ++c) {
+          const int64_t region = (int64_t)(b * nc + c) * G.stride;
+          census_append(A.census, G, &L.ccnt[c], &A.census.ovfcnt[b * nc + c], region, jseg,
+                        at_census && next_chunk == c, x, mu, w, lin, src, e, cell, A.err);
+        }
+      }
+      if (__ballot(nd > 1) != 0) flush_daughters();
     }
 
-    // -------------------------------------------------- census compaction --
-    const uint64_t cen_m = __ballot(at_census);
-    if (cen_m != 0) {
-      for (int c = 0; c < A.nc; ++c) {
-        const uint64_t m = __ballot(at_census && next_chunk == c);
-        if (m == 0) continue;
-        const uint32_t leader = (uint32_t)(__ffsll((long long)m) - 1);
-        uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(&A.census.count[b * A.nc + c], (uint32_t)__popcll(m));
-        base = __shfl(base, (int)leader);
-        if (at_census && next_chunk == c) {
-          const uint64_t slot = (uint64_t)base + rank_below(m);
-          if (slot < (uint64_t)A.cap_r) {
-            const int64_t k = (int64_t)(b * A.nc + c) * A.cap_r + (int64_t)slot;
-            A.census.x[k] = (Real)x;
-            A.census.mu[k] = (Real)mu;
-            A.census.w[k] = w;
-            A.census.lin[k] = lin;
-            A.census.src[k] = src;
-            A.census.e[k] = e;
-            A.census.cell[k] = cell;
-          } else {
-            atomicOr(A.err, ERR_CAPACITY);
-          }
-        }
-      }
+    // ------------------------------------------- next daughter generation --
+    __syncthreads();
+    const uint32_t produced = L.dcnt[gen & 1];
+    if (produced == 0) break;
+    if (gen + 1 >= kMaxGenerations) {
+      if (tid == 0) atomicOr(A.err, ERR_GENERATIONS);
+      break;
     }
-    if (__ballot(nd > 1) != 0) flush_daughters();
+    __syncthreads();
+    if (tid == 0) {
+      L.dcnt[(gen + 1) & 1] = 0u;
+      L.dcur[0] = 0u;
+    }
+    __syncthreads();
+    n_list = produced < (uint32_t)A.dcap ? produced : (uint32_t)A.dcap;
+    ++gen;
   }
 
   // Per-wave counter reduction into LDS.
@@ -381,81 +527,69 @@ __global__ void __launch_bounds__(1024) sweep_kernel(SweepArgs<Real> A) {
     }
   }
   __syncthreads();
-
-  // Flush the work-group histogram (nonzero entries only).
-  double *tal_b = A.tal + (size_t)b * I * 6;
-  for (int j = threadIdx.x; j < I * 6; j += blockDim.x) {
-    const double val = L.hist[j];
-    if (val != 0.0) unsafeAtomicAdd(&tal_b[j], val);
+  if (tid < nc) {
+    const uint32_t cc = L.ccnt[tid];
+    A.census.segcnt[(b * nc + tid) * K + jseg] = cc < (uint32_t)G.seg_cap ? cc : (uint32_t)G.seg_cap;
   }
-  for (int j = threadIdx.x; j < I; j += blockDim.x) {
-    const uint32_t t = L.trk[j];
-    if (t != 0) atomicAdd(&A.tracks[j], (unsigned long long)t);
+  if (tid < 12) {
+    const uint32_t t = L.cnt[tid];
+    if (t != 0) atomicAdd(&A.counters[tid], (unsigned long long)t);
   }
-  if (threadIdx.x < 6) {
-    const double val = L.bnd[threadIdx.x];
-    if (val != 0.0) unsafeAtomicAdd(&A.bnd[b * 6 + threadIdx.x], val);
-  }
-  if (threadIdx.x < (unsigned)A.nc) {
-    const double val = L.wnext[threadIdx.x];
-    if (val != 0.0) unsafeAtomicAdd(&A.wnext[threadIdx.x], val);
-  }
-  if (threadIdx.x < 12) {
-    const uint32_t t = L.cnt[threadIdx.x];
-    if (t != 0) atomicAdd(&A.counters[threadIdx.x], (unsigned long long)t);
-  }
+  if (tid == 0) atomicMax(&A.counters[C_GENERATIONS], (unsigned long long)(gen + 1));
+  flush_tallies(L, I, nc, b, A.tal, A.bnd, A.tracks, A.wnext);
 }
 
 // Source bank at t^0 (Sec. 5.1): unit-weight particles at src_x with
-// isotropic directions from slot 3, in the region of their batch and of the
-// chunk of step 1; their census moments are the step-1 initial condition.
-__global__ void __launch_bounds__(256) source_kernel(SourceArgs A, Bank<double> bank) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= A.n_src) return;
-  uint32_t r[4];
-  draw(A.seed, A.key1, SLOT_BIRTH, (uint32_t)s, 0ull, 0u, r);
-  const double mu = 2.0 * u53(r[0], r[1]) - 1.0;
-  const double x = A.src_x;
-  // Cell of x; a point on an interior edge belongs to the cell it moves into.
-  int32_t cell;
-  if (x <= A.edges[0]) {
-    cell = 0;
-  } else if (x >= A.edges[A.I]) {
-    cell = A.I - 1;
-  } else {
-    int32_t lo = 0, hi = A.I;
-    while (hi - lo > 1) {
-      const int32_t mid = (lo + hi) / 2;
-      if (A.edges[mid] <= x) lo = mid; else hi = mid;
+// isotropic directions from slot 3, appended to the census region of their
+// batch and of their step-1 chunk; their census moments are the step-1
+// initial condition.  Work-group (b, j) creates the sources s = b + B m,
+// m = j, j + K, j + 2K, ... into its own segments.
+__global__ void __launch_bounds__(1024) source_kernel(SourceArgs A, Bank<double> bank) {
+  extern __shared__ double lds_raw[];
+  const int I = A.I, nc = A.nc;
+  const BankGeom G = A.geom;
+  const int K = G.K;
+  Lds L = carve(lds_raw, I, nc, K);
+  zero_lds(lds_raw, I, nc, K);
+  __syncthreads();
+  const int b = blockIdx.x % A.B;
+  const int jseg = blockIdx.x / A.B;
+  const int64_t n_b = (A.n_src > b) ? (A.n_src - b + A.B - 1) / A.B : 0;  // sources of batch b
+  const int64_t n_j = (n_b > jseg) ? (n_b - jseg + K - 1) / K : 0;           // of which this work-group's
+  const int64_t rounds = (n_j + blockDim.x - 1) / blockDim.x;
+  for (int64_t it = 0; it < rounds; ++it) {
+    const int64_t mloc = it * blockDim.x + threadIdx.x;
+    const bool live = mloc < n_j;
+    const int64_t s = (int64_t)b + (int64_t)A.B * ((int64_t)jseg + (int64_t)K * mloc);
+    double mu = 0.0;
+    int32_t cell = 0, chunk = 0;
+    if (live) {
+      uint32_t r[4];
+      draw(A.seed, A.key1, SLOT_BIRTH, (uint32_t)s, 0ull, 0u, r);
+      mu = 2.0 * u53(r[0], r[1]) - 1.0;
+      cell = find_cell(A.edges, I, A.src_x, mu);
+      draw(A.seed, A.key1, SLOT_START, (uint32_t)s, 0ull, 0u, r);
+      chunk = (int32_t)(u53(r[0], r[1]) * (double)nc);
+      if (chunk >= nc) chunk = nc - 1;
+      const double vw = A.v * 1.0;
+      const double c1 = vw * mu;
+      atomicAdd(&L.hist[cell * 6 + 3], vw);
+      atomicAdd(&L.hist[cell * 6 + 4], c1);
+      atomicAdd(&L.hist[cell * 6 + 5], c1 * mu);
+      atomicAdd(&L.wnext[chunk], 1.0);
     }
-    if (x == A.edges[lo] && mu < 0.0 && lo > 0) lo -= 1;
-    cell = lo;
+    for (int c = 0; c < nc; ++c) {
+      const int64_t region = (int64_t)(b * nc + c) * G.stride;
+      census_append(bank, G, &L.ccnt[c], &bank.ovfcnt[b * nc + c], region, jseg, live && chunk == c, A.src_x, mu,
+                    1.0, 0ull, (uint32_t)s, 0u, cell, A.err);
+    }
   }
-  draw(A.seed, A.key1, SLOT_START, (uint32_t)s, 0ull, 0u, r);
-  int32_t chunk = (int32_t)(u53(r[0], r[1]) * (double)A.nc);
-  if (chunk >= A.nc) chunk = A.nc - 1;
-  const int b = (int)(s % A.B);
-  const int reg = b * A.nc + chunk;
-  const uint32_t slot = atomicAdd(&bank.count[reg], 1u);
-  if ((int64_t)slot >= A.cap_r) {
-    atomicOr(A.err, ERR_CAPACITY);
-    return;
+  __syncthreads();
+  if ((int)threadIdx.x < nc) {
+    const uint32_t cc = L.ccnt[threadIdx.x];
+    bank.segcnt[(b * nc + threadIdx.x) * K + jseg] = cc < (uint32_t)G.seg_cap ? cc : (uint32_t)G.seg_cap;
   }
-  const int64_t k = (int64_t)reg * A.cap_r + slot;
-  bank.x[k] = x;
-  bank.mu[k] = mu;
-  bank.w[k] = 1.0;
-  bank.lin[k] = 0ull;
-  bank.src[k] = (uint32_t)s;
-  bank.e[k] = 0u;
-  bank.cell[k] = cell;
-  const double vw = A.v * 1.0;
-  const double c1 = vw * mu;
-  double *t = A.tal + ((size_t)b * A.I + cell) * 6;
-  unsafeAtomicAdd(&t[3], vw);
-  unsafeAtomicAdd(&t[4], c1);
-  unsafeAtomicAdd(&t[5], c1 * mu);
-  unsafeAtomicAdd(&A.wnext[chunk], 1.0);
+  flush_tallies(L, I, nc, b, A.tal, nullptr, nullptr, A.wnext);
 }
 
 __global__ void fill_u32_kernel(uint32_t *p, uint32_t v, int64_t n) {
@@ -474,22 +608,36 @@ __global__ void rotate_chunks_kernel(double *wstart, double *wnext, int nc) {
   }
 }
 
-hipError_t launch_sweep_f64(const SweepArgs<double> &a, int grid, int block, size_t lds, hipStream_t s) {
-  static size_t attr_lds = 64 * 1024;
-  if (lds > attr_lds) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&sweep_kernel<double>),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+static hipError_t allow_lds(const void *fn, size_t lds, size_t *done) {
+  if (lds > *done) {
+    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    attr_lds = lds;
+    *done = lds;
   }
+  return hipSuccess;
+}
+
+hipError_t sweep_occupancy_f64(int block, size_t lds, int *blocks_per_cu) {
+  static size_t done = 64 * 1024;
+  hipError_t e = allow_lds(reinterpret_cast<const void *>(&sweep_kernel<double>), lds, &done);
+  if (e != hipSuccess) return e;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, sweep_kernel<double>, block, lds);
+}
+
+hipError_t launch_sweep_f64(const SweepArgs<double> &a, int grid, int block, size_t lds, hipStream_t s) {
+  static size_t done = 64 * 1024;
+  hipError_t e = allow_lds(reinterpret_cast<const void *>(&sweep_kernel<double>), lds, &done);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(sweep_kernel<double>, dim3(grid), dim3(block), lds, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_source_f64(const SourceArgs &a, const Bank<double> &bank, hipStream_t s) {
-  if (a.n_src == 0) return hipSuccess;
-  const int64_t grid = (a.n_src + 255) / 256;
-  hipLaunchKernelGGL(source_kernel, dim3((unsigned)grid), dim3(256), 0, s, a, bank);
+hipError_t launch_source_f64(const SourceArgs &a, const Bank<double> &bank, int grid, int block, size_t lds,
+                             hipStream_t s) {
+  static size_t done = 64 * 1024;
+  hipError_t e = allow_lds(reinterpret_cast<const void *>(&source_kernel), lds, &done);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(source_kernel, dim3(grid), dim3(block), lds, s, a, bank);
   return hipGetLastError();
 }
 

@@ -47,7 +47,8 @@ class Problem(C.Structure):
 class StepStats(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in ("segments", "collisions", "scatters", "absorptions",
                                           "crossings", "leaks", "census", "splits", "daughters",
-                                          "rr_kill", "rr_survive", "histories", "generations")] + \
+                                          "rr_kill", "rr_survive", "histories", "generations",
+                                          "launches")] + \
                [("kernel_ms", C.c_double), ("bytes_moved", C.c_uint64)]
 
     def as_dict(self):

@@ -46,16 +46,14 @@ def _run_pair(w, steps=None, fixed_windows=None, banks=True, analog=False):
         elif not analog:
             h.solve_losm(implicit=False, **kw)
             sim.solve_losm(opts, implicit=False)
-        cnt = {k: 0 for k in COUNTERS}
         for p in range(w.n_chunks):
-            st = h.sweep_step(n, p)
-            for k in COUNTERS:
-                cnt[k] += st[k]
+            st = h.sweep_step(n, p, stats=(p == w.n_chunks - 1 or p % 2 == 1))
             sim.sweep(n, p)
             if fixed_windows is None and not analog and p < w.n_chunks - 1:
                 h.solve_losm(implicit=True, **kw)
                 sim.solve_losm(opts, implicit=True)
         oc = sim.counters()
+        cnt = {k: st[k] for k in COUNTERS}
         assert cnt == {k: oc[k] for k in COUNTERS}, f"step {n}: counters {cnt} vs {oc}"
         worst = max(worst, _compare_step(n, h, sim, w.name, banks=banks))
         if not analog and fixed_windows is None:
@@ -138,7 +136,7 @@ def test_empty_source():
     h.set_windows(None, 5.0)
     for p in range(w.n_chunks):
         st = h.sweep_step(1, p)
-        assert st["segments"] == 0
+        assert st["segments"] == 0 and st["launches"] == p + 1
     assert np.all(h.read_tallies(H.TALLY_CELLS) == 0.0)
 
 
