@@ -131,6 +131,11 @@ int hww_set_windows(hww_handle *h, const double *centre, double rho);
  * step's counters so far.  Errors: HWW_E_STATE, HWW_E_CAPACITY, HWW_E_DEVICE. */
 int hww_sweep_step(hww_handle *h, int32_t step, int32_t chunk, hww_step_stats *stats);
 
+/* Counters, kernel time and bank bytes of every sweep since init (same
+ * fields as hww_step_stats, summed over all steps; generations is the
+ * maximum).  Synchronises the stream. */
+int hww_read_run_stats(hww_handle *h, hww_step_stats *stats);
+
 /* Solve the HLOSM equations (Sec. 3) from the tallies on the device:
  * semi-implicit (needs the previous step complete; sets windows for the next
  * step) or fully implicit (inside a step after chunk p < n_chunks-1).  With

@@ -113,8 +113,8 @@ typedef struct {
 
 struct orc_sim {
   int32_t I;
-  double *edges, *sig_t, *sig_s, *cratio;
-  double v, dt;
+  double *edges, *sig_t, *sig_s, *cratio, *inv_sig_t;
+  double v, inv_v, dt;
   int32_t n_steps;
   double src_x;
   int64_t n_src, cap;
@@ -161,10 +161,9 @@ static int32_t find_cell(const orc_sim *s, double x, double mu) {
   return lo;
 }
 
-static int32_t chunk_of(const orc_sim *s, uint32_t src, uint64_t lin, uint32_t e) {
-  double ua;
-  draw(s->seed, s->replica, SLOT_START, src, lin, e, &ua, NULL, NULL);
-  int32_t c = (int32_t)(ua * (double)s->n_chunks);
+/* Chunk (window-update interval) of the next step from a uniform variate. */
+static int32_t chunk_from(const orc_sim *s, double u) {
+  int32_t c = (int32_t)(u * (double)s->n_chunks);
   if (c >= s->n_chunks) c = s->n_chunks - 1;
   return c;
 }
@@ -173,7 +172,7 @@ static int batch_of(const orc_sim *s, uint32_t src) { return (int)(src % (uint32
 
 void orc_destroy(orc_sim *s) {
   if (!s) return;
-  free(s->edges); free(s->sig_t); free(s->sig_s); free(s->cratio); free(s->batch_on);
+  free(s->edges); free(s->sig_t); free(s->sig_s); free(s->cratio); free(s->inv_sig_t); free(s->batch_on);
   free(s->centre); free(s->ceil_); free(s->floor_);
   free(s->start); free(s->census); free(s->stack);
   free(s->cur.cells); free(s->cur.bnd); free(s->prev.cells); free(s->prev.bnd);
@@ -216,6 +215,7 @@ int orc_create(const orc_params *p, orc_sim **out) {
   s->sig_t = (double *)malloc(sizeof(double) * I);
   s->sig_s = (double *)malloc(sizeof(double) * I);
   s->cratio = (double *)malloc(sizeof(double) * I);
+  s->inv_sig_t = (double *)malloc(sizeof(double) * I);
   s->centre = (double *)malloc(sizeof(double) * I);
   s->ceil_ = (double *)malloc(sizeof(double) * I);
   s->floor_ = (double *)malloc(sizeof(double) * I);
@@ -227,7 +227,7 @@ int orc_create(const orc_params *p, orc_sim **out) {
   s->census = (particle *)malloc(sizeof(particle) * (size_t)(s->cap > 0 ? s->cap : 1));
   s->cap_stack = 1024;
   s->stack = (particle *)malloc(sizeof(particle) * (size_t)s->cap_stack);
-  if (!s->edges || !s->sig_t || !s->sig_s || !s->cratio || !s->centre || !s->ceil_ ||
+  if (!s->edges || !s->sig_t || !s->sig_s || !s->cratio || !s->inv_sig_t || !s->centre || !s->ceil_ ||
       !s->floor_ || !s->batch_on || !s->tracks || !s->w_chunk_start || !s->w_chunk_next ||
       !s->start || !s->census || !s->stack ||
       tally_alloc(&s->cur, s->B, I) || tally_alloc(&s->prev, s->B, I)) {
@@ -237,7 +237,11 @@ int orc_create(const orc_params *p, orc_sim **out) {
   memcpy(s->edges, p->edges, sizeof(double) * (I + 1));
   memcpy(s->sig_t, p->sigma_t, sizeof(double) * I);
   memcpy(s->sig_s, p->sigma_s, sizeof(double) * I);
-  for (int i = 0; i < I; ++i) s->cratio[i] = s->sig_s[i] / s->sig_t[i];
+  for (int i = 0; i < I; ++i) {
+    s->cratio[i] = s->sig_s[i] / s->sig_t[i];
+    s->inv_sig_t[i] = 1.0 / s->sig_t[i];
+  }
+  s->inv_v = 1.0 / s->v;
   memset(s->batch_on, 1, s->B);
   s->ww_on = 0;
 
@@ -247,8 +251,8 @@ int orc_create(const orc_params *p, orc_sim **out) {
   s->n_census = 0;
   for (int64_t k = 0; k < s->n_src; ++k) {
     particle q;
-    double ua;
-    draw(s->seed, s->replica, SLOT_BIRTH, (uint32_t)k, 0, 0, &ua, NULL, NULL);
+    double ua, ub;
+    draw(s->seed, s->replica, SLOT_BIRTH, (uint32_t)k, 0, 0, &ua, &ub, NULL);
     q.mu = 2.0 * ua - 1.0;
     q.x = s->src_x;
     q.w = 1.0;
@@ -257,7 +261,7 @@ int orc_create(const orc_params *p, orc_sim **out) {
     q.lin = 0;
     q.e = 0;
     q.cell = find_cell(s, q.x, q.mu);
-    q.chunk = chunk_of(s, q.src, q.lin, q.e);
+    q.chunk = chunk_from(s, ub);
     s->census[s->n_census++] = q;
   }
   for (int64_t k = 0; k < s->n_census; ++k) {
@@ -370,7 +374,8 @@ static int transport(orc_sim *s, particle *p) {
     int i = p->cell;
     double ua, ub;
     draw(s->seed, s->replica, SLOT_FLIGHT, p->src, p->lin, p->e, &ua, &ub, NULL);
-    double d_coll = -log(1.0 - ua) / s->sig_t[i];
+    /* Exponential flight distance with mean free path 1/sigma_t. */
+    double d_coll = -log(1.0 - ua) * s->inv_sig_t[i];
     double xl = s->edges[i], xr = s->edges[i + 1];
     double d_bnd;
     if (p->mu > 0.0) d_bnd = (xr - p->x) / p->mu;
@@ -400,7 +405,9 @@ static int transport(orc_sim *s, particle *p) {
       if (xn > xr) xn = xr;
       p->x = xn;
       p->tau = s->dt;
-      p->chunk = chunk_of(s, p->src, p->lin, p->e);
+      /* The flight draw's second variate is not used at census: it picks
+       * the chunk of the next step. */
+      p->chunk = chunk_from(s, ub);
       census_tally(s, &s->cur, p);
       s->counters[ORC_N_CENSUS] += 1;
       if (s->n_census >= s->cap) return -3;
@@ -408,7 +415,7 @@ static int transport(orc_sim *s, particle *p) {
       nadd(&s->w_chunk_next[p->chunk], p->w);
       return 0;
     }
-    p->tau = p->tau - l / s->v;
+    p->tau = p->tau - l * s->inv_v;
     if (ev == 1) {
       int leave_left = (i == 0 && p->mu < 0.0);
       int leave_right = (i == I - 1 && p->mu > 0.0);

@@ -24,18 +24,40 @@ enum { SLOT_FLIGHT = 0, SLOT_EVENT = 1, SLOT_START = 2, SLOT_BIRTH = 3, SLOT_LIN
 // Work-group-local daughter generations per launch before giving up.
 constexpr int kMaxGenerations = 4096;
 
-// Structure-of-arrays particle bank.  Region (batch b, chunk c) holds the
-// particles of batch b whose next step starts in chunk c.  It is cut into K
-// segments of seg_cap slots, segment j written only by work-group j of batch
-// b (so appends need only a work-group-local counter), and one overflow
-// segment of ovf_cap slots shared through a device atomic.
+// Position and direction of a particle (one 16-byte load in FP64).
+template <typename Real>
+struct alignas(2 * sizeof(Real)) XMu {
+  Real x, mu;
+};
+// Identity of a particle: source history, event index, cell.
+struct Tag {
+  uint32_t src, e;
+  int32_t cell;
+};
+// Weight and remaining time of a daughter (one 16-byte load).
+struct alignas(16) WTau {
+  double w, tau;
+};
+// Per-cell data read by every flight: edges, 1/sigma_t, sigma_s/sigma_t.
+struct alignas(32) CellData {
+  double xl, xr, inv_sig, c;
+};
+// Per-cell weight window: centre, ceiling, floor.
+struct alignas(32) Window {
+  double ww, ceil, floor, pad;
+};
+
+// Particle bank as four structure-of-arrays streams.  Region (batch b,
+// chunk c) holds the particles of batch b whose next step starts in chunk c.
+// It is cut into K segments of seg_cap slots, segment j written only by
+// work-group j of batch b (so appends need only a work-group-local counter),
+// and one overflow segment of ovf_cap slots shared through a device atomic.
 template <typename Real>
 struct Bank {
-  Real *x, *mu;
+  XMu<Real> *xm;
   double *w;
   uint64_t *lin;
-  uint32_t *src, *e;
-  int32_t *cell;
+  Tag *tag;
   uint32_t *segcnt;  // [B][nc][K]
   uint32_t *ovfcnt;  // [B][nc]
 };
@@ -48,20 +70,19 @@ struct BankGeom {
 // Daughter buffers: two per work-group, dcap slots each.
 template <typename Real>
 struct Queue {
-  Real *x, *mu;
-  double *w, *tau;
+  XMu<Real> *xm;
+  WTau *wt;
   uint64_t *lin;
-  uint32_t *src, *e;
-  int32_t *cell;
+  Tag *tag;
 };
 
 template <typename Real>
 struct SweepArgs {
   int32_t I, B, nc;
-  double v, dt;
+  double v, inv_v, dt;
   uint32_t seed, key1;  // key1 = replica << 4
-  const double *edges, *sig_t, *cratio;
-  const double *centre, *wceil, *wfloor;
+  const CellData *cells;   // [I]
+  const Window *win;       // [I]
   int32_t ww_on;
   int32_t chunk;
   BankGeom geom;
@@ -73,7 +94,7 @@ struct SweepArgs {
   double *tal;                     // [B][I][6]
   double *bnd;                     // [B][2][3]
   unsigned long long *tracks;      // [I]
-  unsigned long long *counters;    // [C_NCOUNTERS]
+  unsigned long long *counters;    // [2][C_NCOUNTERS]: this step, since init
   double *wnext;                   // [nc]
   uint32_t *err;
 };
@@ -104,7 +125,7 @@ struct LosmArgs {
   double *scratch;                // >= 24 * (I + 4) doubles
   double *factor;                 // [3][2I+3] LU factors of the system for `theta`
   int32_t refactor;               // 1: (re)compute the factors first
-  double *centre, *wceil, *wfloor;
+  Window *win;                    // [I] window centres, ceilings, floors
   double *phi_out, *J_out;        // I+2, I+1 (device)
   uint32_t *err;
   int32_t *status;                // 0 ok, else error bits of this solve

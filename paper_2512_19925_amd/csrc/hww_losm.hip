@@ -172,6 +172,8 @@ __global__ void __launch_bounds__(LOSM_THREADS) losm_kernel(LosmArgs A) {
   const int kc = A.closure_track ? 0 : 3;
   for (int i = tid; i < I; i += T) {
     double p = 0.0, j = 0.0, k = 0.0, cp = 0.0, ck = 0.0;
+    // Independent loads of all batches in flight at once (latency bound).
+#pragma unroll 16
     for (int b = 0; b < A.B; ++b) {
       const double *t = A.tal_ic + ((size_t)b * I + i) * 6;
       p += t[3];
@@ -354,9 +356,12 @@ __global__ void __launch_bounds__(LOSM_THREADS) losm_kernel(LosmArgs A) {
       const double p = u[2 * (i + 1)];
       const double rr = p > 0.0 ? p / mm : 0.0;
       const double ww = s * (rr * (1.0 - A.eps_min) + A.eps_min);
-      A.centre[i] = ww;
-      A.wceil[i] = ww * A.rho;
-      A.wfloor[i] = ww / A.rho;
+      Window wd;
+      wd.ww = ww;
+      wd.ceil = ww * A.rho;
+      wd.floor = ww / A.rho;
+      wd.pad = 0.0;
+      A.win[i] = wd;
     }
   }
 }

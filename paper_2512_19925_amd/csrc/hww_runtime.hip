@@ -26,7 +26,7 @@ struct Layout {
   int64_t total = 0;
   BankGeom geom{};
   int64_t dcap = 0;
-  int64_t off_edges, off_sigt, off_sigs, off_cratio, off_centre, off_ceil, off_floor;
+  int64_t off_edges, off_sigt, off_sigs, off_cells, off_win;
   int64_t off_bank[2], off_segcnt[2], off_ovfcnt[2], off_q;
   int64_t off_tal[2], off_bnd[2], off_tracks, off_counters, off_wstart, off_wnext;
   int64_t off_cursor, off_err, off_status, off_scratch, off_factor, off_phi_out, off_J_out;
@@ -77,39 +77,29 @@ void make_layout(const hww_problem &p, Layout *L) {
   L->off_edges = c.take(8 * (I + 1));
   L->off_sigt = c.take(8 * I);
   L->off_sigs = c.take(8 * I);
-  L->off_cratio = c.take(8 * I);
-  // centre, ceiling and floor are one contiguous [3][I] block
-  L->off_centre = c.take(8 * 3 * I);
-  L->off_ceil = L->off_centre + 8 * I;
-  L->off_floor = L->off_centre + 16 * I;
+  L->off_cells = c.take(sizeof(CellData) * I);
+  L->off_win = c.take(sizeof(Window) * I);
   for (int k = 0; k < 2; ++k) {
     L->off_bank[k] = c.take(0);
-    // x, mu, w, lin, src, e, cell arrays
-    c.take(rb * slots);
-    c.take(rb * slots);
+    // (x, mu), w, lin, (src, e, cell) streams
+    c.take(2 * rb * slots);
     c.take(8 * slots);
     c.take(8 * slots);
-    c.take(4 * slots);
-    c.take(4 * slots);
-    c.take(4 * slots);
+    c.take(sizeof(Tag) * slots);
     L->off_segcnt[k] = c.take(4 * R * K);
     L->off_ovfcnt[k] = c.take(4 * R);
   }
   L->off_q = c.take(0);
-  c.take(rb * dslots);
-  c.take(rb * dslots);
+  c.take(2 * rb * dslots);
+  c.take(sizeof(WTau) * dslots);
   c.take(8 * dslots);
-  c.take(8 * dslots);
-  c.take(8 * dslots);
-  c.take(4 * dslots);
-  c.take(4 * dslots);
-  c.take(4 * dslots);
+  c.take(sizeof(Tag) * dslots);
   for (int k = 0; k < 2; ++k) {
     L->off_tal[k] = c.take(8 * B * I * 6);
     L->off_bnd[k] = c.take(8 * B * 6);
   }
   L->off_tracks = c.take(8 * I);
-  L->off_counters = c.take(8 * C_NCOUNTERS);
+  L->off_counters = c.take(8 * 2 * C_NCOUNTERS);
   L->off_wstart = c.take(8 * nc);
   L->off_wnext = c.take(8 * nc);
   L->off_cursor = c.take(4 * B);
@@ -131,13 +121,10 @@ Bank<Real> bank_view(char *ws, int64_t off, int64_t off_seg, int64_t off_ovf, in
     o = align_up(o + bytes);
     return p;
   };
-  b.x = reinterpret_cast<Real *>(take(sizeof(Real) * slots));
-  b.mu = reinterpret_cast<Real *>(take(sizeof(Real) * slots));
+  b.xm = reinterpret_cast<XMu<Real> *>(take(sizeof(XMu<Real>) * slots));
   b.w = reinterpret_cast<double *>(take(8 * slots));
   b.lin = reinterpret_cast<uint64_t *>(take(8 * slots));
-  b.src = reinterpret_cast<uint32_t *>(take(4 * slots));
-  b.e = reinterpret_cast<uint32_t *>(take(4 * slots));
-  b.cell = reinterpret_cast<int32_t *>(take(4 * slots));
+  b.tag = reinterpret_cast<Tag *>(take(sizeof(Tag) * slots));
   b.segcnt = reinterpret_cast<uint32_t *>(ws + off_seg);
   b.ovfcnt = reinterpret_cast<uint32_t *>(ws + off_ovf);
   return b;
@@ -152,14 +139,10 @@ Queue<Real> queue_view(char *ws, int64_t off, int64_t slots) {
     o = align_up(o + bytes);
     return p;
   };
-  q.x = reinterpret_cast<Real *>(take(sizeof(Real) * slots));
-  q.mu = reinterpret_cast<Real *>(take(sizeof(Real) * slots));
-  q.w = reinterpret_cast<double *>(take(8 * slots));
-  q.tau = reinterpret_cast<double *>(take(8 * slots));
+  q.xm = reinterpret_cast<XMu<Real> *>(take(sizeof(XMu<Real>) * slots));
+  q.wt = reinterpret_cast<WTau *>(take(sizeof(WTau) * slots));
   q.lin = reinterpret_cast<uint64_t *>(take(8 * slots));
-  q.src = reinterpret_cast<uint32_t *>(take(4 * slots));
-  q.e = reinterpret_cast<uint32_t *>(take(4 * slots));
-  q.cell = reinterpret_cast<int32_t *>(take(4 * slots));
+  q.tag = reinterpret_cast<Tag *>(take(sizeof(Tag) * slots));
   return q;
 }
 
@@ -173,7 +156,9 @@ struct hww_handle {
   Layout L;
   hipStream_t stream = nullptr;
   char *ws = nullptr;
-  double *edges, *sig_t, *sig_s, *cratio, *centre, *wceil, *wfloor;
+  double *edges, *sig_t, *sig_s;
+  CellData *cells;
+  Window *win;
   Bank<double> bank[2];
   Queue<double> dq;
   double *tal[2], *bnd[2];
@@ -191,7 +176,11 @@ struct hww_handle {
   double factor_theta = -1.0;  // theta of the LU factors in the workspace
   size_t lds = 0;
   int n_launch = 0;            // sweep launches of the current step
-  hipEvent_t ev[2 * 8] = {};
+  int step_ev0 = 0;            // first event pair of the current step
+  std::vector<hipEvent_t> ev;  // start/stop pairs of every sweep launch since init
+  int ev_used = 0;             // pairs recorded
+  int ev_summed = 0;           // pairs already added into ms_summed
+  double ms_summed = 0.0;
   std::string msg;
 };
 
@@ -276,10 +265,10 @@ int poll_errors(hww_handle *h) {
 SweepArgs<double> base_args(hww_handle *h) {
   SweepArgs<double> a{};
   a.I = h->I; a.B = h->B; a.nc = h->nc;
-  a.v = h->p.speed; a.dt = h->p.dt;
+  a.v = h->p.speed; a.inv_v = 1.0 / h->p.speed; a.dt = h->p.dt;
   a.seed = h->p.seed; a.key1 = h->p.replica << 4;
-  a.edges = h->edges; a.sig_t = h->sig_t; a.cratio = h->cratio;
-  a.centre = h->centre; a.wceil = h->wceil; a.wfloor = h->wfloor;
+  a.cells = h->cells;
+  a.win = h->win;
   a.ww_on = h->ww_on;
   a.geom = h->L.geom;
   a.in_bank = h->bank[h->start_bank];
@@ -343,10 +332,8 @@ int hww_init_problem(const hww_problem *problem, void *dev_workspace, int64_t ws
   h->edges = reinterpret_cast<double *>(ws + L.off_edges);
   h->sig_t = reinterpret_cast<double *>(ws + L.off_sigt);
   h->sig_s = reinterpret_cast<double *>(ws + L.off_sigs);
-  h->cratio = reinterpret_cast<double *>(ws + L.off_cratio);
-  h->centre = reinterpret_cast<double *>(ws + L.off_centre);
-  h->wceil = reinterpret_cast<double *>(ws + L.off_ceil);
-  h->wfloor = reinterpret_cast<double *>(ws + L.off_floor);
+  h->cells = reinterpret_cast<CellData *>(ws + L.off_cells);
+  h->win = reinterpret_cast<Window *>(ws + L.off_win);
   for (int k = 0; k < 2; ++k) {
     h->bank[k] = bank_view<double>(ws, L.off_bank[k], L.off_segcnt[k], L.off_ovfcnt[k], slots);
     h->tal[k] = reinterpret_cast<double *>(ws + L.off_tal[k]);
@@ -378,14 +365,18 @@ int hww_init_problem(const hww_problem *problem, void *dev_workspace, int64_t ws
     if (rc__ != HWW_OK) return bail(rc__);             \
   } while (0)
 
-  for (auto &e : h->ev) INITCHK(hipEventCreate(&e));
   const int I = h->I;
-  std::vector<double> cr(I);
-  for (int i = 0; i < I; ++i) cr[i] = problem->sigma_s[i] / problem->sigma_t[i];
+  std::vector<CellData> cd(I);
+  for (int i = 0; i < I; ++i) {
+    cd[i].xl = problem->edges[i];
+    cd[i].xr = problem->edges[i + 1];
+    cd[i].inv_sig = 1.0 / problem->sigma_t[i];
+    cd[i].c = problem->sigma_s[i] / problem->sigma_t[i];
+  }
   INITCHK(hipMemcpyAsync(h->edges, problem->edges, 8 * (I + 1), hipMemcpyHostToDevice, h->stream));
   INITCHK(hipMemcpyAsync(h->sig_t, problem->sigma_t, 8 * I, hipMemcpyHostToDevice, h->stream));
   INITCHK(hipMemcpyAsync(h->sig_s, problem->sigma_s, 8 * I, hipMemcpyHostToDevice, h->stream));
-  INITCHK(hipMemcpyAsync(h->cratio, cr.data(), 8 * I, hipMemcpyHostToDevice, h->stream));
+  INITCHK(hipMemcpyAsync(h->cells, cd.data(), sizeof(CellData) * I, hipMemcpyHostToDevice, h->stream));
   // Zero everything the kernels accumulate into.
   for (int k = 0; k < 2; ++k) {
     if (zero_counts(h, k) != HWW_OK) return bail(HWW_E_DEVICE);
@@ -393,10 +384,10 @@ int hww_init_problem(const hww_problem *problem, void *dev_workspace, int64_t ws
     INITCHK(launch_fill_f64(h->bnd[k], 0.0, (int64_t)h->B * 6, h->stream));
   }
   INITCHK(launch_fill_u32(reinterpret_cast<uint32_t *>(h->tracks), 0u, 2 * (int64_t)I, h->stream));
-  INITCHK(launch_fill_u32(reinterpret_cast<uint32_t *>(h->counters), 0u, 2 * C_NCOUNTERS, h->stream));
+  INITCHK(launch_fill_u32(reinterpret_cast<uint32_t *>(h->counters), 0u, 4 * C_NCOUNTERS, h->stream));
   INITCHK(launch_fill_f64(h->wstart, 0.0, h->nc, h->stream));
   INITCHK(launch_fill_f64(h->wnext, 0.0, h->nc, h->stream));
-  INITCHK(launch_fill_f64(h->centre, 0.0, 3 * (int64_t)I, h->stream));
+  INITCHK(launch_fill_f64(reinterpret_cast<double *>(h->win), 0.0, 4 * (int64_t)I, h->stream));
   INITCHK(launch_fill_u32(h->err, 0u, 1, h->stream));
   INITCHK(launch_fill_u32(reinterpret_cast<uint32_t *>(h->status), 0u, 1, h->stream));
 
@@ -427,14 +418,15 @@ int hww_set_windows(hww_handle *h, const double *centre, double rho) {
   }
   if (!(rho >= 1.0) || !std::isfinite(rho)) return fail(h, HWW_E_INVALID_ARG, "rho must be >= 1");
   const int I = h->I;
-  std::vector<double> w3(3 * (size_t)I);
+  std::vector<Window> w3(I);
   for (int i = 0; i < I; ++i) {
     if (!(centre[i] > 0.0) || !std::isfinite(centre[i])) return fail(h, HWW_E_NUMERIC, "window centres must be positive and finite");
-    w3[i] = centre[i];
-    w3[I + i] = centre[i] * rho;
-    w3[2 * I + i] = centre[i] / rho;
+    w3[i].ww = centre[i];
+    w3[i].ceil = centre[i] * rho;
+    w3[i].floor = centre[i] / rho;
+    w3[i].pad = 0.0;
   }
-  HIPCHK(h, hipMemcpyAsync(h->centre, w3.data(), 8 * 3 * (size_t)I, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipMemcpyAsync(h->win, w3.data(), sizeof(Window) * (size_t)I, hipMemcpyHostToDevice, h->stream));
   // The host vector must outlive the copy.
   HIPCHK(h, hipStreamSynchronize(h->stream));
   h->ww_on = 1;
@@ -460,6 +452,7 @@ int hww_sweep_step(hww_handle *h, int32_t step, int32_t chunk, hww_step_stats *s
     h->step = step;
     h->next_chunk = 0;
     h->n_launch = 0;
+    h->step_ev0 = h->ev_used;
   } else if (step != h->step || chunk != h->next_chunk) {
     return fail(h, HWW_E_STATE, "chunk out of order");
   }
@@ -467,11 +460,17 @@ int hww_sweep_step(hww_handle *h, int32_t step, int32_t chunk, hww_step_stats *s
   SweepArgs<double> a = base_args(h);
   a.chunk = chunk;
   HIPCHK(h, launch_fill_u32(h->cursor, 0u, h->B, h->stream));
-  const int k = h->n_launch;
+  const int k = h->ev_used;
+  while ((int)h->ev.size() < 2 * (k + 1)) {
+    hipEvent_t e = nullptr;
+    HIPCHK(h, hipEventCreate(&e));
+    h->ev.push_back(e);
+  }
   HIPCHK(h, hipEventRecord(h->ev[2 * k], h->stream));
   HIPCHK(h, launch_sweep_f64(a, h->B * h->K, kBlock, h->lds, h->stream));
   HIPCHK(h, hipEventRecord(h->ev[2 * k + 1], h->stream));
-  h->n_launch = k + 1;
+  h->ev_used = k + 1;
+  h->n_launch += 1;
   h->next_chunk = chunk + 1;
   if (!stats) return HWW_OK;
 
@@ -494,12 +493,43 @@ int hww_sweep_step(hww_handle *h, int32_t step, int32_t chunk, hww_step_stats *s
   stats->generations = cnt[C_GENERATIONS];
   stats->launches = (uint64_t)h->n_launch;
   double ms = 0.0;
-  for (int q = 0; q < h->n_launch; ++q) {
+  for (int q = h->step_ev0; q < h->ev_used; ++q) {
     float t = 0.0f;
     HIPCHK(h, hipEventElapsedTime(&t, h->ev[2 * q], h->ev[2 * q + 1]));
     ms += t;
   }
   stats->kernel_ms = ms;
+  const uint64_t rec = 44, drec = 52;
+  stats->bytes_moved = cnt[C_HISTORIES] * rec + cnt[C_CENSUS] * rec + cnt[C_DAUGHTERS] * 2 * drec;
+  return HWW_OK;
+}
+
+int hww_read_run_stats(hww_handle *h, hww_step_stats *stats) {
+  if (!h || !stats) return HWW_E_INVALID_ARG;
+  unsigned long long cnt[C_NCOUNTERS];
+  HIPCHK(h, hipMemcpyAsync(cnt, h->counters + C_NCOUNTERS, sizeof cnt, hipMemcpyDeviceToHost, h->stream));
+  int rc = poll_errors(h);
+  if (rc != HWW_OK) return rc;
+  for (; h->ev_summed < h->ev_used; ++h->ev_summed) {
+    float t = 0.0f;
+    HIPCHK(h, hipEventElapsedTime(&t, h->ev[2 * h->ev_summed], h->ev[2 * h->ev_summed + 1]));
+    h->ms_summed += t;
+  }
+  stats->segments = cnt[C_SEGMENTS];
+  stats->collisions = cnt[C_COLLISIONS];
+  stats->scatters = cnt[C_SCATTERS];
+  stats->absorptions = cnt[C_ABSORPTIONS];
+  stats->crossings = cnt[C_CROSSINGS];
+  stats->leaks = cnt[C_LEAKS];
+  stats->census = cnt[C_CENSUS];
+  stats->splits = cnt[C_SPLITS];
+  stats->daughters = cnt[C_DAUGHTERS];
+  stats->rr_kill = cnt[C_RR_KILL];
+  stats->rr_survive = cnt[C_RR_SURVIVE];
+  stats->histories = cnt[C_HISTORIES];
+  stats->generations = cnt[C_GENERATIONS];
+  stats->launches = (uint64_t)h->ev_used;
+  stats->kernel_ms = h->ms_summed;
   const uint64_t rec = 44, drec = 52;
   stats->bytes_moved = cnt[C_HISTORIES] * rec + cnt[C_CENSUS] * rec + cnt[C_DAUGHTERS] * 2 * drec;
   return HWW_OK;
@@ -531,7 +561,7 @@ int hww_solve_losm(hww_handle *h, const hww_losm_opts *o, double *phi_out, doubl
   a.eps_min = o->eps_min; a.rho = o->rho;
   a.scratch = h->scratch; a.factor = h->factor;
   a.refactor = (o->theta != h->factor_theta) ? 1 : 0;
-  a.centre = h->centre; a.wceil = h->wceil; a.wfloor = h->wfloor;
+  a.win = h->win;
   a.phi_out = h->phi_out; a.J_out = h->J_out; a.err = h->err; a.status = h->status;
   if (a.refactor) HIPCHK(h, launch_fill_u32(reinterpret_cast<uint32_t *>(h->status), 0u, 1, h->stream));
   HIPCHK(h, launch_losm(a, h->stream));
@@ -556,7 +586,7 @@ int hww_read_tallies(hww_handle *h, int32_t kind, void *out, int64_t out_bytes) 
     case HWW_TALLY_TRACKS: src = h->tracks; bytes = 8 * I; break;
     case HWW_TALLY_PREV_CELLS: src = h->tal[1 - h->cur_tal]; bytes = 8 * B * I * 6; break;
     case HWW_TALLY_PREV_BOUNDARY: src = h->bnd[1 - h->cur_tal]; bytes = 8 * B * 6; break;
-    case HWW_TALLY_WINDOWS: src = h->centre; bytes = 8 * 3 * I; break;
+    case HWW_TALLY_WINDOWS: src = h->win; bytes = 8 * 3 * I; break;
     case HWW_TALLY_BANK_COUNTS: bytes = 16; break;
     default: return fail(h, HWW_E_INVALID_ARG, "unknown tally kind");
   }
@@ -572,9 +602,16 @@ int hww_read_tallies(hww_handle *h, int32_t kind, void *out, int64_t out_bytes) 
     std::memcpy(out, counts, 16);
     return HWW_OK;
   }
-  if (kind == HWW_TALLY_WINDOWS && !h->ww_on) {
+  if (kind == HWW_TALLY_WINDOWS) {
+    std::vector<Window> wv(I);
+    HIPCHK(h, hipMemcpyAsync(wv.data(), h->win, sizeof(Window) * I, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
-    std::memset(out, 0, bytes);
+    double *o = static_cast<double *>(out);
+    for (int64_t i = 0; i < I; ++i) {
+      o[i] = h->ww_on ? wv[i].ww : 0.0;
+      o[I + i] = h->ww_on ? wv[i].ceil : 0.0;
+      o[2 * I + i] = h->ww_on ? wv[i].floor : 0.0;
+    }
     return poll_errors(h);
   }
   HIPCHK(h, hipMemcpyAsync(out, src, bytes, hipMemcpyDeviceToHost, h->stream));
@@ -609,15 +646,21 @@ int hww_read_bank(hww_handle *h, int32_t which, int64_t cap, int64_t *count, dou
                                  : std::min<int64_t>(ovf[r], G.ovf_cap);
       if (n == 0) continue;
       const int64_t k = (int64_t)r * G.stride + (int64_t)j * G.seg_cap;
-      if (x) HIPCHK(h, hipMemcpyAsync(x + o, bk.x + k, 8 * n, hipMemcpyDeviceToHost, h->stream));
-      if (mu) HIPCHK(h, hipMemcpyAsync(mu + o, bk.mu + k, 8 * n, hipMemcpyDeviceToHost, h->stream));
+      std::vector<XMu<double>> xm(n);
+      std::vector<Tag> tg(n);
+      HIPCHK(h, hipMemcpyAsync(xm.data(), bk.xm + k, sizeof(XMu<double>) * n, hipMemcpyDeviceToHost, h->stream));
+      HIPCHK(h, hipMemcpyAsync(tg.data(), bk.tag + k, sizeof(Tag) * n, hipMemcpyDeviceToHost, h->stream));
       if (w) HIPCHK(h, hipMemcpyAsync(w + o, bk.w + k, 8 * n, hipMemcpyDeviceToHost, h->stream));
-      if (src) HIPCHK(h, hipMemcpyAsync(src + o, bk.src + k, 4 * n, hipMemcpyDeviceToHost, h->stream));
       if (lin) HIPCHK(h, hipMemcpyAsync(lin + o, bk.lin + k, 8 * n, hipMemcpyDeviceToHost, h->stream));
-      if (e) HIPCHK(h, hipMemcpyAsync(e + o, bk.e + k, 4 * n, hipMemcpyDeviceToHost, h->stream));
-      if (cell) HIPCHK(h, hipMemcpyAsync(cell + o, bk.cell + k, 4 * n, hipMemcpyDeviceToHost, h->stream));
-      if (chunk)
-        for (int64_t q = 0; q < n; ++q) chunk[o + q] = r % h->nc;
+      HIPCHK(h, hipStreamSynchronize(h->stream));
+      for (int64_t q = 0; q < n; ++q) {
+        if (x) x[o + q] = xm[q].x;
+        if (mu) mu[o + q] = xm[q].mu;
+        if (src) src[o + q] = tg[q].src;
+        if (e) e[o + q] = tg[q].e;
+        if (cell) cell[o + q] = tg[q].cell;
+        if (chunk) chunk[o + q] = r % h->nc;
+      }
       o += n;
     }
   }

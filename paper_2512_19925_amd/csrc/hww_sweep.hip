@@ -46,7 +46,11 @@ __device__ __forceinline__ void draw(uint32_t seed, uint32_t key1, int slot, uin
   r[1] = (uint32_t)lin;
   r[2] = (uint32_t)(lin >> 32);
   r[3] = e;
-  philox4x32_10(r, seed, key1 | (uint32_t)slot);
+  uint32_t k0 = seed, k1 = key1 | (uint32_t)slot;
+  // Keep the round-key schedule local to each draw: otherwise it is hoisted
+  // out of the particle loop for every slot and exhausts the scalar registers.
+  asm volatile("" : "+s"(k0), "+s"(k1));
+  philox4x32_10(r, k0, k1);
 }
 
 // 53-bit uniform on [0,1) from the high bits of two words.
@@ -144,43 +148,65 @@ __device__ inline void flush_tallies(const Lds &L, int I, int nc, int b, double 
 template <typename Real>
 __device__ inline void store_record(const Bank<Real> &bk, int64_t k, double x, double mu, double w,
                                     uint64_t lin, uint32_t src, uint32_t e, int32_t cell) {
-  bk.x[k] = (Real)x;
-  bk.mu[k] = (Real)mu;
+  XMu<Real> xm;
+  xm.x = (Real)x;
+  xm.mu = (Real)mu;
+  bk.xm[k] = xm;
   bk.w[k] = w;
   bk.lin[k] = lin;
-  bk.src[k] = src;
-  bk.e[k] = e;
-  bk.cell[k] = cell;
+  Tag t;
+  t.src = src;
+  t.e = e;
+  t.cell = cell;
+  bk.tag[k] = t;
 }
 
-// Append the census particles of the wave (lanes with `mine`) to region
-// (b, c): the work-group's own segment first, the shared overflow after.
+// Append the census particles of the wave to the regions (b, c) of their
+// next-step chunks c: each lane's slot comes from ballots on the bits of c
+// and one LDS atomic per chunk present (issued by lane c), into the work-
+// group's own segment; what does not fit goes to the shared overflow.
 template <typename Real>
-__device__ inline void census_append(const Bank<Real> &bk, const BankGeom &G, uint32_t *ccnt_c,
-                                     uint32_t *ovfcnt_bc, int64_t region_base, int j, bool mine, double x,
-                                     double mu, double w, uint64_t lin, uint32_t src, uint32_t e,
-                                     int32_t cell, uint32_t *err) {
-  const uint32_t lane = __lane_id();
-  const uint64_t m = __ballot(mine);
-  if (m == 0) return;
-  const int leader = first_lane(m);
+__device__ inline void census_append(const Bank<Real> &bk, const BankGeom &G, uint32_t *ccnt, uint32_t *ovfcnt_b,
+                                     int64_t region_b0, int nc, int j, bool mine, int c, double x, double mu,
+                                     double w, uint64_t lin, uint32_t src, uint32_t e, int32_t cell,
+                                     uint32_t *err) {
+  const int lane = (int)__lane_id();
+  const uint64_t M = __ballot(mine);
+  if (M == 0) return;
+  const uint64_t b0 = __ballot(mine && (c & 1));
+  const uint64_t b1 = __ballot(mine && (c & 2));
+  const uint64_t b2 = __ballot(mine && (c & 4));
+  auto mask_of = [&](int cc) {
+    uint64_t m = M;
+    m &= (cc & 1) ? b0 : ~b0;
+    m &= (cc & 2) ? b1 : ~b1;
+    m &= (cc & 4) ? b2 : ~b2;
+    return m;
+  };
   uint32_t base = 0;
-  if ((int)lane == leader) base = atomicAdd(ccnt_c, (uint32_t)__popcll(m));
-  base = __shfl(base, leader);
-  const uint64_t slot = (uint64_t)base + rank_below(m);
+  if (lane < nc) {
+    const uint32_t nl = (uint32_t)__popcll(mask_of(lane));
+    if (nl != 0) base = atomicAdd(&ccnt[lane], nl);
+  }
+  base = __shfl(base, mine ? c : 0);
+  const uint64_t slot = (uint64_t)base + rank_below(mask_of(c));
   const bool in_seg = mine && slot < (uint64_t)G.seg_cap;
   int64_t k = -1;
-  if (in_seg) k = region_base + (int64_t)j * G.seg_cap + (int64_t)slot;
-  const uint64_t om = __ballot(mine && !in_seg);
-  if (om != 0) {
-    const int ol = first_lane(om);
-    uint32_t ob = 0;
-    if ((int)lane == ol) ob = atomicAdd(ovfcnt_bc, (uint32_t)__popcll(om));
-    ob = __shfl(ob, ol);
-    if (mine && !in_seg) {
-      const uint64_t os = (uint64_t)ob + rank_below(om);
-      if (os < (uint64_t)G.ovf_cap) k = region_base + (int64_t)G.K * G.seg_cap + (int64_t)os;
-      else atomicOr(err, ERR_CAPACITY);
+  if (in_seg) k = region_b0 + (int64_t)c * G.stride + (int64_t)j * G.seg_cap + (int64_t)slot;
+  if (__ballot(mine && !in_seg) != 0) {
+    for (int cc = 0; cc < nc; ++cc) {
+      const bool over = mine && !in_seg && c == cc;
+      const uint64_t om = __ballot(over);
+      if (om == 0) continue;
+      const int ol = first_lane(om);
+      uint32_t ob = 0;
+      if (lane == ol) ob = atomicAdd(&ovfcnt_b[cc], (uint32_t)__popcll(om));
+      ob = __shfl(ob, ol);
+      if (over) {
+        const uint64_t os = (uint64_t)ob + rank_below(om);
+        if (os < (uint64_t)G.ovf_cap) k = region_b0 + (int64_t)cc * G.stride + (int64_t)G.K * G.seg_cap + (int64_t)os;
+        else atomicOr(err, ERR_CAPACITY);
+      }
     }
   }
   if (k >= 0) store_record(bk, k, x, mu, w, lin, src, e, cell);
@@ -254,14 +280,20 @@ __global__ void __launch_bounds__(1024) sweep_kernel(SweepArgs<Real> A) {
         const uint64_t slot = (uint64_t)start + (q - 1);
         if (slot >= (uint64_t)A.dcap) break;
         const int64_t k = qb + (int64_t)slot;
-        A.dq.x[k] = (Real)x;
-        A.dq.mu[k] = (Real)mu;
-        A.dq.w[k] = w;
-        A.dq.tau[k] = tau;
+        XMu<Real> xm;
+        xm.x = (Real)x;
+        xm.mu = (Real)mu;
+        A.dq.xm[k] = xm;
+        WTau wt;
+        wt.w = w;
+        wt.tau = tau;
+        A.dq.wt[k] = wt;
         A.dq.lin[k] = lin_base + q;
-        A.dq.src[k] = src;
-        A.dq.e[k] = e_d;
-        A.dq.cell[k] = cell;
+        Tag tg;
+        tg.src = src;
+        tg.e = e_d;
+        tg.cell = cell;
+        A.dq.tag[k] = tg;
       }
     }
     nd = 0;
@@ -271,8 +303,9 @@ __global__ void __launch_bounds__(1024) sweep_kernel(SweepArgs<Real> A) {
   // kind 0: after an event at index e_ev; kind 1: start of step.
   auto ww_check = [&](int kind, uint32_t e_ev, uint32_t e_daughter, int xi_slot, bool have_xi, double xi) {
     if (!A.ww_on) return;
-    const double ww = A.centre[cell];
-    if (w > A.wceil[cell]) {
+    const Window wd = A.win[cell];
+    const double ww = wd.ww;
+    if (w > wd.ceil) {
       const double ndf = ceil(w / ww);
       if (!(ndf >= 2.0) || ndf > 1.0e9) {
         atomicOr(A.err, ERR_SPLIT);
@@ -292,7 +325,7 @@ __global__ void __launch_bounds__(1024) sweep_kernel(SweepArgs<Real> A) {
       e_d = e_daughter;
       C.splits += 1;
       C.daughters += nd - 1;
-    } else if (w < A.wfloor[cell]) {
+    } else if (w < wd.floor) {
       if (!have_xi) {
         uint32_t r[4];
         draw(A.seed, A.key1, xi_slot, src, lin, e_ev, r);
@@ -361,26 +394,31 @@ __global__ void __launch_bounds__(1024) sweep_kernel(SweepArgs<Real> A) {
           if (!active && rk < take) {
             const int64_t k = tile_base + (int64_t)(tile_next + rk);
             if (from_bank) {
-              x = (double)A.in_bank.x[k];
-              mu = (double)A.in_bank.mu[k];
+              const XMu<Real> xm = A.in_bank.xm[k];
+              const Tag tg = A.in_bank.tag[k];
+              x = (double)xm.x;
+              mu = (double)xm.mu;
               w = A.in_bank.w[k];
               lin = A.in_bank.lin[k];
-              src = A.in_bank.src[k];
-              e = A.in_bank.e[k];
-              cell = A.in_bank.cell[k];
+              src = tg.src;
+              e = tg.e;
+              cell = tg.cell;
               tau = A.dt;
               active = true;
               C.histories += 1;
               ww_check(1, e, e, SLOT_START, false, 0.0);
             } else {
-              x = (double)A.dq.x[k];
-              mu = (double)A.dq.mu[k];
-              w = A.dq.w[k];
-              tau = A.dq.tau[k];
+              const XMu<Real> xm = A.dq.xm[k];
+              const WTau wt = A.dq.wt[k];
+              const Tag tg = A.dq.tag[k];
+              x = (double)xm.x;
+              mu = (double)xm.mu;
+              w = wt.w;
+              tau = wt.tau;
               lin = A.dq.lin[k];
-              src = A.dq.src[k];
-              e = A.dq.e[k];
-              cell = A.dq.cell[k];
+              src = tg.src;
+              e = tg.e;
+              cell = tg.cell;
               active = true;
             }
           }
@@ -402,8 +440,10 @@ __global__ void __launch_bounds__(1024) sweep_kernel(SweepArgs<Real> A) {
         draw(A.seed, A.key1, SLOT_FLIGHT, src, lin, e, r);
         const double ua = u53(r[0], r[1]);
         const double ub = u53(r[2], r[3]);
-        const double d_coll = -log(1.0 - ua) / A.sig_t[i];
-        const double xl = A.edges[i], xr = A.edges[i + 1];
+        const CellData cd = A.cells[i];
+        // Exponential flight distance with mean free path 1/sigma_t.
+        const double d_coll = -log(1.0 - ua) * cd.inv_sig;
+        const double xl = cd.xl, xr = cd.xr;
         double d_bnd;
         if (mu > 0.0) d_bnd = (xr - x) / mu;
         else if (mu < 0.0) d_bnd = (xl - x) / mu;
@@ -431,9 +471,9 @@ __global__ void __launch_bounds__(1024) sweep_kernel(SweepArgs<Real> A) {
           if (xn < xl) xn = xl;
           if (xn > xr) xn = xr;
           x = xn;
-          uint32_t rc[4];
-          draw(A.seed, A.key1, SLOT_START, src, lin, e, rc);
-          next_chunk = (int32_t)(u53(rc[0], rc[1]) * (double)nc);
+          // The flight draw's second variate is unused at census: it picks
+          // the chunk of the next step.
+          next_chunk = (int32_t)(ub * (double)nc);
           if (next_chunk >= nc) next_chunk = nc - 1;
           // Time-crossing tally at t^n (Eq. ct-mc): v*w per particle.
           const double vw = v * w;
@@ -446,7 +486,7 @@ __global__ void __launch_bounds__(1024) sweep_kernel(SweepArgs<Real> A) {
           at_census = true;
           active = false;
         } else {
-          tau = tau - l / v;
+          tau = tau - l * A.inv_v;
           if (ev == 1) {
             const bool out_l = (i == 0 && mu < 0.0);
             const bool out_r = (i == I - 1 && mu > 0.0);
@@ -471,7 +511,7 @@ __global__ void __launch_bounds__(1024) sweep_kernel(SweepArgs<Real> A) {
             if (xn > xr) xn = xr;
             x = xn;
             C.collisions += 1;
-            if (ub < A.cratio[i]) {
+            if (ub < cd.c) {
               uint32_t r1[4];
               draw(A.seed, A.key1, SLOT_EVENT, src, lin, e_ev, r1);
               mu = 2.0 * u53(r1[0], r1[1]) - 1.0;
@@ -486,13 +526,8 @@ __global__ void __launch_bounds__(1024) sweep_kernel(SweepArgs<Real> A) {
       }
 
       // -------------------------------------------------- census appends --
-      if (__ballot(at_census) != 0) {
-        for (int c = 0; c < nc; ++c) {
-          const int64_t region = (int64_t)(b * nc + c) * G.stride;
-          census_append(A.census, G, &L.ccnt[c], &A.census.ovfcnt[b * nc + c], region, jseg,
-                        at_census && next_chunk == c, x, mu, w, lin, src, e, cell, A.err);
-        }
-      }
+      census_append(A.census, G, L.ccnt, &A.census.ovfcnt[b * nc], (int64_t)(b * nc) * G.stride, nc, jseg,
+                    at_census, next_chunk, x, mu, w, lin, src, e, cell, A.err);
       if (__ballot(nd > 1) != 0) flush_daughters();
     }
 
@@ -533,9 +568,15 @@ __global__ void __launch_bounds__(1024) sweep_kernel(SweepArgs<Real> A) {
   }
   if (tid < 12) {
     const uint32_t t = L.cnt[tid];
-    if (t != 0) atomicAdd(&A.counters[tid], (unsigned long long)t);
+    if (t != 0) {
+      atomicAdd(&A.counters[tid], (unsigned long long)t);                // this step
+      atomicAdd(&A.counters[C_NCOUNTERS + tid], (unsigned long long)t);  // since init
+    }
   }
-  if (tid == 0) atomicMax(&A.counters[C_GENERATIONS], (unsigned long long)(gen + 1));
+  if (tid == 0) {
+    atomicMax(&A.counters[C_GENERATIONS], (unsigned long long)(gen + 1));
+    atomicMax(&A.counters[C_NCOUNTERS + C_GENERATIONS], (unsigned long long)(gen + 1));
+  }
   flush_tallies(L, I, nc, b, A.tal, A.bnd, A.tracks, A.wnext);
 }
 
@@ -568,8 +609,7 @@ __global__ void __launch_bounds__(1024) source_kernel(SourceArgs A, Bank<double>
       draw(A.seed, A.key1, SLOT_BIRTH, (uint32_t)s, 0ull, 0u, r);
       mu = 2.0 * u53(r[0], r[1]) - 1.0;
       cell = find_cell(A.edges, I, A.src_x, mu);
-      draw(A.seed, A.key1, SLOT_START, (uint32_t)s, 0ull, 0u, r);
-      chunk = (int32_t)(u53(r[0], r[1]) * (double)nc);
+      chunk = (int32_t)(u53(r[2], r[3]) * (double)nc);
       if (chunk >= nc) chunk = nc - 1;
       const double vw = A.v * 1.0;
       const double c1 = vw * mu;
@@ -578,11 +618,8 @@ __global__ void __launch_bounds__(1024) source_kernel(SourceArgs A, Bank<double>
       atomicAdd(&L.hist[cell * 6 + 5], c1 * mu);
       atomicAdd(&L.wnext[chunk], 1.0);
     }
-    for (int c = 0; c < nc; ++c) {
-      const int64_t region = (int64_t)(b * nc + c) * G.stride;
-      census_append(bank, G, &L.ccnt[c], &bank.ovfcnt[b * nc + c], region, jseg, live && chunk == c, A.src_x, mu,
-                    1.0, 0ull, (uint32_t)s, 0u, cell, A.err);
-    }
+    census_append(bank, G, L.ccnt, &bank.ovfcnt[b * nc], (int64_t)(b * nc) * G.stride, nc, jseg, live, chunk,
+                  A.src_x, mu, 1.0, 0ull, (uint32_t)s, 0u, cell, A.err);
   }
   __syncthreads();
   if ((int)threadIdx.x < nc) {

@@ -25,8 +25,8 @@ TALLY_CELLS, TALLY_BOUNDARY, TALLY_TRACKS, TALLY_PREV_CELLS, TALLY_PREV_BOUNDARY
 
 # Every symbol include/hww.h declares.
 EXPORTS = ["hww_workspace_bytes", "hww_init_problem", "hww_set_windows", "hww_sweep_step",
-           "hww_solve_losm", "hww_read_tallies", "hww_read_bank", "hww_sync", "hww_last_error",
-           "hww_destroy"]
+           "hww_read_run_stats", "hww_solve_losm", "hww_read_tallies", "hww_read_bank", "hww_sync",
+           "hww_last_error", "hww_destroy"]
 
 
 class HwwError(RuntimeError):
@@ -78,6 +78,7 @@ def lib():
         L.hww_init_problem.argtypes = [C.POINTER(Problem), vp, C.c_int64, vp, C.POINTER(vp)]
         L.hww_set_windows.argtypes = [vp, dp, C.c_double]
         L.hww_sweep_step.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(StepStats)]
+        L.hww_read_run_stats.argtypes = [vp, C.POINTER(StepStats)]
         L.hww_solve_losm.argtypes = [vp, C.POINTER(LosmOpts), dp, dp]
         L.hww_read_tallies.argtypes = [vp, C.c_int32, vp, C.c_int64]
         L.hww_read_bank.argtypes = [vp, C.c_int32, C.c_int64, C.POINTER(C.c_int64)] + [vp] * 8
@@ -182,6 +183,11 @@ class Handle:
         self._check("hww_sweep_step", lib().hww_sweep_step(self._h, int(step), int(chunk),
                                                            C.byref(st) if st is not None else None))
         return st.as_dict() if st is not None else None
+
+    def run_stats(self):
+        st = StepStats()
+        self._check("hww_read_run_stats", lib().hww_read_run_stats(self._h, C.byref(st)))
+        return st.as_dict()
 
     def solve_losm(self, theta=0.5, implicit=False, filter=0, ma_k=3, eps_min=1e-3, rho=5.0,
                    closure_track=0, apply_windows=True, want_solution=False):
