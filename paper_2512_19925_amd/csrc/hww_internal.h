@@ -90,13 +90,23 @@ struct SweepArgs {
   Bank<Real> census;
   Queue<Real> dq;
   int64_t dcap;
-  uint32_t *cursor;                // [B] tile cursors of the start bank
+  uint32_t *cursor;                // [B] tile cursors of the start bank (zero at launch)
+  uint32_t *cursor_next;           // [B] the other cursor set, cleared for the next launch
   double *tal;                     // [B][I][6]
   double *bnd;                     // [B][2][3]
   unsigned long long *tracks;      // [I]
   unsigned long long *counters;    // [2][C_NCOUNTERS]: this step, since init
   double *wnext;                   // [nc]
   uint32_t *err;
+};
+
+struct BeginStepArgs {
+  uint32_t *segcnt, *ovfcnt;
+  double *tal, *bnd;
+  unsigned long long *tracks, *counters;
+  double *wstart, *wnext;
+  int64_t n_seg, n_ovf, n_tal, n_bnd, n_tracks;
+  int32_t nc;
 };
 
 struct SourceArgs {
@@ -125,6 +135,7 @@ struct LosmArgs {
   double *scratch;                // >= 24 * (I + 4) doubles
   double *factor;                 // [3][2I+3] LU factors of the system for `theta`
   int32_t refactor;               // 1: (re)compute the factors first
+  int32_t work_in_lds;            // set by the launcher: grid functions fit in LDS
   Window *win;                    // [I] window centres, ceilings, floors
   double *phi_out, *J_out;        // I+2, I+1 (device)
   uint32_t *err;
@@ -147,5 +158,6 @@ hipError_t launch_losm(const LosmArgs &a, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);
 hipError_t launch_rotate_chunks(double *wstart, double *wnext, int nc, hipStream_t s);
+hipError_t launch_begin_step(const BeginStepArgs &a, hipStream_t s);
 
 }  // namespace hww

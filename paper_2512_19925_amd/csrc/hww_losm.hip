@@ -115,24 +115,104 @@ __device__ void affine_scan(double *sp, double *sq, double &P, double &Q) {
   }
 }
 
+// Scale of the closure set: start weight / swept start weight (implicit),
+// 1 (semi-implicit); zero means no start weight has been swept yet.
+__device__ inline double closure_scale(const LosmArgs &A) {
+  if (!A.implicit) return 1.0;
+  double wtot = 0.0, done = 0.0;
+  for (int q = 0; q < A.nc; ++q) {
+    wtot += A.wstart[q];
+    if (q < A.next_chunk) done += A.wstart[q];
+  }
+  return done > 0.0 ? wtot / done : 0.0;
+}
+
+// Phase 1 over many work-groups: per cell, sum the B batch tallies of the
+// initial-condition set (census phi, J, K) and of the closure set, and
+// normalise per source particle.  A work-group takes 64 cells; its four
+// waves each sum a quarter of the batches and combine through LDS.
+__global__ void __launch_bounds__(256) losm_reduce_kernel(LosmArgs A) {
+  const int I = A.I;
+  const int M = I + 2;
+  double *gi_phi = A.scratch + 5 * M;
+  double *gi_J = gi_phi + I;
+  double *gi_K = gi_J + I;
+  double *gc_phi = gi_K + I;
+  double *gc_K = gc_phi + I;
+  __shared__ double part[4][5][64];
+  const double scale = closure_scale(A);
+  if (blockIdx.x == 0 && threadIdx.x < 12) {
+    // Face values: q = (phi L, phi R, P L, P R, F L, F R) of the initial-
+    // condition set (t < 6) and of the closure set (t >= 6).
+    const int t = threadIdx.x;
+    const int set = t / 6, q = t % 6;
+    const int f = q & 1, kind = q >> 1;
+    const double *bs = set == 0 ? A.bnd_ic : A.bnd_cl;
+    double acc = 0.0;
+#pragma unroll 8
+    for (int b = 0; b < A.B; ++b) acc += bs[(b * 2 + f) * 3 + kind];
+    A.scratch[5 * M + 5 * I + t] = (set == 0 ? 1.0 : scale) * acc / (A.n_src * A.dt);
+  }
+  const int kc = A.closure_track ? 0 : 3;
+  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane;
+  double p = 0.0, j = 0.0, k = 0.0, cp = 0.0, ck = 0.0;
+  if (i < I) {
+#pragma unroll 4
+    for (int b = grp; b < A.B; b += 4) {
+      const double *t = A.tal_ic + ((size_t)b * I + i) * 6;
+      p += t[3];
+      j += t[4];
+      k += t[5];
+      const double *tc = A.tal_cl + ((size_t)b * I + i) * 6;
+      cp += tc[kc];
+      ck += tc[kc + 2];
+    }
+  }
+  part[grp][0][lane] = p;
+  part[grp][1][lane] = j;
+  part[grp][2][lane] = k;
+  part[grp][3][lane] = cp;
+  part[grp][4][lane] = ck;
+  __syncthreads();
+  if (grp == 0 && i < I) {
+    p = part[0][0][lane] + part[1][0][lane] + part[2][0][lane] + part[3][0][lane];
+    j = part[0][1][lane] + part[1][1][lane] + part[2][1][lane] + part[3][1][lane];
+    k = part[0][2][lane] + part[1][2][lane] + part[2][2][lane] + part[3][2][lane];
+    cp = part[0][3][lane] + part[1][3][lane] + part[2][3][lane] + part[3][3][lane];
+    ck = part[0][4][lane] + part[1][4][lane] + part[2][4][lane] + part[3][4][lane];
+    const double dxi = A.edges[i + 1] - A.edges[i];
+    const double norm = A.n_src * dxi;
+    gi_phi[i] = p / norm;
+    gi_J[i] = j / norm;
+    gi_K[i] = k / norm;
+    const double normc = A.closure_track ? (A.n_src * dxi * A.dt) : norm;
+    gc_phi[i] = scale * cp / normc;
+    gc_K[i] = scale * ck / normc;
+  }
+}
+
 __global__ void __launch_bounds__(LOSM_THREADS) losm_kernel(LosmArgs A) {
   const int I = A.I;
   const int M = I + 2;
   const int n = 2 * I + 3;
   const int tid = threadIdx.x;
   const int T = blockDim.x;
-  double *S = A.scratch;
+  extern __shared__ double dyn[];
+  double *u = dyn;  // [n] right-hand side, then solution
+  // Working grid functions live in LDS when they fit, else in the global
+  // scratch.
+  double *S = A.work_in_lds ? dyn + n : A.scratch;
   double *phi_o = S;
   double *J_o = phi_o + M;
   double *F_o = J_o + M;
   double *F_n = F_o + M;
   double *tmp = F_n + M;
-  double *gi_phi = tmp + M;
-  double *gi_J = gi_phi + I;
-  double *gi_K = gi_J + I;
-  double *gc_phi = gi_K + I;
-  double *gc_K = gc_phi + I;
-  extern __shared__ double u[];  // [n] right-hand side, then solution
+  const double *gi_phi = A.scratch + 5 * M;
+  const double *gi_J = gi_phi + I;
+  const double *gi_K = gi_J + I;
+  const double *gc_phi = gi_K + I;
+  const double *gc_K = gc_phi + I;
   __shared__ double sp[LOSM_THREADS], sq[LOSM_THREADS];
   __shared__ double face[12];  // ic: phi L/R, P L/R, F L/R; cl: same
   __shared__ double sc[4];     // scale, s, max
@@ -143,21 +223,15 @@ __global__ void __launch_bounds__(LOSM_THREADS) losm_kernel(LosmArgs A) {
   if (tid == 0) {
     bad = (*A.status != 0) ? 1 : 0;  // a failed factorization stays failed
     skip = 0;
-    double wtot = 0.0, done = 0.0, wn = 0.0;
+    double wtot = 0.0, wn = 0.0;
     for (int q = 0; q < A.nc; ++q) {
       wtot += A.wstart[q];
-      if (q < A.next_chunk) done += A.wstart[q];
       wn += A.wnext[q];
     }
-    if (A.implicit) {
-      sc[0] = wtot / done;
-      sc[1] = wtot / A.n_src;
-      // No start weight swept yet: no closures exist, the update is skipped.
-      if (!(done > 0.0)) skip = 1;
-    } else {
-      sc[0] = 1.0;
-      sc[1] = wn / A.n_src;
-    }
+    sc[0] = closure_scale(A);
+    sc[1] = (A.implicit ? wtot : wn) / A.n_src;
+    // No start weight swept yet: no closures exist, the update is skipped.
+    if (A.implicit && !(sc[0] > 0.0)) skip = 1;
   }
   __syncthreads();
   if (bad) return;
@@ -166,40 +240,9 @@ __global__ void __launch_bounds__(LOSM_THREADS) losm_kernel(LosmArgs A) {
     for (int i = tid; i <= I; i += T) A.J_out[i] = 0.0;
     return;
   }
-  const double scale = sc[0];
 
-  // 1. batch sums and normalisation per source particle.
-  const int kc = A.closure_track ? 0 : 3;
-  for (int i = tid; i < I; i += T) {
-    double p = 0.0, j = 0.0, k = 0.0, cp = 0.0, ck = 0.0;
-    // Independent loads of all batches in flight at once (latency bound).
-#pragma unroll 16
-    for (int b = 0; b < A.B; ++b) {
-      const double *t = A.tal_ic + ((size_t)b * I + i) * 6;
-      p += t[3];
-      j += t[4];
-      k += t[5];
-      const double *tc = A.tal_cl + ((size_t)b * I + i) * 6;
-      cp += tc[kc];
-      ck += tc[kc + 2];
-    }
-    const double dxi = A.edges[i + 1] - A.edges[i];
-    const double norm = A.n_src * dxi;
-    gi_phi[i] = p / norm;
-    gi_J[i] = j / norm;
-    gi_K[i] = k / norm;
-    const double normc = A.closure_track ? (A.n_src * dxi * A.dt) : norm;
-    gc_phi[i] = scale * cp / normc;
-    gc_K[i] = scale * ck / normc;
-  }
-  if (tid < 12) {
-    const int set = tid / 6, q = tid % 6;
-    const int f = q & 1, kind = q >> 1;  // q: (phi L, phi R, P L, P R, F L, F R)
-    const double *bs = set == 0 ? A.bnd_ic : A.bnd_cl;
-    double acc = 0.0;
-    for (int b = 0; b < A.B; ++b) acc += bs[(b * 2 + f) * 3 + kind];
-    face[tid] = (set == 0 ? 1.0 : scale) * acc / (A.n_src * A.dt);
-  }
+  // 1. batch sums: done by losm_reduce_kernel into gi_* and gc_*.
+  if (tid < 12) face[tid] = A.scratch[5 * M + 5 * I + tid];
   __syncthreads();
 
   // 2. grid functions.
@@ -372,7 +415,17 @@ hipError_t launch_losm(const LosmArgs &a, hipStream_t s) {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  const size_t lds = (size_t)(2 * a.I + 3) * sizeof(double);
+  hipLaunchKernelGGL(losm_reduce_kernel, dim3((a.I + 63) / 64), dim3(256), 0, s, a);
+  {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  LosmArgs b = a;
+  const size_t lds_min = (size_t)(2 * a.I + 3) * sizeof(double);
+  const size_t lds_full = lds_min + (size_t)5 * (a.I + 2) * sizeof(double);
+  // 16 KB of static LDS for the scans and reductions.
+  b.work_in_lds = lds_full + 17 * 1024 <= 160 * 1024 ? 1 : 0;
+  const size_t lds = b.work_in_lds ? lds_full : lds_min;
   static size_t done = 0;
   if (lds > 32 * 1024 && lds > done) {
     const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&losm_kernel),
@@ -380,7 +433,7 @@ hipError_t launch_losm(const LosmArgs &a, hipStream_t s) {
     if (e != hipSuccess) return e;
     done = lds;
   }
-  hipLaunchKernelGGL(losm_kernel, dim3(1), dim3(LOSM_THREADS), lds, s, a);
+  hipLaunchKernelGGL(losm_kernel, dim3(1), dim3(LOSM_THREADS), lds, s, b);
   return hipGetLastError();
 }
 

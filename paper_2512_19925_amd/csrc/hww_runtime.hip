@@ -102,7 +102,7 @@ void make_layout(const hww_problem &p, Layout *L) {
   L->off_counters = c.take(8 * 2 * C_NCOUNTERS);
   L->off_wstart = c.take(8 * nc);
   L->off_wnext = c.take(8 * nc);
-  L->off_cursor = c.take(4 * B);
+  L->off_cursor = c.take(4 * 2 * B);
   L->off_err = c.take(4);
   L->off_status = c.take(4);
   L->off_scratch = c.take(8 * 24 * (I + 4));
@@ -389,6 +389,7 @@ int hww_init_problem(const hww_problem *problem, void *dev_workspace, int64_t ws
   INITCHK(launch_fill_f64(h->wnext, 0.0, h->nc, h->stream));
   INITCHK(launch_fill_f64(reinterpret_cast<double *>(h->win), 0.0, 4 * (int64_t)I, h->stream));
   INITCHK(launch_fill_u32(h->err, 0u, 1, h->stream));
+  INITCHK(launch_fill_u32(h->cursor, 0u, 2 * (int64_t)h->B, h->stream));
   INITCHK(launch_fill_u32(reinterpret_cast<uint32_t *>(h->status), 0u, 1, h->stream));
 
   // Source bank = census bank of step 0 (bank 1); its tallies fill set 0.
@@ -442,13 +443,17 @@ int hww_sweep_step(hww_handle *h, int32_t step, int32_t chunk, hww_step_stats *s
       return fail(h, HWW_E_STATE, "step out of order");
     // The census bank of the finished step becomes the start bank.
     h->start_bank = 1 - h->start_bank;
-    if (zero_counts(h, 1 - h->start_bank) != HWW_OK) return HWW_E_DEVICE;
     h->cur_tal = 1 - h->cur_tal;
-    HIPCHK(h, launch_fill_f64(h->tal[h->cur_tal], 0.0, (int64_t)h->B * h->I * 6, h->stream));
-    HIPCHK(h, launch_fill_f64(h->bnd[h->cur_tal], 0.0, (int64_t)h->B * 6, h->stream));
-    HIPCHK(h, launch_fill_u32(reinterpret_cast<uint32_t *>(h->tracks), 0u, 2 * (int64_t)h->I, h->stream));
-    HIPCHK(h, launch_fill_u32(reinterpret_cast<uint32_t *>(h->counters), 0u, 2 * C_NCOUNTERS, h->stream));
-    HIPCHK(h, launch_rotate_chunks(h->wstart, h->wnext, h->nc, h->stream));
+    BeginStepArgs bs{};
+    const Bank<double> &cen = h->bank[1 - h->start_bank];
+    bs.segcnt = cen.segcnt; bs.ovfcnt = cen.ovfcnt;
+    bs.tal = h->tal[h->cur_tal]; bs.bnd = h->bnd[h->cur_tal];
+    bs.tracks = h->tracks; bs.counters = h->counters;
+    bs.wstart = h->wstart; bs.wnext = h->wnext;
+    bs.n_seg = (int64_t)h->R * h->K; bs.n_ovf = h->R;
+    bs.n_tal = (int64_t)h->B * h->I * 6; bs.n_bnd = (int64_t)h->B * 6; bs.n_tracks = h->I;
+    bs.nc = h->nc;
+    HIPCHK(h, launch_begin_step(bs, h->stream));
     h->step = step;
     h->next_chunk = 0;
     h->n_launch = 0;
@@ -459,8 +464,9 @@ int hww_sweep_step(hww_handle *h, int32_t step, int32_t chunk, hww_step_stats *s
 
   SweepArgs<double> a = base_args(h);
   a.chunk = chunk;
-  HIPCHK(h, launch_fill_u32(h->cursor, 0u, h->B, h->stream));
   const int k = h->ev_used;
+  a.cursor = h->cursor + (k & 1) * h->B;
+  a.cursor_next = h->cursor + ((k + 1) & 1) * h->B;
   while ((int)h->ev.size() < 2 * (k + 1)) {
     hipEvent_t e = nullptr;
     HIPCHK(h, hipEventCreate(&e));

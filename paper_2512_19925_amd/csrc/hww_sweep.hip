@@ -225,6 +225,9 @@ __global__ void __launch_bounds__(1024) sweep_kernel(SweepArgs<Real> A) {
   const int tid = threadIdx.x;
   const int r_in = b * nc + A.chunk;
   const int64_t in_region = (int64_t)r_in * G.stride;
+  // Tile cursors alternate between two sets; this launch clears the set the
+  // next launch will use.
+  if (blockIdx.x == 0 && tid < A.B) A.cursor_next[tid] = 0u;
   __syncthreads();
   if (tid < nc) L.ccnt[tid] = A.census.segcnt[(b * nc + tid) * K + jseg];
   if (tid == 0) {
@@ -629,6 +632,23 @@ __global__ void __launch_bounds__(1024) source_kernel(SourceArgs A, Bank<double>
   flush_tallies(L, I, nc, b, A.tal, nullptr, nullptr, A.wnext);
 }
 
+// Clear the accumulators of a new time step and hand the census chunk
+// weights of the finished step to the new one (one launch).
+__global__ void begin_step_kernel(BeginStepArgs A) {
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t st = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t j = t0; j < A.n_seg; j += st) A.segcnt[j] = 0u;
+  for (int64_t j = t0; j < A.n_ovf; j += st) A.ovfcnt[j] = 0u;
+  for (int64_t j = t0; j < A.n_tal; j += st) A.tal[j] = 0.0;
+  for (int64_t j = t0; j < A.n_bnd; j += st) A.bnd[j] = 0.0;
+  for (int64_t j = t0; j < A.n_tracks; j += st) A.tracks[j] = 0ull;
+  for (int64_t j = t0; j < C_NCOUNTERS; j += st) A.counters[j] = 0ull;
+  if (t0 < A.nc) {
+    A.wstart[t0] = A.wnext[t0];
+    A.wnext[t0] = 0.0;
+  }
+}
+
 __global__ void fill_u32_kernel(uint32_t *p, uint32_t v, int64_t n) {
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
     p[j] = v;
@@ -691,6 +711,14 @@ hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s) {
   int64_t g = (n + 255) / 256;
   if (g > 4096) g = 4096;
   hipLaunchKernelGGL(fill_f64_kernel, dim3((unsigned)g), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_begin_step(const BeginStepArgs &a, hipStream_t s) {
+  int64_t g = (a.n_tal + 255) / 256;
+  if (g < 1) g = 1;
+  if (g > 1024) g = 1024;
+  hipLaunchKernelGGL(begin_step_kernel, dim3((unsigned)g), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
