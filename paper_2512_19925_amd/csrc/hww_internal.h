@@ -38,9 +38,11 @@ struct Tag {
 struct alignas(16) WTau {
   double w, tau;
 };
-// Per-cell data read by every flight: edges, 1/sigma_t, sigma_s/sigma_t.
-struct alignas(32) CellData {
-  double xl, xr, inv_sig, c;
+// Per-cell data read by every flight, in the flight precision: edges,
+// 1/sigma_t, sigma_s/sigma_t.
+template <typename Real>
+struct alignas(4 * sizeof(Real)) CellData {
+  Real xl, xr, inv_sig, c;
 };
 // Per-cell weight window: centre, ceiling, floor.
 struct alignas(32) Window {
@@ -81,7 +83,7 @@ struct SweepArgs {
   int32_t I, B, nc;
   double v, inv_v, dt;
   uint32_t seed, key1;  // key1 = replica << 4
-  const CellData *cells;   // [I]
+  const CellData<Real> *cells;  // [I]
   const Window *win;       // [I]
   int32_t ww_on;
   int32_t chunk;
@@ -150,10 +152,11 @@ __host__ __device__ inline size_t lds_words(int I, int K) { return (size_t)I + 1
 inline size_t sweep_lds_bytes(int I, int nc, int K) { return lds_doubles(I, nc) * 8 + lds_words(I, K) * 4; }
 
 // Launchers (defined in the .hip files).
-hipError_t sweep_occupancy_f64(int block, size_t lds, int *blocks_per_cu);
-hipError_t launch_sweep_f64(const SweepArgs<double> &a, int grid, int block, size_t lds, hipStream_t s);
-hipError_t launch_source_f64(const SourceArgs &a, const Bank<double> &bank, int grid, int block, size_t lds,
-                             hipStream_t s);
+template <typename Real>
+hipError_t launch_sweep(const SweepArgs<Real> &a, int grid, int block, size_t lds, hipStream_t s);
+template <typename Real>
+hipError_t launch_source(const SourceArgs &a, const Bank<Real> &bank, int grid, int block, size_t lds,
+                         hipStream_t s);
 hipError_t launch_losm(const LosmArgs &a, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);

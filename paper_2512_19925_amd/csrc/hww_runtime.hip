@@ -45,6 +45,7 @@ struct Carver {
 
 bool real_bytes(int precision, int64_t *rb) {
   if (precision == HWW_FP64) { *rb = 8; return true; }
+  if (precision == HWW_FP32) { *rb = 4; return true; }
   return false;
 }
 
@@ -77,7 +78,7 @@ void make_layout(const hww_problem &p, Layout *L) {
   L->off_edges = c.take(8 * (I + 1));
   L->off_sigt = c.take(8 * I);
   L->off_sigs = c.take(8 * I);
-  L->off_cells = c.take(sizeof(CellData) * I);
+  L->off_cells = c.take(4 * rb * I);
   L->off_win = c.take(sizeof(Window) * I);
   for (int k = 0; k < 2; ++k) {
     L->off_bank[k] = c.take(0);
@@ -157,10 +158,15 @@ struct hww_handle {
   hipStream_t stream = nullptr;
   char *ws = nullptr;
   double *edges, *sig_t, *sig_s;
-  CellData *cells;
   Window *win;
+  int fp32 = 0;
+  // Particle streams in the flight precision of the problem (one set used).
   Bank<double> bank[2];
   Queue<double> dq;
+  CellData<double> *cells;
+  Bank<float> bank32[2];
+  Queue<float> dq32;
+  CellData<float> *cells32;
   double *tal[2], *bnd[2];
   unsigned long long *tracks, *counters;
   double *wstart, *wnext;
@@ -262,20 +268,27 @@ int poll_errors(hww_handle *h) {
   return HWW_OK;
 }
 
-SweepArgs<double> base_args(hww_handle *h) {
-  SweepArgs<double> a{};
+template <typename Real>
+SweepArgs<Real> base_args(hww_handle *h) {
+  SweepArgs<Real> a{};
   a.I = h->I; a.B = h->B; a.nc = h->nc;
   a.v = h->p.speed; a.inv_v = 1.0 / h->p.speed; a.dt = h->p.dt;
   a.seed = h->p.seed; a.key1 = h->p.replica << 4;
-  a.cells = h->cells;
   a.win = h->win;
   a.ww_on = h->ww_on;
   a.geom = h->L.geom;
-  a.in_bank = h->bank[h->start_bank];
-  a.census = h->bank[1 - h->start_bank];
-  a.dq = h->dq;
+  if constexpr (sizeof(Real) == 8) {
+    a.cells = h->cells;
+    a.in_bank = h->bank[h->start_bank];
+    a.census = h->bank[1 - h->start_bank];
+    a.dq = h->dq;
+  } else {
+    a.cells = h->cells32;
+    a.in_bank = h->bank32[h->start_bank];
+    a.census = h->bank32[1 - h->start_bank];
+    a.dq = h->dq32;
+  }
   a.dcap = h->L.dcap;
-  a.cursor = h->cursor;
   a.tal = h->tal[h->cur_tal];
   a.bnd = h->bnd[h->cur_tal];
   a.tracks = h->tracks;
@@ -283,6 +296,16 @@ SweepArgs<double> base_args(hww_handle *h) {
   a.wnext = h->wnext;
   a.err = h->err;
   return a;
+}
+
+template <typename Real>
+int launch_chunk(hww_handle *h, int chunk, int k) {
+  SweepArgs<Real> a = base_args<Real>(h);
+  a.chunk = chunk;
+  a.cursor = h->cursor + (k & 1) * h->B;
+  a.cursor_next = h->cursor + ((k + 1) & 1) * h->B;
+  HIPCHK(h, launch_sweep<Real>(a, h->B * h->K, kBlock, h->lds, h->stream));
+  return HWW_OK;
 }
 
 int zero_counts(hww_handle *h, int k) {
@@ -332,14 +355,19 @@ int hww_init_problem(const hww_problem *problem, void *dev_workspace, int64_t ws
   h->edges = reinterpret_cast<double *>(ws + L.off_edges);
   h->sig_t = reinterpret_cast<double *>(ws + L.off_sigt);
   h->sig_s = reinterpret_cast<double *>(ws + L.off_sigs);
-  h->cells = reinterpret_cast<CellData *>(ws + L.off_cells);
+  h->cells = reinterpret_cast<CellData<double> *>(ws + L.off_cells);
   h->win = reinterpret_cast<Window *>(ws + L.off_win);
   for (int k = 0; k < 2; ++k) {
     h->bank[k] = bank_view<double>(ws, L.off_bank[k], L.off_segcnt[k], L.off_ovfcnt[k], slots);
     h->tal[k] = reinterpret_cast<double *>(ws + L.off_tal[k]);
     h->bnd[k] = reinterpret_cast<double *>(ws + L.off_bnd[k]);
   }
+  h->fp32 = problem->precision == HWW_FP32;
   h->dq = queue_view<double>(ws, L.off_q, 2 * (int64_t)h->B * h->K * L.dcap);
+  h->dq32 = queue_view<float>(ws, L.off_q, 2 * (int64_t)h->B * h->K * L.dcap);
+  for (int k = 0; k < 2; ++k)
+    h->bank32[k] = bank_view<float>(ws, L.off_bank[k], L.off_segcnt[k], L.off_ovfcnt[k], slots);
+  h->cells32 = reinterpret_cast<CellData<float> *>(ws + L.off_cells);
   h->tracks = reinterpret_cast<unsigned long long *>(ws + L.off_tracks);
   h->counters = reinterpret_cast<unsigned long long *>(ws + L.off_counters);
   h->wstart = reinterpret_cast<double *>(ws + L.off_wstart);
@@ -366,17 +394,25 @@ int hww_init_problem(const hww_problem *problem, void *dev_workspace, int64_t ws
   } while (0)
 
   const int I = h->I;
-  std::vector<CellData> cd(I);
+  std::vector<CellData<double>> cd(I);
+  std::vector<CellData<float>> cf(I);
   for (int i = 0; i < I; ++i) {
     cd[i].xl = problem->edges[i];
     cd[i].xr = problem->edges[i + 1];
     cd[i].inv_sig = 1.0 / problem->sigma_t[i];
     cd[i].c = problem->sigma_s[i] / problem->sigma_t[i];
+    cf[i].xl = (float)cd[i].xl;
+    cf[i].xr = (float)cd[i].xr;
+    cf[i].inv_sig = (float)cd[i].inv_sig;
+    cf[i].c = (float)cd[i].c;
   }
   INITCHK(hipMemcpyAsync(h->edges, problem->edges, 8 * (I + 1), hipMemcpyHostToDevice, h->stream));
   INITCHK(hipMemcpyAsync(h->sig_t, problem->sigma_t, 8 * I, hipMemcpyHostToDevice, h->stream));
   INITCHK(hipMemcpyAsync(h->sig_s, problem->sigma_s, 8 * I, hipMemcpyHostToDevice, h->stream));
-  INITCHK(hipMemcpyAsync(h->cells, cd.data(), sizeof(CellData) * I, hipMemcpyHostToDevice, h->stream));
+  if (h->fp32)
+    INITCHK(hipMemcpyAsync(h->cells32, cf.data(), sizeof(CellData<float>) * I, hipMemcpyHostToDevice, h->stream));
+  else
+    INITCHK(hipMemcpyAsync(h->cells, cd.data(), sizeof(CellData<double>) * I, hipMemcpyHostToDevice, h->stream));
   // Zero everything the kernels accumulate into.
   for (int k = 0; k < 2; ++k) {
     if (zero_counts(h, k) != HWW_OK) return bail(HWW_E_DEVICE);
@@ -401,7 +437,10 @@ int hww_init_problem(const hww_problem *problem, void *dev_workspace, int64_t ws
   sa.n_src = problem->n_src; sa.seed = problem->seed; sa.key1 = problem->replica << 4;
   sa.edges = h->edges; sa.geom = L.geom;
   sa.tal = h->tal[0]; sa.wnext = h->wnext; sa.err = h->err;
-  INITCHK(launch_source_f64(sa, h->bank[1], h->B * h->K, 256, h->lds, h->stream));
+  if (h->fp32)
+    INITCHK(launch_source<float>(sa, h->bank32[1], h->B * h->K, 256, h->lds, h->stream));
+  else
+    INITCHK(launch_source<double>(sa, h->bank[1], h->B * h->K, 256, h->lds, h->stream));
   int prc = poll_errors(h);
   if (prc != HWW_OK) return bail(prc);
   h->step = 0;
@@ -445,8 +484,8 @@ int hww_sweep_step(hww_handle *h, int32_t step, int32_t chunk, hww_step_stats *s
     h->start_bank = 1 - h->start_bank;
     h->cur_tal = 1 - h->cur_tal;
     BeginStepArgs bs{};
-    const Bank<double> &cen = h->bank[1 - h->start_bank];
-    bs.segcnt = cen.segcnt; bs.ovfcnt = cen.ovfcnt;
+    bs.segcnt = h->bank[1 - h->start_bank].segcnt;
+    bs.ovfcnt = h->bank[1 - h->start_bank].ovfcnt;
     bs.tal = h->tal[h->cur_tal]; bs.bnd = h->bnd[h->cur_tal];
     bs.tracks = h->tracks; bs.counters = h->counters;
     bs.wstart = h->wstart; bs.wnext = h->wnext;
@@ -462,18 +501,15 @@ int hww_sweep_step(hww_handle *h, int32_t step, int32_t chunk, hww_step_stats *s
     return fail(h, HWW_E_STATE, "chunk out of order");
   }
 
-  SweepArgs<double> a = base_args(h);
-  a.chunk = chunk;
   const int k = h->ev_used;
-  a.cursor = h->cursor + (k & 1) * h->B;
-  a.cursor_next = h->cursor + ((k + 1) & 1) * h->B;
   while ((int)h->ev.size() < 2 * (k + 1)) {
     hipEvent_t e = nullptr;
     HIPCHK(h, hipEventCreate(&e));
     h->ev.push_back(e);
   }
   HIPCHK(h, hipEventRecord(h->ev[2 * k], h->stream));
-  HIPCHK(h, launch_sweep_f64(a, h->B * h->K, kBlock, h->lds, h->stream));
+  const int lrc = h->fp32 ? launch_chunk<float>(h, chunk, k) : launch_chunk<double>(h, chunk, k);
+  if (lrc != HWW_OK) return lrc;
   HIPCHK(h, hipEventRecord(h->ev[2 * k + 1], h->stream));
   h->ev_used = k + 1;
   h->n_launch += 1;
@@ -505,7 +541,7 @@ int hww_sweep_step(hww_handle *h, int32_t step, int32_t chunk, hww_step_stats *s
     ms += t;
   }
   stats->kernel_ms = ms;
-  const uint64_t rec = 44, drec = 52;
+  const uint64_t rec = h->fp32 ? 36 : 44, drec = h->fp32 ? 44 : 52;
   stats->bytes_moved = cnt[C_HISTORIES] * rec + cnt[C_CENSUS] * rec + cnt[C_DAUGHTERS] * 2 * drec;
   return HWW_OK;
 }
@@ -536,7 +572,7 @@ int hww_read_run_stats(hww_handle *h, hww_step_stats *stats) {
   stats->generations = cnt[C_GENERATIONS];
   stats->launches = (uint64_t)h->ev_used;
   stats->kernel_ms = h->ms_summed;
-  const uint64_t rec = 44, drec = 52;
+  const uint64_t rec = h->fp32 ? 36 : 44, drec = h->fp32 ? 44 : 52;
   stats->bytes_moved = cnt[C_HISTORIES] * rec + cnt[C_CENSUS] * rec + cnt[C_DAUGHTERS] * 2 * drec;
   return HWW_OK;
 }
@@ -653,13 +689,26 @@ int hww_read_bank(hww_handle *h, int32_t which, int64_t cap, int64_t *count, dou
       if (n == 0) continue;
       const int64_t k = (int64_t)r * G.stride + (int64_t)j * G.seg_cap;
       std::vector<XMu<double>> xm(n);
+      std::vector<XMu<float>> xmf(h->fp32 ? n : 0);
       std::vector<Tag> tg(n);
-      HIPCHK(h, hipMemcpyAsync(xm.data(), bk.xm + k, sizeof(XMu<double>) * n, hipMemcpyDeviceToHost, h->stream));
-      HIPCHK(h, hipMemcpyAsync(tg.data(), bk.tag + k, sizeof(Tag) * n, hipMemcpyDeviceToHost, h->stream));
-      if (w) HIPCHK(h, hipMemcpyAsync(w + o, bk.w + k, 8 * n, hipMemcpyDeviceToHost, h->stream));
-      if (lin) HIPCHK(h, hipMemcpyAsync(lin + o, bk.lin + k, 8 * n, hipMemcpyDeviceToHost, h->stream));
+      if (h->fp32)
+        HIPCHK(h, hipMemcpyAsync(xmf.data(), h->bank32[bi].xm + k, sizeof(XMu<float>) * n, hipMemcpyDeviceToHost,
+                                 h->stream));
+      else
+        HIPCHK(h, hipMemcpyAsync(xm.data(), bk.xm + k, sizeof(XMu<double>) * n, hipMemcpyDeviceToHost, h->stream));
+      // The w, lineage and tag streams sit at precision-dependent offsets.
+      const Tag *tag_d = h->fp32 ? h->bank32[bi].tag : bk.tag;
+      const double *w_d = h->fp32 ? h->bank32[bi].w : bk.w;
+      const uint64_t *lin_d = h->fp32 ? h->bank32[bi].lin : bk.lin;
+      HIPCHK(h, hipMemcpyAsync(tg.data(), tag_d + k, sizeof(Tag) * n, hipMemcpyDeviceToHost, h->stream));
+      if (w) HIPCHK(h, hipMemcpyAsync(w + o, w_d + k, 8 * n, hipMemcpyDeviceToHost, h->stream));
+      if (lin) HIPCHK(h, hipMemcpyAsync(lin + o, lin_d + k, 8 * n, hipMemcpyDeviceToHost, h->stream));
       HIPCHK(h, hipStreamSynchronize(h->stream));
       for (int64_t q = 0; q < n; ++q) {
+        if (h->fp32) {
+          xm[q].x = xmf[q].x;
+          xm[q].mu = xmf[q].mu;
+        }
         if (x) x[o + q] = xm[q].x;
         if (mu) mu[o + q] = xm[q].mu;
         if (src) src[o + q] = tg[q].src;

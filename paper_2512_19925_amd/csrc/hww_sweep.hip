@@ -59,6 +59,19 @@ __device__ __forceinline__ double u53(uint32_t a, uint32_t b) {
   return k * (1.0 / 9007199254740992.0);
 }
 
+// Uniform on [0,1) in the flight precision: 53 bits (FP64) or the 24 high
+// bits of the first word (FP32); 1 - u is exact in both.
+template <typename Real>
+__device__ __forceinline__ Real uflight(uint32_t a, uint32_t b);
+template <>
+__device__ __forceinline__ double uflight<double>(uint32_t a, uint32_t b) { return u53(a, b); }
+template <>
+__device__ __forceinline__ float uflight<float>(uint32_t a, uint32_t) {
+  return (float)(a >> 8) * (1.0f / 16777216.0f);
+}
+__device__ __forceinline__ double log_r(double v) { return log(v); }
+__device__ __forceinline__ float log_r(float v) { return logf(v); }
+
 __device__ __forceinline__ uint32_t rank_below(uint64_t m) {
   return (uint32_t)__popcll(m & __lanemask_lt());
 }
@@ -146,11 +159,11 @@ __device__ inline void flush_tallies(const Lds &L, int I, int nc, int b, double 
 }
 
 template <typename Real>
-__device__ inline void store_record(const Bank<Real> &bk, int64_t k, double x, double mu, double w,
+__device__ inline void store_record(const Bank<Real> &bk, int64_t k, Real x, Real mu, double w,
                                     uint64_t lin, uint32_t src, uint32_t e, int32_t cell) {
   XMu<Real> xm;
-  xm.x = (Real)x;
-  xm.mu = (Real)mu;
+  xm.x = x;
+  xm.mu = mu;
   bk.xm[k] = xm;
   bk.w[k] = w;
   bk.lin[k] = lin;
@@ -167,7 +180,7 @@ __device__ inline void store_record(const Bank<Real> &bk, int64_t k, double x, d
 // group's own segment; what does not fit goes to the shared overflow.
 template <typename Real>
 __device__ inline void census_append(const Bank<Real> &bk, const BankGeom &G, uint32_t *ccnt, uint32_t *ovfcnt_b,
-                                     int64_t region_b0, int nc, int j, bool mine, int c, double x, double mu,
+                                     int64_t region_b0, int nc, int j, bool mine, int c, Real x, Real mu,
                                      double w, uint64_t lin, uint32_t src, uint32_t e, int32_t cell,
                                      uint32_t *err) {
   const int lane = (int)__lane_id();
@@ -246,10 +259,13 @@ __global__ void __launch_bounds__(1024) sweep_kernel(SweepArgs<Real> A) {
 
   const uint32_t lane = __lane_id();
   const double v = A.v;
+  const Real v_r = (Real)A.v, inv_v_r = (Real)A.inv_v, dt_r = (Real)A.dt;
   const int64_t dstride = A.dcap;
 
-  // Lane state.
-  double x = 0.0, mu = 0.0, w = 0.0, tau = 0.0;
+  // Lane state: position, direction and remaining time in the flight
+  // precision, weight in FP64.
+  Real x = 0, mu = 0, tau = 0;
+  double w = 0.0;
   int32_t cell = 0;
   uint32_t src = 0, e = 0;
   uint64_t lin = 0;
@@ -284,12 +300,12 @@ __global__ void __launch_bounds__(1024) sweep_kernel(SweepArgs<Real> A) {
         if (slot >= (uint64_t)A.dcap) break;
         const int64_t k = qb + (int64_t)slot;
         XMu<Real> xm;
-        xm.x = (Real)x;
-        xm.mu = (Real)mu;
+        xm.x = x;
+        xm.mu = mu;
         A.dq.xm[k] = xm;
         WTau wt;
         wt.w = w;
-        wt.tau = tau;
+        wt.tau = (double)tau;
         A.dq.wt[k] = wt;
         A.dq.lin[k] = lin_base + q;
         Tag tg;
@@ -399,14 +415,14 @@ __global__ void __launch_bounds__(1024) sweep_kernel(SweepArgs<Real> A) {
             if (from_bank) {
               const XMu<Real> xm = A.in_bank.xm[k];
               const Tag tg = A.in_bank.tag[k];
-              x = (double)xm.x;
-              mu = (double)xm.mu;
+              x = xm.x;
+              mu = xm.mu;
               w = A.in_bank.w[k];
               lin = A.in_bank.lin[k];
               src = tg.src;
               e = tg.e;
               cell = tg.cell;
-              tau = A.dt;
+              tau = dt_r;
               active = true;
               C.histories += 1;
               ww_check(1, e, e, SLOT_START, false, 0.0);
@@ -414,10 +430,10 @@ __global__ void __launch_bounds__(1024) sweep_kernel(SweepArgs<Real> A) {
               const XMu<Real> xm = A.dq.xm[k];
               const WTau wt = A.dq.wt[k];
               const Tag tg = A.dq.tag[k];
-              x = (double)xm.x;
-              mu = (double)xm.mu;
+              x = xm.x;
+              mu = xm.mu;
               w = wt.w;
-              tau = wt.tau;
+              tau = (Real)wt.tau;
               lin = A.dq.lin[k];
               src = tg.src;
               e = tg.e;
@@ -441,75 +457,76 @@ __global__ void __launch_bounds__(1024) sweep_kernel(SweepArgs<Real> A) {
         const int i = cell;
         uint32_t r[4];
         draw(A.seed, A.key1, SLOT_FLIGHT, src, lin, e, r);
-        const double ua = u53(r[0], r[1]);
-        const double ub = u53(r[2], r[3]);
-        const CellData cd = A.cells[i];
+        const Real ua = uflight<Real>(r[0], r[1]);
+        const Real ub = uflight<Real>(r[2], r[3]);
+        const CellData<Real> cd = A.cells[i];
         // Exponential flight distance with mean free path 1/sigma_t.
-        const double d_coll = -log(1.0 - ua) * cd.inv_sig;
-        const double xl = cd.xl, xr = cd.xr;
-        double d_bnd;
-        if (mu > 0.0) d_bnd = (xr - x) / mu;
-        else if (mu < 0.0) d_bnd = (xl - x) / mu;
-        else d_bnd = __builtin_inf();
-        const double d_cen = v * tau;
+        const Real d_coll = -log_r((Real)1 - ua) * cd.inv_sig;
+        const Real xl = cd.xl, xr = cd.xr;
+        Real d_bnd;
+        if (mu > (Real)0) d_bnd = (xr - x) / mu;
+        else if (mu < (Real)0) d_bnd = (xl - x) / mu;
+        else d_bnd = (Real)__builtin_inf();
+        const Real d_cen = v_r * tau;
         int ev;
-        double l;
+        Real l;
         if (d_cen <= d_bnd && d_cen <= d_coll) { ev = 0; l = d_cen; }
         else if (d_bnd <= d_coll) { ev = 1; l = d_bnd; }
         else { ev = 2; l = d_coll; }
 
-        // Track-length tally of phi, J and K in cell i (Eq. phi-mc).
-        const double wl = w * l;
-        const double t1 = wl * mu;
+        // Track-length tally of phi, J and K in cell i (Eq. phi-mc), in FP64.
+        const double wl = w * (double)l;
+        const double t1 = wl * (double)mu;
         atomicAdd(&L.hist[i * 6 + 0], wl);
         atomicAdd(&L.hist[i * 6 + 1], t1);
-        atomicAdd(&L.hist[i * 6 + 2], t1 * mu);
+        atomicAdd(&L.hist[i * 6 + 2], t1 * (double)mu);
         atomicAdd(&L.trk[i], 1u);
         C.segments += 1;
         const uint32_t e_ev = e;
         e = e_ev + 1;
 
         if (ev == 0) {
-          double xn = x + mu * l;
+          Real xn = x + mu * l;
           if (xn < xl) xn = xl;
           if (xn > xr) xn = xr;
           x = xn;
           // The flight draw's second variate is unused at census: it picks
           // the chunk of the next step.
-          next_chunk = (int32_t)(ub * (double)nc);
+          next_chunk = (int32_t)(ub * (Real)nc);
           if (next_chunk >= nc) next_chunk = nc - 1;
           // Time-crossing tally at t^n (Eq. ct-mc): v*w per particle.
           const double vw = v * w;
-          const double c1 = vw * mu;
+          const double c1 = vw * (double)mu;
           atomicAdd(&L.hist[i * 6 + 3], vw);
           atomicAdd(&L.hist[i * 6 + 4], c1);
-          atomicAdd(&L.hist[i * 6 + 5], c1 * mu);
+          atomicAdd(&L.hist[i * 6 + 5], c1 * (double)mu);
           atomicAdd(&L.wnext[next_chunk], w);
           C.census += 1;
           at_census = true;
           active = false;
         } else {
-          tau = tau - l * A.inv_v;
+          tau = tau - l * inv_v_r;
           if (ev == 1) {
-            const bool out_l = (i == 0 && mu < 0.0);
-            const bool out_r = (i == I - 1 && mu > 0.0);
+            const bool out_l = (i == 0 && mu < (Real)0);
+            const bool out_r = (i == I - 1 && mu > (Real)0);
             if (out_l || out_r) {
               // Edge-crossing estimators at the domain faces (w f(mu)/|mu|).
-              const double am = fabs(mu);
+              const double mud = (double)mu;
+              const double am = fabs(mud);
               double *f = L.bnd + (out_l ? 0 : 3);
               atomicAdd(&f[0], w / am);
               atomicAdd(&f[1], w * (0.5 - am) / am);
-              atomicAdd(&f[2], w * (1.0 / 3.0 - mu * mu) / am);
+              atomicAdd(&f[2], w * (1.0 / 3.0 - mud * mud) / am);
               C.leaks += 1;
               active = false;
             } else {
-              if (mu > 0.0) { x = xr; cell = i + 1; }
+              if (mu > (Real)0) { x = xr; cell = i + 1; }
               else { x = xl; cell = i - 1; }
               C.crossings += 1;
               ww_check(0, e_ev, e, SLOT_EVENT, false, 0.0);
             }
           } else {
-            double xn = x + mu * l;
+            Real xn = x + mu * l;
             if (xn < xl) xn = xl;
             if (xn > xr) xn = xr;
             x = xn;
@@ -517,7 +534,7 @@ __global__ void __launch_bounds__(1024) sweep_kernel(SweepArgs<Real> A) {
             if (ub < cd.c) {
               uint32_t r1[4];
               draw(A.seed, A.key1, SLOT_EVENT, src, lin, e_ev, r1);
-              mu = 2.0 * u53(r1[0], r1[1]) - 1.0;
+              mu = (Real)2 * uflight<Real>(r1[0], r1[1]) - (Real)1;
               C.scatters += 1;
               ww_check(0, e_ev, e, SLOT_EVENT, true, u53(r1[2], r1[3]));
             } else {
@@ -588,7 +605,8 @@ __global__ void __launch_bounds__(1024) sweep_kernel(SweepArgs<Real> A) {
 // batch and of their step-1 chunk; their census moments are the step-1
 // initial condition.  Work-group (b, j) creates the sources s = b + B m,
 // m = j, j + K, j + 2K, ... into its own segments.
-__global__ void __launch_bounds__(1024) source_kernel(SourceArgs A, Bank<double> bank) {
+template <typename Real>
+__global__ void __launch_bounds__(1024) source_kernel(SourceArgs A, Bank<Real> bank) {
   extern __shared__ double lds_raw[];
   const int I = A.I, nc = A.nc;
   const BankGeom G = A.geom;
@@ -601,28 +619,29 @@ __global__ void __launch_bounds__(1024) source_kernel(SourceArgs A, Bank<double>
   const int64_t n_b = (A.n_src > b) ? (A.n_src - b + A.B - 1) / A.B : 0;  // sources of batch b
   const int64_t n_j = (n_b > jseg) ? (n_b - jseg + K - 1) / K : 0;           // of which this work-group's
   const int64_t rounds = (n_j + blockDim.x - 1) / blockDim.x;
+  const Real x0 = (Real)A.src_x;
   for (int64_t it = 0; it < rounds; ++it) {
     const int64_t mloc = it * blockDim.x + threadIdx.x;
     const bool live = mloc < n_j;
     const int64_t s = (int64_t)b + (int64_t)A.B * ((int64_t)jseg + (int64_t)K * mloc);
-    double mu = 0.0;
+    Real mu = 0;
     int32_t cell = 0, chunk = 0;
     if (live) {
       uint32_t r[4];
       draw(A.seed, A.key1, SLOT_BIRTH, (uint32_t)s, 0ull, 0u, r);
-      mu = 2.0 * u53(r[0], r[1]) - 1.0;
-      cell = find_cell(A.edges, I, A.src_x, mu);
-      chunk = (int32_t)(u53(r[2], r[3]) * (double)nc);
+      mu = (Real)2 * uflight<Real>(r[0], r[1]) - (Real)1;
+      cell = find_cell(A.edges, I, (double)x0, (double)mu);
+      chunk = (int32_t)(uflight<Real>(r[2], r[3]) * (Real)nc);
       if (chunk >= nc) chunk = nc - 1;
       const double vw = A.v * 1.0;
-      const double c1 = vw * mu;
+      const double c1 = vw * (double)mu;
       atomicAdd(&L.hist[cell * 6 + 3], vw);
       atomicAdd(&L.hist[cell * 6 + 4], c1);
-      atomicAdd(&L.hist[cell * 6 + 5], c1 * mu);
+      atomicAdd(&L.hist[cell * 6 + 5], c1 * (double)mu);
       atomicAdd(&L.wnext[chunk], 1.0);
     }
     census_append(bank, G, L.ccnt, &bank.ovfcnt[b * nc], (int64_t)(b * nc) * G.stride, nc, jseg, live, chunk,
-                  A.src_x, mu, 1.0, 0ull, (uint32_t)s, 0u, cell, A.err);
+                  x0, mu, 1.0, 0ull, (uint32_t)s, 0u, cell, A.err);
   }
   __syncthreads();
   if ((int)threadIdx.x < nc) {
@@ -674,29 +693,29 @@ static hipError_t allow_lds(const void *fn, size_t lds, size_t *done) {
   return hipSuccess;
 }
 
-hipError_t sweep_occupancy_f64(int block, size_t lds, int *blocks_per_cu) {
+template <typename Real>
+hipError_t launch_sweep(const SweepArgs<Real> &a, int grid, int block, size_t lds, hipStream_t s) {
   static size_t done = 64 * 1024;
-  hipError_t e = allow_lds(reinterpret_cast<const void *>(&sweep_kernel<double>), lds, &done);
+  hipError_t e = allow_lds(reinterpret_cast<const void *>(&sweep_kernel<Real>), lds, &done);
   if (e != hipSuccess) return e;
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, sweep_kernel<double>, block, lds);
-}
-
-hipError_t launch_sweep_f64(const SweepArgs<double> &a, int grid, int block, size_t lds, hipStream_t s) {
-  static size_t done = 64 * 1024;
-  hipError_t e = allow_lds(reinterpret_cast<const void *>(&sweep_kernel<double>), lds, &done);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(sweep_kernel<double>, dim3(grid), dim3(block), lds, s, a);
+  hipLaunchKernelGGL(sweep_kernel<Real>, dim3(grid), dim3(block), lds, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_source_f64(const SourceArgs &a, const Bank<double> &bank, int grid, int block, size_t lds,
-                             hipStream_t s) {
+template <typename Real>
+hipError_t launch_source(const SourceArgs &a, const Bank<Real> &bank, int grid, int block, size_t lds,
+                         hipStream_t s) {
   static size_t done = 64 * 1024;
-  hipError_t e = allow_lds(reinterpret_cast<const void *>(&source_kernel), lds, &done);
+  hipError_t e = allow_lds(reinterpret_cast<const void *>(&source_kernel<Real>), lds, &done);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(source_kernel, dim3(grid), dim3(block), lds, s, a, bank);
+  hipLaunchKernelGGL(source_kernel<Real>, dim3(grid), dim3(block), lds, s, a, bank);
   return hipGetLastError();
 }
+
+template hipError_t launch_sweep<double>(const SweepArgs<double> &, int, int, size_t, hipStream_t);
+template hipError_t launch_sweep<float>(const SweepArgs<float> &, int, int, size_t, hipStream_t);
+template hipError_t launch_source<double>(const SourceArgs &, const Bank<double> &, int, int, size_t, hipStream_t);
+template hipError_t launch_source<float>(const SourceArgs &, const Bank<float> &, int, int, size_t, hipStream_t);
 
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;

@@ -1,0 +1,104 @@
+"""FP32 flight arithmetic (positions, directions, distances in FP32; weights,
+tallies and the LOSM solve in FP64).  A different rounding gives a different
+realisation, so the checks are statistical: every tally within the batch
+standard deviation of the closed-form uncollided pulse solution and of the
+FP64 oracle."""
+import numpy as np
+import pytest
+
+import closed_forms as CF
+from gpu_common import need_gpu, oracle_opts, oracle_sim, say
+from oracle import oracle as O
+from paper_2512_19925_amd import hww as H
+from paper_2512_19925_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _z(per_batch_a, per_batch_b=None, exact=None):
+    ta = per_batch_a.sum(0)
+    sa = CF.batch_sigma(per_batch_a)
+    if per_batch_b is not None:
+        tb = per_batch_b.sum(0)
+        sb = CF.batch_sigma(per_batch_b)
+        s = np.sqrt(sa ** 2 + sb ** 2)
+        d = ta - tb
+    else:
+        s, d = sa, ta - exact
+    m = s > 0
+    return d[m] / s[m]
+
+
+def test_fp32_uncollided_closed_form():
+    need_gpu()
+    w = W.homogeneous("fp32-c0", -3.0, 3.0, 60, 1.0, 0.0, dt=0.25, n_steps=8, n_src=200000, rho=2.0,
+                      eps_min=0.05, bank_capacity=20_000_000)
+    say(f"case {w.name}")
+    h = H.Handle(H.spec_from_workload(w, precision=H.HWW_FP32))
+    edges = w.edges
+    dx = np.diff(edges)
+    zs = []
+
+    def on_step(n, hh, _):
+        cells = hh.read_tallies(H.TALLY_CELLS)
+        t0, t1 = (n - 1) * w.dt, n * w.dt
+        ex_t = np.array([CF.uncollided_cell_time_avg(edges[i], edges[i + 1], t0, t1, 1.0, 1.0) for i in range(60)])
+        ex_c = np.array([CF.uncollided_cell_avg(edges[i], edges[i + 1], t1, 1.0, 1.0) for i in range(60)])
+        for k in range(3):
+            zs.append(_z(cells[..., k] / (w.n_src * dx * w.dt), exact=ex_t[:, k]))
+            zs.append(_z(cells[..., 3 + k] / (w.n_src * dx), exact=ex_c[:, k]))
+
+    H.run(h, w, on_step=on_step, stats=False)
+    z = np.concatenate(zs)
+    say(f"  {len(z)} tallies, mean z^2 {np.mean(z ** 2):.3f}, max |z| {np.abs(z).max():.2f}")
+    assert len(z) > 500
+    assert 0.7 < np.mean(z ** 2) < 1.5
+    assert np.abs(z).max() < 6.0
+
+
+def test_fp32_against_fp64_oracle():
+    # Independent seeds: the FP32 GPU run and the FP64 oracle run estimate
+    # the same expected tallies of the plain hybrid-WW problem.
+    need_gpu()
+    w = W.plain_small().with_(n_src=40000, n_steps=10, bank_capacity=2_000_000)
+    say(f"case {w.name} fp32 vs fp64 oracle")
+    h = H.Handle(H.spec_from_workload(w.with_(seed=7), precision=H.HWW_FP32))
+    g_steps = []
+    H.run(h, w, on_step=lambda n, hh, _: g_steps.append(hh.read_tallies(H.TALLY_CELLS)), stats=False)
+    sim = oracle_sim(w)
+    o_steps = []
+    O.run(sim, w.n_steps, oracle_opts(w), lambda n, s: o_steps.append(s.tallies()[0].copy()))
+    zs = []
+    worst_rel = 0.0
+    for g, o in zip(g_steps, o_steps):
+        for k in (0, 2, 3, 5):
+            zs.append(_z(g[..., k], o[..., k]))
+        tg, to = g[..., 0].sum(0), o[..., 0].sum(0)
+        m = to > 0.01 * to.max()
+        worst_rel = max(worst_rel, float(np.max(np.abs(tg[m] - to[m]) / to[m])))
+    z = np.concatenate(zs)
+    say(f"  {len(z)} tallies, mean z^2 {np.mean(z ** 2):.3f}, max |z| {np.abs(z).max():.2f}, "
+        f"max relative error of track phi (cells above 1% of peak) {worst_rel:.3e}")
+    assert len(z) > 200
+    assert 0.6 < np.mean(z ** 2) < 1.6
+    assert np.abs(z).max() < 6.5
+
+
+def test_fp32_scattering_moments():
+    # Analog FP32 histories: census-bank moments against the closed-form
+    # spatial moments of the pulse (c = 0.9, t = 1.5).
+    need_gpu()
+    w = W.homogeneous("fp32-mom", -20.0, 20.0, 200, 1.0, 0.9, dt=0.1, n_steps=15, n_src=400000,
+                      analog=True)
+    h = H.Handle(H.spec_from_workload(w, precision=H.HWW_FP32))
+    H.run(h, w, stats=False)
+    b = h.read_bank(1)
+    N = w.n_src
+    ex = dict(zip(("m0", "k", "xj", "x2"), CF.moments(0.9, 1.5)))
+    vals = {"m0": b["w"], "k": b["w"] * b["mu"] ** 2, "xj": b["w"] * b["x"] * b["mu"], "x2": b["w"] * b["x"] ** 2}
+    for name, v in vals.items():
+        full = np.zeros(N)
+        full[b["src"]] = v
+        se = full.std() / np.sqrt(N)
+        say(f"  {name}: {full.mean():.6f} vs {ex[name]:.6f} (se {se:.2e})")
+        assert abs(full.mean() - ex[name]) < 4.5 * se
