@@ -828,3 +828,124 @@ int orc_get_bank(const orc_sim *s, int32_t which, double *x, double *mu, double 
   }
   return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Deterministic LOSM march with frozen closures and its adjoint             */
+/* ------------------------------------------------------------------------ */
+
+/* Matrix coefficients of one LOSM step (rows as in orc_losm_step) for given
+ * cross sections: sub-diagonal a, diagonal b, super-diagonal c.  Also the
+ * coefficients of the old-time unknowns in the right-hand side: row r of
+ * the right-hand side is ba[r] u_{r-1} + bb[r] u_r + bc[r] u_{r+1} plus the
+ * closure terms. */
+static void losm_coeffs(int I, const double *edges, const double *sig_t, const double *sig_s, double v,
+                        double dt, double th, double *a, double *b, double *c, double *ba, double *bb,
+                        double *bc) {
+  const int n = 2 * I + 3;
+  const double inv_vdt = 1.0 / (v * dt);
+  for (int r = 0; r < n; ++r) { a[r] = b[r] = c[r] = ba[r] = bb[r] = bc[r] = 0.0; }
+  b[0] = 0.5; c[0] = 1.0;
+  a[n - 1] = 1.0; b[n - 1] = -0.5;
+  for (int i = 1; i <= I; ++i) {
+    const int r = 2 * i;
+    const double dx = edges[i] - edges[i - 1];
+    const double sa = sig_t[i - 1] - sig_s[i - 1];
+    a[r] = -th; b[r] = dx * inv_vdt + th * sa * dx; c[r] = th;
+    /* dx/(v dt) phi_i + (th-1)(J_i - J_{i-1} + sa dx phi_i) */
+    ba[r] = -(th - 1.0); bb[r] = dx * inv_vdt + (th - 1.0) * sa * dx; bc[r] = (th - 1.0);
+  }
+  for (int j = 0; j <= I; ++j) {
+    const int r = 2 * j + 1;
+    const double dxl = j >= 1 ? edges[j] - edges[j - 1] : 0.0;
+    const double dxr = j <= I - 1 ? edges[j + 1] - edges[j] : 0.0;
+    const double stl = j >= 1 ? sig_t[j - 1] : 0.0;
+    const double str = j <= I - 1 ? sig_t[j] : 0.0;
+    const double dxh = 0.5 * (dxr + dxl);
+    const double sh = (stl * dxl + str * dxr) / (dxl + dxr);
+    a[r] = -th / 3.0; b[r] = dxh * inv_vdt + th * sh * dxh; c[r] = th / 3.0;
+    /* dxh/(v dt) J_j + (th-1)((phi_{j+1} - phi_j)/3 + sh dxh J_j) */
+    ba[r] = -(th - 1.0) / 3.0; bb[r] = dxh * inv_vdt + (th - 1.0) * sh * dxh; bc[r] = (th - 1.0) / 3.0;
+  }
+}
+
+int orc_losm_march(int32_t I, const double *edges, const double *sig_t, const double *sig_s, double v,
+                   double dt, double th, int32_t n_steps, const double *F, const double *P,
+                   const double *phi0, const double *J0, double *phi_hist, double *J_hist) {
+  const int M = I + 2;
+  memcpy(phi_hist, phi0, sizeof(double) * M);
+  memcpy(J_hist, J0, sizeof(double) * (I + 1));
+  for (int n = 1; n <= n_steps; ++n) {
+    int rc = orc_losm_step(I, edges, sig_t, sig_s, v, dt, th, phi_hist + (size_t)(n - 1) * M,
+                           J_hist + (size_t)(n - 1) * (I + 1), F + (size_t)(n - 1) * M, F + (size_t)n * M,
+                           P[2 * n], P[2 * n + 1], 0.0, 0.0, NULL, NULL, phi_hist + (size_t)n * M,
+                           J_hist + (size_t)n * (I + 1));
+    if (rc) return rc;
+  }
+  return 0;
+}
+
+/* Gradient of G = sum_n sum_i w[n][i] phi_i^n with respect to sigma_t and
+ * sigma_s of every cell, for the march above (adjoint method):
+ *   A lambda^n = ... is replaced by A^T lambda^n = dG/du^n + B^T lambda^{n+1},
+ *   dG/dp = - sum_n lambda^n . (dA/dp u^n - dB/dp u^{n-1}).
+ * A depends on sigma through the balance diagonal (theta Sigma_a dx) and the
+ * first-moment diagonal (theta Sigma_hat dx_hat, where Sigma_hat dx_hat =
+ * (sigma_t,left dx_left + sigma_t,right dx_right)/2); B through the same
+ * terms times (theta - 1). */
+int orc_losm_adjoint(int32_t I, const double *edges, const double *sig_t, const double *sig_s, double v,
+                     double dt, double th, int32_t n_steps, const double *phi_hist, const double *J_hist,
+                     const double *w, double *g_t, double *g_s) {
+  const int n = 2 * I + 3, M = I + 2;
+  double *a = calloc(n, sizeof(double)), *b = calloc(n, sizeof(double)), *c = calloc(n, sizeof(double));
+  double *ba = calloc(n, sizeof(double)), *bb = calloc(n, sizeof(double)), *bc = calloc(n, sizeof(double));
+  double *at = calloc(n, sizeof(double)), *ct = calloc(n, sizeof(double));
+  double *rhs = calloc(n, sizeof(double)), *lam = calloc(n, sizeof(double)), *lam_next = calloc(n, sizeof(double));
+  double *u = calloc(n, sizeof(double)), *uo = calloc(n, sizeof(double));
+  int rc = 0;
+  if (!a || !b || !c || !ba || !bb || !bc || !at || !ct || !rhs || !lam || !lam_next || !u || !uo) { rc = -1; goto done; }
+  losm_coeffs(I, edges, sig_t, sig_s, v, dt, th, a, b, c, ba, bb, bc);
+  /* A^T: sub-diagonal of row r is c[r-1], super-diagonal is a[r+1]. */
+  for (int r = 0; r < n; ++r) {
+    at[r] = r > 0 ? c[r - 1] : 0.0;
+    ct[r] = r < n - 1 ? a[r + 1] : 0.0;
+  }
+  for (int i = 0; i < I; ++i) { g_t[i] = 0.0; g_s[i] = 0.0; }
+  for (int r = 0; r < n; ++r) lam_next[r] = 0.0;
+  for (int s = n_steps; s >= 1; --s) {
+    /* dG/du^s: weights on the phi entries. */
+    for (int r = 0; r < n; ++r) rhs[r] = 0.0;
+    for (int i = 0; i < M; ++i) rhs[2 * i] = w[(size_t)s * M + i];
+    /* + B^T lambda^{s+1}: column q of B collects rows q-1, q, q+1. */
+    if (s < n_steps) {
+      for (int q = 0; q < n; ++q) {
+        double acc = bb[q] * lam_next[q];
+        if (q + 1 < n) acc += ba[q + 1] * lam_next[q + 1];
+        if (q - 1 >= 0) acc += bc[q - 1] * lam_next[q - 1];
+        rhs[q] += acc;
+      }
+    }
+    rc = orc_thomas(n, at, b, ct, rhs, lam);
+    if (rc) goto done;
+    /* u^s and u^{s-1} in interleaved order. */
+    for (int i = 0; i < M; ++i) { u[2 * i] = phi_hist[(size_t)s * M + i]; uo[2 * i] = phi_hist[(size_t)(s - 1) * M + i]; }
+    for (int j = 0; j <= I; ++j) { u[2 * j + 1] = J_hist[(size_t)s * (I + 1) + j]; uo[2 * j + 1] = J_hist[(size_t)(s - 1) * (I + 1) + j]; }
+    for (int i = 1; i <= I; ++i) {
+      const double dx = edges[i] - edges[i - 1];
+      /* balance row 2i: d/d sigma_a of (A u - B u_old) = th dx phi_i - (th-1) dx phi_i^old */
+      const double db = th * dx * u[2 * i] - (th - 1.0) * dx * uo[2 * i];
+      g_t[i - 1] -= lam[2 * i] * db;
+      g_s[i - 1] += lam[2 * i] * db;
+      /* first-moment rows of the edges i-1 and i: d(Sigma_hat dx_hat)/d sigma_t,i = dx/2 */
+      for (int e = i - 1; e <= i; ++e) {
+        const int r = 2 * e + 1;
+        const double dm = th * 0.5 * dx * u[r] - (th - 1.0) * 0.5 * dx * uo[r];
+        g_t[i - 1] -= lam[r] * dm;
+      }
+    }
+    for (int r = 0; r < n; ++r) lam_next[r] = lam[r];
+  }
+done:
+  free(a); free(b); free(c); free(ba); free(bb); free(bc); free(at); free(ct);
+  free(rhs); free(lam); free(lam_next); free(u); free(uo);
+  return rc;
+}

@@ -90,6 +90,16 @@ int orc_losm_step(int32_t I, const double *edges, const double *sig_t, const dou
                   const double *q_old /* I or NULL */, const double *q_new /* I or NULL */,
                   double *phi_new /* I+2 */, double *J_new /* I+1 */);
 int orc_thomas(int32_t n, const double *a, const double *b, const double *c, const double *d, double *x);
+/* March of n_steps fully implicit LOSM steps with frozen closures F
+ * ((n_steps+1) x (I+2)) and P ((n_steps+1) x 2: P_L, P_R) from phi0, J0;
+ * phi_hist (n_steps+1) x (I+2), J_hist (n_steps+1) x (I+1). */
+int orc_losm_march(int32_t I, const double *edges, const double *sig_t, const double *sig_s, double v,
+                   double dt, double theta, int32_t n_steps, const double *F, const double *P,
+                   const double *phi0, const double *J0, double *phi_hist, double *J_hist);
+/* Gradient of G = sum w[n][i] phi_hist[n][i] with respect to sigma_t, sigma_s. */
+int orc_losm_adjoint(int32_t I, const double *edges, const double *sig_t, const double *sig_s, double v,
+                     double dt, double theta, int32_t n_steps, const double *phi_hist, const double *J_hist,
+                     const double *w, double *g_t, double *g_s);
 void orc_ma_filter(const double *in, int32_t M, int32_t k, double *out);
 int orc_ww_centres(int32_t I, const double *phi_tilde, double eps_min, double scale, double *ww);
 

@@ -64,6 +64,10 @@ def lib():
         L.orc_losm_step.argtypes = ([C.c_int32, dp, dp, dp, C.c_double, C.c_double, C.c_double]
                                     + [dp] * 4 + [C.c_double] * 4 + [dp] * 4)
         L.orc_thomas.argtypes = [C.c_int32, dp, dp, dp, dp, dp]
+        L.orc_losm_march.argtypes = ([C.c_int32, dp, dp, dp, C.c_double, C.c_double, C.c_double, C.c_int32]
+                                     + [dp] * 6)
+        L.orc_losm_adjoint.argtypes = ([C.c_int32, dp, dp, dp, C.c_double, C.c_double, C.c_double, C.c_int32]
+                                       + [dp] * 5)
         L.orc_ma_filter.argtypes = [dp, C.c_int32, C.c_int32, dp]
         L.orc_ww_centres.argtypes = [C.c_int32, dp, C.c_double, C.c_double, dp]
         _lib = L
@@ -143,6 +147,33 @@ def losm_step(edges, sig_t, sig_s, speed, dt, theta, phi_old, J_old, F_old, F_ne
         _dp(phi_old), _dp(J_old), _dp(F_old), _dp(F_new), float(PL), float(PR), float(JL), float(JR),
         _dp(q_old), _dp(q_new), _dp(phi), _dp(J)))
     return phi, J
+
+
+def losm_march(edges, sig_t, sig_s, speed, dt, theta, F, P, phi0, J0):
+    """Fully implicit LOSM march with frozen closures F[n] (I+2), P[n] (2)."""
+    edges, sig_t, sig_s, F, P, phi0, J0 = map(_f64, (edges, sig_t, sig_s, F, P, phi0, J0))
+    I = len(sig_t)
+    N = F.shape[0] - 1
+    assert F.shape == (N + 1, I + 2) and P.shape == (N + 1, 2)
+    phi = np.zeros((N + 1, I + 2))
+    J = np.zeros((N + 1, I + 1))
+    _check("losm_march", lib().orc_losm_march(I, _dp(edges), _dp(sig_t), _dp(sig_s), float(speed), float(dt),
+                                              float(theta), N, _dp(F), _dp(P), _dp(phi0), _dp(J0), _dp(phi),
+                                              _dp(J)))
+    return phi, J
+
+
+def losm_adjoint(edges, sig_t, sig_s, speed, dt, theta, phi_hist, J_hist, weights):
+    """Gradient of sum(weights * phi_hist) with respect to sigma_t, sigma_s."""
+    edges, sig_t, sig_s, phi_hist, J_hist, weights = map(_f64, (edges, sig_t, sig_s, phi_hist, J_hist, weights))
+    I = len(sig_t)
+    N = phi_hist.shape[0] - 1
+    gt = np.zeros(I)
+    gs = np.zeros(I)
+    _check("losm_adjoint", lib().orc_losm_adjoint(I, _dp(edges), _dp(sig_t), _dp(sig_s), float(speed), float(dt),
+                                                  float(theta), N, _dp(phi_hist), _dp(J_hist), _dp(weights),
+                                                  _dp(gt), _dp(gs)))
+    return gt, gs
 
 
 # --------------------------------------------------------------------------
