@@ -145,6 +145,33 @@ int hww_read_run_stats(hww_handle *h, hww_step_stats *stats);
  * J_out: I+1 host doubles (edge currents) or NULL. */
 int hww_solve_losm(hww_handle *h, const hww_losm_opts *opts, double *phi_out, double *J_out);
 
+/* Closures and initial condition that the finished step hands to the next
+ * (Sec. 3): F (I+2: face values and cell averages of F = phi/3 - K at the
+ * time layer), P (2: P_L, P_R of the step, from the face tallies), phi (I+2)
+ * and J (I+1: edge currents by linear interpolation of the cell averages).
+ * Unfiltered, normalised per source particle.  Needs a finished step (or
+ * step 0: the source).  Synchronises the stream. */
+int hww_read_closures(hww_handle *h, double *F, double *P, double *phi, double *J);
+
+/* Deterministic LOSM march (Sec. 3 Eqs. losm-disc, fully implicit theta
+ * scheme) of n_steps <= problem n_steps steps with frozen closures F[n]
+ * ((n_steps+1) x (I+2)) and P[n] ((n_steps+1) x 2), from phi0 (I+2), J0
+ * (I+1), with the per-cell cross sections sigma_t, sigma_s (I each, any
+ * positive values; they need not equal the problem's).  Returns
+ * G = sum_{n,i} weights[n][i] phi_i^n in *G and, if the pointers are not
+ * NULL, the histories phi_hist ((n_steps+1) x (I+2)) and J_hist
+ * ((n_steps+1) x (I+1)).  The march state stays in the workspace for
+ * hww_losm_adjoint.  All arrays are host memory.  Synchronises. */
+int hww_losm_march(hww_handle *h, const double *sigma_t, const double *sigma_s, double theta, int32_t n_steps,
+                   const double *F, const double *P, const double *phi0, const double *J0, const double *weights,
+                   double *phi_hist, double *J_hist, double *G);
+
+/* Gradient of the G of the last hww_losm_march with respect to sigma_t and
+ * sigma_s of every cell (I host doubles each), by the adjoint of the
+ * discretised march: transposed solves backward in time.  I <= 4096.
+ * Errors: HWW_E_STATE without a preceding march.  Synchronises. */
+int hww_losm_adjoint(hww_handle *h, double *grad_sigma_t, double *grad_sigma_s);
+
 /* Copy a tally array of the current step to host memory (raw per-batch sums,
  * not normalised: track sums are w*l, census sums v*w, face sums w f(mu)/|mu|).
  * out_bytes must equal the size of the kind.  Synchronises the stream. */

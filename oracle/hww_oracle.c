@@ -762,6 +762,35 @@ int orc_solve_losm(orc_sim *s, const orc_losm_opts *o, double *phi_out, double *
   return rc;
 }
 
+/* Closures and initial condition that the finished step hands to the next
+ * (Sec. 3): unfiltered F, P_L, P_R, phi, J from the census and face tallies
+ * of the step, exactly as the semi-implicit solve forms them. */
+int orc_get_closures(const orc_sim *s, double *F, double *P, double *phi, double *J) {
+  if (!s || !F || !P || !phi || !J) return -1;
+  if (s->next_chunk != s->n_chunks) return -2;
+  const int I = s->I;
+  double *buf = (double *)calloc((size_t)3 * I, sizeof(double));
+  if (!buf) return -1;
+  grid_fns g = {buf, buf + I, buf + 2 * I, {0}, {0}, {0}};
+  grid_from(s, &s->cur, 0, 1.0, &g);
+  phi[0] = g.fphi[0];
+  phi[I + 1] = g.fphi[1];
+  for (int i = 1; i <= I; ++i) phi[i] = g.phi[i - 1];
+  for (int i = 1; i <= I - 1; ++i) {
+    double dl = s->edges[i] - s->edges[i - 1], dr = s->edges[i + 1] - s->edges[i];
+    J[i] = (dr * g.J[i - 1] + dl * g.J[i]) / (dl + dr);
+  }
+  J[0] = -0.5 * phi[0] + g.fP[0];
+  J[I] = 0.5 * phi[I + 1] - g.fP[1];
+  F[0] = g.fF[0];
+  F[I + 1] = g.fF[1];
+  for (int i = 1; i <= I; ++i) F[i] = g.phi[i - 1] / 3.0 - g.K[i - 1];
+  P[0] = g.fP[0];
+  P[1] = g.fP[1];
+  free(buf);
+  return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Accessors                                                                 */
 /* ------------------------------------------------------------------------ */

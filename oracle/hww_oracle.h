@@ -69,6 +69,9 @@ int orc_set_batch_mask(orc_sim *s, const uint8_t *mask);
 int orc_set_windows(orc_sim *s, const double *centre, double rho);
 int orc_sweep_chunk(orc_sim *s, int32_t step, int32_t chunk);
 int orc_solve_losm(orc_sim *s, const orc_losm_opts *o, double *phi_out, double *J_out);
+/* Unfiltered closures F (I+2), P (2) and initial condition phi (I+2), J (I+1)
+ * that the finished step hands to the next. */
+int orc_get_closures(const orc_sim *s, double *F, double *P, double *phi, double *J);
 
 /* Raw per-batch sums: cur = 1 current step, 0 previous step. */
 int orc_get_tallies(const orc_sim *s, int32_t cur, double *cells /* B*I*6 */, double *bnd /* B*2*3 */);

@@ -53,6 +53,7 @@ def lib():
         L.orc_set_windows.argtypes = [C.c_void_p, dp, C.c_double]
         L.orc_sweep_chunk.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
         L.orc_solve_losm.argtypes = [C.c_void_p, C.c_void_p, dp, dp]
+        L.orc_get_closures.argtypes = [C.c_void_p, dp, dp, dp, dp]
         L.orc_get_tallies.argtypes = [C.c_void_p, C.c_int32, dp, dp]
         L.orc_get_counters.argtypes = [C.c_void_p, C.POINTER(C.c_uint64)]
         L.orc_get_tracks.argtypes = [C.c_void_p, C.POINTER(C.c_uint64)]
@@ -260,6 +261,12 @@ class OracleSim:
         J = np.zeros(self.I + 1)
         _check("solve_losm", lib().orc_solve_losm(self._h, C.byref(o), _dp(phi), _dp(J)))
         return phi, J
+
+    def closures(self):
+        F, P = np.zeros(self.I + 2), np.zeros(2)
+        phi, J = np.zeros(self.I + 2), np.zeros(self.I + 1)
+        _check("closures", lib().orc_get_closures(self._h, _dp(F), _dp(P), _dp(phi), _dp(J)))
+        return F, P, phi, J
 
     # -- reads --------------------------------------------------------------
     def tallies(self, cur=True):

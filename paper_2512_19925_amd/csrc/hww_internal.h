@@ -138,10 +138,27 @@ struct LosmArgs {
   double *factor;                 // [3][2I+3] LU factors of the system for `theta`
   int32_t refactor;               // 1: (re)compute the factors first
   int32_t work_in_lds;            // set by the launcher: grid functions fit in LDS
+  int32_t export_only;            // 1: write phi^{n-1}, J^{n-1}, F^{n-1}, P^{n-1} and stop
+  double *F_out, *P_out;          // I+2, 2 (device) for export_only
   Window *win;                    // [I] window centres, ceilings, floors
   double *phi_out, *J_out;        // I+2, I+1 (device)
   uint32_t *err;
   int32_t *status;                // 0 ok, else error bits of this solve
+};
+
+// Deterministic LOSM march and its adjoint (one work-group each).
+struct MarchArgs {
+  int32_t I, n_steps;
+  double v, dt, theta;
+  const double *edges, *sig_t, *sig_s;  // cross sections of the march
+  const double *F, *P;                  // (n_steps+1) x (I+2), (n_steps+1) x 2
+  const double *phi0, *J0;              // I+2, I+1
+  const double *w;                      // (n_steps+1) x (I+2) functional weights on phi
+  double *factor, *factor_t;            // 3 (2I+3) each: factors of A and A^T
+  double *hist;                         // (n_steps+1) x (2I+3) interleaved u^n
+  double *G;                            // functional value
+  double *g_t, *g_s;                    // I each
+  uint32_t *err;
 };
 
 // Dynamic LDS of the sweep and source kernels: [I][6] + nc + 6 doubles for
@@ -162,5 +179,7 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);
 hipError_t launch_rotate_chunks(double *wstart, double *wnext, int nc, hipStream_t s);
 hipError_t launch_begin_step(const BeginStepArgs &a, hipStream_t s);
+hipError_t launch_march(const MarchArgs &a, hipStream_t s);
+hipError_t launch_adjoint(const MarchArgs &a, hipStream_t s);
 
 }  // namespace hww

@@ -18,65 +18,19 @@
 //      affine recurrence, as a parallel scan over the work-group
 //   6. sets the window centres s [(max(phi,0)/max phi)(1-eps) + eps],
 //      ceiling and floor (Sec. 2 Eq. ww-c&f).
-#include "hww_internal.h"
+#include "hww_losm_dev.h"
 
 namespace hww {
 
 static constexpr int LOSM_THREADS = 1024;
 
-// Row r of the matrix: sub-diagonal a, diagonal b, super-diagonal c.
-__device__ inline void losm_row(const LosmArgs &A, int r, double th, double inv_vdt, double *a, double *b,
-                                double *c) {
-  const int I = A.I, n = 2 * I + 3;
-  if (r == 0) {  // left boundary relation phi_0/2 + J_0 = 2 J_L + P_L
-    *a = 0.0; *b = 0.5; *c = 1.0;
-  } else if (r == n - 1) {  // right boundary relation J_I - phi_{I+1}/2 = 2 J_R - P_R
-    *a = 1.0; *b = -0.5; *c = 0.0;
-  } else if ((r & 1) == 0) {  // balance over cell i = r/2
-    const int i = r / 2;
-    const double dx = A.edges[i] - A.edges[i - 1];
-    const double sa = A.sig_t[i - 1] - A.sig_s[i - 1];
-    *a = -th;
-    *b = dx * inv_vdt + th * sa * dx;
-    *c = th;
-  } else {  // first moment over the half cells around edge i = (r-1)/2
-    const int i = (r - 1) / 2;
-    const double dxl = (i >= 1) ? A.edges[i] - A.edges[i - 1] : 0.0;
-    const double dxr = (i <= I - 1) ? A.edges[i + 1] - A.edges[i] : 0.0;
-    const double stl = (i >= 1) ? A.sig_t[i - 1] : 0.0;
-    const double str = (i <= I - 1) ? A.sig_t[i] : 0.0;
-    const double dxh = 0.5 * (dxr + dxl);
-    const double sh = (stl * dxl + str * dxr) / (dxl + dxr);
-    *a = -th / 3.0;
-    *b = dxh * inv_vdt + th * sh * dxh;
-    *c = th / 3.0;
-  }
-}
-
-// Thomas factors for the forward recurrence d'_i = d_i/den_i + alpha_i d'_{i-1}
-// (alpha_i = -a_i/den_i) and the backward one x_i = d'_i + gamma_i x_{i+1}
-// (gamma_i = -c_i/den_i), den_i = b_i - a_i c_{i-1}/den_{i-1}.
-// factor = [alpha | 1/den | gamma], each 2I+3 long.  One lane; runs once per theta.
+// Thomas factors of the solve matrix for A.theta.  One lane; runs once per theta.
 __global__ void losm_factor_kernel(LosmArgs A) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const int n = 2 * A.I + 3;
-  const double th = A.theta;
   const double inv_vdt = 1.0 / (A.v * A.dt);
-  double *alpha = A.factor, *inv = A.factor + n, *gamma = A.factor + 2 * n;
-  double cp = 0.0;
-  for (int r = 0; r < n; ++r) {
-    double a, b, c;
-    losm_row(A, r, th, inv_vdt, &a, &b, &c);
-    const double den = (r == 0) ? b : b - a * cp;
-    if (den == 0.0 || !isfinite(den)) {
-      atomicOr(A.err, ERR_NUMERIC);
-      *A.status = (int)ERR_NUMERIC;
-      return;
-    }
-    cp = (r < n - 1) ? c / den : 0.0;
-    alpha[r] = (r == 0) ? 0.0 : -a / den;
-    inv[r] = 1.0 / den;
-    gamma[r] = -cp;
+  if (!losm_factor_seq(A.I, A.edges, A.sig_t, A.sig_s, A.theta, inv_vdt, false, A.factor)) {
+    atomicOr(A.err, ERR_NUMERIC);
+    *A.status = (int)ERR_NUMERIC;
   }
 }
 
@@ -88,30 +42,6 @@ __device__ void ma_filter_dev(const double *in, double *out, int M, int k) {
     double acc = 0.0;
     for (int l = -km; l <= km; ++l) acc += in[m - l - 1];
     out[m - 1] = acc / (double)(2 * km + 1);
-  }
-}
-
-// Inclusive scan of affine maps y -> p + q y across the work-group (thread
-// order), Hillis-Steele in LDS.  On return (P, Q) of thread t compose the
-// maps of threads 0..t (later maps applied last).
-__device__ void affine_scan(double *sp, double *sq, double &P, double &Q) {
-  const int t = threadIdx.x;
-  sp[t] = P;
-  sq[t] = Q;
-  __syncthreads();
-  for (int o = 1; o < (int)blockDim.x; o <<= 1) {
-    double pp = 0.0, qq = 1.0;
-    const bool has = t >= o;
-    if (has) { pp = sp[t - o]; qq = sq[t - o]; }
-    __syncthreads();
-    if (has) {
-      // this map after the earlier one: y -> P + Q (pp + qq y)
-      P = P + Q * pp;
-      Q = Q * qq;
-      sp[t] = P;
-      sq[t] = Q;
-    }
-    __syncthreads();
   }
 }
 
@@ -281,6 +211,20 @@ __global__ void __launch_bounds__(LOSM_THREADS) losm_kernel(LosmArgs A) {
   }
   __syncthreads();
 
+  if (A.export_only) {
+    // Closures and initial condition of the finished step, unfiltered.
+    for (int i = tid; i <= I + 1; i += T) {
+      A.phi_out[i] = phi_o[i];
+      A.F_out[i] = F_o[i];
+    }
+    for (int i = tid; i <= I; i += T) A.J_out[i] = J_o[i];
+    if (tid == 0) {
+      A.P_out[0] = PL;
+      A.P_out[1] = PR;
+    }
+    return;
+  }
+
   // 3. moving-average filter.
   if (A.filter == 1) {
     double *arrs[3] = {F_n + 1, F_o + 1, phi_o + 1};
@@ -299,71 +243,12 @@ __global__ void __launch_bounds__(LOSM_THREADS) losm_kernel(LosmArgs A) {
   // 4. right-hand side.
   const double th = A.theta;
   const double inv_vdt = 1.0 / (A.v * A.dt);
-  for (int r = tid; r < n; r += T) {
-    double d;
-    if (r == 0) {
-      d = PL;
-    } else if (r == n - 1) {
-      d = -PR;
-    } else if ((r & 1) == 0) {
-      const int i = r / 2;
-      const double dx = A.edges[i] - A.edges[i - 1];
-      const double sa = A.sig_t[i - 1] - A.sig_s[i - 1];
-      d = dx * inv_vdt * phi_o[i] + (th - 1.0) * (J_o[i] - J_o[i - 1] + sa * dx * phi_o[i]);
-    } else {
-      const int i = (r - 1) / 2;
-      const double dxl = (i >= 1) ? A.edges[i] - A.edges[i - 1] : 0.0;
-      const double dxr = (i <= I - 1) ? A.edges[i + 1] - A.edges[i] : 0.0;
-      const double stl = (i >= 1) ? A.sig_t[i - 1] : 0.0;
-      const double str = (i <= I - 1) ? A.sig_t[i] : 0.0;
-      const double dxh = 0.5 * (dxr + dxl);
-      const double sh = (stl * dxl + str * dxr) / (dxl + dxr);
-      d = dxh * inv_vdt * J_o[i] + th * (F_n[i + 1] - F_n[i])
-        + (th - 1.0) * ((phi_o[i + 1] - phi_o[i]) / 3.0 + sh * dxh * J_o[i] - (F_o[i + 1] - F_o[i]));
-    }
-    u[r] = d;
-  }
+  for (int r = tid; r < n; r += T)
+    u[r] = losm_rhs(I, A.edges, A.sig_t, A.sig_s, th, inv_vdt, r, phi_o, J_o, F_o, F_n, PL, PR);
   __syncthreads();
 
   // 5. substitutions as parallel scans of affine recurrences.
-  const double *alpha = A.factor, *inv = A.factor + n, *gamma = A.factor + 2 * n;
-  const int m = (n + T - 1) / T;
-  const int r0 = tid * m, r1 = min(r0 + m, n);
-  {
-    double P = 0.0, Q = 1.0;  // composite map of this thread's rows
-    for (int r = r0; r < r1; ++r) {
-      const double al = alpha[r];
-      P = u[r] * inv[r] + al * P;
-      Q = al * Q;
-    }
-    affine_scan(sp, sq, P, Q);
-    double y = (tid == 0) ? 0.0 : sp[tid - 1];  // d' of the row before this thread's first
-    for (int r = r0; r < r1; ++r) {
-      y = u[r] * inv[r] + alpha[r] * y;
-      u[r] = y;
-    }
-  }
-  __syncthreads();
-  {
-    // backward: thread t takes the mirrored block so that the scan runs from the end
-    const int tb = T - 1 - tid;
-    const int b0 = tb * m, b1 = min(b0 + m, n);
-    double P = 0.0, Q = 1.0;
-    for (int r = b1 - 1; r >= b0; --r) {
-      const double g = (r == n - 1) ? 0.0 : gamma[r];
-      P = u[r] + g * P;
-      Q = g * Q;
-    }
-    affine_scan(sp, sq, P, Q);
-    double y = (tid == 0) ? 0.0 : sp[tid - 1];  // x of the row after this block
-    __syncthreads();
-    for (int r = b1 - 1; r >= b0; --r) {
-      const double g = (r == n - 1) ? 0.0 : gamma[r];
-      y = u[r] + g * y;
-      u[r] = y;
-    }
-  }
-  __syncthreads();
+  losm_solve_scans(u, n, A.factor, sp, sq);
   for (int i = tid; i <= I + 1; i += T) A.phi_out[i] = u[2 * i];
   for (int i = tid; i <= I; i += T) A.J_out[i] = u[2 * i + 1];
 

@@ -1,0 +1,190 @@
+// Device building blocks of the LOSM solves (Sec. 3, Eqs. losm-0, losm-1,
+// losm-disc-bc): matrix and old-time coefficients of the interleaved
+// tridiagonal system [phi_0, J_0, phi_1, J_1, ..., J_I, phi_{I+1}], its
+// Thomas factors, and the substitutions as parallel scans of affine
+// recurrences over one work-group.
+#pragma once
+
+#include "hww_internal.h"
+
+namespace hww {
+
+// Row r of the matrix: sub-diagonal a, diagonal b, super-diagonal c.
+// The half-cell cross section at edge j averages the two cells touching it.
+__device__ inline void losm_row(int I, const double *edges, const double *sig_t, const double *sig_s, double th,
+                                double inv_vdt, int r, double *a, double *b, double *c) {
+  const int n = 2 * I + 3;
+  if (r == 0) {  // left boundary relation phi_0/2 + J_0 = 2 J_L + P_L
+    *a = 0.0; *b = 0.5; *c = 1.0;
+  } else if (r == n - 1) {  // right boundary relation J_I - phi_{I+1}/2 = 2 J_R - P_R
+    *a = 1.0; *b = -0.5; *c = 0.0;
+  } else if ((r & 1) == 0) {  // balance over cell i = r/2
+    const int i = r / 2;
+    const double dx = edges[i] - edges[i - 1];
+    const double sa = sig_t[i - 1] - sig_s[i - 1];
+    *a = -th;
+    *b = dx * inv_vdt + th * sa * dx;
+    *c = th;
+  } else {  // first moment over the half cells around edge j = (r-1)/2
+    const int j = (r - 1) / 2;
+    const double dxl = (j >= 1) ? edges[j] - edges[j - 1] : 0.0;
+    const double dxr = (j <= I - 1) ? edges[j + 1] - edges[j] : 0.0;
+    const double stl = (j >= 1) ? sig_t[j - 1] : 0.0;
+    const double str = (j <= I - 1) ? sig_t[j] : 0.0;
+    const double dxh = 0.5 * (dxr + dxl);
+    const double sh = (stl * dxl + str * dxr) / (dxl + dxr);
+    *a = -th / 3.0;
+    *b = dxh * inv_vdt + th * sh * dxh;
+    *c = th / 3.0;
+  }
+}
+
+// Coefficients of the old-time unknowns in row r of the right-hand side:
+// d_r = ba u_{r-1} + bb u_r + bc u_{r+1} + closure terms.
+__device__ inline void losm_brow(int I, const double *edges, const double *sig_t, const double *sig_s, double th,
+                                 double inv_vdt, int r, double *ba, double *bb, double *bc) {
+  const int n = 2 * I + 3;
+  if (r == 0 || r == n - 1) {
+    *ba = 0.0; *bb = 0.0; *bc = 0.0;
+  } else if ((r & 1) == 0) {
+    const int i = r / 2;
+    const double dx = edges[i] - edges[i - 1];
+    const double sa = sig_t[i - 1] - sig_s[i - 1];
+    *ba = -(th - 1.0);
+    *bb = dx * inv_vdt + (th - 1.0) * sa * dx;
+    *bc = (th - 1.0);
+  } else {
+    const int j = (r - 1) / 2;
+    const double dxl = (j >= 1) ? edges[j] - edges[j - 1] : 0.0;
+    const double dxr = (j <= I - 1) ? edges[j + 1] - edges[j] : 0.0;
+    const double stl = (j >= 1) ? sig_t[j - 1] : 0.0;
+    const double str = (j <= I - 1) ? sig_t[j] : 0.0;
+    const double dxh = 0.5 * (dxr + dxl);
+    const double sh = (stl * dxl + str * dxr) / (dxl + dxr);
+    *ba = -(th - 1.0) / 3.0;
+    *bb = dxh * inv_vdt + (th - 1.0) * sh * dxh;
+    *bc = (th - 1.0) / 3.0;
+  }
+}
+
+// Right-hand side of row r from the old state (phi_o [I+2], J_o [I+1]), the
+// closures at the old and new time (F_o, F_n [I+2]) and P_L, P_R.
+__device__ inline double losm_rhs(int I, const double *edges, const double *sig_t, const double *sig_s, double th,
+                                  double inv_vdt, int r, const double *phi_o, const double *J_o, const double *F_o,
+                                  const double *F_n, double PL, double PR) {
+  const int n = 2 * I + 3;
+  if (r == 0) return PL;
+  if (r == n - 1) return -PR;
+  if ((r & 1) == 0) {
+    const int i = r / 2;
+    const double dx = edges[i] - edges[i - 1];
+    const double sa = sig_t[i - 1] - sig_s[i - 1];
+    return dx * inv_vdt * phi_o[i] + (th - 1.0) * (J_o[i] - J_o[i - 1] + sa * dx * phi_o[i]);
+  }
+  const int j = (r - 1) / 2;
+  const double dxl = (j >= 1) ? edges[j] - edges[j - 1] : 0.0;
+  const double dxr = (j <= I - 1) ? edges[j + 1] - edges[j] : 0.0;
+  const double stl = (j >= 1) ? sig_t[j - 1] : 0.0;
+  const double str = (j <= I - 1) ? sig_t[j] : 0.0;
+  const double dxh = 0.5 * (dxr + dxl);
+  const double sh = (stl * dxl + str * dxr) / (dxl + dxr);
+  return dxh * inv_vdt * J_o[j] + th * (F_n[j + 1] - F_n[j])
+       + (th - 1.0) * ((phi_o[j + 1] - phi_o[j]) / 3.0 + sh * dxh * J_o[j] - (F_o[j + 1] - F_o[j]));
+}
+
+// Thomas factors of the matrix (or of its transpose) for the forward
+// recurrence d'_r = d_r/den_r + alpha_r d'_{r-1} and the backward one
+// x_r = d'_r + gamma_r x_{r+1}: factor = [alpha | 1/den | gamma], each n long.
+// One lane.  Returns false on a zero or non-finite pivot.
+__device__ inline bool losm_factor_seq(int I, const double *edges, const double *sig_t, const double *sig_s,
+                                       double th, double inv_vdt, bool transpose, double *factor) {
+  const int n = 2 * I + 3;
+  double *alpha = factor, *inv = factor + n, *gamma = factor + 2 * n;
+  double cp = 0.0;
+  double a_next, b_next, c_next;
+  losm_row(I, edges, sig_t, sig_s, th, inv_vdt, 0, &a_next, &b_next, &c_next);
+  double c_prev = 0.0;
+  for (int r = 0; r < n; ++r) {
+    const double a = a_next, b = b_next, c = c_next;
+    if (r + 1 < n) losm_row(I, edges, sig_t, sig_s, th, inv_vdt, r + 1, &a_next, &b_next, &c_next);
+    // transpose: sub-diagonal of row r is c_{r-1}, super-diagonal is a_{r+1}
+    const double sub = transpose ? c_prev : a;
+    const double sup = transpose ? (r + 1 < n ? a_next : 0.0) : c;
+    c_prev = c;
+    const double den = (r == 0) ? b : b - sub * cp;
+    if (den == 0.0 || !isfinite(den)) return false;
+    cp = (r < n - 1) ? sup / den : 0.0;
+    alpha[r] = (r == 0) ? 0.0 : -sub / den;
+    inv[r] = 1.0 / den;
+    gamma[r] = -cp;
+  }
+  return true;
+}
+
+// Inclusive scan of affine maps y -> p + q y across the work-group (thread
+// order), Hillis-Steele in LDS.  On return (P, Q) of thread t compose the
+// maps of threads 0..t (later maps applied last).
+__device__ inline void affine_scan(double *sp, double *sq, double &P, double &Q) {
+  const int t = threadIdx.x;
+  sp[t] = P;
+  sq[t] = Q;
+  __syncthreads();
+  for (int o = 1; o < (int)blockDim.x; o <<= 1) {
+    double pp = 0.0, qq = 1.0;
+    const bool has = t >= o;
+    if (has) { pp = sp[t - o]; qq = sq[t - o]; }
+    __syncthreads();
+    if (has) {
+      P = P + Q * pp;
+      Q = Q * qq;
+      sp[t] = P;
+      sq[t] = Q;
+    }
+    __syncthreads();
+  }
+}
+
+// Solve with the factors, in place: u holds the right-hand side on entry
+// and the solution on return (all threads of the work-group call this).
+__device__ inline void losm_solve_scans(double *u, int n, const double *factor, double *sp, double *sq) {
+  const double *alpha = factor, *inv = factor + n, *gamma = factor + 2 * n;
+  const int T = blockDim.x, tid = threadIdx.x;
+  const int m = (n + T - 1) / T;
+  {
+    const int r0 = tid * m, r1 = min(r0 + m, n);
+    double P = 0.0, Q = 1.0;
+    for (int r = r0; r < r1; ++r) {
+      const double al = alpha[r];
+      P = u[r] * inv[r] + al * P;
+      Q = al * Q;
+    }
+    affine_scan(sp, sq, P, Q);
+    double y = (tid == 0) ? 0.0 : sp[tid - 1];
+    for (int r = r0; r < r1; ++r) {
+      y = u[r] * inv[r] + alpha[r] * y;
+      u[r] = y;
+    }
+  }
+  __syncthreads();
+  {
+    const int tb = T - 1 - tid;  // mirrored block: the scan runs from the end
+    const int b0 = tb * m, b1 = min(b0 + m, n);
+    double P = 0.0, Q = 1.0;
+    for (int r = b1 - 1; r >= b0; --r) {
+      const double g = (r == n - 1) ? 0.0 : gamma[r];
+      P = u[r] + g * P;
+      Q = g * Q;
+    }
+    affine_scan(sp, sq, P, Q);
+    double y = (tid == 0) ? 0.0 : sp[tid - 1];
+    __syncthreads();
+    for (int r = b1 - 1; r >= b0; --r) {
+      const double g = (r == n - 1) ? 0.0 : gamma[r];
+      y = u[r] + g * y;
+      u[r] = y;
+    }
+  }
+  __syncthreads();
+}
+
+}  // namespace hww

@@ -30,6 +30,9 @@ struct Layout {
   int64_t off_bank[2], off_segcnt[2], off_ovfcnt[2], off_q;
   int64_t off_tal[2], off_bnd[2], off_tracks, off_counters, off_wstart, off_wnext;
   int64_t off_cursor, off_err, off_status, off_scratch, off_factor, off_phi_out, off_J_out;
+  int64_t off_F_out, off_P_out;
+  int64_t off_m_sig, off_m_F, off_m_P, off_m_phi0, off_m_J0, off_m_w, off_m_hist, off_m_fac, off_m_fact, off_m_G,
+      off_m_g;
 };
 
 int64_t align_up(int64_t v) { return (v + 255) & ~int64_t(255); }
@@ -110,6 +113,21 @@ void make_layout(const hww_problem &p, Layout *L) {
   L->off_factor = c.take(8 * 3 * (2 * I + 3));
   L->off_phi_out = c.take(8 * (I + 2));
   L->off_J_out = c.take(8 * (I + 1));
+  L->off_F_out = c.take(8 * (I + 2));
+  L->off_P_out = c.take(8 * 2);
+  // Deterministic march of up to n_steps steps and its adjoint.
+  const int64_t N1 = (int64_t)p.n_steps + 1, n = 2 * I + 3;
+  L->off_m_sig = c.take(8 * 2 * I);
+  L->off_m_F = c.take(8 * N1 * (I + 2));
+  L->off_m_P = c.take(8 * N1 * 2);
+  L->off_m_phi0 = c.take(8 * (I + 2));
+  L->off_m_J0 = c.take(8 * (I + 1));
+  L->off_m_w = c.take(8 * N1 * (I + 2));
+  L->off_m_hist = c.take(8 * N1 * n);
+  L->off_m_fac = c.take(8 * 3 * n);
+  L->off_m_fact = c.take(8 * 3 * n);
+  L->off_m_G = c.take(8);
+  L->off_m_g = c.take(8 * 2 * I);
   L->total = c.cur;
 }
 
@@ -184,6 +202,8 @@ struct hww_handle {
   int n_launch = 0;            // sweep launches of the current step
   int step_ev0 = 0;            // first event pair of the current step
   std::vector<hipEvent_t> ev;  // start/stop pairs of every sweep launch since init
+  MarchArgs march{};           // last deterministic march (its state stays in the workspace)
+  int march_ok = 0;
   int ev_used = 0;             // pairs recorded
   int ev_summed = 0;           // pairs already added into ms_summed
   double ms_summed = 0.0;
@@ -615,6 +635,104 @@ int hww_solve_losm(hww_handle *h, const hww_losm_opts *o, double *phi_out, doubl
     return poll_errors(h);
   }
   return HWW_OK;
+}
+
+int hww_read_closures(hww_handle *h, double *F, double *P, double *phi, double *J) {
+  if (!h || !F || !P || !phi || !J) return HWW_E_INVALID_ARG;
+  if (h->fatal) return fail(h, h->fatal, "an earlier error left the problem invalid");
+  if (h->next_chunk != h->nc) return fail(h, HWW_E_STATE, "closures need a finished step");
+  LosmArgs a{};
+  a.I = h->I; a.B = h->B; a.nc = h->nc;
+  a.v = h->p.speed; a.dt = h->p.dt; a.n_src = (double)h->p.n_src;
+  a.edges = h->edges; a.sig_t = h->sig_t; a.sig_s = h->sig_s;
+  a.tal_ic = h->tal[h->cur_tal]; a.bnd_ic = h->bnd[h->cur_tal];
+  a.tal_cl = a.tal_ic; a.bnd_cl = a.bnd_ic;
+  a.wstart = h->wstart; a.wnext = h->wnext; a.next_chunk = h->next_chunk;
+  a.theta = h->factor_theta > 0.0 ? h->factor_theta : 0.5;
+  a.implicit = 0; a.filter = 0; a.apply_windows = 0;
+  a.scratch = h->scratch; a.factor = h->factor;
+  a.refactor = (a.theta != h->factor_theta) ? 1 : 0;
+  a.win = h->win;
+  a.phi_out = h->phi_out; a.J_out = h->J_out; a.err = h->err; a.status = h->status;
+  a.export_only = 1;
+  a.F_out = reinterpret_cast<double *>(h->ws + h->L.off_F_out);
+  a.P_out = reinterpret_cast<double *>(h->ws + h->L.off_P_out);
+  if (a.refactor) HIPCHK(h, launch_fill_u32(reinterpret_cast<uint32_t *>(h->status), 0u, 1, h->stream));
+  HIPCHK(h, launch_losm(a, h->stream));
+  h->factor_theta = a.theta;
+  const int I = h->I;
+  HIPCHK(h, hipMemcpyAsync(F, a.F_out, 8 * (size_t)(I + 2), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipMemcpyAsync(P, a.P_out, 16, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipMemcpyAsync(phi, h->phi_out, 8 * (size_t)(I + 2), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipMemcpyAsync(J, h->J_out, 8 * (size_t)(I + 1), hipMemcpyDeviceToHost, h->stream));
+  return poll_errors(h);
+}
+
+int hww_losm_march(hww_handle *h, const double *sigma_t, const double *sigma_s, double theta, int32_t n_steps,
+                   const double *F, const double *P, const double *phi0, const double *J0, const double *weights,
+                   double *phi_hist, double *J_hist, double *G) {
+  if (!h || !sigma_t || !sigma_s || !F || !P || !phi0 || !J0 || !weights || !G) return HWW_E_INVALID_ARG;
+  if (n_steps < 1 || n_steps > h->p.n_steps) return fail(h, HWW_E_INVALID_ARG, "n_steps out of range");
+  if (!(theta > 0.0 && theta <= 1.0)) return fail(h, HWW_E_INVALID_ARG, "theta must be in (0, 1]");
+  const int I = h->I;
+  for (int i = 0; i < I; ++i)
+    if (!(sigma_t[i] > 0.0) || !(sigma_s[i] >= 0.0) || !std::isfinite(sigma_t[i]) || !std::isfinite(sigma_s[i]))
+      return fail(h, HWW_E_INVALID_ARG, "march cross sections must be positive and finite");
+  const Layout &L = h->L;
+  char *ws = h->ws;
+  MarchArgs &a = h->march;
+  a = MarchArgs{};
+  a.I = I; a.n_steps = n_steps; a.v = h->p.speed; a.dt = h->p.dt; a.theta = theta;
+  a.edges = h->edges;
+  double *msig = reinterpret_cast<double *>(ws + L.off_m_sig);
+  a.sig_t = msig; a.sig_s = msig + I;
+  a.F = reinterpret_cast<double *>(ws + L.off_m_F);
+  a.P = reinterpret_cast<double *>(ws + L.off_m_P);
+  a.phi0 = reinterpret_cast<double *>(ws + L.off_m_phi0);
+  a.J0 = reinterpret_cast<double *>(ws + L.off_m_J0);
+  a.w = reinterpret_cast<double *>(ws + L.off_m_w);
+  a.hist = reinterpret_cast<double *>(ws + L.off_m_hist);
+  a.factor = reinterpret_cast<double *>(ws + L.off_m_fac);
+  a.factor_t = reinterpret_cast<double *>(ws + L.off_m_fact);
+  a.G = reinterpret_cast<double *>(ws + L.off_m_G);
+  a.g_t = reinterpret_cast<double *>(ws + L.off_m_g);
+  a.g_s = a.g_t + I;
+  a.err = h->err;
+  const size_t N1 = (size_t)n_steps + 1, M = (size_t)I + 2, n = 2 * (size_t)I + 3;
+  HIPCHK(h, hipMemcpyAsync(msig, sigma_t, 8 * I, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipMemcpyAsync(msig + I, sigma_s, 8 * I, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipMemcpyAsync(const_cast<double *>(a.F), F, 8 * N1 * M, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipMemcpyAsync(const_cast<double *>(a.P), P, 8 * N1 * 2, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipMemcpyAsync(const_cast<double *>(a.phi0), phi0, 8 * M, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipMemcpyAsync(const_cast<double *>(a.J0), J0, 8 * (M - 1), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipMemcpyAsync(const_cast<double *>(a.w), weights, 8 * N1 * M, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, launch_march(a, h->stream));
+  HIPCHK(h, hipMemcpyAsync(G, a.G, 8, hipMemcpyDeviceToHost, h->stream));
+  std::vector<double> hist;
+  if (phi_hist || J_hist) {
+    hist.resize(N1 * n);
+    HIPCHK(h, hipMemcpyAsync(hist.data(), a.hist, 8 * N1 * n, hipMemcpyDeviceToHost, h->stream));
+  }
+  int rc = poll_errors(h);
+  if (rc != HWW_OK) return rc;
+  for (size_t s = 0; s < N1; ++s) {
+    if (phi_hist)
+      for (size_t i = 0; i < M; ++i) phi_hist[s * M + i] = hist[s * n + 2 * i];
+    if (J_hist)
+      for (size_t j = 0; j + 1 < M; ++j) J_hist[s * (M - 1) + j] = hist[s * n + 2 * j + 1];
+  }
+  h->march_ok = 1;
+  return HWW_OK;
+}
+
+int hww_losm_adjoint(hww_handle *h, double *grad_sigma_t, double *grad_sigma_s) {
+  if (!h || !grad_sigma_t || !grad_sigma_s) return HWW_E_INVALID_ARG;
+  if (!h->march_ok) return fail(h, HWW_E_STATE, "the adjoint needs a preceding hww_losm_march");
+  if (h->I > 4 * 1024) return fail(h, HWW_E_INVALID_ARG, "the adjoint handles I <= 4096");
+  HIPCHK(h, launch_adjoint(h->march, h->stream));
+  HIPCHK(h, hipMemcpyAsync(grad_sigma_t, h->march.g_t, 8 * (size_t)h->I, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipMemcpyAsync(grad_sigma_s, h->march.g_s, 8 * (size_t)h->I, hipMemcpyDeviceToHost, h->stream));
+  return poll_errors(h);
 }
 
 int hww_read_tallies(hww_handle *h, int32_t kind, void *out, int64_t out_bytes) {

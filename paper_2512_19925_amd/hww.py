@@ -25,8 +25,8 @@ TALLY_CELLS, TALLY_BOUNDARY, TALLY_TRACKS, TALLY_PREV_CELLS, TALLY_PREV_BOUNDARY
 
 # Every symbol include/hww.h declares.
 EXPORTS = ["hww_workspace_bytes", "hww_init_problem", "hww_set_windows", "hww_sweep_step",
-           "hww_read_run_stats", "hww_solve_losm", "hww_read_tallies", "hww_read_bank", "hww_sync",
-           "hww_last_error", "hww_destroy"]
+           "hww_read_run_stats", "hww_solve_losm", "hww_read_closures", "hww_losm_march", "hww_losm_adjoint",
+           "hww_read_tallies", "hww_read_bank", "hww_sync", "hww_last_error", "hww_destroy"]
 
 
 class HwwError(RuntimeError):
@@ -81,6 +81,9 @@ def lib():
         L.hww_read_run_stats.argtypes = [vp, C.POINTER(StepStats)]
         L.hww_solve_losm.argtypes = [vp, C.POINTER(LosmOpts), dp, dp]
         L.hww_read_tallies.argtypes = [vp, C.c_int32, vp, C.c_int64]
+        L.hww_read_closures.argtypes = [vp, dp, dp, dp, dp]
+        L.hww_losm_march.argtypes = [vp, dp, dp, C.c_double, C.c_int32] + [dp] * 8
+        L.hww_losm_adjoint.argtypes = [vp, dp, dp]
         L.hww_read_bank.argtypes = [vp, C.c_int32, C.c_int64, C.POINTER(C.c_int64)] + [vp] * 8
         L.hww_sync.argtypes = [vp]
         L.hww_last_error.argtypes = [vp]
@@ -220,6 +223,31 @@ class Handle:
             *[out[k].ctypes.data for k in ("x", "mu", "w", "src", "lin", "e", "cell", "chunk")]))
         m = int(cnt.value)
         return {k: v[:m] for k, v in out.items()}
+
+    def read_closures(self):
+        """(F, P, phi, J) that the finished step hands to the next."""
+        F, P = np.zeros(self.I + 2), np.zeros(2)
+        phi, J = np.zeros(self.I + 2), np.zeros(self.I + 1)
+        self._check("hww_read_closures", lib().hww_read_closures(self._h, _dp(F), _dp(P), _dp(phi), _dp(J)))
+        return F, P, phi, J
+
+    def losm_march(self, sigma_t, sigma_s, theta, F, P, phi0, J0, weights, histories=False):
+        st, ss, F, P, phi0, J0, w = map(_f64, (sigma_t, sigma_s, F, P, phi0, J0, weights))
+        N = F.shape[0] - 1
+        assert st.shape == (self.I,) and ss.shape == (self.I,) and F.shape == (N + 1, self.I + 2)
+        assert P.shape == (N + 1, 2) and w.shape == F.shape
+        ph = np.zeros((N + 1, self.I + 2)) if histories else None
+        jh = np.zeros((N + 1, self.I + 1)) if histories else None
+        G = C.c_double()
+        self._check("hww_losm_march", lib().hww_losm_march(
+            self._h, _dp(st), _dp(ss), float(theta), N, _dp(F), _dp(P), _dp(phi0), _dp(J0), _dp(w),
+            _dp(ph), _dp(jh), C.byref(G)))
+        return (G.value, ph, jh) if histories else G.value
+
+    def losm_adjoint(self):
+        gt, gs = np.zeros(self.I), np.zeros(self.I)
+        self._check("hww_losm_adjoint", lib().hww_losm_adjoint(self._h, _dp(gt), _dp(gs)))
+        return gt, gs
 
     def sync(self):
         self._check("hww_sync", lib().hww_sync(self._h))

@@ -116,3 +116,15 @@ def adjoint_slab(seed: int = 1, n_src: int = 1_000_000) -> Workload:
 
 
 ADJOINT_CELLS = (600, 700)  # functional cells [600, 700)
+
+
+def adjoint_weights(w: Workload, n_steps: int, cells=ADJOINT_CELLS) -> np.ndarray:
+    """Weights of G = sum over cells [lo, hi) of the time integral of phi over
+    n_steps steps by the trapezoidal rule: w[n][1 + i] for cell i (the first
+    and last phi entries are the face values)."""
+    lo, hi = cells
+    W = np.zeros((n_steps + 1, w.n_cells + 2))
+    W[:, 1 + lo:1 + hi] = w.dt
+    W[0] *= 0.5
+    W[n_steps] *= 0.5
+    return W
