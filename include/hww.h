@@ -183,6 +183,61 @@ int hww_read_tallies(hww_handle *h, int32_t kind, void *out, int64_t out_bytes);
 int hww_read_bank(hww_handle *h, int32_t which, int64_t cap, int64_t *count, double *x, double *mu,
                   double *w, uint32_t *src, uint64_t *lin, uint32_t *e, int32_t *cell, int32_t *chunk);
 
+/* ---------------------------------------------------------------------------
+ * Batches of replicas.  Many independent problems of uneven size (mesh,
+ * cross sections, particle count, batch count) run as one handle: every
+ * sweep_step is one persistent launch over the work units (replica, batch,
+ * segment) of all replicas, biggest replicas first, and every solve_losm is
+ * one batched launch with one work-group per replica.  Each replica keeps
+ * the keying of its own problem (seed, replica), so its results equal those
+ * of a handle of its own up to the summation order of the tallies.
+ *
+ * On a batch handle:
+ *  - hww_set_windows takes the replicas' centres concatenated in replica
+ *    order (sum of I_r values), or NULL for analog;
+ *  - hww_solve_losm writes phi_out (sum of I_r+2) and J_out (sum of I_r+1)
+ *    concatenated in replica order;
+ *  - hww_read_tallies writes each replica's array of the kind, concatenated
+ *    in replica order (out_bytes = the sum of their sizes);
+ *  - hww_sweep_step / hww_read_run_stats sum the counters over replicas;
+ *  - hww_read_bank, hww_read_closures, hww_losm_march and hww_losm_adjoint
+ *    return an error: read one replica through hww_batch_replica.
+ * ------------------------------------------------------------------------- */
+
+/* Bytes of device workspace of a batch of n problems (< 0 on invalid input).
+ * All problems must share precision, n_chunks and n_steps; 1 <= n <= 65535. */
+int64_t hww_batch_workspace_bytes(const hww_problem *problems, int32_t n);
+
+/* Like hww_init_problem for n problems at once (each validated as there);
+ * builds every replica's source bank.  The handle is released with
+ * hww_destroy. */
+int hww_init_batch(const hww_problem *problems, int32_t n, void *dev_workspace, int64_t ws_bytes,
+                   void *hip_stream, hww_handle **out);
+
+/* Read-only view of replica r of a batch, owned by the batch (hww_destroy on
+ * it does nothing).  The read calls (hww_read_tallies, hww_read_bank,
+ * hww_read_closures, hww_sync, hww_last_error) act on that replica alone;
+ * the others return HWW_E_STATE. */
+int hww_batch_replica(hww_handle *batch, int32_t r, hww_handle **view);
+
+/* Launch shape of the sweep picked by hww_autotune. */
+typedef struct hww_tune_result {
+  int32_t block;   /* threads per work-group: 256, 512 or 1024                  */
+  int32_t tile;    /* particles a wavefront claims per refill: 64 .. 512        */
+  int32_t grid;    /* work-groups of a launch (batches: compute units x 1..4)   */
+  int32_t trials;  /* shapes measured                                            */
+  double ms;       /* best measured sweep time of the trial chunk              */
+} hww_tune_result;
+
+/* Measure the sweep of chunk 0 of step 1 under every launch shape (block
+ * size, tile size and, for batches, the persistent grid) twice, keep the
+ * fastest for every later sweep, and restore the state of step 0.  Must run
+ * before the first hww_sweep_step (windows may already be set).  The shape
+ * changes no result beyond the summation order of the tallies.
+ * Errors: HWW_E_STATE after the first sweep, HWW_E_CAPACITY if a trial
+ * overflows.  Synchronises. */
+int hww_autotune(hww_handle *h, hww_tune_result *best);
+
 /* Wait for the stream and report any pending device error. */
 int hww_sync(hww_handle *h);
 

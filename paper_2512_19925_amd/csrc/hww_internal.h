@@ -87,6 +87,7 @@ struct SweepArgs {
   const Window *win;       // [I]
   int32_t ww_on;
   int32_t chunk;
+  int32_t tile;            // start-bank / daughter tile a wave claims at a time
   BankGeom geom;
   Bank<Real> in_bank;
   Bank<Real> census;
@@ -99,6 +100,40 @@ struct SweepArgs {
   unsigned long long *tracks;      // [I]
   unsigned long long *counters;    // [2][C_NCOUNTERS]: this step, since init
   double *wnext;                   // [nc]
+  uint32_t *err;
+};
+
+// One replica of a batched problem: everything a sweep unit of the replica
+// needs, with both banks, both tally sets and both cursor sets; the launch
+// selects the current ones.
+template <typename Real>
+struct ReplicaDesc {
+  int32_t I, B, nc;
+  double v, inv_v, dt;
+  uint32_t seed, key1;
+  const CellData<Real> *cells;
+  const Window *win;
+  BankGeom geom;
+  Bank<Real> bank[2];
+  double *tal[2], *bnd[2];
+  unsigned long long *tracks, *counters;
+  double *wnext;
+  uint32_t *cursor;  // [2][B]
+};
+
+// Persistent launch over the work units (replica, batch, segment) of all
+// replicas: unit code = replica << 16 | batch << 8 | segment.
+template <typename Real>
+struct BatchSweepArgs {
+  const ReplicaDesc<Real> *desc;
+  const uint32_t *units;
+  uint32_t n_units;
+  uint32_t *work;      // [2] unit counters; launch parity `par` uses work[par]
+  int32_t par;         // cursor set and unit counter of this launch
+  int32_t start_bank;  // start bank and current tally set
+  int32_t chunk, ww_on, tile;
+  Queue<Real> dq;      // daughter buffers: 2 per work-group of the grid
+  int64_t dcap;
   uint32_t *err;
 };
 
@@ -146,6 +181,18 @@ struct LosmArgs {
   int32_t *status;                // 0 ok, else error bits of this solve
 };
 
+// One replica of a batched LOSM solve: its arguments with both tally sets;
+// the per-call options come from LosmCall.
+struct LosmReplica {
+  LosmArgs a;
+  const double *tal[2], *bnd[2];
+};
+struct LosmCall {
+  int32_t cur;  // current tally set
+  int32_t implicit, next_chunk, filter, ma_k, closure_track, apply_windows, export_only, refactor, work_in_lds;
+  double theta, eps_min, rho;
+};
+
 // Deterministic LOSM march and its adjoint (one work-group each).
 struct MarchArgs {
   int32_t I, n_steps;
@@ -174,7 +221,12 @@ hipError_t launch_sweep(const SweepArgs<Real> &a, int grid, int block, size_t ld
 template <typename Real>
 hipError_t launch_source(const SourceArgs &a, const Bank<Real> &bank, int grid, int block, size_t lds,
                          hipStream_t s);
+template <typename Real>
+hipError_t launch_sweep_batch(const BatchSweepArgs<Real> &a, int grid, int block, size_t lds, hipStream_t s);
 hipError_t launch_losm(const LosmArgs &a, hipStream_t s);
+hipError_t launch_losm_batch(const LosmReplica *tab, int n, int max_I, const LosmCall &c, hipStream_t s);
+size_t losm_batch_lds(int max_I, int *work_in_lds);
+hipError_t launch_begin_step_batch(const BeginStepArgs *tab, int n, int64_t max_tal, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);
 hipError_t launch_rotate_chunks(double *wstart, double *wnext, int nc, hipStream_t s);

@@ -25,13 +25,17 @@ namespace hww {
 static constexpr int LOSM_THREADS = 1024;
 
 // Thomas factors of the solve matrix for A.theta.  One lane; runs once per theta.
-__global__ void losm_factor_kernel(LosmArgs A) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ inline void losm_factor_body(const LosmArgs &A) {
   const double inv_vdt = 1.0 / (A.v * A.dt);
   if (!losm_factor_seq(A.I, A.edges, A.sig_t, A.sig_s, A.theta, inv_vdt, false, A.factor)) {
     atomicOr(A.err, ERR_NUMERIC);
     *A.status = (int)ERR_NUMERIC;
   }
+}
+
+__global__ void losm_factor_kernel(LosmArgs A) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  losm_factor_body(A);
 }
 
 __device__ void ma_filter_dev(const double *in, double *out, int M, int k) {
@@ -61,7 +65,7 @@ __device__ inline double closure_scale(const LosmArgs &A) {
 // initial-condition set (census phi, J, K) and of the closure set, and
 // normalise per source particle.  A work-group takes 64 cells; its four
 // waves each sum a quarter of the batches and combine through LDS.
-__global__ void __launch_bounds__(256) losm_reduce_kernel(LosmArgs A) {
+__device__ inline void losm_reduce_body(const LosmArgs &A, int blk) {
   const int I = A.I;
   const int M = I + 2;
   double *gi_phi = A.scratch + 5 * M;
@@ -71,7 +75,7 @@ __global__ void __launch_bounds__(256) losm_reduce_kernel(LosmArgs A) {
   double *gc_K = gc_phi + I;
   __shared__ double part[4][5][64];
   const double scale = closure_scale(A);
-  if (blockIdx.x == 0 && threadIdx.x < 12) {
+  if (blk == 0 && threadIdx.x < 12) {
     // Face values: q = (phi L, phi R, P L, P R, F L, F R) of the initial-
     // condition set (t < 6) and of the closure set (t >= 6).
     const int t = threadIdx.x;
@@ -85,7 +89,7 @@ __global__ void __launch_bounds__(256) losm_reduce_kernel(LosmArgs A) {
   }
   const int kc = A.closure_track ? 0 : 3;
   const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
-  const int i = blockIdx.x * 64 + lane;
+  const int i = blk * 64 + lane;
   double p = 0.0, j = 0.0, k = 0.0, cp = 0.0, ck = 0.0;
   if (i < I) {
 #pragma unroll 4
@@ -122,13 +126,14 @@ __global__ void __launch_bounds__(256) losm_reduce_kernel(LosmArgs A) {
   }
 }
 
-__global__ void __launch_bounds__(LOSM_THREADS) losm_kernel(LosmArgs A) {
+__global__ void __launch_bounds__(256) losm_reduce_kernel(LosmArgs A) { losm_reduce_body(A, (int)blockIdx.x); }
+
+__device__ __forceinline__ void losm_body(const LosmArgs &A, double *dyn) {
   const int I = A.I;
   const int M = I + 2;
   const int n = 2 * I + 3;
   const int tid = threadIdx.x;
   const int T = blockDim.x;
-  extern __shared__ double dyn[];
   double *u = dyn;  // [n] right-hand side, then solution
   // Working grid functions live in LDS when they fit, else in the global
   // scratch.
@@ -294,6 +299,93 @@ __global__ void __launch_bounds__(LOSM_THREADS) losm_kernel(LosmArgs A) {
   }
 }
 
+__global__ void __launch_bounds__(LOSM_THREADS) losm_kernel(LosmArgs A) {
+  extern __shared__ double dyn[];
+  losm_body(A, dyn);
+}
+
+// Batched solves: replica r of the table takes block r (factor, solve) or
+// row r of the grid (reduce); the call options are shared.
+__device__ inline LosmArgs losm_batch_args(const LosmReplica &R, const LosmCall &c) {
+  LosmArgs A = R.a;
+  if (!c.implicit) {
+    A.tal_ic = R.tal[c.cur]; A.bnd_ic = R.bnd[c.cur];
+    A.tal_cl = A.tal_ic; A.bnd_cl = A.bnd_ic;
+  } else {
+    A.tal_ic = R.tal[1 - c.cur]; A.bnd_ic = R.bnd[1 - c.cur];
+    A.tal_cl = R.tal[c.cur]; A.bnd_cl = R.bnd[c.cur];
+  }
+  A.next_chunk = c.next_chunk;
+  A.theta = c.theta;
+  A.implicit = c.implicit; A.filter = c.filter; A.ma_k = c.ma_k;
+  A.closure_track = c.closure_track; A.apply_windows = c.apply_windows;
+  A.eps_min = c.eps_min; A.rho = c.rho;
+  A.refactor = c.refactor; A.work_in_lds = c.work_in_lds; A.export_only = c.export_only;
+  return A;
+}
+
+__global__ void losm_factor_batch_kernel(const LosmReplica *tab, LosmCall c) {
+  if (threadIdx.x != 0) return;
+  const LosmArgs A = losm_batch_args(tab[blockIdx.x], c);
+  *A.status = 0;
+  losm_factor_body(A);
+}
+
+__global__ void __launch_bounds__(256) losm_reduce_batch_kernel(const LosmReplica *tab, LosmCall c) {
+  const LosmArgs A = losm_batch_args(tab[blockIdx.y], c);
+  if ((int)blockIdx.x * 64 >= A.I && blockIdx.x != 0) return;
+  losm_reduce_body(A, (int)blockIdx.x);
+}
+
+__global__ void __launch_bounds__(LOSM_THREADS) losm_batch_kernel(const LosmReplica *tab, LosmCall c) {
+  extern __shared__ double dyn[];
+  const LosmArgs A = losm_batch_args(tab[blockIdx.x], c);
+  losm_body(A, dyn);
+}
+
+// Dynamic LDS of a solve of I cells: the unknowns, and the working grid
+// functions when they fit beside the 16 KB of static LDS.
+static size_t losm_lds(int I, int *work_in_lds) {
+  const size_t lds_min = (size_t)(2 * I + 3) * sizeof(double);
+  const size_t lds_full = lds_min + (size_t)5 * (I + 2) * sizeof(double);
+  *work_in_lds = lds_full + 17 * 1024 <= 160 * 1024 ? 1 : 0;
+  return *work_in_lds ? lds_full : lds_min;
+}
+
+static hipError_t allow_losm_lds(const void *fn, size_t lds, size_t *done) {
+  if (lds > 32 * 1024 && lds > *done) {
+    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    *done = lds;
+  }
+  return hipSuccess;
+}
+
+size_t losm_batch_lds(int max_I, int *work_in_lds) { return losm_lds(max_I, work_in_lds); }
+
+hipError_t launch_losm_batch(const LosmReplica *tab, int n, int max_I, const LosmCall &c, hipStream_t s) {
+  if (c.refactor) {
+    hipLaunchKernelGGL(losm_factor_batch_kernel, dim3(n), dim3(64), 0, s, tab, c);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(losm_reduce_batch_kernel, dim3((max_I + 63) / 64, n), dim3(256), 0, s, tab, c);
+  {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  int wil = 0;
+  const size_t lds = losm_lds(max_I, &wil);
+  if (wil != c.work_in_lds) return hipErrorInvalidValue;
+  static size_t done = 0;
+  {
+    const hipError_t e = allow_losm_lds(reinterpret_cast<const void *>(&losm_batch_kernel), lds, &done);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(losm_batch_kernel, dim3(n), dim3(LOSM_THREADS), lds, s, tab, c);
+  return hipGetLastError();
+}
+
 hipError_t launch_losm(const LosmArgs &a, hipStream_t s) {
   if (a.refactor) {
     hipLaunchKernelGGL(losm_factor_kernel, dim3(1), dim3(64), 0, s, a);
@@ -306,17 +398,11 @@ hipError_t launch_losm(const LosmArgs &a, hipStream_t s) {
     if (e != hipSuccess) return e;
   }
   LosmArgs b = a;
-  const size_t lds_min = (size_t)(2 * a.I + 3) * sizeof(double);
-  const size_t lds_full = lds_min + (size_t)5 * (a.I + 2) * sizeof(double);
-  // 16 KB of static LDS for the scans and reductions.
-  b.work_in_lds = lds_full + 17 * 1024 <= 160 * 1024 ? 1 : 0;
-  const size_t lds = b.work_in_lds ? lds_full : lds_min;
+  const size_t lds = losm_lds(a.I, &b.work_in_lds);
   static size_t done = 0;
-  if (lds > 32 * 1024 && lds > done) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&losm_kernel),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  {
+    const hipError_t e = allow_losm_lds(reinterpret_cast<const void *>(&losm_kernel), lds, &done);
     if (e != hipSuccess) return e;
-    done = lds;
   }
   hipLaunchKernelGGL(losm_kernel, dim3(1), dim3(LOSM_THREADS), lds, s, b);
   return hipGetLastError();

@@ -20,7 +20,10 @@ namespace {
 
 constexpr double kSegSlack = 2.0;   // segment capacity / fair share of a work-group
 constexpr double kOvfShare = 0.5;   // overflow capacity / fair share of a region
-constexpr int kBlock = 512;         // threads per sweep work-group
+constexpr int kBlock = 512;         // threads per sweep work-group (default; see hww_autotune)
+constexpr int kTile = 256;          // particles a wave claims per tile (default)
+constexpr int64_t kUnitParticles = 2048;  // start particles per batched work unit and launch
+constexpr int kGridMax = 1024;      // work-groups of a batched launch at most
 
 struct Layout {
   int64_t total = 0;
@@ -63,11 +66,23 @@ int segments_per_batch(int I, int B, int nc) {
   return K;
 }
 
-void make_layout(const hww_problem &p, Layout *L) {
+// Segments per batch of a replica of a batched problem: about
+// kUnitParticles start particles per unit and launch.
+int member_segments(const hww_problem &p) {
+  const int64_t per = (int64_t)p.n_batches * p.n_chunks * kUnitParticles;
+  int64_t K = (p.n_src + per - 1) / per;
+  if (K < 1) K = 1;
+  if (K > 64) K = 64;
+  return (int)K;
+}
+
+// Workspace layout of one problem.  A replica of a batch (member = true)
+// has no daughter buffers (the batch's are shared) and no march arrays.
+void make_layout(const hww_problem &p, Layout *L, bool member = false) {
   const int64_t I = p.n_cells, B = p.n_batches, nc = p.n_chunks, R = B * nc;
   int64_t rb = 8;
   real_bytes(p.precision, &rb);
-  const int K = segments_per_batch((int)I, (int)B, (int)nc);
+  const int K = member ? member_segments(p) : segments_per_batch((int)I, (int)B, (int)nc);
   BankGeom &G = L->geom;
   G.K = K;
   const double share = (double)p.bank_capacity / (double)R;
@@ -76,7 +91,7 @@ void make_layout(const hww_problem &p, Layout *L) {
   G.stride = (int64_t)K * G.seg_cap + G.ovf_cap;
   L->dcap = std::max<int64_t>(4096, (p.bank_capacity + B * K - 1) / (B * K));
   const int64_t slots = R * G.stride;
-  const int64_t dslots = 2 * B * K * L->dcap;
+  const int64_t dslots = member ? 0 : 2 * B * K * L->dcap;
   Carver c;
   L->off_edges = c.take(8 * (I + 1));
   L->off_sigt = c.take(8 * I);
@@ -116,7 +131,7 @@ void make_layout(const hww_problem &p, Layout *L) {
   L->off_F_out = c.take(8 * (I + 2));
   L->off_P_out = c.take(8 * 2);
   // Deterministic march of up to n_steps steps and its adjoint.
-  const int64_t N1 = (int64_t)p.n_steps + 1, n = 2 * I + 3;
+  const int64_t N1 = member ? 0 : (int64_t)p.n_steps + 1, n = member ? 0 : 2 * I + 3;
   L->off_m_sig = c.take(8 * 2 * I);
   L->off_m_F = c.take(8 * N1 * (I + 2));
   L->off_m_P = c.take(8 * N1 * 2);
@@ -199,6 +214,26 @@ struct hww_handle {
   int fatal = 0;
   double factor_theta = -1.0;  // theta of the LU factors in the workspace
   size_t lds = 0;
+  int block = kBlock, tile = kTile, grid = 0;  // sweep launch shape (grid: batched launches)
+  int is_view = 0;             // a replica of a batch, for reads only
+  // Batch of replicas (is_batch): the replicas are handles of their own
+  // whose small per-replica arrays live in shared arrays of the batch.
+  int is_batch = 0;
+  std::vector<hww_handle *> rep;
+  int max_I = 0, max_K = 0, cus = 256;
+  uint32_t n_units = 0;
+  void *desc = nullptr;              // ReplicaDesc<Real>[n]
+  uint32_t *units = nullptr, *work = nullptr, *cursor_all = nullptr;
+  LosmReplica *losm_tab = nullptr;
+  BeginStepArgs *bs_tab = nullptr;   // [2][n]
+  double *phi_cat = nullptr, *J_cat = nullptr;
+  unsigned long long *counters_all = nullptr;
+  uint32_t *segcnt_all[2] = {nullptr, nullptr}, *ovfcnt_all[2] = {nullptr, nullptr};
+  int64_t n_seg_all = 0, n_ovf_all = 0, n_phi_all = 0, n_J_all = 0, n_cur_all = 0;
+  int64_t bdcap = 0;                 // daughter slots per buffer of a batched launch
+  Queue<double> bq;
+  Queue<float> bq32;
+  int losm_wil = 0;
   int n_launch = 0;            // sweep launches of the current step
   int step_ev0 = 0;            // first event pair of the current step
   std::vector<hipEvent_t> ev;  // start/stop pairs of every sweep launch since init
@@ -265,7 +300,10 @@ int census_total(hww_handle *h, int bank_idx, uint64_t *total) {
 
 // Read the device error word and the census occupancy; map them to an ABI
 // code.  Errors are sticky: the problem must be re-initialised.
+int poll_batch(hww_handle *h);
+
 int poll_errors(hww_handle *h) {
+  if (h->is_batch) return poll_batch(h);
   uint32_t e = 0;
   HIPCHK(h, hipMemcpyAsync(&e, h->err, 4, hipMemcpyDeviceToHost, h->stream));
   uint64_t cen = 0;
@@ -320,11 +358,30 @@ SweepArgs<Real> base_args(hww_handle *h) {
 
 template <typename Real>
 int launch_chunk(hww_handle *h, int chunk, int k) {
+  if (h->is_batch) {
+    BatchSweepArgs<Real> a{};
+    a.desc = reinterpret_cast<const ReplicaDesc<Real> *>(h->desc);
+    a.units = h->units;
+    a.n_units = h->n_units;
+    a.work = h->work;
+    a.par = k & 1;
+    a.start_bank = h->start_bank;
+    a.chunk = chunk;
+    a.ww_on = h->ww_on;
+    a.tile = h->tile;
+    if constexpr (sizeof(Real) == 8) a.dq = h->bq;
+    else a.dq = h->bq32;
+    a.dcap = h->bdcap;
+    a.err = h->err;
+    HIPCHK(h, launch_sweep_batch<Real>(a, h->grid, h->block, h->lds, h->stream));
+    return HWW_OK;
+  }
   SweepArgs<Real> a = base_args<Real>(h);
   a.chunk = chunk;
+  a.tile = h->tile;
   a.cursor = h->cursor + (k & 1) * h->B;
   a.cursor_next = h->cursor + ((k + 1) & 1) * h->B;
-  HIPCHK(h, launch_sweep<Real>(a, h->B * h->K, kBlock, h->lds, h->stream));
+  HIPCHK(h, launch_sweep<Real>(a, h->B * h->K, h->block, h->lds, h->stream));
   return HWW_OK;
 }
 
@@ -332,6 +389,347 @@ int zero_counts(hww_handle *h, int k) {
   HIPCHK(h, launch_fill_u32(h->bank[k].segcnt, 0u, (int64_t)h->R * h->K, h->stream));
   HIPCHK(h, launch_fill_u32(h->bank[k].ovfcnt, 0u, h->R, h->stream));
   return HWW_OK;
+}
+
+// Point the handle's arrays into its part of the workspace.
+void carve_handle(hww_handle *h, const hww_problem &problem, char *ws, const Layout &L, hipStream_t stream) {
+  h->p = problem;
+  h->p.edges = h->p.sigma_t = h->p.sigma_s = nullptr;
+  h->I = problem.n_cells;
+  h->B = problem.n_batches;
+  h->nc = problem.n_chunks;
+  h->R = h->B * h->nc;
+  h->L = L;
+  h->K = L.geom.K;
+  h->lds = sweep_lds_bytes(h->I, h->nc, h->K);
+  h->stream = stream;
+  h->ws = ws;
+  const int64_t slots = (int64_t)h->R * L.geom.stride;
+  h->edges = reinterpret_cast<double *>(ws + L.off_edges);
+  h->sig_t = reinterpret_cast<double *>(ws + L.off_sigt);
+  h->sig_s = reinterpret_cast<double *>(ws + L.off_sigs);
+  h->cells = reinterpret_cast<CellData<double> *>(ws + L.off_cells);
+  h->win = reinterpret_cast<Window *>(ws + L.off_win);
+  for (int k = 0; k < 2; ++k) {
+    h->bank[k] = bank_view<double>(ws, L.off_bank[k], L.off_segcnt[k], L.off_ovfcnt[k], slots);
+    h->bank32[k] = bank_view<float>(ws, L.off_bank[k], L.off_segcnt[k], L.off_ovfcnt[k], slots);
+    h->tal[k] = reinterpret_cast<double *>(ws + L.off_tal[k]);
+    h->bnd[k] = reinterpret_cast<double *>(ws + L.off_bnd[k]);
+  }
+  h->fp32 = problem.precision == HWW_FP32;
+  h->dq = queue_view<double>(ws, L.off_q, 2 * (int64_t)h->B * h->K * L.dcap);
+  h->dq32 = queue_view<float>(ws, L.off_q, 2 * (int64_t)h->B * h->K * L.dcap);
+  h->cells32 = reinterpret_cast<CellData<float> *>(ws + L.off_cells);
+  h->tracks = reinterpret_cast<unsigned long long *>(ws + L.off_tracks);
+  h->counters = reinterpret_cast<unsigned long long *>(ws + L.off_counters);
+  h->wstart = reinterpret_cast<double *>(ws + L.off_wstart);
+  h->wnext = reinterpret_cast<double *>(ws + L.off_wnext);
+  h->cursor = reinterpret_cast<uint32_t *>(ws + L.off_cursor);
+  h->err = reinterpret_cast<uint32_t *>(ws + L.off_err);
+  h->status = reinterpret_cast<int32_t *>(ws + L.off_status);
+  h->scratch = reinterpret_cast<double *>(ws + L.off_scratch);
+  h->factor = reinterpret_cast<double *>(ws + L.off_factor);
+  h->phi_out = reinterpret_cast<double *>(ws + L.off_phi_out);
+  h->J_out = reinterpret_cast<double *>(ws + L.off_J_out);
+}
+
+// Upload the mesh, clear every accumulator and build the source bank at t^0
+// (the census bank of step 0, bank 1; its tallies fill set 0).  Queues work
+// only; the caller polls.
+int prime_handle(hww_handle *h, const hww_problem &problem) {
+  const int I = h->I;
+  std::vector<CellData<double>> cd(I);
+  std::vector<CellData<float>> cf(I);
+  for (int i = 0; i < I; ++i) {
+    cd[i].xl = problem.edges[i];
+    cd[i].xr = problem.edges[i + 1];
+    cd[i].inv_sig = 1.0 / problem.sigma_t[i];
+    cd[i].c = problem.sigma_s[i] / problem.sigma_t[i];
+    cf[i].xl = (float)cd[i].xl;
+    cf[i].xr = (float)cd[i].xr;
+    cf[i].inv_sig = (float)cd[i].inv_sig;
+    cf[i].c = (float)cd[i].c;
+  }
+  HIPCHK(h, hipMemcpyAsync(h->edges, problem.edges, 8 * (I + 1), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipMemcpyAsync(h->sig_t, problem.sigma_t, 8 * I, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipMemcpyAsync(h->sig_s, problem.sigma_s, 8 * I, hipMemcpyHostToDevice, h->stream));
+  if (h->fp32)
+    HIPCHK(h, hipMemcpyAsync(h->cells32, cf.data(), sizeof(CellData<float>) * I, hipMemcpyHostToDevice, h->stream));
+  else
+    HIPCHK(h, hipMemcpyAsync(h->cells, cd.data(), sizeof(CellData<double>) * I, hipMemcpyHostToDevice, h->stream));
+  for (int k = 0; k < 2; ++k) {
+    if (zero_counts(h, k) != HWW_OK) return HWW_E_DEVICE;
+    HIPCHK(h, launch_fill_f64(h->tal[k], 0.0, (int64_t)h->B * I * 6, h->stream));
+    HIPCHK(h, launch_fill_f64(h->bnd[k], 0.0, (int64_t)h->B * 6, h->stream));
+  }
+  HIPCHK(h, launch_fill_u32(reinterpret_cast<uint32_t *>(h->tracks), 0u, 2 * (int64_t)I, h->stream));
+  HIPCHK(h, launch_fill_u32(reinterpret_cast<uint32_t *>(h->counters), 0u, 4 * C_NCOUNTERS, h->stream));
+  HIPCHK(h, launch_fill_f64(h->wstart, 0.0, h->nc, h->stream));
+  HIPCHK(h, launch_fill_f64(h->wnext, 0.0, h->nc, h->stream));
+  HIPCHK(h, launch_fill_f64(reinterpret_cast<double *>(h->win), 0.0, 4 * (int64_t)I, h->stream));
+  HIPCHK(h, launch_fill_u32(h->err, 0u, 1, h->stream));
+  HIPCHK(h, launch_fill_u32(h->cursor, 0u, 2 * (int64_t)h->B, h->stream));
+  HIPCHK(h, launch_fill_u32(reinterpret_cast<uint32_t *>(h->status), 0u, 1, h->stream));
+  h->start_bank = 0;
+  h->cur_tal = 0;
+  SourceArgs sa{};
+  sa.I = I; sa.B = h->B; sa.nc = h->nc;
+  sa.v = problem.speed; sa.dt = problem.dt; sa.src_x = problem.src_x;
+  sa.n_src = problem.n_src; sa.seed = problem.seed; sa.key1 = problem.replica << 4;
+  sa.edges = h->edges; sa.geom = h->L.geom;
+  sa.tal = h->tal[0]; sa.wnext = h->wnext; sa.err = h->err;
+  if (h->fp32)
+    HIPCHK(h, launch_source<float>(sa, h->bank32[1], h->B * h->K, 256, h->lds, h->stream));
+  else
+    HIPCHK(h, launch_source<double>(sa, h->bank[1], h->B * h->K, 256, h->lds, h->stream));
+  h->step = 0;
+  h->next_chunk = h->nc;
+  return HWW_OK;
+}
+
+void destroy_events(hww_handle *h) {
+  for (auto &e : h->ev)
+    if (e) (void)hipEventDestroy(e);
+  h->ev.clear();
+}
+
+// ---------------------------------------------------------------- batches --
+// Workspace of a batch: shared arrays first (replica and unit tables, the
+// replicas' counters, segment counts, cursors and solve outputs side by side
+// so that one copy reads them all, the daughter buffers of the persistent
+// grid), then one member layout per replica.
+struct BatchLayout {
+  int64_t total = 0;
+  std::vector<Layout> L;
+  std::vector<int64_t> base;
+  std::vector<uint32_t> units;
+  int64_t off_desc, off_units, off_work, off_err, off_counters, off_seg[2], off_ovf[2], off_cursor, off_phi, off_J,
+      off_losm, off_bs, off_q;
+  int64_t n_seg = 0, n_ovf = 0, n_cur = 0, n_phi = 0, n_J = 0, dcap = 0;
+  int max_I = 0, max_K = 0;
+};
+
+int make_batch_layout(const hww_problem *probs, int n, BatchLayout *BL, std::string *why) {
+  if (!probs || n < 1 || n > 65535) { *why = "need 1..65535 problems"; return HWW_E_INVALID_ARG; }
+  for (int r = 0; r < n; ++r) {
+    const int rc = validate(&probs[r], why);
+    if (rc != HWW_OK) { *why = "replica " + std::to_string(r) + ": " + *why; return rc; }
+    if (probs[r].precision != probs[0].precision || probs[r].n_chunks != probs[0].n_chunks ||
+        probs[r].n_steps != probs[0].n_steps) {
+      *why = "replicas must share precision, n_chunks and n_steps";
+      return HWW_E_INVALID_ARG;
+    }
+  }
+  const int nc = probs[0].n_chunks;
+  BL->L.resize(n);
+  std::vector<int> order(n);
+  for (int r = 0; r < n; ++r) {
+    make_layout(probs[r], &BL->L[r], true);
+    order[r] = r;
+    const Layout &L = BL->L[r];
+    BL->max_I = std::max(BL->max_I, probs[r].n_cells);
+    BL->max_K = std::max(BL->max_K, L.geom.K);
+    const int64_t R = (int64_t)probs[r].n_batches * nc;
+    BL->n_seg += R * L.geom.K;
+    BL->n_ovf += R;
+    BL->n_cur += 2 * (int64_t)probs[r].n_batches;
+    BL->n_phi += probs[r].n_cells + 2;
+    BL->n_J += probs[r].n_cells + 1;
+    BL->dcap = std::max(BL->dcap, (probs[r].bank_capacity + (int64_t)probs[r].n_batches * L.geom.K - 1) /
+                                      ((int64_t)probs[r].n_batches * L.geom.K));
+  }
+  BL->dcap = std::max<int64_t>(BL->dcap, 4096);
+  if (sweep_lds_bytes(BL->max_I, nc, BL->max_K) > 160 * 1024) { *why = "too many cells for the LDS histogram"; return HWW_E_INVALID_ARG; }
+  // Units: biggest replicas first; the units of one batch next to each other.
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return probs[a].n_src > probs[b].n_src; });
+  BL->units.clear();
+  for (int r : order)
+    for (int b = 0; b < probs[r].n_batches; ++b)
+      for (int j = 0; j < BL->L[r].geom.K; ++j) BL->units.push_back(((uint32_t)r << 16) | ((uint32_t)b << 8) | (uint32_t)j);
+  int64_t rb = 8;
+  real_bytes(probs[0].precision, &rb);
+  Carver c;
+  BL->off_desc = c.take((int64_t)n * (int64_t)std::max(sizeof(ReplicaDesc<double>), sizeof(ReplicaDesc<float>)));
+  BL->off_units = c.take(4 * (int64_t)BL->units.size());
+  BL->off_work = c.take(8);
+  BL->off_err = c.take(4);
+  BL->off_counters = c.take(8 * 2 * C_NCOUNTERS * (int64_t)n);
+  for (int k = 0; k < 2; ++k) {
+    BL->off_seg[k] = c.take(4 * BL->n_seg);
+    BL->off_ovf[k] = c.take(4 * BL->n_ovf);
+  }
+  BL->off_cursor = c.take(4 * BL->n_cur);
+  BL->off_phi = c.take(8 * BL->n_phi);
+  BL->off_J = c.take(8 * BL->n_J);
+  BL->off_losm = c.take((int64_t)sizeof(LosmReplica) * n);
+  BL->off_bs = c.take((int64_t)sizeof(BeginStepArgs) * 2 * n);
+  const int64_t qslots = 2 * (int64_t)kGridMax * BL->dcap;
+  BL->off_q = c.take(0);
+  c.take(2 * rb * qslots);
+  c.take(sizeof(WTau) * qslots);
+  c.take(8 * qslots);
+  c.take(sizeof(Tag) * qslots);
+  BL->base.resize(n);
+  for (int r = 0; r < n; ++r) BL->base[r] = c.take(BL->L[r].total);
+  BL->total = c.cur;
+  return HWW_OK;
+}
+
+template <typename Real>
+ReplicaDesc<Real> replica_desc(hww_handle *r) {
+  ReplicaDesc<Real> d{};
+  d.I = r->I; d.B = r->B; d.nc = r->nc;
+  d.v = r->p.speed; d.inv_v = 1.0 / r->p.speed; d.dt = r->p.dt;
+  d.seed = r->p.seed; d.key1 = r->p.replica << 4;
+  d.win = r->win;
+  d.geom = r->L.geom;
+  for (int k = 0; k < 2; ++k) {
+    if constexpr (sizeof(Real) == 8) d.bank[k] = r->bank[k];
+    else d.bank[k] = r->bank32[k];
+    d.tal[k] = r->tal[k];
+    d.bnd[k] = r->bnd[k];
+  }
+  if constexpr (sizeof(Real) == 8) d.cells = r->cells;
+  else d.cells = r->cells32;
+  d.tracks = r->tracks;
+  d.counters = r->counters;
+  d.wnext = r->wnext;
+  d.cursor = r->cursor;
+  return d;
+}
+
+LosmArgs replica_losm_args(hww_handle *r) {
+  LosmArgs a{};
+  a.I = r->I; a.B = r->B; a.nc = r->nc;
+  a.v = r->p.speed; a.dt = r->p.dt; a.n_src = (double)r->p.n_src;
+  a.edges = r->edges; a.sig_t = r->sig_t; a.sig_s = r->sig_s;
+  a.wstart = r->wstart; a.wnext = r->wnext;
+  a.scratch = r->scratch; a.factor = r->factor;
+  a.win = r->win;
+  a.phi_out = r->phi_out; a.J_out = r->J_out; a.err = r->err; a.status = r->status;
+  a.F_out = reinterpret_cast<double *>(r->ws + r->L.off_F_out);
+  a.P_out = reinterpret_cast<double *>(r->ws + r->L.off_P_out);
+  return a;
+}
+
+BeginStepArgs begin_args(hww_handle *h) {
+  BeginStepArgs bs{};
+  bs.segcnt = h->bank[1 - h->start_bank].segcnt;
+  bs.ovfcnt = h->bank[1 - h->start_bank].ovfcnt;
+  bs.tal = h->tal[h->cur_tal]; bs.bnd = h->bnd[h->cur_tal];
+  bs.tracks = h->tracks; bs.counters = h->counters;
+  bs.wstart = h->wstart; bs.wnext = h->wnext;
+  bs.n_seg = (int64_t)h->R * h->K; bs.n_ovf = h->R;
+  bs.n_tal = (int64_t)h->B * h->I * 6; bs.n_bnd = (int64_t)h->B * 6; bs.n_tracks = h->I;
+  bs.nc = h->nc;
+  return bs;
+}
+
+// Swap the start and census banks and the tally sets (batch and replicas).
+void flip_banks(hww_handle *h) {
+  h->start_bank = 1 - h->start_bank;
+  h->cur_tal = 1 - h->cur_tal;
+  for (hww_handle *r : h->rep) {
+    r->start_bank = h->start_bank;
+    r->cur_tal = h->cur_tal;
+  }
+}
+
+// Queue the clearing of the new step's accumulators (after flip_banks).
+int begin_step(hww_handle *h) {
+  if (h->is_batch) {
+    HIPCHK(h, launch_begin_step_batch(h->bs_tab + (size_t)h->start_bank * h->rep.size(), (int)h->rep.size(),
+                                      (int64_t)64 * h->max_I * 6, h->stream));
+  } else {
+    HIPCHK(h, launch_begin_step(begin_args(h), h->stream));
+  }
+  return HWW_OK;
+}
+
+void sync_replica_state(hww_handle *h) {
+  for (hww_handle *r : h->rep) {
+    r->step = h->step;
+    r->next_chunk = h->next_chunk;
+    r->start_bank = h->start_bank;
+    r->cur_tal = h->cur_tal;
+    r->ww_on = h->ww_on;
+    r->factor_theta = h->factor_theta;
+  }
+}
+
+int poll_batch(hww_handle *h) {
+  uint32_t e = 0;
+  HIPCHK(h, hipMemcpyAsync(&e, h->err, 4, hipMemcpyDeviceToHost, h->stream));
+  const int cb = 1 - h->start_bank;
+  std::vector<uint32_t> seg((size_t)h->n_seg_all), ovf((size_t)h->n_ovf_all);
+  HIPCHK(h, hipMemcpyAsync(seg.data(), h->segcnt_all[cb], 4 * seg.size(), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipMemcpyAsync(ovf.data(), h->ovfcnt_all[cb], 4 * ovf.size(), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (e & (ERR_CAPACITY | ERR_SPLIT | ERR_GENERATIONS)) {
+    h->fatal = HWW_E_CAPACITY;
+    return fail(h, HWW_E_CAPACITY, (e & ERR_SPLIT) ? "a split exceeded 1e9 daughters"
+                                   : (e & ERR_GENERATIONS) ? "too many daughter generations"
+                                                           : "bank segment or daughter buffer overflow");
+  }
+  for (size_t q = 0; q < h->rep.size(); ++q) {
+    hww_handle *r = h->rep[q];
+    const int64_t so = r->bank[cb].segcnt - h->segcnt_all[cb], oo = r->bank[cb].ovfcnt - h->ovfcnt_all[cb];
+    uint64_t t = 0;
+    for (int64_t j = 0; j < (int64_t)r->R * r->K; ++j) t += std::min<uint64_t>(seg[so + j], (uint64_t)r->L.geom.seg_cap);
+    for (int64_t j = 0; j < r->R; ++j) t += std::min<uint64_t>(ovf[oo + j], (uint64_t)r->L.geom.ovf_cap);
+    if (t > (uint64_t)r->p.bank_capacity) {
+      h->fatal = HWW_E_CAPACITY;
+      return fail(h, HWW_E_CAPACITY, "census bank of replica " + std::to_string(q) + " exceeds bank_capacity");
+    }
+  }
+  if (e & ERR_NUMERIC) {
+    h->fatal = HWW_E_NUMERIC;
+    return fail(h, HWW_E_NUMERIC, "non-finite or non-positive window, or zero pivot in the LOSM solve");
+  }
+  return HWW_OK;
+}
+
+// Counters of the batch or problem: part 0 this step, 1 since init.
+int read_counters(hww_handle *h, int part, unsigned long long out[C_NCOUNTERS]) {
+  const size_t n = h->is_batch ? h->rep.size() : 1;
+  std::vector<unsigned long long> all(n * 2 * C_NCOUNTERS);
+  HIPCHK(h, hipMemcpyAsync(all.data(), h->is_batch ? h->counters_all : h->counters, 8 * all.size(),
+                           hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  for (int q = 0; q < C_NCOUNTERS; ++q) out[q] = 0;
+  for (size_t r = 0; r < n; ++r)
+    for (int q = 0; q < C_NCOUNTERS; ++q) {
+      const unsigned long long v = all[(r * 2 + part) * C_NCOUNTERS + q];
+      if (q == C_GENERATIONS) out[q] = std::max(out[q], v);
+      else out[q] += v;
+    }
+  return HWW_OK;
+}
+
+void fill_stats(hww_handle *h, const unsigned long long *cnt, hww_step_stats *stats) {
+  stats->segments = cnt[C_SEGMENTS];
+  stats->collisions = cnt[C_COLLISIONS];
+  stats->scatters = cnt[C_SCATTERS];
+  stats->absorptions = cnt[C_ABSORPTIONS];
+  stats->crossings = cnt[C_CROSSINGS];
+  stats->leaks = cnt[C_LEAKS];
+  stats->census = cnt[C_CENSUS];
+  stats->splits = cnt[C_SPLITS];
+  stats->daughters = cnt[C_DAUGHTERS];
+  stats->rr_kill = cnt[C_RR_KILL];
+  stats->rr_survive = cnt[C_RR_SURVIVE];
+  stats->histories = cnt[C_HISTORIES];
+  stats->generations = cnt[C_GENERATIONS];
+  const uint64_t rec = h->fp32 ? 36 : 44, drec = h->fp32 ? 44 : 52;
+  stats->bytes_moved = cnt[C_HISTORIES] * rec + cnt[C_CENSUS] * rec + cnt[C_DAUGHTERS] * 2 * drec;
+}
+
+// Default launch shape of a batch: as many work-groups per compute unit as
+// the LDS histogram and the thread limit allow, up to four.
+int default_grid(hww_handle *h, int block) {
+  int wpc = 4;
+  while (wpc > 1 && ((size_t)wpc * h->lds > 160 * 1024 || wpc * block > 2048)) --wpc;
+  return std::min(kGridMax, h->cus * wpc);
 }
 
 }  // namespace
@@ -359,160 +757,63 @@ int hww_init_problem(const hww_problem *problem, void *dev_workspace, int64_t ws
   if (reinterpret_cast<uintptr_t>(dev_workspace) % 256 != 0) return fail(nullptr, HWW_E_INVALID_ARG, "workspace not 256-byte aligned");
 
   hww_handle *h = new hww_handle();
-  h->p = *problem;
-  h->p.edges = h->p.sigma_t = h->p.sigma_s = nullptr;
-  h->I = problem->n_cells;
-  h->B = problem->n_batches;
-  h->nc = problem->n_chunks;
-  h->R = h->B * h->nc;
-  h->L = L;
-  h->K = L.geom.K;
-  h->lds = sweep_lds_bytes(h->I, h->nc, h->K);
-  h->stream = reinterpret_cast<hipStream_t>(hip_stream);
-  h->ws = reinterpret_cast<char *>(dev_workspace);
-  char *ws = h->ws;
-  const int64_t slots = (int64_t)h->R * L.geom.stride;
-  h->edges = reinterpret_cast<double *>(ws + L.off_edges);
-  h->sig_t = reinterpret_cast<double *>(ws + L.off_sigt);
-  h->sig_s = reinterpret_cast<double *>(ws + L.off_sigs);
-  h->cells = reinterpret_cast<CellData<double> *>(ws + L.off_cells);
-  h->win = reinterpret_cast<Window *>(ws + L.off_win);
-  for (int k = 0; k < 2; ++k) {
-    h->bank[k] = bank_view<double>(ws, L.off_bank[k], L.off_segcnt[k], L.off_ovfcnt[k], slots);
-    h->tal[k] = reinterpret_cast<double *>(ws + L.off_tal[k]);
-    h->bnd[k] = reinterpret_cast<double *>(ws + L.off_bnd[k]);
-  }
-  h->fp32 = problem->precision == HWW_FP32;
-  h->dq = queue_view<double>(ws, L.off_q, 2 * (int64_t)h->B * h->K * L.dcap);
-  h->dq32 = queue_view<float>(ws, L.off_q, 2 * (int64_t)h->B * h->K * L.dcap);
-  for (int k = 0; k < 2; ++k)
-    h->bank32[k] = bank_view<float>(ws, L.off_bank[k], L.off_segcnt[k], L.off_ovfcnt[k], slots);
-  h->cells32 = reinterpret_cast<CellData<float> *>(ws + L.off_cells);
-  h->tracks = reinterpret_cast<unsigned long long *>(ws + L.off_tracks);
-  h->counters = reinterpret_cast<unsigned long long *>(ws + L.off_counters);
-  h->wstart = reinterpret_cast<double *>(ws + L.off_wstart);
-  h->wnext = reinterpret_cast<double *>(ws + L.off_wnext);
-  h->cursor = reinterpret_cast<uint32_t *>(ws + L.off_cursor);
-  h->err = reinterpret_cast<uint32_t *>(ws + L.off_err);
-  h->status = reinterpret_cast<int32_t *>(ws + L.off_status);
-  h->scratch = reinterpret_cast<double *>(ws + L.off_scratch);
-  h->factor = reinterpret_cast<double *>(ws + L.off_factor);
-  h->phi_out = reinterpret_cast<double *>(ws + L.off_phi_out);
-  h->J_out = reinterpret_cast<double *>(ws + L.off_J_out);
-
-  auto bail = [&](int code) {
+  carve_handle(h, *problem, reinterpret_cast<char *>(dev_workspace), L, reinterpret_cast<hipStream_t>(hip_stream));
+  rc = prime_handle(h, *problem);
+  if (rc == HWW_OK) rc = poll_errors(h);
+  if (rc != HWW_OK) {
     g_init_error = h->msg;
-    for (auto &e : h->ev)
-      if (e) (void)hipEventDestroy(e);
+    destroy_events(h);
     delete h;
-    return code;
-  };
-#define INITCHK(expr)                                  \
-  do {                                                 \
-    int rc__ = check_hip(h, (expr), #expr);            \
-    if (rc__ != HWW_OK) return bail(rc__);             \
-  } while (0)
-
-  const int I = h->I;
-  std::vector<CellData<double>> cd(I);
-  std::vector<CellData<float>> cf(I);
-  for (int i = 0; i < I; ++i) {
-    cd[i].xl = problem->edges[i];
-    cd[i].xr = problem->edges[i + 1];
-    cd[i].inv_sig = 1.0 / problem->sigma_t[i];
-    cd[i].c = problem->sigma_s[i] / problem->sigma_t[i];
-    cf[i].xl = (float)cd[i].xl;
-    cf[i].xr = (float)cd[i].xr;
-    cf[i].inv_sig = (float)cd[i].inv_sig;
-    cf[i].c = (float)cd[i].c;
+    return rc;
   }
-  INITCHK(hipMemcpyAsync(h->edges, problem->edges, 8 * (I + 1), hipMemcpyHostToDevice, h->stream));
-  INITCHK(hipMemcpyAsync(h->sig_t, problem->sigma_t, 8 * I, hipMemcpyHostToDevice, h->stream));
-  INITCHK(hipMemcpyAsync(h->sig_s, problem->sigma_s, 8 * I, hipMemcpyHostToDevice, h->stream));
-  if (h->fp32)
-    INITCHK(hipMemcpyAsync(h->cells32, cf.data(), sizeof(CellData<float>) * I, hipMemcpyHostToDevice, h->stream));
-  else
-    INITCHK(hipMemcpyAsync(h->cells, cd.data(), sizeof(CellData<double>) * I, hipMemcpyHostToDevice, h->stream));
-  // Zero everything the kernels accumulate into.
-  for (int k = 0; k < 2; ++k) {
-    if (zero_counts(h, k) != HWW_OK) return bail(HWW_E_DEVICE);
-    INITCHK(launch_fill_f64(h->tal[k], 0.0, (int64_t)h->B * I * 6, h->stream));
-    INITCHK(launch_fill_f64(h->bnd[k], 0.0, (int64_t)h->B * 6, h->stream));
-  }
-  INITCHK(launch_fill_u32(reinterpret_cast<uint32_t *>(h->tracks), 0u, 2 * (int64_t)I, h->stream));
-  INITCHK(launch_fill_u32(reinterpret_cast<uint32_t *>(h->counters), 0u, 4 * C_NCOUNTERS, h->stream));
-  INITCHK(launch_fill_f64(h->wstart, 0.0, h->nc, h->stream));
-  INITCHK(launch_fill_f64(h->wnext, 0.0, h->nc, h->stream));
-  INITCHK(launch_fill_f64(reinterpret_cast<double *>(h->win), 0.0, 4 * (int64_t)I, h->stream));
-  INITCHK(launch_fill_u32(h->err, 0u, 1, h->stream));
-  INITCHK(launch_fill_u32(h->cursor, 0u, 2 * (int64_t)h->B, h->stream));
-  INITCHK(launch_fill_u32(reinterpret_cast<uint32_t *>(h->status), 0u, 1, h->stream));
-
-  // Source bank = census bank of step 0 (bank 1); its tallies fill set 0.
-  h->start_bank = 0;
-  h->cur_tal = 0;
-  SourceArgs sa{};
-  sa.I = I; sa.B = h->B; sa.nc = h->nc;
-  sa.v = problem->speed; sa.dt = problem->dt; sa.src_x = problem->src_x;
-  sa.n_src = problem->n_src; sa.seed = problem->seed; sa.key1 = problem->replica << 4;
-  sa.edges = h->edges; sa.geom = L.geom;
-  sa.tal = h->tal[0]; sa.wnext = h->wnext; sa.err = h->err;
-  if (h->fp32)
-    INITCHK(launch_source<float>(sa, h->bank32[1], h->B * h->K, 256, h->lds, h->stream));
-  else
-    INITCHK(launch_source<double>(sa, h->bank[1], h->B * h->K, 256, h->lds, h->stream));
-  int prc = poll_errors(h);
-  if (prc != HWW_OK) return bail(prc);
-  h->step = 0;
-  h->next_chunk = h->nc;
   *out = h;
   return HWW_OK;
-#undef INITCHK
 }
 
 int hww_set_windows(hww_handle *h, const double *centre, double rho) {
   if (!h) return HWW_E_INVALID_ARG;
+  if (h->is_view) return fail(h, HWW_E_STATE, "a replica view is read-only");
   if (!centre) {
     h->ww_on = 0;
+    sync_replica_state(h);
     return HWW_OK;
   }
   if (!(rho >= 1.0) || !std::isfinite(rho)) return fail(h, HWW_E_INVALID_ARG, "rho must be >= 1");
-  const int I = h->I;
-  std::vector<Window> w3(I);
-  for (int i = 0; i < I; ++i) {
+  std::vector<hww_handle *> targets = h->is_batch ? h->rep : std::vector<hww_handle *>{h};
+  int64_t total = 0;
+  for (hww_handle *t : targets) total += t->I;
+  std::vector<Window> w3((size_t)total);
+  for (int64_t i = 0; i < total; ++i) {
     if (!(centre[i] > 0.0) || !std::isfinite(centre[i])) return fail(h, HWW_E_NUMERIC, "window centres must be positive and finite");
     w3[i].ww = centre[i];
     w3[i].ceil = centre[i] * rho;
     w3[i].floor = centre[i] / rho;
     w3[i].pad = 0.0;
   }
-  HIPCHK(h, hipMemcpyAsync(h->win, w3.data(), sizeof(Window) * (size_t)I, hipMemcpyHostToDevice, h->stream));
-  // The host vector must outlive the copy.
+  int64_t o = 0;
+  for (hww_handle *t : targets) {
+    HIPCHK(h, hipMemcpyAsync(t->win, w3.data() + o, sizeof(Window) * (size_t)t->I, hipMemcpyHostToDevice, h->stream));
+    o += t->I;
+  }
+  // The host vector must outlive the copies.
   HIPCHK(h, hipStreamSynchronize(h->stream));
   h->ww_on = 1;
+  sync_replica_state(h);
   return HWW_OK;
 }
 
 int hww_sweep_step(hww_handle *h, int32_t step, int32_t chunk, hww_step_stats *stats) {
   if (!h) return HWW_E_INVALID_ARG;
+  if (h->is_view) return fail(h, HWW_E_STATE, "a replica view is read-only");
   if (h->fatal) return fail(h, h->fatal, "an earlier error left the problem invalid");
   if (chunk < 0 || chunk >= h->nc) return fail(h, HWW_E_INVALID_ARG, "chunk out of range");
   if (chunk == 0) {
     if (h->next_chunk != h->nc || step != h->step + 1 || step > h->p.n_steps)
       return fail(h, HWW_E_STATE, "step out of order");
     // The census bank of the finished step becomes the start bank.
-    h->start_bank = 1 - h->start_bank;
-    h->cur_tal = 1 - h->cur_tal;
-    BeginStepArgs bs{};
-    bs.segcnt = h->bank[1 - h->start_bank].segcnt;
-    bs.ovfcnt = h->bank[1 - h->start_bank].ovfcnt;
-    bs.tal = h->tal[h->cur_tal]; bs.bnd = h->bnd[h->cur_tal];
-    bs.tracks = h->tracks; bs.counters = h->counters;
-    bs.wstart = h->wstart; bs.wnext = h->wnext;
-    bs.n_seg = (int64_t)h->R * h->K; bs.n_ovf = h->R;
-    bs.n_tal = (int64_t)h->B * h->I * 6; bs.n_bnd = (int64_t)h->B * 6; bs.n_tracks = h->I;
-    bs.nc = h->nc;
-    HIPCHK(h, launch_begin_step(bs, h->stream));
+    flip_banks(h);
+    int rc = begin_step(h);
+    if (rc != HWW_OK) return rc;
     h->step = step;
     h->next_chunk = 0;
     h->n_launch = 0;
@@ -534,25 +835,15 @@ int hww_sweep_step(hww_handle *h, int32_t step, int32_t chunk, hww_step_stats *s
   h->ev_used = k + 1;
   h->n_launch += 1;
   h->next_chunk = chunk + 1;
+  sync_replica_state(h);
   if (!stats) return HWW_OK;
 
   unsigned long long cnt[C_NCOUNTERS];
-  HIPCHK(h, hipMemcpyAsync(cnt, h->counters, sizeof cnt, hipMemcpyDeviceToHost, h->stream));
-  int rc = poll_errors(h);
+  int rc = read_counters(h, 0, cnt);
   if (rc != HWW_OK) return rc;
-  stats->segments = cnt[C_SEGMENTS];
-  stats->collisions = cnt[C_COLLISIONS];
-  stats->scatters = cnt[C_SCATTERS];
-  stats->absorptions = cnt[C_ABSORPTIONS];
-  stats->crossings = cnt[C_CROSSINGS];
-  stats->leaks = cnt[C_LEAKS];
-  stats->census = cnt[C_CENSUS];
-  stats->splits = cnt[C_SPLITS];
-  stats->daughters = cnt[C_DAUGHTERS];
-  stats->rr_kill = cnt[C_RR_KILL];
-  stats->rr_survive = cnt[C_RR_SURVIVE];
-  stats->histories = cnt[C_HISTORIES];
-  stats->generations = cnt[C_GENERATIONS];
+  rc = poll_errors(h);
+  if (rc != HWW_OK) return rc;
+  fill_stats(h, cnt, stats);
   stats->launches = (uint64_t)h->n_launch;
   double ms = 0.0;
   for (int q = h->step_ev0; q < h->ev_used; ++q) {
@@ -561,49 +852,59 @@ int hww_sweep_step(hww_handle *h, int32_t step, int32_t chunk, hww_step_stats *s
     ms += t;
   }
   stats->kernel_ms = ms;
-  const uint64_t rec = h->fp32 ? 36 : 44, drec = h->fp32 ? 44 : 52;
-  stats->bytes_moved = cnt[C_HISTORIES] * rec + cnt[C_CENSUS] * rec + cnt[C_DAUGHTERS] * 2 * drec;
   return HWW_OK;
 }
 
 int hww_read_run_stats(hww_handle *h, hww_step_stats *stats) {
   if (!h || !stats) return HWW_E_INVALID_ARG;
   unsigned long long cnt[C_NCOUNTERS];
-  HIPCHK(h, hipMemcpyAsync(cnt, h->counters + C_NCOUNTERS, sizeof cnt, hipMemcpyDeviceToHost, h->stream));
-  int rc = poll_errors(h);
+  int rc = read_counters(h, 1, cnt);
+  if (rc != HWW_OK) return rc;
+  rc = poll_errors(h);
   if (rc != HWW_OK) return rc;
   for (; h->ev_summed < h->ev_used; ++h->ev_summed) {
     float t = 0.0f;
     HIPCHK(h, hipEventElapsedTime(&t, h->ev[2 * h->ev_summed], h->ev[2 * h->ev_summed + 1]));
     h->ms_summed += t;
   }
-  stats->segments = cnt[C_SEGMENTS];
-  stats->collisions = cnt[C_COLLISIONS];
-  stats->scatters = cnt[C_SCATTERS];
-  stats->absorptions = cnt[C_ABSORPTIONS];
-  stats->crossings = cnt[C_CROSSINGS];
-  stats->leaks = cnt[C_LEAKS];
-  stats->census = cnt[C_CENSUS];
-  stats->splits = cnt[C_SPLITS];
-  stats->daughters = cnt[C_DAUGHTERS];
-  stats->rr_kill = cnt[C_RR_KILL];
-  stats->rr_survive = cnt[C_RR_SURVIVE];
-  stats->histories = cnt[C_HISTORIES];
-  stats->generations = cnt[C_GENERATIONS];
+  fill_stats(h, cnt, stats);
   stats->launches = (uint64_t)h->ev_used;
   stats->kernel_ms = h->ms_summed;
-  const uint64_t rec = h->fp32 ? 36 : 44, drec = h->fp32 ? 44 : 52;
-  stats->bytes_moved = cnt[C_HISTORIES] * rec + cnt[C_CENSUS] * rec + cnt[C_DAUGHTERS] * 2 * drec;
   return HWW_OK;
 }
 
 int hww_solve_losm(hww_handle *h, const hww_losm_opts *o, double *phi_out, double *J_out) {
   if (!h || !o) return HWW_E_INVALID_ARG;
+  if (h->is_view) return fail(h, HWW_E_STATE, "a replica view is read-only");
   if (h->fatal) return fail(h, h->fatal, "an earlier error left the problem invalid");
   if (!(o->theta > 0.0 && o->theta <= 1.0) || o->ma_k < 0 || (o->filter != 0 && o->filter != 1))
     return fail(h, HWW_E_INVALID_ARG, "bad LOSM options");
   if (o->apply_windows && (!(o->rho >= 1.0) || !(o->eps_min > 0.0 && o->eps_min <= 1.0)))
     return fail(h, HWW_E_INVALID_ARG, "bad window options");
+  if (h->is_batch) {
+    if (!o->implicit) {
+      if (h->next_chunk != h->nc || h->step >= h->p.n_steps) return fail(h, HWW_E_STATE, "semi-implicit solve needs a finished step");
+    } else if (h->step < 1 || h->next_chunk < 1 || h->next_chunk >= h->nc) {
+      return fail(h, HWW_E_STATE, "implicit solve needs a step in progress");
+    }
+    LosmCall c{};
+    c.cur = h->cur_tal;
+    c.implicit = o->implicit; c.next_chunk = h->next_chunk; c.filter = o->filter; c.ma_k = o->ma_k;
+    c.closure_track = o->closure_track; c.apply_windows = o->apply_windows; c.export_only = 0;
+    c.refactor = (o->theta != h->factor_theta) ? 1 : 0;
+    c.work_in_lds = h->losm_wil;
+    c.theta = o->theta; c.eps_min = o->eps_min; c.rho = o->rho;
+    HIPCHK(h, launch_losm_batch(h->losm_tab, (int)h->rep.size(), h->max_I, c, h->stream));
+    h->factor_theta = o->theta;
+    if (o->apply_windows) h->ww_on = 1;
+    sync_replica_state(h);
+    if (phi_out || J_out) {
+      if (phi_out) HIPCHK(h, hipMemcpyAsync(phi_out, h->phi_cat, 8 * (size_t)h->n_phi_all, hipMemcpyDeviceToHost, h->stream));
+      if (J_out) HIPCHK(h, hipMemcpyAsync(J_out, h->J_cat, 8 * (size_t)h->n_J_all, hipMemcpyDeviceToHost, h->stream));
+      return poll_errors(h);
+    }
+    return HWW_OK;
+  }
   LosmArgs a{};
   a.I = h->I; a.B = h->B; a.nc = h->nc;
   a.v = h->p.speed; a.dt = h->p.dt; a.n_src = (double)h->p.n_src;
@@ -639,6 +940,7 @@ int hww_solve_losm(hww_handle *h, const hww_losm_opts *o, double *phi_out, doubl
 
 int hww_read_closures(hww_handle *h, double *F, double *P, double *phi, double *J) {
   if (!h || !F || !P || !phi || !J) return HWW_E_INVALID_ARG;
+  if (h->is_batch) return fail(h, HWW_E_STATE, "read the closures of a replica through hww_batch_replica");
   if (h->fatal) return fail(h, h->fatal, "an earlier error left the problem invalid");
   if (h->next_chunk != h->nc) return fail(h, HWW_E_STATE, "closures need a finished step");
   LosmArgs a{};
@@ -672,6 +974,7 @@ int hww_losm_march(hww_handle *h, const double *sigma_t, const double *sigma_s, 
                    const double *F, const double *P, const double *phi0, const double *J0, const double *weights,
                    double *phi_hist, double *J_hist, double *G) {
   if (!h || !sigma_t || !sigma_s || !F || !P || !phi0 || !J0 || !weights || !G) return HWW_E_INVALID_ARG;
+  if (h->is_batch || h->is_view) return fail(h, HWW_E_STATE, "the march runs on a single problem");
   if (n_steps < 1 || n_steps > h->p.n_steps) return fail(h, HWW_E_INVALID_ARG, "n_steps out of range");
   if (!(theta > 0.0 && theta <= 1.0)) return fail(h, HWW_E_INVALID_ARG, "theta must be in (0, 1]");
   const int I = h->I;
@@ -727,7 +1030,7 @@ int hww_losm_march(hww_handle *h, const double *sigma_t, const double *sigma_s, 
 
 int hww_losm_adjoint(hww_handle *h, double *grad_sigma_t, double *grad_sigma_s) {
   if (!h || !grad_sigma_t || !grad_sigma_s) return HWW_E_INVALID_ARG;
-  if (!h->march_ok) return fail(h, HWW_E_STATE, "the adjoint needs a preceding hww_losm_march");
+  if (h->is_batch || h->is_view || !h->march_ok) return fail(h, HWW_E_STATE, "the adjoint needs a preceding hww_losm_march");
   if (h->I > 4 * 1024) return fail(h, HWW_E_INVALID_ARG, "the adjoint handles I <= 4096");
   HIPCHK(h, launch_adjoint(h->march, h->stream));
   HIPCHK(h, hipMemcpyAsync(grad_sigma_t, h->march.g_t, 8 * (size_t)h->I, hipMemcpyDeviceToHost, h->stream));
@@ -737,6 +1040,36 @@ int hww_losm_adjoint(hww_handle *h, double *grad_sigma_t, double *grad_sigma_s) 
 
 int hww_read_tallies(hww_handle *h, int32_t kind, void *out, int64_t out_bytes) {
   if (!h || !out) return HWW_E_INVALID_ARG;
+  if (h->is_batch) {
+    int64_t need = 0;
+    for (hww_handle *r : h->rep) {
+      const int64_t I = r->I, B = r->B;
+      switch (kind) {
+        case HWW_TALLY_CELLS: case HWW_TALLY_PREV_CELLS: need += 8 * B * I * 6; break;
+        case HWW_TALLY_BOUNDARY: case HWW_TALLY_PREV_BOUNDARY: need += 8 * B * 6; break;
+        case HWW_TALLY_TRACKS: need += 8 * I; break;
+        case HWW_TALLY_WINDOWS: need += 8 * 3 * I; break;
+        case HWW_TALLY_BANK_COUNTS: need += 16; break;
+        default: return fail(h, HWW_E_INVALID_ARG, "unknown tally kind");
+      }
+    }
+    if (out_bytes != need) return fail(h, HWW_E_INVALID_ARG, "out_bytes does not match the tally kind");
+    char *o = static_cast<char *>(out);
+    for (hww_handle *r : h->rep) {
+      int64_t sz = 0;
+      switch (kind) {
+        case HWW_TALLY_CELLS: case HWW_TALLY_PREV_CELLS: sz = 8 * (int64_t)r->B * r->I * 6; break;
+        case HWW_TALLY_BOUNDARY: case HWW_TALLY_PREV_BOUNDARY: sz = 8 * (int64_t)r->B * 6; break;
+        case HWW_TALLY_TRACKS: sz = 8 * (int64_t)r->I; break;
+        case HWW_TALLY_WINDOWS: sz = 8 * 3 * (int64_t)r->I; break;
+        default: sz = 16; break;
+      }
+      const int rc = hww_read_tallies(r, kind, o, sz);
+      if (rc != HWW_OK) return fail(h, rc, r->msg);
+      o += sz;
+    }
+    return poll_errors(h);
+  }
   const int64_t I = h->I, B = h->B;
   const void *src = nullptr;
   int64_t bytes = 0;
@@ -781,6 +1114,7 @@ int hww_read_tallies(hww_handle *h, int32_t kind, void *out, int64_t out_bytes) 
 int hww_read_bank(hww_handle *h, int32_t which, int64_t cap, int64_t *count, double *x, double *mu, double *w,
                   uint32_t *src, uint64_t *lin, uint32_t *e, int32_t *cell, int32_t *chunk) {
   if (!h || !count || (which != 0 && which != 1)) return HWW_E_INVALID_ARG;
+  if (h->is_batch) return fail(h, HWW_E_INVALID_ARG, "read the bank of a replica through hww_batch_replica");
   if (which == 0 && h->step == 0) {
     *count = 0;
     return HWW_OK;
@@ -841,6 +1175,246 @@ int hww_read_bank(hww_handle *h, int32_t which, int64_t cap, int64_t *count, dou
   return HWW_OK;
 }
 
+int64_t hww_batch_workspace_bytes(const hww_problem *problems, int32_t n) {
+  std::string why;
+  BatchLayout BL;
+  if (make_batch_layout(problems, n, &BL, &why) != HWW_OK) return HWW_E_INVALID_ARG;
+  return BL.total;
+}
+
+int hww_init_batch(const hww_problem *problems, int32_t n, void *dev_workspace, int64_t ws_bytes, void *hip_stream,
+                   hww_handle **out) {
+  std::string why;
+  if (!out) return fail(nullptr, HWW_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  BatchLayout BL;
+  int rc = make_batch_layout(problems, n, &BL, &why);
+  if (rc != HWW_OK) return fail(nullptr, rc, why);
+  if (!dev_workspace || ws_bytes < BL.total) return fail(nullptr, HWW_E_INVALID_ARG, "workspace too small");
+  if (reinterpret_cast<uintptr_t>(dev_workspace) % 256 != 0) return fail(nullptr, HWW_E_INVALID_ARG, "workspace not 256-byte aligned");
+  char *ws = reinterpret_cast<char *>(dev_workspace);
+  hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+
+  hww_handle *h = new hww_handle();
+  h->is_batch = 1;
+  h->p = problems[0];
+  h->p.edges = h->p.sigma_t = h->p.sigma_s = nullptr;
+  h->nc = problems[0].n_chunks;
+  h->fp32 = problems[0].precision == HWW_FP32;
+  h->stream = stream;
+  h->ws = ws;
+  h->max_I = BL.max_I;
+  h->max_K = BL.max_K;
+  h->lds = sweep_lds_bytes(BL.max_I, h->nc, BL.max_K);
+  h->n_units = (uint32_t)BL.units.size();
+  h->desc = ws + BL.off_desc;
+  h->units = reinterpret_cast<uint32_t *>(ws + BL.off_units);
+  h->work = reinterpret_cast<uint32_t *>(ws + BL.off_work);
+  h->err = reinterpret_cast<uint32_t *>(ws + BL.off_err);
+  h->counters_all = reinterpret_cast<unsigned long long *>(ws + BL.off_counters);
+  for (int k = 0; k < 2; ++k) {
+    h->segcnt_all[k] = reinterpret_cast<uint32_t *>(ws + BL.off_seg[k]);
+    h->ovfcnt_all[k] = reinterpret_cast<uint32_t *>(ws + BL.off_ovf[k]);
+  }
+  h->cursor_all = reinterpret_cast<uint32_t *>(ws + BL.off_cursor);
+  h->phi_cat = reinterpret_cast<double *>(ws + BL.off_phi);
+  h->J_cat = reinterpret_cast<double *>(ws + BL.off_J);
+  h->losm_tab = reinterpret_cast<LosmReplica *>(ws + BL.off_losm);
+  h->bs_tab = reinterpret_cast<BeginStepArgs *>(ws + BL.off_bs);
+  h->n_seg_all = BL.n_seg; h->n_ovf_all = BL.n_ovf; h->n_cur_all = BL.n_cur;
+  h->n_phi_all = BL.n_phi; h->n_J_all = BL.n_J;
+  h->bdcap = BL.dcap;
+  h->bq = queue_view<double>(ws, BL.off_q, 2 * (int64_t)kGridMax * BL.dcap);
+  h->bq32 = queue_view<float>(ws, BL.off_q, 2 * (int64_t)kGridMax * BL.dcap);
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+    h->cus = cus;
+  h->grid = default_grid(h, h->block);
+  (void)losm_batch_lds(h->max_I, &h->losm_wil);
+
+  auto bail = [&](int code) {
+    g_init_error = h->msg;
+    hww_destroy(h);
+    return code;
+  };
+  // Replicas: member layouts whose small arrays sit in the shared ones.
+  int64_t so = 0, oo = 0, co = 0, po = 0, jo = 0;
+  h->rep.resize(n, nullptr);
+  for (int r = 0; r < n; ++r) {
+    hww_handle *m = new hww_handle();
+    h->rep[r] = m;
+    carve_handle(m, problems[r], ws + BL.base[r], BL.L[r], stream);
+    m->is_view = 1;
+    const int64_t R = (int64_t)m->R, K = m->K;
+    for (int k = 0; k < 2; ++k) {
+      m->bank[k].segcnt = m->bank32[k].segcnt = h->segcnt_all[k] + so;
+      m->bank[k].ovfcnt = m->bank32[k].ovfcnt = h->ovfcnt_all[k] + oo;
+    }
+    so += R * K;
+    oo += R;
+    m->counters = h->counters_all + (int64_t)r * 2 * C_NCOUNTERS;
+    m->cursor = h->cursor_all + co;
+    co += 2 * (int64_t)m->B;
+    m->phi_out = h->phi_cat + po;
+    m->J_out = h->J_cat + jo;
+    po += m->I + 2;
+    jo += m->I + 1;
+    m->err = h->err;
+    rc = prime_handle(m, problems[r]);
+    if (rc != HWW_OK) {
+      h->msg = "replica " + std::to_string(r) + ": " + m->msg;
+      return bail(rc);
+    }
+  }
+  HIPCHK(h, launch_fill_u32(h->work, 0u, 2, h->stream));
+  // Device tables.
+  std::vector<ReplicaDesc<double>> d64(n);
+  std::vector<ReplicaDesc<float>> d32(n);
+  std::vector<LosmReplica> lt(n);
+  std::vector<BeginStepArgs> bs(2 * (size_t)n);
+  for (int r = 0; r < n; ++r) {
+    hww_handle *m = h->rep[r];
+    if (h->fp32) d32[r] = replica_desc<float>(m);
+    else d64[r] = replica_desc<double>(m);
+    lt[r].a = replica_losm_args(m);
+    for (int k = 0; k < 2; ++k) {
+      lt[r].tal[k] = m->tal[k];
+      lt[r].bnd[k] = m->bnd[k];
+      m->start_bank = m->cur_tal = k;
+      bs[(size_t)k * n + r] = begin_args(m);
+    }
+    m->start_bank = m->cur_tal = 0;
+  }
+  if (h->fp32)
+    rc = check_hip(h, hipMemcpyAsync(h->desc, d32.data(), sizeof(ReplicaDesc<float>) * n, hipMemcpyHostToDevice, stream), "desc");
+  else
+    rc = check_hip(h, hipMemcpyAsync(h->desc, d64.data(), sizeof(ReplicaDesc<double>) * n, hipMemcpyHostToDevice, stream), "desc");
+  if (rc == HWW_OK) rc = check_hip(h, hipMemcpyAsync(h->units, BL.units.data(), 4 * BL.units.size(), hipMemcpyHostToDevice, stream), "units");
+  if (rc == HWW_OK) rc = check_hip(h, hipMemcpyAsync(h->losm_tab, lt.data(), sizeof(LosmReplica) * n, hipMemcpyHostToDevice, stream), "losm table");
+  if (rc == HWW_OK) rc = check_hip(h, hipMemcpyAsync(h->bs_tab, bs.data(), sizeof(BeginStepArgs) * bs.size(), hipMemcpyHostToDevice, stream), "step table");
+  if (rc == HWW_OK) rc = check_hip(h, hipStreamSynchronize(stream), "sync");
+  if (rc == HWW_OK) rc = poll_errors(h);
+  if (rc != HWW_OK) return bail(rc);
+  h->start_bank = 0;
+  h->cur_tal = 0;
+  h->step = 0;
+  h->next_chunk = h->nc;
+  sync_replica_state(h);
+  *out = h;
+  return HWW_OK;
+}
+
+int hww_batch_replica(hww_handle *h, int32_t r, hww_handle **view) {
+  if (!h || !view) return HWW_E_INVALID_ARG;
+  *view = nullptr;
+  if (!h->is_batch) return fail(h, HWW_E_STATE, "not a batch");
+  if (r < 0 || r >= (int32_t)h->rep.size()) return fail(h, HWW_E_INVALID_ARG, "replica out of range");
+  *view = h->rep[r];
+  return HWW_OK;
+}
+
+int hww_autotune(hww_handle *h, hww_tune_result *best) {
+  if (!h || !best) return HWW_E_INVALID_ARG;
+  if (h->is_view) return fail(h, HWW_E_STATE, "a replica view is read-only");
+  if (h->fatal) return fail(h, h->fatal, "an earlier error left the problem invalid");
+  if (h->step != 0) return fail(h, HWW_E_STATE, "the tuner runs before the first sweep");
+  std::vector<hww_handle *> reps = h->is_batch ? h->rep : std::vector<hww_handle *>{h};
+  // Save what a trial sweep changes beyond the banks and tally sets that the
+  // first real step clears anyway: the source chunk weights and the counters.
+  std::vector<double> wsave(reps.size() * (size_t)h->nc);
+  const size_t ncnt = reps.size() * 2 * C_NCOUNTERS;
+  std::vector<unsigned long long> csave(ncnt);
+  unsigned long long *cdev = h->is_batch ? h->counters_all : h->counters;
+  for (size_t r = 0; r < reps.size(); ++r)
+    HIPCHK(h, hipMemcpyAsync(wsave.data() + r * h->nc, reps[r]->wnext, 8 * h->nc, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipMemcpyAsync(csave.data(), cdev, 8 * ncnt, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(h, hipEventCreate(&e0));
+  HIPCHK(h, hipEventCreate(&e1));
+  auto clear_cursors = [&]() -> int {
+    if (h->is_batch) {
+      HIPCHK(h, launch_fill_u32(h->cursor_all, 0u, h->n_cur_all, h->stream));
+      HIPCHK(h, launch_fill_u32(h->work, 0u, 2, h->stream));
+    } else {
+      HIPCHK(h, launch_fill_u32(h->cursor, 0u, 2 * (int64_t)h->B, h->stream));
+    }
+    return HWW_OK;
+  };
+  auto trial = [&](int block, int tile, int grid, float *ms) -> int {
+    h->block = block;
+    h->tile = tile;
+    h->grid = grid;
+    int rc = clear_cursors();
+    if (rc != HWW_OK) return rc;
+    flip_banks(h);
+    rc = begin_step(h);
+    if (rc == HWW_OK) rc = check_hip(h, hipEventRecord(e0, h->stream), "event");
+    if (rc == HWW_OK) rc = h->fp32 ? launch_chunk<float>(h, 0, 0) : launch_chunk<double>(h, 0, 0);
+    if (rc == HWW_OK) rc = check_hip(h, hipEventRecord(e1, h->stream), "event");
+    if (rc == HWW_OK) rc = check_hip(h, hipEventSynchronize(e1), "event");
+    if (rc == HWW_OK) rc = check_hip(h, hipEventElapsedTime(ms, e0, e1), "event");
+    flip_banks(h);
+    return rc;
+  };
+  const int blocks[3] = {256, 512, 1024};
+  const int tiles[4] = {64, 128, 256, 512};
+  float best_ms = 0.0f;
+  int bb = h->block, bt = h->tile, bg = h->grid, trials = 0;
+  float ms = 0.0f;
+  int rc = trial(kBlock, kTile, h->is_batch ? default_grid(h, kBlock) : 0, &ms);  // warm-up
+  for (int bi = 0; rc == HWW_OK && bi < 3; ++bi) {
+    std::vector<int> grids;
+    if (h->is_batch) {
+      for (int wpc = 1; wpc <= 4; ++wpc)
+        if ((size_t)wpc * h->lds <= 160 * 1024 && wpc * blocks[bi] <= 2048 && h->cus * wpc <= kGridMax)
+          grids.push_back(h->cus * wpc);
+    } else {
+      grids.push_back(0);
+    }
+    for (int g : grids)
+      for (int ti = 0; rc == HWW_OK && ti < 4; ++ti) {
+        float m = 0.0f, mbest = 1e30f;
+        for (int rep = 0; rc == HWW_OK && rep < 2; ++rep) {
+          rc = trial(blocks[bi], tiles[ti], g, &m);
+          mbest = std::min(mbest, m);
+        }
+        ++trials;
+        if (rc == HWW_OK && (trials == 1 || mbest < best_ms)) {
+          best_ms = mbest;
+          bb = blocks[bi];
+          bt = tiles[ti];
+          bg = g;
+        }
+      }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != HWW_OK) return rc;
+  // Restore the state of step 0.
+  for (size_t r = 0; r < reps.size(); ++r) {
+    HIPCHK(h, hipMemcpyAsync(reps[r]->wnext, wsave.data() + r * h->nc, 8 * h->nc, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, launch_fill_f64(reps[r]->tal[1], 0.0, (int64_t)reps[r]->B * reps[r]->I * 6, h->stream));
+    HIPCHK(h, launch_fill_f64(reps[r]->bnd[1], 0.0, (int64_t)reps[r]->B * 6, h->stream));
+    HIPCHK(h, launch_fill_u32(reinterpret_cast<uint32_t *>(reps[r]->tracks), 0u, 2 * (int64_t)reps[r]->I, h->stream));
+  }
+  HIPCHK(h, hipMemcpyAsync(cdev, csave.data(), 8 * ncnt, hipMemcpyHostToDevice, h->stream));
+  rc = clear_cursors();
+  if (rc != HWW_OK) return rc;
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  h->block = bb;
+  h->tile = bt;
+  h->grid = bg;
+  rc = poll_errors(h);
+  if (rc != HWW_OK) return rc;
+  best->block = bb;
+  best->tile = bt;
+  best->grid = h->is_batch ? bg : h->B * h->K;
+  best->trials = trials;
+  best->ms = best_ms;
+  return HWW_OK;
+}
+
 int hww_sync(hww_handle *h) {
   if (!h) return HWW_E_INVALID_ARG;
   return poll_errors(h);
@@ -851,10 +1425,10 @@ const char *hww_last_error(const hww_handle *h) {
 }
 
 void hww_destroy(hww_handle *h) {
-  if (!h) return;
+  if (!h || h->is_view) return;
   (void)hipStreamSynchronize(h->stream);
-  for (auto &e : h->ev)
-    if (e) (void)hipEventDestroy(e);
+  destroy_events(h);
+  for (hww_handle *r : h->rep) delete r;
   delete h;
 }
 

@@ -20,8 +20,6 @@
 
 namespace hww {
 
-static constexpr int TILE = 256;
-
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of the two published
 // 32x32 -> 64 multiplies; key bumped by the Weyl constants between rounds.
 __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
@@ -225,22 +223,23 @@ __device__ inline void census_append(const Bank<Real> &bk, const BankGeom &G, ui
   if (k >= 0) store_record(bk, k, x, mu, w, lin, src, e, cell);
 }
 
+// One work unit: the particles of chunk A.chunk in the start-bank region of
+// batch b (tiles shared with the other units of the batch through the
+// batch's cursor) and all their daughters, with census appends into segment
+// jseg of the batch's regions.  The work-group's daughter buffers are number
+// qslot of nq.  Starts and ends with the LDS histogram free for reuse.
 template <typename Real>
-__global__ void __launch_bounds__(1024) sweep_kernel(SweepArgs<Real> A) {
-  extern __shared__ double lds_raw[];
+__device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int jseg, int qslot, int nq,
+                                           double *lds_raw) {
   const int I = A.I, nc = A.nc;
   const BankGeom G = A.geom;
   const int K = G.K;
+  const uint32_t TILE = (uint32_t)A.tile;
   Lds L = carve(lds_raw, I, nc, K);
   zero_lds(lds_raw, I, nc, K);
-  const int b = blockIdx.x % A.B;
-  const int jseg = blockIdx.x / A.B;
   const int tid = threadIdx.x;
   const int r_in = b * nc + A.chunk;
   const int64_t in_region = (int64_t)r_in * G.stride;
-  // Tile cursors alternate between two sets; this launch clears the set the
-  // next launch will use.
-  if (blockIdx.x == 0 && tid < A.B) A.cursor_next[tid] = 0u;
   __syncthreads();
   if (tid < nc) L.ccnt[tid] = A.census.segcnt[(b * nc + tid) * K + jseg];
   if (tid == 0) {
@@ -251,7 +250,7 @@ __global__ void __launch_bounds__(1024) sweep_kernel(SweepArgs<Real> A) {
       if (n > cap) n = cap;
       L.nseg[s] = n;
       L.tstart[s] = acc;
-      acc += (n + TILE - 1) / TILE;
+      acc += (n + TILE - 1u) / TILE;
     }
     L.tstart[K + 1] = acc;
   }
@@ -293,7 +292,7 @@ __global__ void __launch_bounds__(1024) sweep_kernel(SweepArgs<Real> A) {
       if (lane == 0) base = atomicAdd(&L.dcnt[out_buf], total);
       base = __shfl(base, 0);
       if ((uint64_t)base + total > (uint64_t)A.dcap && lane == 0) atomicOr(A.err, ERR_CAPACITY);
-      const int64_t qb = ((int64_t)out_buf * gridDim.x + blockIdx.x) * dstride;
+      const int64_t qb = ((int64_t)out_buf * nq + qslot) * dstride;
       const uint32_t start = base + incl - cntd;
       for (uint32_t q = 1; q <= cntd; ++q) {
         const uint64_t slot = (uint64_t)start + (q - 1);
@@ -366,7 +365,7 @@ __global__ void __launch_bounds__(1024) sweep_kernel(SweepArgs<Real> A) {
     const bool from_bank = (gen == 0);
     const int in_buf = (gen + 1) & 1;  // buffer written by the previous generation
     out_buf = gen & 1;
-    const int64_t in_qbase = ((int64_t)in_buf * gridDim.x + blockIdx.x) * dstride;
+    const int64_t in_qbase = ((int64_t)in_buf * nq + qslot) * dstride;
 
     int64_t tile_base = 0;
     uint32_t tile_next = 0, tile_end = 0;
@@ -384,14 +383,14 @@ __global__ void __launch_bounds__(1024) sweep_kernel(SweepArgs<Real> A) {
               if (t < L.tstart[K + 1]) {
                 int s = K;
                 while (L.tstart[s] > t) --s;
-                const uint32_t off = (t - L.tstart[s]) * (uint32_t)TILE;
-                tl = min((uint32_t)TILE, L.nseg[s] - off);
+                const uint32_t off = (t - L.tstart[s]) * TILE;
+                tl = min(TILE, L.nseg[s] - off);
                 tb = in_region + (s < K ? (int64_t)s * G.seg_cap : (int64_t)K * G.seg_cap) + off;
               }
             } else {
-              const uint32_t t0 = atomicAdd(L.dcur, (uint32_t)TILE);
+              const uint32_t t0 = atomicAdd(L.dcur, TILE);
               if (t0 < n_list) {
-                tl = min((uint32_t)TILE, n_list - t0);
+                tl = min(TILE, n_list - t0);
                 tb = in_qbase + t0;
               }
             }
@@ -600,6 +599,58 @@ __global__ void __launch_bounds__(1024) sweep_kernel(SweepArgs<Real> A) {
   flush_tallies(L, I, nc, b, A.tal, A.bnd, A.tracks, A.wnext);
 }
 
+// One problem: grid = B * K work-groups; work-group g is the unit
+// (batch g mod B, segment g / B).
+template <typename Real>
+__global__ void __launch_bounds__(1024) sweep_kernel(SweepArgs<Real> A) {
+  extern __shared__ double lds_raw[];
+  // Tile cursors alternate between two sets; this launch clears the set the
+  // next launch will use.
+  if (blockIdx.x == 0 && (int)threadIdx.x < A.B) A.cursor_next[threadIdx.x] = 0u;
+  sweep_unit<Real>(A, (int)(blockIdx.x % A.B), (int)(blockIdx.x / A.B), (int)blockIdx.x, (int)gridDim.x, lds_raw);
+}
+
+// Many problems (replicas) in one persistent launch: each work-group claims
+// units from the launch's counter until none is left.  The unit table lists
+// the biggest replicas first and the units of one batch next to each other,
+// so the units that share a batch's tiles run at the same time.
+template <typename Real>
+__global__ void __launch_bounds__(1024) sweep_batch_kernel(BatchSweepArgs<Real> P) {
+  extern __shared__ double lds_raw[];
+  __shared__ uint32_t s_unit;
+  const int par = P.par;
+  if (blockIdx.x == 0 && threadIdx.x == 0) P.work[1 - par] = 0u;
+  for (;;) {
+    if (threadIdx.x == 0) s_unit = atomicAdd(&P.work[par], 1u);
+    __syncthreads();
+    const uint32_t u = __builtin_amdgcn_readfirstlane(s_unit);
+    if (u >= P.n_units) break;
+    const uint32_t code = __builtin_amdgcn_readfirstlane(P.units[u]);
+    const int r = (int)(code >> 16), b = (int)((code >> 8) & 0xFFu), jseg = (int)(code & 0xFFu);
+    const ReplicaDesc<Real> &D = P.desc[r];
+    SweepArgs<Real> A;
+    A.I = D.I; A.B = D.B; A.nc = D.nc;
+    A.v = D.v; A.inv_v = D.inv_v; A.dt = D.dt;
+    // The key words feed an asm operand that must live in scalar registers.
+    A.seed = __builtin_amdgcn_readfirstlane(D.seed);
+    A.key1 = __builtin_amdgcn_readfirstlane(D.key1);
+    A.cells = D.cells; A.win = D.win;
+    A.ww_on = P.ww_on; A.chunk = P.chunk; A.tile = P.tile;
+    A.geom = D.geom;
+    A.in_bank = D.bank[P.start_bank];
+    A.census = D.bank[1 - P.start_bank];
+    A.dq = P.dq; A.dcap = P.dcap;
+    A.cursor = D.cursor + par * D.B;
+    A.cursor_next = D.cursor + (1 - par) * D.B;
+    A.tal = D.tal[P.start_bank]; A.bnd = D.bnd[P.start_bank];
+    A.tracks = D.tracks; A.counters = D.counters; A.wnext = D.wnext;
+    A.err = P.err;
+    if (jseg == 0 && threadIdx.x == 0) A.cursor_next[b] = 0u;
+    sweep_unit<Real>(A, b, jseg, (int)blockIdx.x, (int)gridDim.x, lds_raw);
+    __syncthreads();
+  }
+}
+
 // Source bank at t^0 (Sec. 5.1): unit-weight particles at src_x with
 // isotropic directions from slot 3, appended to the census region of their
 // batch and of their step-1 chunk; their census moments are the step-1
@@ -653,7 +704,7 @@ __global__ void __launch_bounds__(1024) source_kernel(SourceArgs A, Bank<Real> b
 
 // Clear the accumulators of a new time step and hand the census chunk
 // weights of the finished step to the new one (one launch).
-__global__ void begin_step_kernel(BeginStepArgs A) {
+__device__ inline void begin_step_body(const BeginStepArgs &A) {
   const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t st = (int64_t)gridDim.x * blockDim.x;
   for (int64_t j = t0; j < A.n_seg; j += st) A.segcnt[j] = 0u;
@@ -667,6 +718,11 @@ __global__ void begin_step_kernel(BeginStepArgs A) {
     A.wnext[t0] = 0.0;
   }
 }
+
+__global__ void begin_step_kernel(BeginStepArgs A) { begin_step_body(A); }
+
+// All replicas of a batch: row blockIdx.y of the grid serves replica y.
+__global__ void begin_step_batch_kernel(const BeginStepArgs *tab) { begin_step_body(tab[blockIdx.y]); }
 
 __global__ void fill_u32_kernel(uint32_t *p, uint32_t v, int64_t n) {
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
@@ -712,6 +768,17 @@ hipError_t launch_source(const SourceArgs &a, const Bank<Real> &bank, int grid, 
   return hipGetLastError();
 }
 
+template <typename Real>
+hipError_t launch_sweep_batch(const BatchSweepArgs<Real> &a, int grid, int block, size_t lds, hipStream_t s) {
+  static size_t done = 64 * 1024;
+  hipError_t e = allow_lds(reinterpret_cast<const void *>(&sweep_batch_kernel<Real>), lds, &done);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(sweep_batch_kernel<Real>, dim3(grid), dim3(block), lds, s, a);
+  return hipGetLastError();
+}
+
+template hipError_t launch_sweep_batch<double>(const BatchSweepArgs<double> &, int, int, size_t, hipStream_t);
+template hipError_t launch_sweep_batch<float>(const BatchSweepArgs<float> &, int, int, size_t, hipStream_t);
 template hipError_t launch_sweep<double>(const SweepArgs<double> &, int, int, size_t, hipStream_t);
 template hipError_t launch_sweep<float>(const SweepArgs<float> &, int, int, size_t, hipStream_t);
 template hipError_t launch_source<double>(const SourceArgs &, const Bank<double> &, int, int, size_t, hipStream_t);
@@ -738,6 +805,14 @@ hipError_t launch_begin_step(const BeginStepArgs &a, hipStream_t s) {
   if (g < 1) g = 1;
   if (g > 1024) g = 1024;
   hipLaunchKernelGGL(begin_step_kernel, dim3((unsigned)g), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_begin_step_batch(const BeginStepArgs *tab, int n, int64_t max_tal, hipStream_t s) {
+  int64_t g = (max_tal + 255) / 256;
+  if (g < 1) g = 1;
+  if (g > 64) g = 64;
+  hipLaunchKernelGGL(begin_step_batch_kernel, dim3((unsigned)g, (unsigned)n), dim3(256), 0, s, tab);
   return hipGetLastError();
 }
 

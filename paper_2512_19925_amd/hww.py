@@ -26,7 +26,8 @@ TALLY_CELLS, TALLY_BOUNDARY, TALLY_TRACKS, TALLY_PREV_CELLS, TALLY_PREV_BOUNDARY
 # Every symbol include/hww.h declares.
 EXPORTS = ["hww_workspace_bytes", "hww_init_problem", "hww_set_windows", "hww_sweep_step",
            "hww_read_run_stats", "hww_solve_losm", "hww_read_closures", "hww_losm_march", "hww_losm_adjoint",
-           "hww_read_tallies", "hww_read_bank", "hww_sync", "hww_last_error", "hww_destroy"]
+           "hww_read_tallies", "hww_read_bank", "hww_batch_workspace_bytes", "hww_init_batch",
+           "hww_batch_replica", "hww_autotune", "hww_sync", "hww_last_error", "hww_destroy"]
 
 
 class HwwError(RuntimeError):
@@ -61,6 +62,14 @@ class LosmOpts(C.Structure):
                 ("closure_track", C.c_int32), ("apply_windows", C.c_int32)]
 
 
+class TuneResult(C.Structure):
+    _fields_ = [("block", C.c_int32), ("tile", C.c_int32), ("grid", C.c_int32), ("trials", C.c_int32),
+                ("ms", C.c_double)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -85,6 +94,11 @@ def lib():
         L.hww_losm_march.argtypes = [vp, dp, dp, C.c_double, C.c_int32] + [dp] * 8
         L.hww_losm_adjoint.argtypes = [vp, dp, dp]
         L.hww_read_bank.argtypes = [vp, C.c_int32, C.c_int64, C.POINTER(C.c_int64)] + [vp] * 8
+        L.hww_batch_workspace_bytes.argtypes = [C.POINTER(Problem), C.c_int32]
+        L.hww_batch_workspace_bytes.restype = C.c_int64
+        L.hww_init_batch.argtypes = [C.POINTER(Problem), C.c_int32, vp, C.c_int64, vp, C.POINTER(vp)]
+        L.hww_batch_replica.argtypes = [vp, C.c_int32, C.POINTER(vp)]
+        L.hww_autotune.argtypes = [vp, C.POINTER(TuneResult)]
         L.hww_sync.argtypes = [vp]
         L.hww_last_error.argtypes = [vp]
         L.hww_last_error.restype = C.c_char_p
@@ -139,6 +153,18 @@ def workspace_bytes(spec: ProblemSpec) -> int:
 class Handle:
     """One problem on the GPU.  Owns its torch workspace tensor."""
 
+    @classmethod
+    def _view(cls, ptr, spec, owner):
+        """Read-only view of one replica of a Batch (owned by the batch)."""
+        v = cls.__new__(cls)
+        v.spec = spec
+        v.I = len(spec.sigma_t)
+        v.B = int(spec.n_batches)
+        v.n_chunks = int(spec.n_chunks)
+        v._h = ptr
+        v._owner = owner
+        return v
+
     def __init__(self, spec: ProblemSpec, device="cuda", stream=None):
         import torch
         self.spec = spec
@@ -162,9 +188,18 @@ class Handle:
             raise HwwError(where, rc, lib().hww_last_error(self._h).decode())
 
     def close(self):
+        if getattr(self, "_owner", None) is not None:
+            self._h = None  # a view: the batch owns it
+            return
         if getattr(self, "_h", None):
             lib().hww_destroy(self._h)
             self._h = None
+
+    def autotune(self):
+        """Pick the fastest sweep launch shape (before the first sweep)."""
+        r = TuneResult()
+        self._check("hww_autotune", lib().hww_autotune(self._h, C.byref(r)))
+        return r.as_dict()
 
     def __del__(self):
         try:
@@ -248,6 +283,115 @@ class Handle:
         gt, gs = np.zeros(self.I), np.zeros(self.I)
         self._check("hww_losm_adjoint", lib().hww_losm_adjoint(self._h, _dp(gt), _dp(gs)))
         return gt, gs
+
+    def sync(self):
+        self._check("hww_sync", lib().hww_sync(self._h))
+
+
+class Batch:
+    """Many replicas of uneven size in one handle: one persistent sweep launch
+    per chunk and one batched LOSM launch per solve for all of them."""
+
+    def __init__(self, specs, device="cuda", stream=None):
+        import torch
+        self.specs = list(specs)
+        self.n = len(self.specs)
+        self.I = [len(s.sigma_t) for s in self.specs]
+        self.B = [int(s.n_batches) for s in self.specs]
+        self.n_chunks = int(self.specs[0].n_chunks)
+        self._probs = (Problem * self.n)(*[s.to_c() for s in self.specs])
+        nbytes = lib().hww_batch_workspace_bytes(self._probs, self.n)
+        if nbytes < 0:
+            raise HwwError("hww_batch_workspace_bytes", nbytes)
+        self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.workspace.device)
+        h = C.c_void_p()
+        rc = lib().hww_init_batch(self._probs, self.n, C.c_void_p(self.workspace.data_ptr()), int(nbytes),
+                                  C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if rc != HWW_OK:
+            raise HwwError("hww_init_batch", rc, lib().hww_last_error(None).decode())
+        self._h = h
+        self._views = {}
+
+    def _check(self, where, rc):
+        if rc != HWW_OK:
+            raise HwwError(where, rc, lib().hww_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            for v in self._views.values():
+                v._h = None
+            lib().hww_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def replica(self, r) -> Handle:
+        """Read-only Handle of replica r (tallies, bank, closures)."""
+        if r not in self._views:
+            v = C.c_void_p()
+            self._check("hww_batch_replica", lib().hww_batch_replica(self._h, int(r), C.byref(v)))
+            self._views[r] = Handle._view(v, self.specs[r], self)
+        return self._views[r]
+
+    def set_windows(self, centres, rho):
+        if centres is None:
+            self._check("hww_set_windows", lib().hww_set_windows(self._h, None, float(rho)))
+            return
+        c = _f64(np.concatenate([np.asarray(x, dtype=np.float64) for x in centres]))
+        assert c.shape == (sum(self.I),)
+        self._check("hww_set_windows", lib().hww_set_windows(self._h, _dp(c), float(rho)))
+
+    def sweep_step(self, step, chunk, stats=True):
+        st = StepStats() if stats else None
+        self._check("hww_sweep_step", lib().hww_sweep_step(self._h, int(step), int(chunk),
+                                                           C.byref(st) if st is not None else None))
+        return st.as_dict() if st is not None else None
+
+    def run_stats(self):
+        st = StepStats()
+        self._check("hww_read_run_stats", lib().hww_read_run_stats(self._h, C.byref(st)))
+        return st.as_dict()
+
+    def solve_losm(self, theta=0.5, implicit=False, filter=0, ma_k=3, eps_min=1e-3, rho=5.0,
+                   closure_track=0, apply_windows=True, want_solution=False):
+        o = LosmOpts(float(theta), int(implicit), int(filter), int(ma_k), float(eps_min), float(rho),
+                     int(closure_track), int(apply_windows))
+        phi = np.zeros(sum(i + 2 for i in self.I)) if want_solution else None
+        J = np.zeros(sum(i + 1 for i in self.I)) if want_solution else None
+        self._check("hww_solve_losm", lib().hww_solve_losm(self._h, C.byref(o), _dp(phi), _dp(J)))
+        if not want_solution:
+            return None
+        ps = np.split(phi, np.cumsum([i + 2 for i in self.I])[:-1])
+        js = np.split(J, np.cumsum([i + 1 for i in self.I])[:-1])
+        return ps, js
+
+    def read_tallies(self, kind=TALLY_CELLS):
+        """List of per-replica arrays (same shapes as Handle.read_tallies)."""
+        def shape(I, B):
+            return {TALLY_CELLS: ((B, I, 6), np.float64), TALLY_BOUNDARY: ((B, 2, 3), np.float64),
+                    TALLY_TRACKS: ((I,), np.uint64), TALLY_PREV_CELLS: ((B, I, 6), np.float64),
+                    TALLY_PREV_BOUNDARY: ((B, 2, 3), np.float64), TALLY_WINDOWS: ((3, I), np.float64),
+                    TALLY_BANK_COUNTS: ((2,), np.uint64)}[kind]
+        shapes = [shape(I, B) for I, B in zip(self.I, self.B)]
+        sizes = [int(np.prod(sh)) * 8 for sh, _ in shapes]
+        buf = np.zeros(sum(sizes), dtype=np.uint8)
+        self._check("hww_read_tallies", lib().hww_read_tallies(self._h, int(kind), buf.ctypes.data, buf.nbytes))
+        out, o = [], 0
+        for (sh, dt), sz in zip(shapes, sizes):
+            out.append(buf[o:o + sz].view(dt).reshape(sh).copy())
+            o += sz
+        return out
+
+    def autotune(self):
+        """Pick the fastest persistent launch shape (before the first sweep)."""
+        r = TuneResult()
+        self._check("hww_autotune", lib().hww_autotune(self._h, C.byref(r)))
+        return r.as_dict()
 
     def sync(self):
         self._check("hww_sync", lib().hww_sync(self._h))

@@ -46,3 +46,30 @@ def test_workspace_bytes_and_validation():
         with pytest.raises(H.HwwError) as ei:
             H.workspace_bytes(spec)
         assert ei.value.code == -1
+
+
+def _batch_bytes(specs):
+    probs = (H.Problem * len(specs))(*[s.to_c() for s in specs])
+    return H.lib().hww_batch_workspace_bytes(probs, len(specs))
+
+
+def test_batch_workspace_bytes_and_validation():
+    ws = W.batched_replicas(n_replicas=16)
+    specs = [H.spec_from_workload(w) for w in ws]
+    n = _batch_bytes(specs)
+    assert n > 0 and n % 256 == 0
+    # The batch holds every replica's banks and tallies.
+    assert n > sum(w.n_src for w in ws) * 44 * 2
+    # Replicas must share precision, chunk count and step count.
+    for kw in (dict(n_chunks=3), dict(precision=H.HWW_FP32), dict(n_steps=7)):
+        bad = list(specs)
+        bad[5] = H.spec_from_workload(ws[5])
+        for k, v in kw.items():
+            setattr(bad[5], k, v)
+        assert _batch_bytes(bad) == -1
+    # An invalid replica invalidates the batch.
+    bad = list(specs)
+    bad[3] = H.spec_from_workload(ws[3])
+    bad[3].n_batches = 0
+    assert _batch_bytes(bad) == -1
+    assert _batch_bytes([]) == -1
