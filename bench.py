@@ -9,14 +9,18 @@ histories with their daughters, and three fully implicit solves.
 Prints one JSON line: particle segments/s over the timed steps (inputs
 resident in HBM), the sweep kernel's HBM-roofline figures measured with HIP
 events on the library's stream, the figure-of-merit gain over the plain
-(analog) FP64 sweep of the same problem, and the CPU oracle timed on a
-bounded sample of the same workload.
+(analog) FP64 sweep of the same problem, the CPU oracle timed on a bounded
+sample of the same workload, and two side figures: the batched form (256
+uneven replicas, one persistent launch per chunk) against one handle per
+replica, and the FP32 flight arithmetic against FP64 on the precision form.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -27,6 +31,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "particle segments/s and FOM per time step vs plain FP64 sweep, 1 MI355X"
 HBM_PEAK_GBS = 8000.0
+# HBM traffic of the sweep kernel measured by rocprofv3 on this same command
+# (FETCH_SIZE and WRITE_SIZE, scaled by a plain-copy calibration); valid only
+# for the kernel sources it was measured on.
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "sweep_full-1000c-c0.9-rho5_hbm_traffic.md")
+SWEEP_SOURCES = [os.path.join(ROOT, "paper_2512_19925_amd", "csrc", f) for f in ("hww_sweep.hip", "hww_internal.h")]
 
 
 def parse():
@@ -40,6 +49,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-analog", action="store_true", help="skip the plain-sweep FOM comparison")
     ap.add_argument("--sweep", action="store_true", help="also run every (c, rho) pair of the workload")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-form figures")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 figures")
+    ap.add_argument("--batch-steps", type=int, default=50)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--out", default=None, help="also write per-step records (JSON) here")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -121,11 +133,125 @@ def run_fom(w, steps_total, warmup, analog):
     return foms
 
 
+def sweep_source_hash():
+    h = hashlib.sha256()
+    for f in SWEEP_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per sweep launch from the committed rocprofv3 summary, or
+    None when the kernel sources differ from the measured ones."""
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    m_hash = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", text)
+    m_val = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m_hash or not m_val or m_hash.group(1) != sweep_source_hash():
+        return None
+    return float(m_val.group(1))
+
+
+def _batch_steps(bt, steps, kw, first=1):
+    for n in range(first, steps + 1):
+        bt.solve_losm(implicit=False, **kw)
+        for p in range(bt.n_chunks):
+            bt.sweep_step(n, p, stats=False)
+            if p < bt.n_chunks - 1:
+                bt.solve_losm(implicit=True, **kw)
+
+
+def run_batched(steps, compare_steps=10):
+    """The batched form: 256 uneven replicas, one persistent sweep launch per
+    chunk and one batched LOSM launch per solve, launch shape autotuned.
+    Compared with one handle per replica run one after another over the
+    first compare_steps steps."""
+    import torch
+    from paper_2512_19925_amd import hww as H
+    from paper_2512_19925_amd import workloads as W
+    ws = W.batched_replicas(n_steps=steps)
+    w0 = ws[0]
+    kw = dict(theta=w0.theta, filter=w0.filter, ma_k=w0.ma_k, eps_min=w0.eps_min, rho=w0.rho,
+              closure_track=w0.closure_track)
+    bt = H.Batch([H.spec_from_workload(w) for w in ws])
+    tune = bt.autotune()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _batch_steps(bt, compare_steps, kw)
+    torch.cuda.synchronize()
+    wall_cmp = time.perf_counter() - t0
+    seg_cmp = bt.run_stats()["segments"]
+    t1 = time.perf_counter()
+    _batch_steps(bt, steps, kw, first=compare_steps + 1)
+    torch.cuda.synchronize()
+    wall = wall_cmp + (time.perf_counter() - t1)
+    st = bt.run_stats()
+    bt.close()
+    del bt
+    torch.cuda.empty_cache()
+    # One handle per replica, same steps.
+    seg_single, wall_single = 0, 0.0
+    for w in ws:
+        h = H.Handle(H.spec_from_workload(w))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for n in range(1, compare_steps + 1):
+            h.solve_losm(implicit=False, **kw)
+            for p in range(h.n_chunks):
+                h.sweep_step(n, p, stats=False)
+                if p < h.n_chunks - 1:
+                    h.solve_losm(implicit=True, **kw)
+        torch.cuda.synchronize()
+        wall_single += time.perf_counter() - t0
+        seg_single += h.run_stats()["segments"]
+        h.close()
+        del h
+    torch.cuda.empty_cache()
+    return {"workload": f"{len(ws)} replicas, sigma_t~U[0.5,2], c~U[0.3,0.99], cells~logU[100,2000], "
+                        f"particles~logU[1e3,1e6] (sum {sum(w.n_src for w in ws)}), [-20,20], dt=0.1, "
+                        f"{steps} steps, HWW rho=5 eps_min=1e-3 MA k=3, 3 window updates per step",
+            "segments_per_s": st["segments"] / wall, "ms_per_step": wall * 1e3 / steps,
+            "kernel_segments_per_s": st["segments"] / (st["kernel_ms"] * 1e-3) if st["kernel_ms"] else None,
+            "kernel_achieved_GBs": st["bytes_moved"] / (st["kernel_ms"] * 1e-3) / 1e9 if st["kernel_ms"] else None,
+            "autotune": tune,
+            "steps_1_to_%d" % compare_steps: {
+                "batched_segments_per_s": seg_cmp / wall_cmp,
+                "one_handle_per_replica_segments_per_s": seg_single / wall_single,
+                "speedup": (seg_cmp / wall_cmp) / (seg_single / wall_single)}}
+
+
+def run_fp32_pair(steps=20, n_src=10_000_000):
+    """FP32 against FP64 flight arithmetic on the precision form (the small
+    problem's geometry with 1e7 particles), HWW as the small problem."""
+    from paper_2512_19925_amd import hww as H
+    from paper_2512_19925_amd import workloads as W
+    w = W.precision_form(n_src=n_src)
+    out = {"workload": f"{w.name}: {w.n_cells} cells on [{w.x_lo},{w.x_hi}], c=0.9, {n_src:.0e} particles, "
+                       f"dt={w.dt}, steps 1-{steps}, HWW rho={w.rho} unfiltered"}
+    for prec, name in ((H.HWW_FP32, "fp32"), (H.HWW_FP64, "fp64")):
+        import torch
+        h = H.Handle(H.spec_from_workload(w, precision=prec))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        H.run(h, w, steps=steps, stats=False)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st = h.run_stats()
+        h.close()
+        out[f"{name}_segments_per_s"] = st["segments"] / wall
+        out[f"{name}_kernel_segments_per_s"] = st["segments"] / (st["kernel_ms"] * 1e-3)
+    out["fp32_over_fp64_kernel"] = out["fp32_kernel_segments_per_s"] / out["fp64_kernel_segments_per_s"]
+    return out
+
+
 def cpu_baseline(w, budget_s):
     """The oracle, as it stands, on a bounded sample: the same problem with
     fewer source particles, as many steps as fit in about budget_s."""
     from oracle import oracle as O
-    frac = 10
+    frac = 4
     n = max(w.n_src // frac, 1000)
     ws = w.with_(n_src=n, bank_capacity=4 * n + 4096)
     sim = O.OracleSim(ws.edges, ws.sigma_t, ws.sigma_s, ws.speed, ws.dt, ws.n_steps, ws.src_x, ws.n_src,
@@ -191,7 +317,7 @@ def main():
                    "n_src": w.n_src, "n_cells": w.n_cells, "time_steps": args.steps},
         "kernel_segments_per_s": hww["segments"] / (hww["kernel_ms"] * 1e-3) if hww["kernel_ms"] else None,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "sweep_kernel<double>",
                      "launches": hww["launches"], "avg_launch_ms": hww["kernel_ms"] / max(hww["launches"], 1),
                      "bytes_per_launch": hww["bytes_moved"] / max(hww["launches"], 1)},
@@ -206,6 +332,10 @@ def main():
                        "hww_over_plain_first_last": [ratio[0], ratio[-1]] if ratio else None,
                        "plain_segments_per_s": ana["segments"] / ana["wall_s"],
                        "plain_ms_per_step": ana["wall_s"] * 1e3 / args.steps}
+    if not args.no_batch:
+        line["batched"] = run_batched(args.batch_steps)
+    if not args.no_fp32:
+        line["fp32"] = run_fp32_pair()
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     if args.out:

@@ -51,6 +51,22 @@ __device__ __forceinline__ void draw(uint32_t seed, uint32_t key1, int slot, uin
   philox4x32_10(r, k0, k1);
 }
 
+// Same draw with a slot that differs between lanes (the key's second word
+// then lives in a vector register).
+__device__ __forceinline__ void draw_lane(uint32_t seed, uint32_t key1, int slot, uint32_t src,
+                                          uint64_t lin, uint32_t e, uint32_t r[4]) {
+  r[0] = src;
+  r[1] = (uint32_t)lin;
+  r[2] = (uint32_t)(lin >> 32);
+  r[3] = e;
+  uint32_t k0 = seed, k1 = key1 | (uint32_t)slot;
+  asm volatile("" : "+s"(k0), "+v"(k1));
+  philox4x32_10(r, k0, k1);
+}
+
+// Window and event actions of a lane (bit flags).
+enum : uint32_t { WW_ROULETTE = 1u, WW_SPLIT = 2u, EV_DRAW = 4u, EV_SCATTER = 8u };
+
 // 53-bit uniform on [0,1) from the high bits of two words.
 __device__ __forceinline__ double u53(uint32_t a, uint32_t b) {
   const double k = (double)(a >> 5) * 67108864.0 + (double)(b >> 6);
@@ -89,10 +105,17 @@ __device__ __forceinline__ int32_t find_cell(const double *edges, int I, double 
   return lo;
 }
 
-struct LaneCounters {
-  uint32_t segments, collisions, scatters, absorptions, crossings, leaks, census;
-  uint32_t splits, daughters, rr_kill, rr_survive, histories;
+// Events of a lane in one pass of the event loop (bit flags), counted per
+// wave by ballots: no per-lane counter registers.  A lane can pass a
+// start-of-step check and a post-event check in the same pass, so the
+// start-of-step outcomes that leave it alive have bits of their own.
+enum : uint32_t {
+  EVB_CENSUS = 1u, EVB_LEAK = 2u, EVB_CROSS = 4u, EVB_SCATTER = 8u, EVB_ABSORB = 16u,
+  EVB_RR_SURVIVE = 32u, EVB_RR_KILL = 64u, EVB_SPLIT = 128u, EVB_START_SURVIVE = 256u, EVB_START_SPLIT = 512u
 };
+constexpr int kEventKinds = 10;
+__device__ constexpr int kEventSlot[kEventKinds] = {C_CENSUS, C_LEAKS, C_CROSSINGS, C_SCATTERS, C_ABSORPTIONS,
+                                                    C_RR_SURVIVE, C_RR_KILL, C_SPLITS, C_RR_SURVIVE, C_SPLITS};
 
 // Shared-memory carve-up common to the sweep and source kernels.
 struct Lds {
@@ -269,12 +292,23 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
   uint32_t src = 0, e = 0;
   uint64_t lin = 0;
   bool active = false;
+  uint32_t start_act = 0u;  // start-of-step window action of a lane just loaded
   // Pending split of this lane: the daughters copy the lane state.
   uint32_t nd = 0;
   uint64_t lin_base = 0;
   uint32_t e_d = 0;
-  LaneCounters C = {};
+  uint32_t evb = 0u;  // EVB_* events not yet counted
   int out_buf = 0;
+
+  // Add the wave's pending events to the work-group counters (converged).
+  auto count_events = [&]() {
+#pragma unroll
+    for (int q = 0; q < kEventKinds; ++q) {
+      const uint64_t m = __ballot(((evb >> q) & 1u) != 0u);
+      if (m != 0 && lane == 0) atomicAdd(&L.cnt[kEventSlot[q]], (uint32_t)__popcll(m));
+    }
+    evb = 0u;
+  };
 
   // Write the pending daughters of all lanes of the wave into the work-
   // group's buffer `out_buf` (converged call).
@@ -288,6 +322,7 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
     }
     const uint32_t total = __shfl(incl, 63);
     if (total != 0) {
+      if (lane == 0) atomicAdd(&L.cnt[C_DAUGHTERS], total);
       uint32_t base = 0;
       if (lane == 0) base = atomicAdd(&L.dcnt[out_buf], total);
       base = __shfl(base, 0);
@@ -317,46 +352,50 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
     nd = 0;
   };
 
-  // Weight-window check of the lane's particle in its cell (Sec. 2).
-  // kind 0: after an event at index e_ev; kind 1: start of step.
-  auto ww_check = [&](int kind, uint32_t e_ev, uint32_t e_daughter, int xi_slot, bool have_xi, double xi) {
-    if (!A.ww_on) return;
+  // Weight-window check of the lane's particle in its cell (Sec. 2), in
+  // two parts so that the random draws of all lanes of a wave are made by
+  // one converged call per kind.  classify() decides from the weight alone:
+  // 0 inside the window, WW_ROULETTE below the floor, WW_SPLIT above the
+  // ceiling (an impossible split raises an error and ends the particle).
+  auto classify = [&]() -> uint32_t {
+    if (!A.ww_on) return 0u;
     const Window wd = A.win[cell];
-    const double ww = wd.ww;
     if (w > wd.ceil) {
-      const double ndf = ceil(w / ww);
+      const double ndf = ceil(w / wd.ww);
       if (!(ndf >= 2.0) || ndf > 1.0e9) {
         atomicOr(A.err, ERR_SPLIT);
         active = false;
-        return;
+        return 0u;
       }
       if (ndf - 1.0 > (double)A.dcap) {
         atomicOr(A.err, ERR_CAPACITY);
         active = false;
-        return;
+        return 0u;
       }
-      uint32_t r[4];
-      draw(A.seed, A.key1, kind == 0 ? SLOT_LIN_EVENT : SLOT_LIN_START, src, lin, e_ev, r);
-      lin_base = (uint64_t)r[0] | ((uint64_t)r[1] << 32);
-      nd = (uint32_t)ndf;
-      w = w / ndf;
-      e_d = e_daughter;
-      C.splits += 1;
-      C.daughters += nd - 1;
-    } else if (w < wd.floor) {
-      if (!have_xi) {
-        uint32_t r[4];
-        draw(A.seed, A.key1, xi_slot, src, lin, e_ev, r);
-        xi = u53(r[2], r[3]);
-      }
-      if (xi < w / ww) {
-        w = ww;
-        C.rr_survive += 1;
-      } else {
-        C.rr_kill += 1;
-        active = false;
-      }
+      return WW_SPLIT;
     }
+    return w < wd.floor ? WW_ROULETTE : 0u;
+  };
+  // Roulette with the uniform xi: survive at the window centre or die.
+  auto roulette = [&](double xi, bool at_start) {
+    const double ww = A.win[cell].ww;
+    if (xi < w / ww) {
+      w = ww;
+      evb |= at_start ? EVB_START_SURVIVE : EVB_RR_SURVIVE;
+    } else {
+      evb |= EVB_RR_KILL;
+      active = false;
+    }
+  };
+  // Split into N_d = ceil(w / ww) equal daughters; the lane keeps daughter
+  // 0, the others take lineage base + j and the event index e_daughter.
+  auto split = [&](const uint32_t r[4], uint32_t e_daughter, bool at_start) {
+    const double ndf = ceil(w / A.win[cell].ww);
+    lin_base = (uint64_t)r[0] | ((uint64_t)r[1] << 32);
+    nd = (uint32_t)ndf;
+    w = w / ndf;
+    e_d = e_daughter;
+    evb |= at_start ? EVB_START_SPLIT : EVB_SPLIT;
   };
 
   int gen = 0;
@@ -423,8 +462,7 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
               cell = tg.cell;
               tau = dt_r;
               active = true;
-              C.histories += 1;
-              ww_check(1, e, e, SLOT_START, false, 0.0);
+              start_act = classify();
             } else {
               const XMu<Real> xm = A.dq.xm[k];
               const WTau wt = A.dq.wt[k];
@@ -440,11 +478,24 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
               active = true;
             }
           }
+          if (from_bank && lane == 0) atomicAdd(&L.cnt[C_HISTORIES], take);
           tile_next += take;
         }
+        // Start-of-step checks of the lanes just loaded: one draw, from
+        // slot 2 (roulette) or slot 5 (lineage of a split) per lane.
+        if (__ballot(start_act != 0u) != 0) {
+          if (start_act != 0u) {
+            uint32_t r[4];
+            draw_lane(A.seed, A.key1, start_act == WW_SPLIT ? SLOT_LIN_START : SLOT_START, src, lin, e, r);
+            if (start_act == WW_SPLIT) split(r, e, true);
+            else roulette(u53(r[2], r[3]), true);
+          }
+        }
+        start_act = 0u;
         flush_daughters();
       }
       if (__ballot(active) == 0) {
+        count_events();
         if (exhausted && tile_next == tile_end) break;
         continue;
       }
@@ -452,6 +503,8 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
       // --------------------------------------------------------- segment --
       bool at_census = false;
       int32_t next_chunk = 0;
+      uint32_t act = 0u;  // EV_DRAW | EV_SCATTER | WW_ROULETTE | WW_SPLIT
+      uint32_t e_ev = 0u;
       if (active) {
         const int i = cell;
         uint32_t r[4];
@@ -480,8 +533,7 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
         atomicAdd(&L.hist[i * 6 + 1], t1);
         atomicAdd(&L.hist[i * 6 + 2], t1 * (double)mu);
         atomicAdd(&L.trk[i], 1u);
-        C.segments += 1;
-        const uint32_t e_ev = e;
+        e_ev = e;
         e = e_ev + 1;
 
         if (ev == 0) {
@@ -500,7 +552,7 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
           atomicAdd(&L.hist[i * 6 + 4], c1);
           atomicAdd(&L.hist[i * 6 + 5], c1 * (double)mu);
           atomicAdd(&L.wnext[next_chunk], w);
-          C.census += 1;
+          evb |= EVB_CENSUS;
           at_census = true;
           active = false;
         } else {
@@ -516,31 +568,48 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
               atomicAdd(&f[0], w / am);
               atomicAdd(&f[1], w * (0.5 - am) / am);
               atomicAdd(&f[2], w * (1.0 / 3.0 - mud * mud) / am);
-              C.leaks += 1;
+              evb |= EVB_LEAK;
               active = false;
             } else {
               if (mu > (Real)0) { x = xr; cell = i + 1; }
               else { x = xl; cell = i - 1; }
-              C.crossings += 1;
-              ww_check(0, e_ev, e, SLOT_EVENT, false, 0.0);
+              evb |= EVB_CROSS;
+              act = classify();
+              if (act == WW_ROULETTE) act |= EV_DRAW;
             }
           } else {
             Real xn = x + mu * l;
             if (xn < xl) xn = xl;
             if (xn > xr) xn = xr;
             x = xn;
-            C.collisions += 1;
             if (ub < cd.c) {
-              uint32_t r1[4];
-              draw(A.seed, A.key1, SLOT_EVENT, src, lin, e_ev, r1);
-              mu = (Real)2 * uflight<Real>(r1[0], r1[1]) - (Real)1;
-              C.scatters += 1;
-              ww_check(0, e_ev, e, SLOT_EVENT, true, u53(r1[2], r1[3]));
+              evb |= EVB_SCATTER;
+              act = classify() | EV_DRAW | EV_SCATTER;
             } else {
-              C.absorptions += 1;
+              evb |= EVB_ABSORB;
               active = false;
             }
           }
+        }
+      }
+
+      // Post-event draws, one converged call per kind: slot 1 gives the
+      // scattering direction (first variate) and the roulette uniform
+      // (second); slot 4 gives the lineage base of a split.  The window
+      // check follows the new direction, as in the serial order.
+      if (__ballot((act & EV_DRAW) != 0u) != 0) {
+        if ((act & EV_DRAW) != 0u) {
+          uint32_t r1[4];
+          draw(A.seed, A.key1, SLOT_EVENT, src, lin, e_ev, r1);
+          if (act & EV_SCATTER) mu = (Real)2 * uflight<Real>(r1[0], r1[1]) - (Real)1;
+          if (act & WW_ROULETTE) roulette(u53(r1[2], r1[3]), false);
+        }
+      }
+      if (__ballot((act & WW_SPLIT) != 0u) != 0) {
+        if ((act & WW_SPLIT) != 0u) {
+          uint32_t r2[4];
+          draw(A.seed, A.key1, SLOT_LIN_EVENT, src, lin, e_ev, r2);
+          split(r2, e, false);
         }
       }
 
@@ -548,6 +617,12 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
       census_append(A.census, G, L.ccnt, &A.census.ovfcnt[b * nc], (int64_t)(b * nc) * G.stride, nc, jseg,
                     at_census, next_chunk, x, mu, w, lin, src, e, cell, A.err);
       if (__ballot(nd > 1) != 0) flush_daughters();
+      count_events();
+      // Nothing of a split outlives the pass (this keeps the split state
+      // out of the registers carried around the loop).
+      nd = 0;
+      lin_base = 0;
+      e_d = 0;
     }
 
     // ------------------------------------------- next daughter generation --
@@ -568,17 +643,12 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
     ++gen;
   }
 
-  // Per-wave counter reduction into LDS.
-  {
-    uint32_t vals[12] = {C.segments, C.collisions, C.scatters, C.absorptions, C.crossings, C.leaks,
-                         C.census, C.splits, C.daughters, C.rr_kill, C.rr_survive, C.histories};
-#pragma unroll
-    for (int q = 0; q < 12; ++q) {
-      uint32_t s = vals[q];
-#pragma unroll
-      for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
-      if (lane == 0 && s != 0) atomicAdd(&L.cnt[q], s);
-    }
+  // Every segment ends in exactly one of census, leak, crossing or collision
+  // (scatter or absorption).
+  __syncthreads();
+  if (tid == 0) {
+    L.cnt[C_COLLISIONS] = L.cnt[C_SCATTERS] + L.cnt[C_ABSORPTIONS];
+    L.cnt[C_SEGMENTS] = L.cnt[C_CENSUS] + L.cnt[C_LEAKS] + L.cnt[C_CROSSINGS] + L.cnt[C_COLLISIONS];
   }
   __syncthreads();
   if (tid < nc) {
@@ -615,7 +685,9 @@ __global__ void __launch_bounds__(1024) sweep_kernel(SweepArgs<Real> A) {
 // the biggest replicas first and the units of one batch next to each other,
 // so the units that share a batch's tiles run at the same time.
 template <typename Real>
-__global__ void __launch_bounds__(1024) sweep_batch_kernel(BatchSweepArgs<Real> P) {
+__global__ void __launch_bounds__(1024) sweep_batch_kernel(BatchSweepArgs<Real> P,
+                                                           const ReplicaDesc<Real> *__restrict__ desc,
+                                                           const uint32_t *__restrict__ units) {
   extern __shared__ double lds_raw[];
   __shared__ uint32_t s_unit;
   const int par = P.par;
@@ -625,9 +697,9 @@ __global__ void __launch_bounds__(1024) sweep_batch_kernel(BatchSweepArgs<Real> 
     __syncthreads();
     const uint32_t u = __builtin_amdgcn_readfirstlane(s_unit);
     if (u >= P.n_units) break;
-    const uint32_t code = __builtin_amdgcn_readfirstlane(P.units[u]);
+    const uint32_t code = __builtin_amdgcn_readfirstlane(units[u]);
     const int r = (int)(code >> 16), b = (int)((code >> 8) & 0xFFu), jseg = (int)(code & 0xFFu);
-    const ReplicaDesc<Real> &D = P.desc[r];
+    const ReplicaDesc<Real> &D = desc[r];
     SweepArgs<Real> A;
     A.I = D.I; A.B = D.B; A.nc = D.nc;
     A.v = D.v; A.inv_v = D.inv_v; A.dt = D.dt;
@@ -773,7 +845,7 @@ hipError_t launch_sweep_batch(const BatchSweepArgs<Real> &a, int grid, int block
   static size_t done = 64 * 1024;
   hipError_t e = allow_lds(reinterpret_cast<const void *>(&sweep_batch_kernel<Real>), lds, &done);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(sweep_batch_kernel<Real>, dim3(grid), dim3(block), lds, s, a);
+  hipLaunchKernelGGL(sweep_batch_kernel<Real>, dim3(grid), dim3(block), lds, s, a, a.desc, a.units);
   return hipGetLastError();
 }
 
