@@ -93,8 +93,6 @@ struct SweepArgs {
   Bank<Real> census;
   Queue<Real> dq;
   int64_t dcap;
-  uint32_t *cursor;                // [B] tile cursors of the start bank (zero at launch)
-  uint32_t *cursor_next;           // [B] the other cursor set, cleared for the next launch
   double *tal;                     // [B][I][6]
   double *bnd;                     // [B][2][3]
   unsigned long long *tracks;      // [I]
@@ -104,7 +102,7 @@ struct SweepArgs {
 };
 
 // One replica of a batched problem: everything a sweep unit of the replica
-// needs, with both banks, both tally sets and both cursor sets; the launch
+// needs, with both banks and both tally sets; the launch
 // selects the current ones.
 template <typename Real>
 struct ReplicaDesc {
@@ -118,7 +116,6 @@ struct ReplicaDesc {
   double *tal[2], *bnd[2];
   unsigned long long *tracks, *counters;
   double *wnext;
-  uint32_t *cursor;  // [2][B]
 };
 
 // Persistent launch over the work units (replica, batch, segment) of all
@@ -129,7 +126,7 @@ struct BatchSweepArgs {
   const uint32_t *units;
   uint32_t n_units;
   uint32_t *work;      // [2] unit counters; launch parity `par` uses work[par]
-  int32_t par;         // cursor set and unit counter of this launch
+  int32_t par;         // unit counter of this launch (the other one is cleared for the next)
   int32_t start_bank;  // start bank and current tally set
   int32_t chunk, ww_on, tile;
   Queue<Real> dq;      // daughter buffers: 2 per work-group of the grid
@@ -209,20 +206,27 @@ struct MarchArgs {
 };
 
 // Dynamic LDS of the sweep and source kernels: [I][6] + nc + 6 doubles for
-// the histogram, then 32-bit words for segment counts, counters, cursors and
-// the start-bank tile table.
+// the histogram, then 32-bit words for segment counts, counters, the tile counter and
+// the start-bank tile table.  A sweep that keeps the per-cell records in
+// LDS puts them first (cell_bytes per cell: CellData and Window).
 __host__ __device__ inline size_t lds_doubles(int I, int nc) { return (size_t)I * 6 + nc + 6; }
 __host__ __device__ inline size_t lds_words(int I, int K) { return (size_t)I + 16 + 8 + 2 + 1 + (K + 2) + (K + 1); }
-inline size_t sweep_lds_bytes(int I, int nc, int K) { return lds_doubles(I, nc) * 8 + lds_words(I, K) * 4; }
+inline size_t sweep_lds_bytes(int I, int nc, int K, size_t cell_bytes = 0) {
+  return (size_t)I * cell_bytes + lds_doubles(I, nc) * 8 + lds_words(I, K) * 4;
+}
+template <typename Real>
+constexpr size_t lds_cell_bytes() { return sizeof(CellData<Real>) + sizeof(Window); }
+constexpr size_t kLdsBytes = 160 * 1024;  // LDS of one gfx950 compute unit
 
 // Launchers (defined in the .hip files).
 template <typename Real>
-hipError_t launch_sweep(const SweepArgs<Real> &a, int grid, int block, size_t lds, hipStream_t s);
+hipError_t launch_sweep(const SweepArgs<Real> &a, bool cells_lds, int grid, int block, size_t lds, hipStream_t s);
 template <typename Real>
 hipError_t launch_source(const SourceArgs &a, const Bank<Real> &bank, int grid, int block, size_t lds,
                          hipStream_t s);
 template <typename Real>
-hipError_t launch_sweep_batch(const BatchSweepArgs<Real> &a, int grid, int block, size_t lds, hipStream_t s);
+hipError_t launch_sweep_batch(const BatchSweepArgs<Real> &a, bool cells_lds, int grid, int block, size_t lds,
+                              hipStream_t s);
 hipError_t launch_losm(const LosmArgs &a, hipStream_t s);
 hipError_t launch_losm_batch(const LosmReplica *tab, int n, int max_I, const LosmCall &c, hipStream_t s);
 size_t losm_batch_lds(int max_I, int *work_in_lds);

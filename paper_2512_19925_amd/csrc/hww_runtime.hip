@@ -28,11 +28,12 @@ constexpr int kGridMax = 1024;      // work-groups of a batched launch at most
 struct Layout {
   int64_t total = 0;
   BankGeom geom{};
+  bool cells_lds = false;  // the sweep keeps the per-cell records in LDS
   int64_t dcap = 0;
   int64_t off_edges, off_sigt, off_sigs, off_cells, off_win;
   int64_t off_bank[2], off_segcnt[2], off_ovfcnt[2], off_q;
   int64_t off_tal[2], off_bnd[2], off_tracks, off_counters, off_wstart, off_wnext;
-  int64_t off_cursor, off_err, off_status, off_scratch, off_factor, off_phi_out, off_J_out;
+  int64_t off_err, off_status, off_scratch, off_factor, off_phi_out, off_J_out;
   int64_t off_F_out, off_P_out;
   int64_t off_m_sig, off_m_F, off_m_P, off_m_phi0, off_m_J0, off_m_w, off_m_hist, off_m_fac, off_m_fact, off_m_G,
       off_m_g;
@@ -55,11 +56,21 @@ bool real_bytes(int precision, int64_t *rb) {
   return false;
 }
 
-// Work-groups per batch: the grid is B * K persistent work-groups, about two
-// per compute unit of a 256-CU MI355X when the LDS histogram allows it.
-int segments_per_batch(int I, int B, int nc) {
-  const size_t lds = sweep_lds_bytes(I, nc, 64);
-  const int target = lds <= 80 * 1024 ? 512 : 256;
+// Launch shape of one problem.  The grid is B * K persistent work-groups.
+// When the per-cell records fit in LDS beside the histogram, one work-group
+// of 1024 threads per compute unit of a 256-CU MI355X keeps them there (no
+// dependent global load per flight); otherwise two of 512 threads per
+// compute unit when the histogram allows it, else one.
+int segments_per_batch(int I, int B, int nc, int precision, bool *cells_lds) {
+  const size_t cb = precision == HWW_FP32 ? lds_cell_bytes<float>() : lds_cell_bytes<double>();
+  int target;
+  if (sweep_lds_bytes(I, nc, 64, cb) <= kLdsBytes) {
+    *cells_lds = true;
+    target = 256;
+  } else {
+    *cells_lds = false;
+    target = sweep_lds_bytes(I, nc, 64) <= kLdsBytes / 2 ? 512 : 256;
+  }
   int K = (target + B / 2) / B;
   if (K < 1) K = 1;
   if (K > 64) K = 64;
@@ -82,7 +93,9 @@ void make_layout(const hww_problem &p, Layout *L, bool member = false) {
   const int64_t I = p.n_cells, B = p.n_batches, nc = p.n_chunks, R = B * nc;
   int64_t rb = 8;
   real_bytes(p.precision, &rb);
-  const int K = member ? member_segments(p) : segments_per_batch((int)I, (int)B, (int)nc);
+  bool cells_lds = false;
+  const int K = member ? member_segments(p) : segments_per_batch((int)I, (int)B, (int)nc, p.precision, &cells_lds);
+  L->cells_lds = cells_lds;
   BankGeom &G = L->geom;
   G.K = K;
   const double share = (double)p.bank_capacity / (double)R;
@@ -121,7 +134,6 @@ void make_layout(const hww_problem &p, Layout *L, bool member = false) {
   L->off_counters = c.take(8 * 2 * C_NCOUNTERS);
   L->off_wstart = c.take(8 * nc);
   L->off_wnext = c.take(8 * nc);
-  L->off_cursor = c.take(4 * 2 * B);
   L->off_err = c.take(4);
   L->off_status = c.take(4);
   L->off_scratch = c.take(8 * 24 * (I + 4));
@@ -203,7 +215,7 @@ struct hww_handle {
   double *tal[2], *bnd[2];
   unsigned long long *tracks, *counters;
   double *wstart, *wnext;
-  uint32_t *cursor, *err;
+  uint32_t *err;
   int32_t *status;
   double *scratch, *factor, *phi_out, *J_out;
 
@@ -215,6 +227,7 @@ struct hww_handle {
   double factor_theta = -1.0;  // theta of the LU factors in the workspace
   size_t lds = 0;
   int block = kBlock, tile = kTile, grid = 0;  // sweep launch shape (grid: batched launches)
+  bool cells_lds = false;      // the sweep keeps the per-cell records in LDS
   int is_view = 0;             // a replica of a batch, for reads only
   // Batch of replicas (is_batch): the replicas are handles of their own
   // whose small per-replica arrays live in shared arrays of the batch.
@@ -223,13 +236,13 @@ struct hww_handle {
   int max_I = 0, max_K = 0, cus = 256;
   uint32_t n_units = 0;
   void *desc = nullptr;              // ReplicaDesc<Real>[n]
-  uint32_t *units = nullptr, *work = nullptr, *cursor_all = nullptr;
+  uint32_t *units = nullptr, *work = nullptr;
   LosmReplica *losm_tab = nullptr;
   BeginStepArgs *bs_tab = nullptr;   // [2][n]
   double *phi_cat = nullptr, *J_cat = nullptr;
   unsigned long long *counters_all = nullptr;
   uint32_t *segcnt_all[2] = {nullptr, nullptr}, *ovfcnt_all[2] = {nullptr, nullptr};
-  int64_t n_seg_all = 0, n_ovf_all = 0, n_phi_all = 0, n_J_all = 0, n_cur_all = 0;
+  int64_t n_seg_all = 0, n_ovf_all = 0, n_phi_all = 0, n_J_all = 0;
   int64_t bdcap = 0;                 // daughter slots per buffer of a batched launch
   Queue<double> bq;
   Queue<float> bq32;
@@ -373,15 +386,13 @@ int launch_chunk(hww_handle *h, int chunk, int k) {
     else a.dq = h->bq32;
     a.dcap = h->bdcap;
     a.err = h->err;
-    HIPCHK(h, launch_sweep_batch<Real>(a, h->grid, h->block, h->lds, h->stream));
+    HIPCHK(h, launch_sweep_batch<Real>(a, h->cells_lds, h->grid, h->block, h->lds, h->stream));
     return HWW_OK;
   }
   SweepArgs<Real> a = base_args<Real>(h);
   a.chunk = chunk;
   a.tile = h->tile;
-  a.cursor = h->cursor + (k & 1) * h->B;
-  a.cursor_next = h->cursor + ((k + 1) & 1) * h->B;
-  HIPCHK(h, launch_sweep<Real>(a, h->B * h->K, h->block, h->lds, h->stream));
+  HIPCHK(h, launch_sweep<Real>(a, h->cells_lds, h->B * h->K, h->block, h->lds, h->stream));
   return HWW_OK;
 }
 
@@ -401,7 +412,10 @@ void carve_handle(hww_handle *h, const hww_problem &problem, char *ws, const Lay
   h->R = h->B * h->nc;
   h->L = L;
   h->K = L.geom.K;
-  h->lds = sweep_lds_bytes(h->I, h->nc, h->K);
+  h->cells_lds = L.cells_lds;
+  const size_t cb = problem.precision == HWW_FP32 ? lds_cell_bytes<float>() : lds_cell_bytes<double>();
+  h->lds = sweep_lds_bytes(h->I, h->nc, h->K, h->cells_lds ? cb : 0);
+  h->block = h->cells_lds ? 1024 : kBlock;
   h->stream = stream;
   h->ws = ws;
   const int64_t slots = (int64_t)h->R * L.geom.stride;
@@ -424,7 +438,6 @@ void carve_handle(hww_handle *h, const hww_problem &problem, char *ws, const Lay
   h->counters = reinterpret_cast<unsigned long long *>(ws + L.off_counters);
   h->wstart = reinterpret_cast<double *>(ws + L.off_wstart);
   h->wnext = reinterpret_cast<double *>(ws + L.off_wnext);
-  h->cursor = reinterpret_cast<uint32_t *>(ws + L.off_cursor);
   h->err = reinterpret_cast<uint32_t *>(ws + L.off_err);
   h->status = reinterpret_cast<int32_t *>(ws + L.off_status);
   h->scratch = reinterpret_cast<double *>(ws + L.off_scratch);
@@ -468,7 +481,6 @@ int prime_handle(hww_handle *h, const hww_problem &problem) {
   HIPCHK(h, launch_fill_f64(h->wnext, 0.0, h->nc, h->stream));
   HIPCHK(h, launch_fill_f64(reinterpret_cast<double *>(h->win), 0.0, 4 * (int64_t)I, h->stream));
   HIPCHK(h, launch_fill_u32(h->err, 0u, 1, h->stream));
-  HIPCHK(h, launch_fill_u32(h->cursor, 0u, 2 * (int64_t)h->B, h->stream));
   HIPCHK(h, launch_fill_u32(reinterpret_cast<uint32_t *>(h->status), 0u, 1, h->stream));
   h->start_bank = 0;
   h->cur_tal = 0;
@@ -495,7 +507,7 @@ void destroy_events(hww_handle *h) {
 
 // ---------------------------------------------------------------- batches --
 // Workspace of a batch: shared arrays first (replica and unit tables, the
-// replicas' counters, segment counts, cursors and solve outputs side by side
+// replicas' counters, segment counts and solve outputs side by side
 // so that one copy reads them all, the daughter buffers of the persistent
 // grid), then one member layout per replica.
 struct BatchLayout {
@@ -503,9 +515,9 @@ struct BatchLayout {
   std::vector<Layout> L;
   std::vector<int64_t> base;
   std::vector<uint32_t> units;
-  int64_t off_desc, off_units, off_work, off_err, off_counters, off_seg[2], off_ovf[2], off_cursor, off_phi, off_J,
+  int64_t off_desc, off_units, off_work, off_err, off_counters, off_seg[2], off_ovf[2], off_phi, off_J,
       off_losm, off_bs, off_q;
-  int64_t n_seg = 0, n_ovf = 0, n_cur = 0, n_phi = 0, n_J = 0, dcap = 0;
+  int64_t n_seg = 0, n_ovf = 0, n_phi = 0, n_J = 0, dcap = 0;
   int max_I = 0, max_K = 0;
 };
 
@@ -532,7 +544,6 @@ int make_batch_layout(const hww_problem *probs, int n, BatchLayout *BL, std::str
     const int64_t R = (int64_t)probs[r].n_batches * nc;
     BL->n_seg += R * L.geom.K;
     BL->n_ovf += R;
-    BL->n_cur += 2 * (int64_t)probs[r].n_batches;
     BL->n_phi += probs[r].n_cells + 2;
     BL->n_J += probs[r].n_cells + 1;
     BL->dcap = std::max(BL->dcap, (probs[r].bank_capacity + (int64_t)probs[r].n_batches * L.geom.K - 1) /
@@ -558,7 +569,6 @@ int make_batch_layout(const hww_problem *probs, int n, BatchLayout *BL, std::str
     BL->off_seg[k] = c.take(4 * BL->n_seg);
     BL->off_ovf[k] = c.take(4 * BL->n_ovf);
   }
-  BL->off_cursor = c.take(4 * BL->n_cur);
   BL->off_phi = c.take(8 * BL->n_phi);
   BL->off_J = c.take(8 * BL->n_J);
   BL->off_losm = c.take((int64_t)sizeof(LosmReplica) * n);
@@ -594,7 +604,6 @@ ReplicaDesc<Real> replica_desc(hww_handle *r) {
   d.tracks = r->tracks;
   d.counters = r->counters;
   d.wnext = r->wnext;
-  d.cursor = r->cursor;
   return d;
 }
 
@@ -1205,7 +1214,13 @@ int hww_init_batch(const hww_problem *problems, int32_t n, void *dev_workspace, 
   h->ws = ws;
   h->max_I = BL.max_I;
   h->max_K = BL.max_K;
-  h->lds = sweep_lds_bytes(BL.max_I, h->nc, BL.max_K);
+  {
+    const size_t cb = h->fp32 ? lds_cell_bytes<float>() : lds_cell_bytes<double>();
+    h->cells_lds = sweep_lds_bytes(BL.max_I, h->nc, BL.max_K, cb) <= kLdsBytes;
+    h->lds = sweep_lds_bytes(BL.max_I, h->nc, BL.max_K, h->cells_lds ? cb : 0);
+    // One work-group per compute unit when the LDS allows no more: make it wide.
+    h->block = h->lds > kLdsBytes / 2 ? 1024 : kBlock;
+  }
   h->n_units = (uint32_t)BL.units.size();
   h->desc = ws + BL.off_desc;
   h->units = reinterpret_cast<uint32_t *>(ws + BL.off_units);
@@ -1216,12 +1231,11 @@ int hww_init_batch(const hww_problem *problems, int32_t n, void *dev_workspace, 
     h->segcnt_all[k] = reinterpret_cast<uint32_t *>(ws + BL.off_seg[k]);
     h->ovfcnt_all[k] = reinterpret_cast<uint32_t *>(ws + BL.off_ovf[k]);
   }
-  h->cursor_all = reinterpret_cast<uint32_t *>(ws + BL.off_cursor);
   h->phi_cat = reinterpret_cast<double *>(ws + BL.off_phi);
   h->J_cat = reinterpret_cast<double *>(ws + BL.off_J);
   h->losm_tab = reinterpret_cast<LosmReplica *>(ws + BL.off_losm);
   h->bs_tab = reinterpret_cast<BeginStepArgs *>(ws + BL.off_bs);
-  h->n_seg_all = BL.n_seg; h->n_ovf_all = BL.n_ovf; h->n_cur_all = BL.n_cur;
+  h->n_seg_all = BL.n_seg; h->n_ovf_all = BL.n_ovf;
   h->n_phi_all = BL.n_phi; h->n_J_all = BL.n_J;
   h->bdcap = BL.dcap;
   h->bq = queue_view<double>(ws, BL.off_q, 2 * (int64_t)kGridMax * BL.dcap);
@@ -1238,7 +1252,7 @@ int hww_init_batch(const hww_problem *problems, int32_t n, void *dev_workspace, 
     return code;
   };
   // Replicas: member layouts whose small arrays sit in the shared ones.
-  int64_t so = 0, oo = 0, co = 0, po = 0, jo = 0;
+  int64_t so = 0, oo = 0, po = 0, jo = 0;
   h->rep.resize(n, nullptr);
   for (int r = 0; r < n; ++r) {
     hww_handle *m = new hww_handle();
@@ -1253,8 +1267,6 @@ int hww_init_batch(const hww_problem *problems, int32_t n, void *dev_workspace, 
     so += R * K;
     oo += R;
     m->counters = h->counters_all + (int64_t)r * 2 * C_NCOUNTERS;
-    m->cursor = h->cursor_all + co;
-    co += 2 * (int64_t)m->B;
     m->phi_out = h->phi_cat + po;
     m->J_out = h->J_cat + jo;
     po += m->I + 2;
@@ -1332,20 +1344,15 @@ int hww_autotune(hww_handle *h, hww_tune_result *best) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCHK(h, hipEventCreate(&e0));
   HIPCHK(h, hipEventCreate(&e1));
-  auto clear_cursors = [&]() -> int {
-    if (h->is_batch) {
-      HIPCHK(h, launch_fill_u32(h->cursor_all, 0u, h->n_cur_all, h->stream));
-      HIPCHK(h, launch_fill_u32(h->work, 0u, 2, h->stream));
-    } else {
-      HIPCHK(h, launch_fill_u32(h->cursor, 0u, 2 * (int64_t)h->B, h->stream));
-    }
+  auto clear_work = [&]() -> int {
+    if (h->is_batch) HIPCHK(h, launch_fill_u32(h->work, 0u, 2, h->stream));
     return HWW_OK;
   };
   auto trial = [&](int block, int tile, int grid, float *ms) -> int {
     h->block = block;
     h->tile = tile;
     h->grid = grid;
-    int rc = clear_cursors();
+    int rc = clear_work();
     if (rc != HWW_OK) return rc;
     flip_banks(h);
     rc = begin_step(h);
@@ -1399,7 +1406,7 @@ int hww_autotune(hww_handle *h, hww_tune_result *best) {
     HIPCHK(h, launch_fill_u32(reinterpret_cast<uint32_t *>(reps[r]->tracks), 0u, 2 * (int64_t)reps[r]->I, h->stream));
   }
   HIPCHK(h, hipMemcpyAsync(cdev, csave.data(), 8 * ncnt, hipMemcpyHostToDevice, h->stream));
-  rc = clear_cursors();
+  rc = clear_work();
   if (rc != HWW_OK) return rc;
   HIPCHK(h, hipStreamSynchronize(h->stream));
   h->block = bb;

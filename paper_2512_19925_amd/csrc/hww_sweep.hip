@@ -126,7 +126,7 @@ struct Lds {
   uint32_t *cnt;    // [16]
   uint32_t *ccnt;   // [8]   census appends of this work-group per chunk
   uint32_t *dcnt;   // [2]   daughters per buffer
-  uint32_t *dcur;   // [1]   daughter tile cursor
+  uint32_t *dcur;   // [1]   tile counter: start-bank tiles (generation 0), then daughter slots
   uint32_t *tstart; // [K+2] first tile of each start-bank segment
   uint32_t *nseg;   // [K+1] particles of each start-bank segment
 };
@@ -247,17 +247,32 @@ __device__ inline void census_append(const Bank<Real> &bk, const BankGeom &G, ui
 }
 
 // One work unit: the particles of chunk A.chunk in the start-bank region of
-// batch b (tiles shared with the other units of the batch through the
-// batch's cursor) and all their daughters, with census appends into segment
-// jseg of the batch's regions.  The work-group's daughter buffers are number
-// qslot of nq.  Starts and ends with the LDS histogram free for reuse.
-template <typename Real>
+// batch b, tiles jseg, jseg + K, jseg + 2K, ... of it (claimed by the waves
+// through a work-group counter in LDS), and all their daughters, with census
+// appends into segment jseg of the batch's regions.  The work-group's
+// daughter buffers are number qslot of nq.  With kCellsLds the per-cell
+// records are copied into LDS first.  Starts and ends with the LDS free for
+// reuse.
+template <typename Real, bool kCellsLds>
 __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int jseg, int qslot, int nq,
                                            double *lds_raw) {
   const int I = A.I, nc = A.nc;
   const BankGeom G = A.geom;
   const int K = G.K;
   const uint32_t TILE = (uint32_t)A.tile;
+  const CellData<Real> *cellp = A.cells;
+  const Window *winp = A.win;
+  if constexpr (kCellsLds) {
+    CellData<Real> *sc = reinterpret_cast<CellData<Real> *>(lds_raw);
+    Window *sw = reinterpret_cast<Window *>(sc + I);
+    for (int j = threadIdx.x; j < I; j += blockDim.x) {
+      sc[j] = A.cells[j];
+      sw[j] = A.win[j];
+    }
+    cellp = sc;
+    winp = sw;
+    lds_raw = reinterpret_cast<double *>(sw + I);
+  }
   Lds L = carve(lds_raw, I, nc, K);
   zero_lds(lds_raw, I, nc, K);
   const int tid = threadIdx.x;
@@ -359,7 +374,7 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
   // ceiling (an impossible split raises an error and ends the particle).
   auto classify = [&]() -> uint32_t {
     if (!A.ww_on) return 0u;
-    const Window wd = A.win[cell];
+    const Window wd = winp[cell];
     if (w > wd.ceil) {
       const double ndf = ceil(w / wd.ww);
       if (!(ndf >= 2.0) || ndf > 1.0e9) {
@@ -378,7 +393,7 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
   };
   // Roulette with the uniform xi: survive at the window centre or die.
   auto roulette = [&](double xi, bool at_start) {
-    const double ww = A.win[cell].ww;
+    const double ww = winp[cell].ww;
     if (xi < w / ww) {
       w = ww;
       evb |= at_start ? EVB_START_SURVIVE : EVB_RR_SURVIVE;
@@ -390,7 +405,7 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
   // Split into N_d = ceil(w / ww) equal daughters; the lane keeps daughter
   // 0, the others take lineage base + j and the event index e_daughter.
   auto split = [&](const uint32_t r[4], uint32_t e_daughter, bool at_start) {
-    const double ndf = ceil(w / A.win[cell].ww);
+    const double ndf = ceil(w / winp[cell].ww);
     lin_base = (uint64_t)r[0] | ((uint64_t)r[1] << 32);
     nd = (uint32_t)ndf;
     w = w / ndf;
@@ -418,7 +433,8 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
           uint32_t tl = 0;
           if (lane == 0) {
             if (from_bank) {
-              const uint32_t t = atomicAdd(&A.cursor[b], 1u);
+              // Tiles of this unit: jseg, jseg + K, ... of the region.
+              const uint32_t t = (uint32_t)jseg + (uint32_t)K * atomicAdd(L.dcur, 1u);
               if (t < L.tstart[K + 1]) {
                 int s = K;
                 while (L.tstart[s] > t) --s;
@@ -511,7 +527,7 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
         draw(A.seed, A.key1, SLOT_FLIGHT, src, lin, e, r);
         const Real ua = uflight<Real>(r[0], r[1]);
         const Real ub = uflight<Real>(r[2], r[3]);
-        const CellData<Real> cd = A.cells[i];
+        const CellData<Real> cd = cellp[i];
         // Exponential flight distance with mean free path 1/sigma_t.
         const Real d_coll = -log_r((Real)1 - ua) * cd.inv_sig;
         const Real xl = cd.xl, xr = cd.xr;
@@ -671,20 +687,18 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
 
 // One problem: grid = B * K work-groups; work-group g is the unit
 // (batch g mod B, segment g / B).
-template <typename Real>
+template <typename Real, bool kCellsLds>
 __global__ void __launch_bounds__(1024) sweep_kernel(SweepArgs<Real> A) {
   extern __shared__ double lds_raw[];
-  // Tile cursors alternate between two sets; this launch clears the set the
-  // next launch will use.
-  if (blockIdx.x == 0 && (int)threadIdx.x < A.B) A.cursor_next[threadIdx.x] = 0u;
-  sweep_unit<Real>(A, (int)(blockIdx.x % A.B), (int)(blockIdx.x / A.B), (int)blockIdx.x, (int)gridDim.x, lds_raw);
+  sweep_unit<Real, kCellsLds>(A, (int)(blockIdx.x % A.B), (int)(blockIdx.x / A.B), (int)blockIdx.x,
+                              (int)gridDim.x, lds_raw);
 }
 
 // Many problems (replicas) in one persistent launch: each work-group claims
 // units from the launch's counter until none is left.  The unit table lists
 // the biggest replicas first and the units of one batch next to each other,
 // so the units that share a batch's tiles run at the same time.
-template <typename Real>
+template <typename Real, bool kCellsLds>
 __global__ void __launch_bounds__(1024) sweep_batch_kernel(BatchSweepArgs<Real> P,
                                                            const ReplicaDesc<Real> *__restrict__ desc,
                                                            const uint32_t *__restrict__ units) {
@@ -712,13 +726,10 @@ __global__ void __launch_bounds__(1024) sweep_batch_kernel(BatchSweepArgs<Real> 
     A.in_bank = D.bank[P.start_bank];
     A.census = D.bank[1 - P.start_bank];
     A.dq = P.dq; A.dcap = P.dcap;
-    A.cursor = D.cursor + par * D.B;
-    A.cursor_next = D.cursor + (1 - par) * D.B;
     A.tal = D.tal[P.start_bank]; A.bnd = D.bnd[P.start_bank];
     A.tracks = D.tracks; A.counters = D.counters; A.wnext = D.wnext;
     A.err = P.err;
-    if (jseg == 0 && threadIdx.x == 0) A.cursor_next[b] = 0u;
-    sweep_unit<Real>(A, b, jseg, (int)blockIdx.x, (int)gridDim.x, lds_raw);
+    sweep_unit<Real, kCellsLds>(A, b, jseg, (int)blockIdx.x, (int)gridDim.x, lds_raw);
     __syncthreads();
   }
 }
@@ -822,11 +833,14 @@ static hipError_t allow_lds(const void *fn, size_t lds, size_t *done) {
 }
 
 template <typename Real>
-hipError_t launch_sweep(const SweepArgs<Real> &a, int grid, int block, size_t lds, hipStream_t s) {
-  static size_t done = 64 * 1024;
-  hipError_t e = allow_lds(reinterpret_cast<const void *>(&sweep_kernel<Real>), lds, &done);
+hipError_t launch_sweep(const SweepArgs<Real> &a, bool cells_lds, int grid, int block, size_t lds, hipStream_t s) {
+  static size_t done[2] = {64 * 1024, 64 * 1024};
+  const void *fn = cells_lds ? reinterpret_cast<const void *>(&sweep_kernel<Real, true>)
+                             : reinterpret_cast<const void *>(&sweep_kernel<Real, false>);
+  hipError_t e = allow_lds(fn, lds, &done[cells_lds ? 1 : 0]);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(sweep_kernel<Real>, dim3(grid), dim3(block), lds, s, a);
+  if (cells_lds) hipLaunchKernelGGL((sweep_kernel<Real, true>), dim3(grid), dim3(block), lds, s, a);
+  else hipLaunchKernelGGL((sweep_kernel<Real, false>), dim3(grid), dim3(block), lds, s, a);
   return hipGetLastError();
 }
 
@@ -841,18 +855,24 @@ hipError_t launch_source(const SourceArgs &a, const Bank<Real> &bank, int grid, 
 }
 
 template <typename Real>
-hipError_t launch_sweep_batch(const BatchSweepArgs<Real> &a, int grid, int block, size_t lds, hipStream_t s) {
-  static size_t done = 64 * 1024;
-  hipError_t e = allow_lds(reinterpret_cast<const void *>(&sweep_batch_kernel<Real>), lds, &done);
+hipError_t launch_sweep_batch(const BatchSweepArgs<Real> &a, bool cells_lds, int grid, int block, size_t lds,
+                              hipStream_t s) {
+  static size_t done[2] = {64 * 1024, 64 * 1024};
+  const void *fn = cells_lds ? reinterpret_cast<const void *>(&sweep_batch_kernel<Real, true>)
+                             : reinterpret_cast<const void *>(&sweep_batch_kernel<Real, false>);
+  hipError_t e = allow_lds(fn, lds, &done[cells_lds ? 1 : 0]);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(sweep_batch_kernel<Real>, dim3(grid), dim3(block), lds, s, a, a.desc, a.units);
+  if (cells_lds)
+    hipLaunchKernelGGL((sweep_batch_kernel<Real, true>), dim3(grid), dim3(block), lds, s, a, a.desc, a.units);
+  else
+    hipLaunchKernelGGL((sweep_batch_kernel<Real, false>), dim3(grid), dim3(block), lds, s, a, a.desc, a.units);
   return hipGetLastError();
 }
 
-template hipError_t launch_sweep_batch<double>(const BatchSweepArgs<double> &, int, int, size_t, hipStream_t);
-template hipError_t launch_sweep_batch<float>(const BatchSweepArgs<float> &, int, int, size_t, hipStream_t);
-template hipError_t launch_sweep<double>(const SweepArgs<double> &, int, int, size_t, hipStream_t);
-template hipError_t launch_sweep<float>(const SweepArgs<float> &, int, int, size_t, hipStream_t);
+template hipError_t launch_sweep_batch<double>(const BatchSweepArgs<double> &, bool, int, int, size_t, hipStream_t);
+template hipError_t launch_sweep_batch<float>(const BatchSweepArgs<float> &, bool, int, int, size_t, hipStream_t);
+template hipError_t launch_sweep<double>(const SweepArgs<double> &, bool, int, int, size_t, hipStream_t);
+template hipError_t launch_sweep<float>(const SweepArgs<float> &, bool, int, int, size_t, hipStream_t);
 template hipError_t launch_source<double>(const SourceArgs &, const Bank<double> &, int, int, size_t, hipStream_t);
 template hipError_t launch_source<float>(const SourceArgs &, const Bank<float> &, int, int, size_t, hipStream_t);
 
