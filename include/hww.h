@@ -76,7 +76,8 @@ typedef struct hww_step_stats {
   uint64_t splits, daughters, rr_kill, rr_survive, histories;
   uint64_t generations;   /* most daughter generations of any work-group in one launch, + 1 */
   uint64_t launches;      /* sweep-kernel launches of the step so far                   */
-  double kernel_ms;       /* summed sweep-kernel time of those launches (HIP events)    */
+  double kernel_ms;       /* summed sweep-kernel time of those launches made with timing
+                             on (HIP events; see hww_set_timing)                       */
   uint64_t bytes_moved;   /* algorithmic bank bytes read + written by those launches    */
 } hww_step_stats;
 
@@ -133,8 +134,17 @@ int hww_sweep_step(hww_handle *h, int32_t step, int32_t chunk, hww_step_stats *s
 
 /* Counters, kernel time and bank bytes of every sweep since init (same
  * fields as hww_step_stats, summed over all steps; generations is the
- * maximum).  Synchronises the stream. */
+ * maximum; kernel_ms covers the launches made with timing on, launches
+ * counts all).  Synchronises the stream. */
 int hww_read_run_stats(hww_handle *h, hww_step_stats *stats);
+
+/* Turn the timing of sweep launches on (default, on != 0) or off.  With
+ * timing on, every hww_sweep_step records a HIP event on the handle's
+ * stream before and after its launch, which hww_step_stats.kernel_ms sums;
+ * each record adds a few microseconds between the launches.  With timing
+ * off nothing is recorded and kernel_ms stays at the sum of the timed
+ * launches. */
+int hww_set_timing(hww_handle *h, int32_t on);
 
 /* Solve the HLOSM equations (Sec. 3) from the tallies on the device:
  * semi-implicit (needs the previous step complete; sets windows for the next

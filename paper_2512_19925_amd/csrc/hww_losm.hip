@@ -23,6 +23,7 @@
 namespace hww {
 
 static constexpr int LOSM_THREADS = 1024;
+static constexpr int LOSM_REDUCE_THREADS = 512;
 
 // Thomas factors of the solve matrix for A.theta.  One lane; runs once per theta.
 __device__ inline void losm_factor_body(const LosmArgs &A) {
@@ -63,8 +64,8 @@ __device__ inline double closure_scale(const LosmArgs &A) {
 
 // Phase 1 over many work-groups: per cell, sum the B batch tallies of the
 // initial-condition set (census phi, J, K) and of the closure set, and
-// normalise per source particle.  A work-group takes 64 cells; its four
-// waves each sum a quarter of the batches and combine through LDS.
+// normalise per source particle.  A work-group takes 64 cells; its waves
+// each sum a share of the batches and combine through LDS.
 __device__ inline void losm_reduce_body(const LosmArgs &A, int blk) {
   const int I = A.I;
   const int M = I + 2;
@@ -73,7 +74,8 @@ __device__ inline void losm_reduce_body(const LosmArgs &A, int blk) {
   double *gi_K = gi_J + I;
   double *gc_phi = gi_K + I;
   double *gc_K = gc_phi + I;
-  __shared__ double part[4][5][64];
+  constexpr int NG = LOSM_REDUCE_THREADS / 64;  // wave groups, each summing a share of the batches
+  __shared__ double part[NG][5][64];
   const double scale = closure_scale(A);
   if (blk == 0 && threadIdx.x < 12) {
     // Face values: q = (phi L, phi R, P L, P R, F L, F R) of the initial-
@@ -93,7 +95,7 @@ __device__ inline void losm_reduce_body(const LosmArgs &A, int blk) {
   double p = 0.0, j = 0.0, k = 0.0, cp = 0.0, ck = 0.0;
   if (i < I) {
 #pragma unroll 4
-    for (int b = grp; b < A.B; b += 4) {
+    for (int b = grp; b < A.B; b += NG) {
       const double *t = A.tal_ic + ((size_t)b * I + i) * 6;
       p += t[3];
       j += t[4];
@@ -110,11 +112,15 @@ __device__ inline void losm_reduce_body(const LosmArgs &A, int blk) {
   part[grp][4][lane] = ck;
   __syncthreads();
   if (grp == 0 && i < I) {
-    p = part[0][0][lane] + part[1][0][lane] + part[2][0][lane] + part[3][0][lane];
-    j = part[0][1][lane] + part[1][1][lane] + part[2][1][lane] + part[3][1][lane];
-    k = part[0][2][lane] + part[1][2][lane] + part[2][2][lane] + part[3][2][lane];
-    cp = part[0][3][lane] + part[1][3][lane] + part[2][3][lane] + part[3][3][lane];
-    ck = part[0][4][lane] + part[1][4][lane] + part[2][4][lane] + part[3][4][lane];
+    p = j = k = cp = ck = 0.0;
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      p += part[g][0][lane];
+      j += part[g][1][lane];
+      k += part[g][2][lane];
+      cp += part[g][3][lane];
+      ck += part[g][4][lane];
+    }
     const double dxi = A.edges[i + 1] - A.edges[i];
     const double norm = A.n_src * dxi;
     gi_phi[i] = p / norm;
@@ -126,7 +132,9 @@ __device__ inline void losm_reduce_body(const LosmArgs &A, int blk) {
   }
 }
 
-__global__ void __launch_bounds__(256) losm_reduce_kernel(LosmArgs A) { losm_reduce_body(A, (int)blockIdx.x); }
+__global__ void __launch_bounds__(LOSM_REDUCE_THREADS) losm_reduce_kernel(LosmArgs A) {
+  losm_reduce_body(A, (int)blockIdx.x);
+}
 
 __device__ __forceinline__ void losm_body(const LosmArgs &A, double *dyn) {
   const int I = A.I;
@@ -331,7 +339,7 @@ __global__ void losm_factor_batch_kernel(const LosmReplica *tab, LosmCall c) {
   losm_factor_body(A);
 }
 
-__global__ void __launch_bounds__(256) losm_reduce_batch_kernel(const LosmReplica *tab, LosmCall c) {
+__global__ void __launch_bounds__(LOSM_REDUCE_THREADS) losm_reduce_batch_kernel(const LosmReplica *tab, LosmCall c) {
   const LosmArgs A = losm_batch_args(tab[blockIdx.y], c);
   if ((int)blockIdx.x * 64 >= A.I && blockIdx.x != 0) return;
   losm_reduce_body(A, (int)blockIdx.x);
@@ -369,7 +377,7 @@ hipError_t launch_losm_batch(const LosmReplica *tab, int n, int max_I, const Los
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(losm_reduce_batch_kernel, dim3((max_I + 63) / 64, n), dim3(256), 0, s, tab, c);
+  hipLaunchKernelGGL(losm_reduce_batch_kernel, dim3((max_I + 63) / 64, n), dim3(LOSM_REDUCE_THREADS), 0, s, tab, c);
   {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -392,7 +400,7 @@ hipError_t launch_losm(const LosmArgs &a, hipStream_t s) {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(losm_reduce_kernel, dim3((a.I + 63) / 64), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(losm_reduce_kernel, dim3((a.I + 63) / 64), dim3(LOSM_REDUCE_THREADS), 0, s, a);
   {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -121,27 +121,50 @@ __device__ inline bool losm_factor_seq(int I, const double *edges, const double 
   return true;
 }
 
-// Inclusive scan of affine maps y -> p + q y across the work-group (thread
-// order), Hillis-Steele in LDS.  On return (P, Q) of thread t compose the
-// maps of threads 0..t (later maps applied last).
-__device__ inline void affine_scan(double *sp, double *sq, double &P, double &Q) {
-  const int t = threadIdx.x;
-  sp[t] = P;
-  sq[t] = Q;
-  __syncthreads();
-  for (int o = 1; o < (int)blockDim.x; o <<= 1) {
-    double pp = 0.0, qq = 1.0;
-    const bool has = t >= o;
-    if (has) { pp = sp[t - o]; qq = sq[t - o]; }
-    __syncthreads();
-    if (has) {
+// Scan of affine maps y -> p + q y across the work-group in thread order:
+// returns, for thread t, the composition of the maps of threads 0..t-1
+// applied to y = 0 (0 for thread 0).  Within a wave by shuffles, across the
+// (at most 16) waves through LDS: two barriers.  sp, sq: >= 48 doubles each.
+__device__ inline double affine_scan_excl(double *sp, double *sq, double P, double Q) {
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6, nw = (int)(blockDim.x >> 6);
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const double pp = __shfl_up(P, o), qq = __shfl_up(Q, o);
+    if (lane >= o) {
       P = P + Q * pp;
       Q = Q * qq;
-      sp[t] = P;
-      sq[t] = Q;
     }
-    __syncthreads();
   }
+  // In-wave exclusive map (identity for lane 0).
+  double pe = __shfl_up(P, 1), qe = __shfl_up(Q, 1);
+  if (lane == 0) {
+    pe = 0.0;
+    qe = 1.0;
+  }
+  if (lane == 63) {
+    sp[wv] = P;
+    sq[wv] = Q;
+  }
+  __syncthreads();
+  if (wv == 0) {
+    double p = lane < nw ? sp[lane] : 0.0, q = lane < nw ? sq[lane] : 1.0;
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) {
+      const double pp = __shfl_up(p, o), qq = __shfl_up(q, o);
+      if (lane >= o) {
+        p = p + q * pp;
+        q = q * qq;
+      }
+    }
+    if (lane < nw) {
+      sp[32 + lane] = p;
+      sq[32 + lane] = q;
+    }
+  }
+  __syncthreads();
+  // Maps of the earlier waves, applied to 0, then this wave's lanes before t.
+  const double pw = wv > 0 ? sp[32 + wv - 1] : 0.0;
+  return pe + qe * pw;
 }
 
 // Solve with the factors, in place: u holds the right-hand side on entry
@@ -158,8 +181,7 @@ __device__ inline void losm_solve_scans(double *u, int n, const double *factor, 
       P = u[r] * inv[r] + al * P;
       Q = al * Q;
     }
-    affine_scan(sp, sq, P, Q);
-    double y = (tid == 0) ? 0.0 : sp[tid - 1];
+    double y = affine_scan_excl(sp, sq, P, Q);
     for (int r = r0; r < r1; ++r) {
       y = u[r] * inv[r] + alpha[r] * y;
       u[r] = y;
@@ -175,9 +197,7 @@ __device__ inline void losm_solve_scans(double *u, int n, const double *factor, 
       P = u[r] + g * P;
       Q = g * Q;
     }
-    affine_scan(sp, sq, P, Q);
-    double y = (tid == 0) ? 0.0 : sp[tid - 1];
-    __syncthreads();
+    double y = affine_scan_excl(sp, sq, P, Q);
     for (int r = b1 - 1; r >= b0; --r) {
       const double g = (r == n - 1) ? 0.0 : gamma[r];
       y = u[r] + g * y;

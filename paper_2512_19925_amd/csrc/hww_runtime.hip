@@ -248,6 +248,8 @@ struct hww_handle {
   Queue<float> bq32;
   int losm_wil = 0;
   int n_launch = 0;            // sweep launches of the current step
+  int timing = 1;              // record HIP events around every sweep launch
+  int64_t launch_count = 0;    // sweep launches since init (timed or not)
   int step_ev0 = 0;            // first event pair of the current step
   std::vector<hipEvent_t> ev;  // start/stop pairs of every sweep launch since init
   MarchArgs march{};           // last deterministic march (its state stays in the workspace)
@@ -832,16 +834,24 @@ int hww_sweep_step(hww_handle *h, int32_t step, int32_t chunk, hww_step_stats *s
   }
 
   const int k = h->ev_used;
-  while ((int)h->ev.size() < 2 * (k + 1)) {
-    hipEvent_t e = nullptr;
-    HIPCHK(h, hipEventCreate(&e));
-    h->ev.push_back(e);
+  if (h->timing) {
+    while ((int)h->ev.size() < 2 * (k + 1)) {
+      hipEvent_t e = nullptr;
+      // Timing only: no system-scope fence at the record (the stream is
+      // synchronised before any elapsed time is read).
+      HIPCHK(h, hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
+      h->ev.push_back(e);
+    }
+    HIPCHK(h, hipEventRecord(h->ev[2 * k], h->stream));
   }
-  HIPCHK(h, hipEventRecord(h->ev[2 * k], h->stream));
-  const int lrc = h->fp32 ? launch_chunk<float>(h, chunk, k) : launch_chunk<double>(h, chunk, k);
+  const int lrc = h->fp32 ? launch_chunk<float>(h, chunk, (int)(h->launch_count & 1))
+                          : launch_chunk<double>(h, chunk, (int)(h->launch_count & 1));
   if (lrc != HWW_OK) return lrc;
-  HIPCHK(h, hipEventRecord(h->ev[2 * k + 1], h->stream));
-  h->ev_used = k + 1;
+  if (h->timing) {
+    HIPCHK(h, hipEventRecord(h->ev[2 * k + 1], h->stream));
+    h->ev_used = k + 1;
+  }
+  h->launch_count += 1;
   h->n_launch += 1;
   h->next_chunk = chunk + 1;
   sync_replica_state(h);
@@ -877,7 +887,7 @@ int hww_read_run_stats(hww_handle *h, hww_step_stats *stats) {
     h->ms_summed += t;
   }
   fill_stats(h, cnt, stats);
-  stats->launches = (uint64_t)h->ev_used;
+  stats->launches = (uint64_t)h->launch_count;
   stats->kernel_ms = h->ms_summed;
   return HWW_OK;
 }
@@ -1342,8 +1352,8 @@ int hww_autotune(hww_handle *h, hww_tune_result *best) {
   HIPCHK(h, hipMemcpyAsync(csave.data(), cdev, 8 * ncnt, hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  HIPCHK(h, hipEventCreate(&e0));
-  HIPCHK(h, hipEventCreate(&e1));
+  HIPCHK(h, hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
+  HIPCHK(h, hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
   auto clear_work = [&]() -> int {
     if (h->is_batch) HIPCHK(h, launch_fill_u32(h->work, 0u, 2, h->stream));
     return HWW_OK;
@@ -1359,7 +1369,7 @@ int hww_autotune(hww_handle *h, hww_tune_result *best) {
     if (rc == HWW_OK) rc = check_hip(h, hipEventRecord(e0, h->stream), "event");
     if (rc == HWW_OK) rc = h->fp32 ? launch_chunk<float>(h, 0, 0) : launch_chunk<double>(h, 0, 0);
     if (rc == HWW_OK) rc = check_hip(h, hipEventRecord(e1, h->stream), "event");
-    if (rc == HWW_OK) rc = check_hip(h, hipEventSynchronize(e1), "event");
+    if (rc == HWW_OK) rc = check_hip(h, hipStreamSynchronize(h->stream), "sync");
     if (rc == HWW_OK) rc = check_hip(h, hipEventElapsedTime(ms, e0, e1), "event");
     flip_banks(h);
     return rc;
@@ -1419,6 +1429,13 @@ int hww_autotune(hww_handle *h, hww_tune_result *best) {
   best->grid = h->is_batch ? bg : h->B * h->K;
   best->trials = trials;
   best->ms = best_ms;
+  return HWW_OK;
+}
+
+int hww_set_timing(hww_handle *h, int32_t on) {
+  if (!h) return HWW_E_INVALID_ARG;
+  if (h->is_view) return fail(h, HWW_E_STATE, "a replica view is read-only");
+  h->timing = on ? 1 : 0;
   return HWW_OK;
 }
 

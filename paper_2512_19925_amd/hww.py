@@ -27,7 +27,7 @@ TALLY_CELLS, TALLY_BOUNDARY, TALLY_TRACKS, TALLY_PREV_CELLS, TALLY_PREV_BOUNDARY
 EXPORTS = ["hww_workspace_bytes", "hww_init_problem", "hww_set_windows", "hww_sweep_step",
            "hww_read_run_stats", "hww_solve_losm", "hww_read_closures", "hww_losm_march", "hww_losm_adjoint",
            "hww_read_tallies", "hww_read_bank", "hww_batch_workspace_bytes", "hww_init_batch",
-           "hww_batch_replica", "hww_autotune", "hww_sync", "hww_last_error", "hww_destroy"]
+           "hww_batch_replica", "hww_autotune", "hww_set_timing", "hww_sync", "hww_last_error", "hww_destroy"]
 
 
 class HwwError(RuntimeError):
@@ -99,6 +99,7 @@ def lib():
         L.hww_init_batch.argtypes = [C.POINTER(Problem), C.c_int32, vp, C.c_int64, vp, C.POINTER(vp)]
         L.hww_batch_replica.argtypes = [vp, C.c_int32, C.POINTER(vp)]
         L.hww_autotune.argtypes = [vp, C.POINTER(TuneResult)]
+        L.hww_set_timing.argtypes = [vp, C.c_int32]
         L.hww_sync.argtypes = [vp]
         L.hww_last_error.argtypes = [vp]
         L.hww_last_error.restype = C.c_char_p
@@ -194,6 +195,10 @@ class Handle:
         if getattr(self, "_h", None):
             lib().hww_destroy(self._h)
             self._h = None
+
+    def set_timing(self, on=True):
+        """HIP-event timing of every sweep launch (on by default)."""
+        self._check("hww_set_timing", lib().hww_set_timing(self._h, int(bool(on))))
 
     def autotune(self):
         """Pick the fastest sweep launch shape (before the first sweep)."""
@@ -386,6 +391,10 @@ class Batch:
             out.append(buf[o:o + sz].view(dt).reshape(sh).copy())
             o += sz
         return out
+
+    def set_timing(self, on=True):
+        """HIP-event timing of every sweep launch (on by default)."""
+        self._check("hww_set_timing", lib().hww_set_timing(self._h, int(bool(on))))
 
     def autotune(self):
         """Pick the fastest persistent launch shape (before the first sweep)."""

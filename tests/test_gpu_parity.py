@@ -165,3 +165,29 @@ def test_error_paths():
         for p in range(w2.n_chunks):
             h2.sweep_step(1, p)
     assert e.value.code == -3
+
+
+def test_timing_off_records_nothing_and_changes_nothing():
+    # Without the timing events the sweep is the same; kernel_ms stays 0.
+    need_gpu()
+    w = W.plain_small().with_(name="timing", n_src=3000, n_steps=3)
+    sim = oracle_sim(w)
+    h = H.Handle(H.spec_from_workload(w))
+    h.set_timing(False)
+    opts = oracle_opts(w)
+    kw = dict(theta=w.theta, filter=w.filter, ma_k=w.ma_k, eps_min=w.eps_min, rho=w.rho,
+              closure_track=w.closure_track)
+    for n in range(1, 4):
+        h.solve_losm(implicit=False, **kw)
+        sim.solve_losm(opts, implicit=False)
+        for p in range(w.n_chunks):
+            st = h.sweep_step(n, p, stats=(p == w.n_chunks - 1))
+            sim.sweep(n, p)
+            if p < w.n_chunks - 1:
+                h.solve_losm(implicit=True, **kw)
+                sim.solve_losm(opts, implicit=True)
+        assert st["kernel_ms"] == 0.0 and st["launches"] == w.n_chunks
+        _compare_step(n, h, sim, w.name)
+    tot = h.run_stats()
+    assert tot["kernel_ms"] == 0.0 and tot["launches"] == 3 * w.n_chunks
+    h.close()
