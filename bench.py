@@ -113,9 +113,22 @@ def run_gpu(w, steps_total, warmup, analog, timing=True):
     return d
 
 
-def run_fom(w, steps_total, warmup, analog):
+def fom_error(cells, n_src, dx, dt, ref):
+    """FOM_Error without the runtime (Sec. 5, Eq. FOM_error): 1 / mean over
+    cells with reference flux of ((phi_mc - phi_ref) / phi_ref)^2; a cell the
+    particles have not reached counts as error 1."""
+    phi = cells[..., 0].sum(0) / (n_src * dx * dt)
+    m = ref > 0
+    if not np.any(m):
+        return 0.0
+    return 1.0 / np.mean(((phi[m] - ref[m]) / ref[m]) ** 2)
+
+
+def run_fom(w, steps_total, warmup, analog, ref):
     """Per-step pass: tau^n is the wall time of step n (solves, sweeps and the
-    wait for them), FOM_sigma^n from the batch spread of the track flux."""
+    wait for them); FOM_sigma^n from the batch spread of the track flux and
+    FOM_Error^n from its error against the reference pulse solution ref
+    ([steps, I] step and cell averages)."""
     import torch
     from paper_2512_19925_amd import hww as H
     h = H.Handle(H.spec_from_workload(w))
@@ -131,7 +144,8 @@ def run_fom(w, steps_total, warmup, analog):
         tau = time.perf_counter() - t0
         if n > warmup:
             cells = h.read_tallies(H.TALLY_CELLS)
-            foms.append(fom_sigma(cells, w.n_src, dx, w.dt) / tau)
+            foms.append((fom_sigma(cells, w.n_src, dx, w.dt) / tau,
+                         fom_error(cells, w.n_src, dx, w.dt, ref[n - 1]) / tau))
     h.close()
     return foms
 
@@ -250,6 +264,39 @@ def run_fp32_pair(steps=20, n_src=10_000_000):
     return out
 
 
+def run_sweep(total, warmup, n_src):
+    """Every (c, rho) pair of the full-scale workload: end-to-end segments/s
+    and the FOM gains of HWW over the plain sweep of the same c."""
+    from paper_2512_19925_amd import hww as H
+    from paper_2512_19925_amd import pulse_reference as P
+    from paper_2512_19925_amd import workloads as W
+    out = []
+    for c in W.FULL_SCALE_C:
+        w0 = W.full_scale(c=c, n_src=n_src)
+        ref = P.cell_step_averages(w0.edges, w0.dt, total, c)
+        ana = run_gpu(w0.with_(analog=True), total, warmup, analog=True, timing=False)
+        f_a = run_fom(w0.with_(analog=True), total, warmup, analog=True, ref=ref)
+        for rho in W.FULL_SCALE_RHO:
+            w = W.full_scale(c=c, rho=rho, n_src=n_src)
+            rec = {"c": c, "rho": rho, "plain_segments_per_s": ana["segments"] / ana["wall_s"]}
+            try:
+                g = run_gpu(w, total, warmup, analog=False, timing=False)
+                f_h = run_fom(w, total, warmup, analog=False, ref=ref)
+            except H.HwwError as e:
+                rec["error"] = str(e)
+                out.append(rec)
+                continue
+            r_sig = [a[0] / b[0] for a, b in zip(f_h, f_a) if b[0] > 0]
+            r_err = [a[1] / b[1] for a, b in zip(f_h, f_a) if b[1] > 0]
+            rec.update({"segments_per_s": g["segments"] / g["wall_s"],
+                        "ms_per_step": g["wall_s"] * 1e3 / (total - warmup),
+                        "fom_sigma_over_plain_mean": float(np.mean(r_sig)) if r_sig else None,
+                        "fom_error_over_plain_mean": float(np.mean(r_err)) if r_err else None})
+            out.append(rec)
+            print(json.dumps(rec), file=sys.stderr, flush=True)
+    return out
+
+
 def cpu_baseline(w, budget_s):
     """The oracle, as it stands, on a bounded sample: the same problem with
     fewer source particles, as many steps as fit in about budget_s."""
@@ -330,15 +377,23 @@ def main():
                      "bytes_per_launch": tim["bytes_moved"] / max(tim["launches"], 1)},
     }
     if not args.no_analog:
+        from paper_2512_19925_amd import pulse_reference as P
         ana = run_gpu(w.with_(analog=True), total, args.warmup, analog=True, timing=False)
-        f_h = run_fom(w, total, args.warmup, analog=False)
-        f_a = run_fom(w.with_(analog=True), total, args.warmup, analog=True)
-        ratio = [a / b for a, b in zip(f_h, f_a) if b > 0]
-        line["fom"] = {"kind": "FOM_sigma of the track-length flux per time step, tau = step wall time",
-                       "hww_over_plain_mean": float(np.mean(ratio)) if ratio else None,
-                       "hww_over_plain_first_last": [ratio[0], ratio[-1]] if ratio else None,
+        ref = P.cell_step_averages(w.edges, w.dt, total, args.c)
+        f_h = run_fom(w, total, args.warmup, analog=False, ref=ref)
+        f_a = run_fom(w.with_(analog=True), total, args.warmup, analog=True, ref=ref)
+        r_sig = [a[0] / b[0] for a, b in zip(f_h, f_a) if b[0] > 0]
+        r_err = [a[1] / b[1] for a, b in zip(f_h, f_a) if b[1] > 0]
+        line["fom"] = {"kind": "per time step, tau = step wall time; FOM_sigma from the batch spread of the "
+                               "track-length flux, FOM_Error against the closed-form pulse solution",
+                       "sigma_hww_over_plain_mean": float(np.mean(r_sig)) if r_sig else None,
+                       "sigma_hww_over_plain_first_last": [r_sig[0], r_sig[-1]] if r_sig else None,
+                       "error_hww_over_plain_mean": float(np.mean(r_err)) if r_err else None,
+                       "error_hww_over_plain_first_last": [r_err[0], r_err[-1]] if r_err else None,
                        "plain_segments_per_s": ana["segments"] / ana["wall_s"],
                        "plain_ms_per_step": ana["wall_s"] * 1e3 / args.steps}
+    if args.sweep:
+        line["sweep"] = run_sweep(total, args.warmup, args.n_src)
     if not args.no_batch:
         line["batched"] = run_batched(args.batch_steps)
     if not args.no_fp32:

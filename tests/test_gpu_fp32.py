@@ -102,3 +102,40 @@ def test_fp32_scattering_moments():
         se = full.std() / np.sqrt(N)
         say(f"  {name}: {full.mean():.6f} vs {ex[name]:.6f} (se {se:.2e})")
         assert abs(full.mean() - ex[name]) < 4.5 * se
+
+
+@pytest.mark.parametrize("precision", [H.HWW_FP32, H.HWW_FP64])
+def test_precision_form_against_the_pulse_solution(precision):
+    # The precision form (200 cells on [-20, 20], c = 0.9, 20 steps of 0.1,
+    # windows from the LOSM solves) at 1e7 particles: the track-length flux
+    # of every reached cell and step against the closed-form pulse solution,
+    # within the batch standard deviation.
+    need_gpu()
+    from paper_2512_19925_amd import pulse_reference as P
+    w = W.precision_form()
+    say(f"case {w.name} precision {precision}")
+    ref = P.cell_step_averages(w.edges, w.dt, w.n_steps, 0.9)
+    dx = np.diff(w.edges)
+    h = H.Handle(H.spec_from_workload(w, precision=precision))
+    zs, rel = [], []
+
+    def on_step(n, hh, _):
+        cells = hh.read_tallies(H.TALLY_CELLS)
+        per = cells[..., 0] / (w.n_src * dx * w.dt)
+        r = ref[n - 1]
+        m = r > 1e-3 * r.max()
+        zs.append(_z(per[:, m], exact=r[m]))
+        rel.append(np.abs(per.sum(0)[m] / r[m] - 1.0))
+
+    H.run(h, w, on_step=on_step, stats=False)
+    h.close()
+    z = np.concatenate(zs)
+    rr = np.concatenate(rel)
+    say(f"  {len(z)} cell-steps, mean z^2 {np.mean(z ** 2):.3f}, max |z| {np.abs(z).max():.2f}, "
+        f"median relative error {np.median(rr):.2e}, max {rr.max():.2e}")
+    # The windows couple the batches (every batch is split and rouletted
+    # against windows from the tallies of all), so the batch spread can only
+    # overestimate the error of the sum: no lower bound on mean z^2.
+    assert len(z) > 150
+    assert np.mean(z ** 2) < 1.6
+    assert np.abs(z).max() < 5.0

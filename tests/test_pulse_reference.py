@@ -1,0 +1,83 @@
+"""The reference pulse flux (closed-form plane-source solution, evaluated by
+quadrature) against what fixes it independently: the exact total weight and
+second spatial moment of the transport equation, the uncollided closed form
+at c = 0, scaling in sigma_t and v, and the Monte Carlo oracle."""
+import math
+
+import numpy as np
+import pytest
+
+import closed_forms as CF
+from gpu_common import oracle_sim
+from paper_2512_19925_amd import pulse_reference as P
+from paper_2512_19925_amd import workloads as W
+
+
+def _cone_integral(f, t, n=600):
+    # x = t sin(theta) clusters the nodes at the light-cone edges.
+    th, w = np.polynomial.legendre.leggauss(n)
+    th = th * (math.pi / 2)
+    w = w * (math.pi / 2)
+    x = t * np.sin(th)
+    return float(np.sum(w * t * np.cos(th) * f(x)))
+
+
+@pytest.mark.parametrize("c", [0.3, 0.9, 0.99])
+@pytest.mark.parametrize("t", [0.2, 1.0, 4.0])
+def test_total_weight_and_second_moment(c, t):
+    m0, _, _, x2 = CF.moments(c, t)
+    assert abs(_cone_integral(lambda x: P.flux(x, t, c), t) / m0 - 1.0) < 1e-12
+    assert abs(_cone_integral(lambda x: x * x * P.flux(x, t, c), t) / x2 - 1.0) < 1e-12
+
+
+def test_no_scattering_is_the_uncollided_closed_form():
+    edges = np.linspace(-2.0, 2.0, 41)
+    ref = P.cell_step_averages(edges, 0.25, 6, 0.0)
+    for n in (1, 3, 6):
+        ex = [CF.uncollided_cell_time_avg(edges[i], edges[i + 1], 0.25 * (n - 1), 0.25 * n, 1.0, 1.0)[0]
+              for i in range(40)]
+        np.testing.assert_allclose(ref[n - 1], ex, rtol=1e-10, atol=1e-14)
+
+
+def test_quadrature_converged_and_symmetric():
+    edges = np.linspace(-3.0, 3.0, 61)
+    a = P.cell_step_averages(edges, 0.1, 12, 0.9)
+    b = P.cell_step_averages(edges, 0.1, 12, 0.9, nx=24, nt=24)
+    m = b > 0
+    assert np.max(np.abs(a[m] - b[m]) / b[m]) < 1e-5
+    np.testing.assert_allclose(a, a[:, ::-1], rtol=1e-12, atol=1e-15)
+
+
+def test_scaling_in_sigma_t_and_speed():
+    # Total weight of the step averages: sum_i dx_i phi_i = (1/dt) int e^{-(1-c) sigma_t v t} v dt.
+    edges = np.linspace(-10.0, 10.0, 401)
+    st, v, c, dt = 1.7, 0.6, 0.8, 0.2
+    ref = P.cell_step_averages(edges, dt, 5, c, sigma_t=st, v=v)
+    lam = (1.0 - c) * st * v
+    for n in range(1, 6):
+        exact = v * (math.exp(-lam * (n - 1) * dt) - math.exp(-lam * n * dt)) / (lam * dt)
+        assert abs(float(np.sum(ref[n - 1] * np.diff(edges))) / exact - 1.0) < 1e-6
+
+
+def test_agrees_with_the_oracle_monte_carlo():
+    # Analog oracle run, c = 0.9: per-cell track-length flux within the batch
+    # standard deviation of the reference.
+    w = W.homogeneous("ref-mc", -3.0, 3.0, 60, 1.0, 0.9, dt=0.1, n_steps=12, n_src=200_000,
+                      bank_capacity=400_000, n_batches=32)
+    sim = oracle_sim(w)
+    ref = P.cell_step_averages(w.edges, w.dt, w.n_steps, 0.9)
+    dx = np.diff(w.edges)
+    zs = []
+    for n in range(1, w.n_steps + 1):
+        for p in range(w.n_chunks):
+            sim.sweep(n, p)
+        cells, _ = sim.tallies()
+        per = cells[..., 0] / (w.n_src * dx[None, :] * w.dt)
+        tot = per.sum(0)
+        sig = CF.batch_sigma(per)
+        m = (ref[n - 1] > 0) & (sig > 0)
+        zs.append((tot[m] - ref[n - 1][m]) / sig[m])
+    z = np.concatenate(zs)
+    assert len(z) > 120
+    assert 0.7 < float(np.mean(z * z)) < 1.4, float(np.mean(z * z))
+    assert float(np.max(np.abs(z))) < 5.0
