@@ -79,7 +79,7 @@ def _step(h, w, n, analog, kw, stats):
     st = None
     for p in range(w.n_chunks):
         st = h.sweep_step(n, p, stats=(stats and p == w.n_chunks - 1))
-        if not analog and p < w.n_chunks - 1:
+        if not analog and not w.lagged and p < w.n_chunks - 1:
             h.solve_losm(implicit=True, **kw)
     return st
 
@@ -93,8 +93,7 @@ def run_gpu(w, steps_total, warmup, analog, timing=True):
     from paper_2512_19925_amd import hww as H
     h = H.Handle(H.spec_from_workload(w))
     h.set_timing(timing)
-    kw = dict(theta=w.theta, filter=w.filter, ma_k=w.ma_k, eps_min=w.eps_min, rho=w.rho,
-              closure_track=w.closure_track)
+    kw = H.losm_kwargs(w)
     for n in range(1, warmup + 1):
         _step(h, w, n, analog, kw, stats=False)
     base = h.run_stats()
@@ -134,8 +133,7 @@ def run_fom(w, steps_total, warmup, analog, ref):
     h = H.Handle(H.spec_from_workload(w))
     h.set_timing(False)
     dx = np.diff(w.edges)
-    kw = dict(theta=w.theta, filter=w.filter, ma_k=w.ma_k, eps_min=w.eps_min, rho=w.rho,
-              closure_track=w.closure_track)
+    kw = H.losm_kwargs(w)
     foms = []
     torch.cuda.synchronize()
     for n in range(1, steps_total + 1):
@@ -191,8 +189,7 @@ def run_batched(steps, compare_steps=10):
     from paper_2512_19925_amd import workloads as W
     ws = W.batched_replicas(n_steps=steps)
     w0 = ws[0]
-    kw = dict(theta=w0.theta, filter=w0.filter, ma_k=w0.ma_k, eps_min=w0.eps_min, rho=w0.rho,
-              closure_track=w0.closure_track)
+    kw = H.losm_kwargs(w0)
     bt = H.Batch([H.spec_from_workload(w) for w in ws])
     tune = bt.autotune()
     torch.cuda.synchronize()
@@ -261,6 +258,40 @@ def run_fp32_pair(steps=20, n_src=10_000_000):
         out[f"{name}_segments_per_s"] = st["segments"] / wall
         out[f"{name}_kernel_segments_per_s"] = st["segments"] / (st["kernel_ms"] * 1e-3)
     out["fp32_over_fp64_kernel"] = out["fp32_kernel_segments_per_s"] / out["fp64_kernel_segments_per_s"]
+    return out
+
+
+def run_methods(total, warmup, n_src, c, rho, ref):
+    """The paper's comparison of weight-window methods (Sec. 5) on the
+    full-scale workload: HWW without filter, with the moving average (k = 3)
+    and with the Fourier filter (kappa = 30), lagged weight windows, each
+    against the plain sweep: FOM ratios averaged over the timed steps and
+    end-to-end segments/s."""
+    from paper_2512_19925_amd import hww as H
+    from paper_2512_19925_amd import workloads as W
+    w0 = W.full_scale(c=c, rho=rho, n_src=n_src)
+    f_a = run_fom(w0.with_(analog=True), total, warmup, analog=True, ref=ref)
+    out = {}
+    # Lagged windows trail the particle front; the particles that outrun
+    # them split the bank past its capacity of 4e7 unless eps_min is raised
+    # (eps_min = 0.05 peaks at 7e7 particles, 0.2 at 2.5e7), so LWW runs with
+    # eps_min = 0.2.
+    for name, w in (("HWW", w0.with_(filter=0)), ("HWW-MA", w0), ("HWW-F", w0.with_(filter=2, kappa=30)),
+                    ("LWW eps_min=0.2", w0.with_(filter=0, lagged=True, eps_min=0.2))):
+        rec = {}
+        try:
+            g = run_gpu(w, total, warmup, analog=False, timing=False)
+            f_h = run_fom(w, total, warmup, analog=False, ref=ref)
+        except H.HwwError as e:
+            out[name] = {"error": str(e)}
+            continue
+        r_sig = [a[0] / b[0] for a, b in zip(f_h, f_a) if b[0] > 0]
+        r_err = [a[1] / b[1] for a, b in zip(f_h, f_a) if b[1] > 0]
+        rec["segments_per_s"] = g["segments"] / g["wall_s"]
+        rec["fom_sigma_over_plain_mean"] = float(np.mean(r_sig)) if r_sig else None
+        rec["fom_error_over_plain_mean"] = float(np.mean(r_err)) if r_err else None
+        out[name] = rec
+        print(json.dumps({name: rec}), file=sys.stderr, flush=True)
     return out
 
 
@@ -392,6 +423,7 @@ def main():
                        "error_hww_over_plain_first_last": [r_err[0], r_err[-1]] if r_err else None,
                        "plain_segments_per_s": ana["segments"] / ana["wall_s"],
                        "plain_ms_per_step": ana["wall_s"] * 1e3 / args.steps}
+        line["methods"] = run_methods(total, args.warmup, args.n_src, args.c, args.rho, ref)
     if args.sweep:
         line["sweep"] = run_sweep(total, args.warmup, args.n_src)
     if not args.no_batch:

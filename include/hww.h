@@ -87,13 +87,21 @@ typedef struct hww_losm_opts {
   int32_t implicit;       /* 0: semi-implicit at step start (lagged closures F^{n-1}, P^{n-1});
                              1: fully implicit inside the step with the closures of the chunks
                                 already swept, scaled by W_start / W_done          */
-  int32_t filter;         /* 0: none, 1: moving average (Eq. moving_average)      */
+  int32_t filter;         /* 0: none, 1: moving average (Eq. moving_average),
+                             2: Fourier low pass (Eqs. fft, ifft): of the discrete Fourier
+                                transform of each grid function of M values keep the
+                                frequencies 0..kappa and their negatives (real output) */
   int32_t ma_k;           /* moving-average half width k                          */
   double eps_min;         /* window floor of Eq. ww-center, 0 < eps_min <= 1      */
   double rho;             /* window width rho >= 1 (Eq. ww-c&f)                   */
   int32_t closure_track;  /* 0: closures from time-layer (census) tallies;
                              1: from track-length tallies of the step            */
   int32_t apply_windows;  /* 1: set the window centres from the solution         */
+  int32_t kappa;          /* Fourier cutoff (filter 2), >= 0                     */
+  int32_t lagged;         /* 1: lagged weight windows (Sec. 5): no LOSM solve; the window
+                             shape is the Monte Carlo track-length flux of the previous step
+                             (semi-implicit calls only; a step with no track flux, such as
+                             the source, leaves the windows as they are)          */
 } hww_losm_opts;
 
 /* Tally kinds for hww_read_tallies. */

@@ -22,6 +22,9 @@
  *                       for theta = 1/2, 1st order for theta = 1; discrete
  *                       balance identity
  *   orc_ma_filter       brute-force sums, constants and linear functions kept
+ *   orc_fourier_filter  numpy's real FFT low pass, identity for kappa >= M/2,
+ *                       the mean for kappa = 0, single cosine modes kept or
+ *                       removed exactly
  *   orc_ww_centres      max cell = scale exactly, floor eps*scale, shape
  *   sweep (uncollided)  closed-form c = 0 pulse solution for all six tallies
  *   sweep (streaming)   exact geometric track lengths, single particles
@@ -559,6 +562,40 @@ void orc_ma_filter(const double *in, int32_t M, int32_t k, double *out) {
   }
 }
 
+/* Fourier filter (Sec. 4, Eqs. fft and ifft) on chi_1..chi_M: the discrete
+ * Fourier transform X_j = sum_m chi_m exp(-i 2 pi j m / M), the modes with
+ * frequency |j| <= kappa kept (j and M - j: the real low pass), the others
+ * zeroed, and the inverse transform (1/M) sum_j X_j exp(i 2 pi j m / M).
+ * Written as the definition, O(M^2). */
+void orc_fourier_filter(const double *in, int32_t M, int32_t kappa, double *out) {
+  const double two_pi = 6.283185307179586476925286766559;
+  double *xr = (double *)calloc((size_t)M, sizeof(double));
+  double *xi = (double *)calloc((size_t)M, sizeof(double));
+  if (!xr || !xi) { free(xr); free(xi); return; }
+  for (int j = 0; j < M; ++j) {
+    int f = j <= M - j ? j : M - j;            /* |frequency| of mode j */
+    if (f > kappa) continue;
+    double re = 0.0, im = 0.0;
+    for (int m = 1; m <= M; ++m) {
+      double a = two_pi * (double)(((int64_t)j * m) % M) / (double)M;
+      re += in[m - 1] * cos(a);
+      im -= in[m - 1] * sin(a);
+    }
+    xr[j] = re; xi[j] = im;
+  }
+  for (int m = 1; m <= M; ++m) {
+    double acc = 0.0;
+    for (int j = 0; j < M; ++j) {
+      int f = j <= M - j ? j : M - j;
+      if (f > kappa) continue;
+      double a = two_pi * (double)(((int64_t)j * m) % M) / (double)M;
+      acc += xr[j] * cos(a) - xi[j] * sin(a);  /* Re(X_j e^{i a}) */
+    }
+    out[m - 1] = acc / (double)M;
+  }
+  free(xr); free(xi);
+}
+
 /* Window centres (Sec. 2, Eq. ww-center) from the auxiliary flux, with
  * negative values clamped to zero, times the weight scale of the step. */
 int orc_ww_centres(int32_t I, const double *phi, double eps_min, double scale, double *ww) {
@@ -675,8 +712,9 @@ static void grid_from(const orc_sim *s, const tally_set *t, int track, double sc
 
 int orc_solve_losm(orc_sim *s, const orc_losm_opts *o, double *phi_out, double *J_out) {
   if (!s || !o) return -1;
-  if (!(o->theta > 0.0 && o->theta <= 1.0) || o->ma_k < 0) return -1;
+  if (!(o->theta > 0.0 && o->theta <= 1.0) || o->ma_k < 0 || o->kappa < 0) return -1;
   if (o->apply_windows && (!(o->rho >= 1.0) || !(o->eps_min > 0.0 && o->eps_min <= 1.0))) return -1;
+  if (o->lagged && (o->implicit || !o->apply_windows)) return -1;
   const int I = s->I;
   const tally_set *ic, *cl;
   double scale = 1.0;
@@ -700,6 +738,31 @@ int orc_solve_losm(orc_sim *s, const orc_losm_opts *o, double *phi_out, double *
       return 0;
     }
     scale = nval(&wtot) / nval(&done);
+  }
+
+  if (o->lagged) {
+    /* Lagged weight windows (Sec. 5): the window shape is the Monte Carlo
+     * track-length flux of the finished step; no LOSM solve.  A step without
+     * track flux (the source) leaves the windows as they are. */
+    double *buf = (double *)calloc((size_t)4 * I, sizeof(double));
+    if (!buf) return -1;
+    grid_fns g = {buf, buf + I, buf + 2 * I, {0}, {0}, {0}};
+    grid_from(s, ic, 1, 1.0, &g);
+    if (phi_out) {
+      phi_out[0] = phi_out[I + 1] = 0.0;
+      memcpy(phi_out + 1, g.phi, sizeof(double) * I);
+    }
+    if (J_out) memset(J_out, 0, sizeof(double) * (I + 1));
+    double mx = 0.0;
+    for (int i = 0; i < I; ++i) mx = g.phi[i] > mx ? g.phi[i] : mx;
+    const double sc = nval(&wtot) / (double)s->n_src;
+    int rc = 0;
+    if (mx > 0.0 && sc > 0.0) {
+      rc = orc_ww_centres(I, g.phi, o->eps_min, sc, buf + 3 * I);
+      if (rc == 0) rc = orc_set_windows(s, buf + 3 * I, o->rho);
+    }
+    free(buf);
+    return rc;
   }
 
   double *buf = (double *)calloc((size_t)20 * (I + 2), sizeof(double));
@@ -742,6 +805,11 @@ int orc_solve_losm(orc_sim *s, const orc_losm_opts *o, double *phi_out, double *
     orc_ma_filter(F_o + 1, I, o->ma_k, tmp); memcpy(F_o + 1, tmp, sizeof(double) * I);
     orc_ma_filter(phi_o + 1, I, o->ma_k, tmp); memcpy(phi_o + 1, tmp, sizeof(double) * I);
     orc_ma_filter(J_o, I + 1, o->ma_k, tmp2); memcpy(J_o, tmp2, sizeof(double) * (I + 1));
+  } else if (o->filter == 2) {
+    orc_fourier_filter(F_n + 1, I, o->kappa, tmp); memcpy(F_n + 1, tmp, sizeof(double) * I);
+    orc_fourier_filter(F_o + 1, I, o->kappa, tmp); memcpy(F_o + 1, tmp, sizeof(double) * I);
+    orc_fourier_filter(phi_o + 1, I, o->kappa, tmp); memcpy(phi_o + 1, tmp, sizeof(double) * I);
+    orc_fourier_filter(J_o, I + 1, o->kappa, tmp2); memcpy(J_o, tmp2, sizeof(double) * (I + 1));
   } else if (o->filter != 0) {
     free(buf);
     return -1;

@@ -47,12 +47,14 @@ typedef struct orc_params {
 typedef struct orc_losm_opts {
   double theta;
   int32_t implicit;      /* 0: semi-implicit (lagged closures), 1: fully implicit */
-  int32_t filter;        /* 0: none, 1: moving average */
+  int32_t filter;        /* 0: none, 1: moving average, 2: Fourier low pass */
   int32_t ma_k;
   double eps_min;
   double rho;
   int32_t closure_track; /* 0: census (time-layer) closures, 1: track-length closures */
   int32_t apply_windows;
+  int32_t kappa;         /* Fourier cutoff */
+  int32_t lagged;        /* 1: windows from the previous step's track-length flux, no solve */
 } orc_losm_opts;
 
 typedef struct orc_sim orc_sim;
@@ -104,6 +106,7 @@ int orc_losm_adjoint(int32_t I, const double *edges, const double *sig_t, const 
                      double dt, double theta, int32_t n_steps, const double *phi_hist, const double *J_hist,
                      const double *w, double *g_t, double *g_s);
 void orc_ma_filter(const double *in, int32_t M, int32_t k, double *out);
+void orc_fourier_filter(const double *in, int32_t M, int32_t kappa, double *out);
 int orc_ww_centres(int32_t I, const double *phi_tilde, double eps_min, double scale, double *ww);
 
 #ifdef __cplusplus

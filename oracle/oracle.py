@@ -70,6 +70,7 @@ def lib():
         L.orc_losm_adjoint.argtypes = ([C.c_int32, dp, dp, dp, C.c_double, C.c_double, C.c_double, C.c_int32]
                                        + [dp] * 5)
         L.orc_ma_filter.argtypes = [dp, C.c_int32, C.c_int32, dp]
+        L.orc_fourier_filter.argtypes = [dp, C.c_int32, C.c_int32, dp]
         L.orc_ww_centres.argtypes = [C.c_int32, dp, C.c_double, C.c_double, dp]
         _lib = L
     return _lib
@@ -122,6 +123,13 @@ def ma_filter(chi, k):
     chi = _f64(chi)
     out = np.zeros_like(chi)
     lib().orc_ma_filter(_dp(chi), len(chi), int(k), _dp(out))
+    return out
+
+
+def fourier_filter(chi, kappa):
+    chi = _f64(chi)
+    out = np.zeros_like(chi)
+    lib().orc_fourier_filter(_dp(chi), len(chi), int(kappa), _dp(out))
     return out
 
 
@@ -192,7 +200,8 @@ class _Params(C.Structure):
 class _Opts(C.Structure):
     _fields_ = [("theta", C.c_double), ("implicit", C.c_int32), ("filter", C.c_int32),
                 ("ma_k", C.c_int32), ("eps_min", C.c_double), ("rho", C.c_double),
-                ("closure_track", C.c_int32), ("apply_windows", C.c_int32)]
+                ("closure_track", C.c_int32), ("apply_windows", C.c_int32), ("kappa", C.c_int32),
+                ("lagged", C.c_int32)]
 
 
 @dataclass
@@ -203,6 +212,8 @@ class LosmOpts:
     eps_min: float = 1e-3
     rho: float = 5.0
     closure_track: int = 0
+    kappa: int = 30
+    lagged: int = 0
 
 
 class OracleSim:
@@ -256,7 +267,8 @@ class OracleSim:
 
     def solve_losm(self, opts: LosmOpts, implicit: bool, apply_windows=True):
         o = _Opts(float(opts.theta), int(implicit), int(opts.filter), int(opts.ma_k),
-                  float(opts.eps_min), float(opts.rho), int(opts.closure_track), int(apply_windows))
+                  float(opts.eps_min), float(opts.rho), int(opts.closure_track), int(apply_windows),
+                  int(opts.kappa), int(opts.lagged))
         phi = np.zeros(self.I + 2)
         J = np.zeros(self.I + 1)
         _check("solve_losm", lib().orc_solve_losm(self._h, C.byref(o), _dp(phi), _dp(J)))
@@ -324,7 +336,7 @@ def run(sim: OracleSim, steps, opts: LosmOpts | None, on_step=None, windows=None
             sim.set_windows(windows(n), opts.rho if opts else 5.0)
         for p in range(sim.n_chunks):
             sim.sweep(n, p)
-            if opts is not None and windows is None and p < sim.n_chunks - 1:
+            if opts is not None and windows is None and not opts.lagged and p < sim.n_chunks - 1:
                 sim.solve_losm(opts, implicit=True)
         if on_step is not None:
             on_step(n, sim)

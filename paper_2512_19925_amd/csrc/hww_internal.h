@@ -165,6 +165,7 @@ struct LosmArgs {
   int32_t next_chunk;             // chunks already swept in the step (implicit solve)
   double theta;
   int32_t implicit, filter, ma_k, closure_track, apply_windows;
+  int32_t kappa, lagged;          // Fourier cutoff; windows from the previous step's track flux
   double eps_min, rho;
   double *scratch;                // >= 24 * (I + 4) doubles
   double *factor;                 // [3][2I+3] LU factors of the system for `theta`
@@ -187,6 +188,7 @@ struct LosmReplica {
 struct LosmCall {
   int32_t cur;  // current tally set
   int32_t implicit, next_chunk, filter, ma_k, closure_track, apply_windows, export_only, refactor, work_in_lds;
+  int32_t kappa, lagged;
   double theta, eps_min, rho;
 };
 

@@ -50,6 +50,57 @@ __device__ void ma_filter_dev(const double *in, double *out, int M, int k) {
   }
 }
 
+// Fourier low pass (Sec. 4, Eqs. fft and ifft) of in[0..M) into out: of the
+// discrete Fourier transform keep the frequencies 0..kappa and their
+// negatives (the real low pass; kappa >= M/2 keeps everything).  The kept
+// coefficients go to xc (2 (M/2 + 1) doubles).  One wave per coefficient,
+// then one thread per output value; the phase factors are advanced by
+// complex multiplication (no table, so no LDS bank conflicts).
+__device__ void fourier_filter_dev(const double *in, double *out, int M, int kappa, double *xc) {
+  const int T = blockDim.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = T >> 6;
+  const int kk = kappa < M / 2 ? kappa : M / 2;
+  double *xr = xc, *xi = xc + (M / 2 + 1);
+  for (int j = wv; j <= kk; j += nw) {
+    // e^{-i 2 pi j m / M} at m = lane, advanced by e^{-i 2 pi 64 j / M}.
+    double s0, c0, sd, cd;
+    sincospi(2.0 * (double)(((int64_t)j * lane) % M) / (double)M, &s0, &c0);
+    sincospi(2.0 * (double)((64 * (int64_t)j) % M) / (double)M, &sd, &cd);
+    double zr = c0, zi = -s0;
+    const double wr = cd, wi = -sd;
+    double re = 0.0, im = 0.0;
+    for (int m = lane; m < M; m += 64) {
+      re += in[m] * zr;
+      im += in[m] * zi;
+      const double t = zr * wr - zi * wi;
+      zi = zr * wi + zi * wr;
+      zr = t;
+    }
+    for (int o = 32; o >= 1; o >>= 1) {
+      re += __shfl_xor(re, o);
+      im += __shfl_xor(im, o);
+    }
+    if (lane == 0) {
+      xr[j] = re;
+      xi[j] = im;
+    }
+  }
+  __syncthreads();
+  for (int m = tid; m < M; m += T) {
+    double sm, cm;
+    sincospi(2.0 * (double)m / (double)M, &sm, &cm);
+    double zr = 1.0, zi = 0.0, acc = xr[0];
+    for (int j = 1; j <= kk; ++j) {
+      const double t = zr * cm - zi * sm;  // e^{i 2 pi j m / M}
+      zi = zr * sm + zi * cm;
+      zr = t;
+      const double term = xr[j] * zr - xi[j] * zi;
+      acc += (2 * j == M) ? term : 2.0 * term;
+    }
+    out[m] = acc / (double)M;
+  }
+  __syncthreads();
+}
+
 // Scale of the closure set: start weight / swept start weight (implicit),
 // 1 (semi-implicit); zero means no start weight has been swept yet.
 __device__ inline double closure_scale(const LosmArgs &A) {
@@ -238,7 +289,28 @@ __device__ __forceinline__ void losm_body(const LosmArgs &A, double *dyn) {
     return;
   }
 
-  // 3. moving-average filter.
+  // Lagged weight windows: the shape is the previous step's Monte Carlo
+  // track-length flux (the closure set read as track tallies), no solve.
+  if (A.lagged) {
+    for (int i = tid; i <= I + 1; i += T) u[2 * i] = (i == 0 || i == I + 1) ? 0.0 : gc_phi[i - 1];
+    for (int i = tid; i <= I; i += T) u[2 * i + 1] = 0.0;
+    __syncthreads();
+  } else {
+  // 3. filters.
+  if (A.filter == 2) {
+    // Coefficients: after the working grid functions in LDS when they fit
+    // there too, else in the global scratch.
+    double *xc = A.work_in_lds == 2 ? S + 5 * M : A.scratch + 12 * M;
+    double *arrs[3] = {F_n + 1, F_o + 1, phi_o + 1};
+    for (int q = 0; q < 3; ++q) {
+      fourier_filter_dev(arrs[q], tmp, I, A.kappa, xc);
+      for (int i = tid; i < I; i += T) arrs[q][i] = tmp[i];
+      __syncthreads();
+    }
+    fourier_filter_dev(J_o, tmp, I + 1, A.kappa, xc);
+    for (int i = tid; i <= I; i += T) J_o[i] = tmp[i];
+    __syncthreads();
+  }
   if (A.filter == 1) {
     double *arrs[3] = {F_n + 1, F_o + 1, phi_o + 1};
     for (int q = 0; q < 3; ++q) {
@@ -262,6 +334,7 @@ __device__ __forceinline__ void losm_body(const LosmArgs &A, double *dyn) {
 
   // 5. substitutions as parallel scans of affine recurrences.
   losm_solve_scans(u, n, A.factor, sp, sq);
+  }
   for (int i = tid; i <= I + 1; i += T) A.phi_out[i] = u[2 * i];
   for (int i = tid; i <= I; i += T) A.J_out[i] = u[2 * i + 1];
 
@@ -285,9 +358,15 @@ __device__ __forceinline__ void losm_body(const LosmArgs &A, double *dyn) {
       double mm = red[0];
       for (int q = 1; q < (T >> 6); ++q) mm = red[q] > mm ? red[q] : mm;
       sc[2] = mm;
-      if (!(mm > 0.0)) bad = 1;
+      // A lagged shape without any track flux (the first step) leaves the
+      // windows as they are.
+      if (!(mm > 0.0)) {
+        if (A.lagged && !bad) skip = 1;
+        else bad = 1;
+      }
     }
     __syncthreads();
+    if (skip && !bad) return;
     if (bad) {
       if (tid == 0) atomicOr(A.err, ERR_NUMERIC);
       return;
@@ -326,6 +405,7 @@ __device__ inline LosmArgs losm_batch_args(const LosmReplica &R, const LosmCall 
   A.next_chunk = c.next_chunk;
   A.theta = c.theta;
   A.implicit = c.implicit; A.filter = c.filter; A.ma_k = c.ma_k;
+  A.kappa = c.kappa; A.lagged = c.lagged;
   A.closure_track = c.closure_track; A.apply_windows = c.apply_windows;
   A.eps_min = c.eps_min; A.rho = c.rho;
   A.refactor = c.refactor; A.work_in_lds = c.work_in_lds; A.export_only = c.export_only;
@@ -351,13 +431,16 @@ __global__ void __launch_bounds__(LOSM_THREADS) losm_batch_kernel(const LosmRepl
   losm_body(A, dyn);
 }
 
-// Dynamic LDS of a solve of I cells: the unknowns, and the working grid
-// functions when they fit beside the 16 KB of static LDS.
+// Dynamic LDS of a solve of I cells: the unknowns; then, when they fit
+// beside the 16 KB of static LDS, the working grid functions (work_in_lds
+// 1) and also the Fourier filter's coefficients (2).
 static size_t losm_lds(int I, int *work_in_lds) {
   const size_t lds_min = (size_t)(2 * I + 3) * sizeof(double);
   const size_t lds_full = lds_min + (size_t)5 * (I + 2) * sizeof(double);
-  *work_in_lds = lds_full + 17 * 1024 <= 160 * 1024 ? 1 : 0;
-  return *work_in_lds ? lds_full : lds_min;
+  const size_t lds_four = lds_full + (size_t)((I + 2) + 4) * sizeof(double);
+  const size_t budget = 160 * 1024 - 17 * 1024;
+  *work_in_lds = lds_four <= budget ? 2 : (lds_full <= budget ? 1 : 0);
+  return *work_in_lds == 2 ? lds_four : (*work_in_lds == 1 ? lds_full : lds_min);
 }
 
 static hipError_t allow_losm_lds(const void *fn, size_t lds, size_t *done) {

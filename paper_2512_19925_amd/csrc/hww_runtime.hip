@@ -896,8 +896,17 @@ int hww_solve_losm(hww_handle *h, const hww_losm_opts *o, double *phi_out, doubl
   if (!h || !o) return HWW_E_INVALID_ARG;
   if (h->is_view) return fail(h, HWW_E_STATE, "a replica view is read-only");
   if (h->fatal) return fail(h, h->fatal, "an earlier error left the problem invalid");
-  if (!(o->theta > 0.0 && o->theta <= 1.0) || o->ma_k < 0 || (o->filter != 0 && o->filter != 1))
+  if (!(o->theta > 0.0 && o->theta <= 1.0) || o->ma_k < 0 || o->filter < 0 || o->filter > 2 || o->kappa < 0)
     return fail(h, HWW_E_INVALID_ARG, "bad LOSM options");
+  if (o->lagged && (o->implicit || !o->apply_windows))
+    return fail(h, HWW_E_INVALID_ARG, "lagged windows are set at the start of a step");
+  if (o->lagged && h->step == 0 && h->next_chunk == h->nc) {
+    // The source has no track-length flux: the first step runs with the
+    // windows as they are (none unless set).
+    if (phi_out) std::memset(phi_out, 0, 8 * (size_t)(h->is_batch ? h->n_phi_all : h->I + 2));
+    if (J_out) std::memset(J_out, 0, 8 * (size_t)(h->is_batch ? h->n_J_all : h->I + 1));
+    return HWW_OK;
+  }
   if (o->apply_windows && (!(o->rho >= 1.0) || !(o->eps_min > 0.0 && o->eps_min <= 1.0)))
     return fail(h, HWW_E_INVALID_ARG, "bad window options");
   if (h->is_batch) {
@@ -909,7 +918,8 @@ int hww_solve_losm(hww_handle *h, const hww_losm_opts *o, double *phi_out, doubl
     LosmCall c{};
     c.cur = h->cur_tal;
     c.implicit = o->implicit; c.next_chunk = h->next_chunk; c.filter = o->filter; c.ma_k = o->ma_k;
-    c.closure_track = o->closure_track; c.apply_windows = o->apply_windows; c.export_only = 0;
+    c.closure_track = o->lagged ? 1 : o->closure_track; c.apply_windows = o->apply_windows; c.export_only = 0;
+    c.kappa = o->kappa; c.lagged = o->lagged;
     c.refactor = (o->theta != h->factor_theta) ? 1 : 0;
     c.work_in_lds = h->losm_wil;
     c.theta = o->theta; c.eps_min = o->eps_min; c.rho = o->rho;
@@ -939,7 +949,8 @@ int hww_solve_losm(hww_handle *h, const hww_losm_opts *o, double *phi_out, doubl
   }
   a.wstart = h->wstart; a.wnext = h->wnext; a.next_chunk = h->next_chunk;
   a.theta = o->theta; a.implicit = o->implicit; a.filter = o->filter; a.ma_k = o->ma_k;
-  a.closure_track = o->closure_track; a.apply_windows = o->apply_windows;
+  a.closure_track = o->lagged ? 1 : o->closure_track; a.apply_windows = o->apply_windows;
+  a.kappa = o->kappa; a.lagged = o->lagged;
   a.eps_min = o->eps_min; a.rho = o->rho;
   a.scratch = h->scratch; a.factor = h->factor;
   a.refactor = (o->theta != h->factor_theta) ? 1 : 0;

@@ -59,7 +59,8 @@ class StepStats(C.Structure):
 class LosmOpts(C.Structure):
     _fields_ = [("theta", C.c_double), ("implicit", C.c_int32), ("filter", C.c_int32),
                 ("ma_k", C.c_int32), ("eps_min", C.c_double), ("rho", C.c_double),
-                ("closure_track", C.c_int32), ("apply_windows", C.c_int32)]
+                ("closure_track", C.c_int32), ("apply_windows", C.c_int32), ("kappa", C.c_int32),
+                ("lagged", C.c_int32)]
 
 
 class TuneResult(C.Structure):
@@ -233,9 +234,9 @@ class Handle:
         return st.as_dict()
 
     def solve_losm(self, theta=0.5, implicit=False, filter=0, ma_k=3, eps_min=1e-3, rho=5.0,
-                   closure_track=0, apply_windows=True, want_solution=False):
+                   closure_track=0, apply_windows=True, want_solution=False, kappa=30, lagged=0):
         o = LosmOpts(float(theta), int(implicit), int(filter), int(ma_k), float(eps_min), float(rho),
-                     int(closure_track), int(apply_windows))
+                     int(closure_track), int(apply_windows), int(kappa), int(lagged))
         phi = np.zeros(self.I + 2) if want_solution else None
         J = np.zeros(self.I + 1) if want_solution else None
         self._check("hww_solve_losm", lib().hww_solve_losm(self._h, C.byref(o), _dp(phi), _dp(J)))
@@ -363,9 +364,9 @@ class Batch:
         return st.as_dict()
 
     def solve_losm(self, theta=0.5, implicit=False, filter=0, ma_k=3, eps_min=1e-3, rho=5.0,
-                   closure_track=0, apply_windows=True, want_solution=False):
+                   closure_track=0, apply_windows=True, want_solution=False, kappa=30, lagged=0):
         o = LosmOpts(float(theta), int(implicit), int(filter), int(ma_k), float(eps_min), float(rho),
-                     int(closure_track), int(apply_windows))
+                     int(closure_track), int(apply_windows), int(kappa), int(lagged))
         phi = np.zeros(sum(i + 2 for i in self.I)) if want_solution else None
         J = np.zeros(sum(i + 1 for i in self.I)) if want_solution else None
         self._check("hww_solve_losm", lib().hww_solve_losm(self._h, C.byref(o), _dp(phi), _dp(J)))
@@ -414,21 +415,26 @@ def spec_from_workload(w, precision=HWW_FP64) -> ProblemSpec:
                        n_chunks=w.n_chunks)
 
 
+def losm_kwargs(w):
+    """solve_losm keywords of a Workload."""
+    return dict(theta=w.theta, filter=w.filter, ma_k=w.ma_k, eps_min=w.eps_min, rho=w.rho,
+                closure_track=w.closure_track, kappa=w.kappa, lagged=int(w.lagged))
+
+
 def run(h: Handle, w, steps=None, on_step=None, analog=None, stats=True):
     """Time loop of the method (Sec. 3): semi-implicit solve at the start of
     each step, then the chunks of histories with a fully implicit solve after
     each chunk but the last.  Calls only the C ABI."""
     analog = w.analog if analog is None else analog
     steps = w.n_steps if steps is None else steps
-    kw = dict(theta=w.theta, filter=w.filter, ma_k=w.ma_k, eps_min=w.eps_min, rho=w.rho,
-              closure_track=w.closure_track)
+    kw = losm_kwargs(w)
     for n in range(1, steps + 1):
         if not analog:
             h.solve_losm(implicit=False, **kw)
         chunk_stats = []
         for p in range(h.n_chunks):
             chunk_stats.append(h.sweep_step(n, p, stats=stats))
-            if not analog and p < h.n_chunks - 1:
+            if not analog and not w.lagged and p < h.n_chunks - 1:
                 h.solve_losm(implicit=True, **kw)
         if on_step is not None:
             on_step(n, h, chunk_stats)

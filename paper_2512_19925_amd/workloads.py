@@ -38,8 +38,10 @@ class Workload:
     rho: float = 5.0
     eps_min: float = 1e-3
     theta: float = 0.5         # Crank-Nicolson
-    filter: int = 0            # 0 none, 1 moving average
+    filter: int = 0            # 0 none, 1 moving average, 2 Fourier low pass
     ma_k: int = 3
+    kappa: int = 30            # Fourier cutoff
+    lagged: bool = False       # windows from the previous step's track-length flux (no LOSM)
     closure_track: int = 0
     analog: bool = False
 

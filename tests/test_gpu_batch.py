@@ -35,8 +35,7 @@ def uneven_replicas(n_steps=5):
 
 
 def _kw(w):
-    return dict(theta=w.theta, filter=w.filter, ma_k=w.ma_k, eps_min=w.eps_min, rho=w.rho,
-                closure_track=w.closure_track)
+    return H.losm_kwargs(w)
 
 
 def _run_batch_vs_oracle(ws, steps, tune=False, check=None, banks=True):
@@ -91,6 +90,11 @@ def test_uneven_replicas_match_their_oracles():
 def test_autotuned_batch_matches_oracles():
     ws = [w.with_(theta=1.0, closure_track=1) for w in uneven_replicas(n_steps=3)]
     _run_batch_vs_oracle(ws, steps=3, tune=True)
+
+
+def test_batch_fourier_filter_matches_oracles():
+    ws = [w.with_(filter=2, kappa=12) for w in uneven_replicas(n_steps=3)]
+    _run_batch_vs_oracle(ws, steps=3)
 
 
 def test_batched_form_sampled_replicas():

@@ -163,3 +163,27 @@ def test_ww_centres():
     np.testing.assert_allclose((ww / s - eps) / (1 - eps), np.clip(phi, 0, None) / 2.0, rtol=1e-12, atol=1e-15)
     with pytest.raises(O.OracleError):
         O.ww_centres(np.array([-1.0, 0.0]), eps, 1.0)
+
+
+@pytest.mark.parametrize("M", [7, 64, 201, 400])
+def test_fourier_filter_properties(M):
+    rng = np.random.default_rng(M)
+    x = rng.normal(size=M)
+    # Every frequency kept: the identity.
+    np.testing.assert_allclose(O.fourier_filter(x, M // 2 + 1), x, rtol=0, atol=1e-12)
+    # Only the zero frequency kept: the mean everywhere.
+    np.testing.assert_allclose(O.fourier_filter(x, 0), np.full(M, x.mean()), rtol=0, atol=1e-13)
+    # The real low pass of numpy's FFT.
+    for kappa in (1, 3, M // 4):
+        X = np.fft.rfft(x)
+        X[kappa + 1:] = 0.0
+        np.testing.assert_allclose(O.fourier_filter(x, kappa), np.fft.irfft(X, n=M), rtol=0, atol=1e-12)
+
+
+def test_fourier_filter_keeps_and_removes_single_modes():
+    M = 120
+    m = np.arange(1, M + 1)
+    low = np.cos(2 * np.pi * 3 * m / M)
+    high = 0.5 * np.sin(2 * np.pi * 9 * m / M)
+    np.testing.assert_allclose(O.fourier_filter(low + high, 5), low, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(O.fourier_filter(low + high, 9), low + high, rtol=0, atol=1e-12)

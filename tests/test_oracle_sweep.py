@@ -233,3 +233,29 @@ def test_windows_do_not_bias_tallies():
     assert len(z) > 150
     assert 0.7 < (z ** 2).mean() < 1.5
     assert np.abs(z).max() < 6.5
+
+
+def test_lagged_windows_are_the_previous_track_flux():
+    # Lagged weight windows: at the start of step n the window shape is the
+    # track-length flux of step n - 1 (normalised by its maximum, floored at
+    # eps_min) times the weight scale of the bank the step starts from.
+    # (The lagged shape trails the particles; eps_min = 0.05 bounds the
+    # splitting where they outrun it.)
+    w = W.plain_small().with_(n_src=3000, n_steps=4, eps_min=0.05, bank_capacity=30_000)
+    sim = O.OracleSim(w.edges, w.sigma_t, w.sigma_s, w.speed, w.dt, w.n_steps, w.src_x, w.n_src,
+                      w.capacity(), w.seed, w.replica, w.n_batches, w.n_chunks)
+    opts = O.LosmOpts(theta=w.theta, eps_min=w.eps_min, rho=w.rho, lagged=1)
+    dx = np.diff(w.edges)
+    for n in range(1, w.n_steps + 1):
+        if n > 1:
+            cells, _ = sim.tallies()
+            phi = cells[..., 0].sum(0) / (w.n_src * dx * w.dt)
+            _, _, _, w_next = sim.state()
+            s = w_next.sum() / w.n_src
+            expect = s * (np.maximum(phi, 0.0) / phi.max() * (1.0 - w.eps_min) + w.eps_min)
+        sim.solve_losm(opts, implicit=False)
+        if n > 1:
+            np.testing.assert_allclose(sim.windows()[0], expect, rtol=1e-13)
+            np.testing.assert_allclose(sim.windows()[1], expect * w.rho, rtol=1e-13)
+        for p in range(w.n_chunks):
+            sim.sweep(n, p)
