@@ -168,9 +168,10 @@ struct LosmArgs {
   int32_t kappa, lagged;          // Fourier cutoff; windows from the previous step's track flux
   double eps_min, rho;
   double *scratch;                // >= 24 * (I + 4) doubles
-  double *factor;                 // [3][2I+3] LU factors of the system for `theta`
+  double *factor;                 // [4][2I+3] LU factors of the system for `theta`, old-time diagonal
   int32_t refactor;               // 1: (re)compute the factors first
   int32_t work_in_lds;            // set by the launcher: grid functions fit in LDS
+  int32_t ic_cached;              // 1: the batch sums of tal_ic/bnd_ic are already in the scratch
   int32_t export_only;            // 1: write phi^{n-1}, J^{n-1}, F^{n-1}, P^{n-1} and stop
   double *F_out, *P_out;          // I+2, 2 (device) for export_only
   Window *win;                    // [I] window centres, ceilings, floors
@@ -188,7 +189,7 @@ struct LosmReplica {
 struct LosmCall {
   int32_t cur;  // current tally set
   int32_t implicit, next_chunk, filter, ma_k, closure_track, apply_windows, export_only, refactor, work_in_lds;
-  int32_t kappa, lagged;
+  int32_t kappa, lagged, ic_cached;
   double theta, eps_min, rho;
 };
 

@@ -25,9 +25,19 @@ namespace hww {
 static constexpr int LOSM_THREADS = 1024;
 static constexpr int LOSM_REDUCE_THREADS = 512;
 
-// Thomas factors of the solve matrix for A.theta.  One lane; runs once per theta.
+// Thomas factors of the solve matrix for A.theta, then the old-time
+// diagonal of every row: factor = [alpha | 1/den | gamma | bb], each 2I+3
+// long.  The elimination runs on one lane, the diagonals on all; once per
+// theta.
 __device__ inline void losm_factor_body(const LosmArgs &A) {
   const double inv_vdt = 1.0 / (A.v * A.dt);
+  const int n = 2 * A.I + 3;
+  for (int r = threadIdx.x; r < n; r += blockDim.x) {
+    double ba, bb, bc;
+    losm_brow(A.I, A.edges, A.sig_t, A.sig_s, A.theta, inv_vdt, r, &ba, &bb, &bc);
+    A.factor[3 * n + r] = bb;
+  }
+  if (threadIdx.x != 0) return;
   if (!losm_factor_seq(A.I, A.edges, A.sig_t, A.sig_s, A.theta, inv_vdt, false, A.factor)) {
     atomicOr(A.err, ERR_NUMERIC);
     *A.status = (int)ERR_NUMERIC;
@@ -35,7 +45,7 @@ __device__ inline void losm_factor_body(const LosmArgs &A) {
 }
 
 __global__ void losm_factor_kernel(LosmArgs A) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (blockIdx.x != 0) return;
   losm_factor_body(A);
 }
 
@@ -101,6 +111,20 @@ __device__ void fourier_filter_dev(const double *in, double *out, int M, int kap
   __syncthreads();
 }
 
+// Fourier low pass of the cell values f[1..I] of a grid function into the
+// spare buffer, face values f[0], f[I+1] copied; the two pointers swap.
+__device__ __forceinline__ void fourier_cells_swap(double *&f, double *&spare, int I, int kappa, double *xc) {
+  fourier_filter_dev(f + 1, spare + 1, I, kappa, xc);
+  if (threadIdx.x == 0) {
+    spare[0] = f[0];
+    spare[I + 1] = f[I + 1];
+  }
+  __syncthreads();
+  double *t = f;
+  f = spare;
+  spare = t;
+}
+
 // Scale of the closure set: start weight / swept start weight (implicit),
 // 1 (semi-implicit); zero means no start weight has been swept yet.
 __device__ inline double closure_scale(const LosmArgs &A) {
@@ -113,47 +137,68 @@ __device__ inline double closure_scale(const LosmArgs &A) {
   return done > 0.0 ? wtot / done : 0.0;
 }
 
+// Layout of a solve's working arrays (M = I + 2 doubles each): six grid
+// functions, in LDS when they fit (work_in_lds) else at the start of the
+// global scratch; the batch sums of the reduction after them; the Fourier
+// coefficients after those.
+__device__ inline double *losm_sums(const LosmArgs &A) { return A.scratch + 6 * (A.I + 2); }
+__device__ inline double *losm_fourier_scratch(const LosmArgs &A) { return A.scratch + 12 * (A.I + 2) + 16; }
+
 // Phase 1 over many work-groups: per cell, sum the B batch tallies of the
 // initial-condition set (census phi, J, K) and of the closure set, and
 // normalise per source particle.  A work-group takes 64 cells; its waves
-// each sum a share of the batches and combine through LDS.
+// each sum a share of the batches and combine through LDS.  With ic_cached
+// the sums of the initial-condition set are still in the scratch from an
+// earlier solve of the same step and only the closure set is read.
 __device__ inline void losm_reduce_body(const LosmArgs &A, int blk) {
   const int I = A.I;
-  const int M = I + 2;
-  double *gi_phi = A.scratch + 5 * M;
+  double *gi_phi = losm_sums(A);
   double *gi_J = gi_phi + I;
   double *gi_K = gi_J + I;
   double *gc_phi = gi_K + I;
   double *gc_K = gc_phi + I;
+  double *faces = gc_K + I;
   constexpr int NG = LOSM_REDUCE_THREADS / 64;  // wave groups, each summing a share of the batches
   __shared__ double part[NG][5][64];
   const double scale = closure_scale(A);
+  const bool ic = !A.ic_cached;
   if (blk == 0 && threadIdx.x < 12) {
     // Face values: q = (phi L, phi R, P L, P R, F L, F R) of the initial-
     // condition set (t < 6) and of the closure set (t >= 6).
     const int t = threadIdx.x;
     const int set = t / 6, q = t % 6;
     const int f = q & 1, kind = q >> 1;
-    const double *bs = set == 0 ? A.bnd_ic : A.bnd_cl;
-    double acc = 0.0;
+    if (set == 1 || ic) {
+      const double *bs = set == 0 ? A.bnd_ic : A.bnd_cl;
+      double acc = 0.0;
 #pragma unroll 8
-    for (int b = 0; b < A.B; ++b) acc += bs[(b * 2 + f) * 3 + kind];
-    A.scratch[5 * M + 5 * I + t] = (set == 0 ? 1.0 : scale) * acc / (A.n_src * A.dt);
+      for (int b = 0; b < A.B; ++b) acc += bs[(b * 2 + f) * 3 + kind];
+      faces[t] = (set == 0 ? 1.0 : scale) * acc / (A.n_src * A.dt);
+    }
   }
   const int kc = A.closure_track ? 0 : 3;
   const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
   const int i = blk * 64 + lane;
   double p = 0.0, j = 0.0, k = 0.0, cp = 0.0, ck = 0.0;
   if (i < I) {
+    if (ic) {
 #pragma unroll 4
-    for (int b = grp; b < A.B; b += NG) {
-      const double *t = A.tal_ic + ((size_t)b * I + i) * 6;
-      p += t[3];
-      j += t[4];
-      k += t[5];
-      const double *tc = A.tal_cl + ((size_t)b * I + i) * 6;
-      cp += tc[kc];
-      ck += tc[kc + 2];
+      for (int b = grp; b < A.B; b += NG) {
+        const double *t = A.tal_ic + ((size_t)b * I + i) * 6;
+        p += t[3];
+        j += t[4];
+        k += t[5];
+        const double *tc = A.tal_cl + ((size_t)b * I + i) * 6;
+        cp += tc[kc];
+        ck += tc[kc + 2];
+      }
+    } else {
+#pragma unroll 4
+      for (int b = grp; b < A.B; b += NG) {
+        const double *tc = A.tal_cl + ((size_t)b * I + i) * 6;
+        cp += tc[kc];
+        ck += tc[kc + 2];
+      }
     }
   }
   part[grp][0][lane] = p;
@@ -174,9 +219,11 @@ __device__ inline void losm_reduce_body(const LosmArgs &A, int blk) {
     }
     const double dxi = A.edges[i + 1] - A.edges[i];
     const double norm = A.n_src * dxi;
-    gi_phi[i] = p / norm;
-    gi_J[i] = j / norm;
-    gi_K[i] = k / norm;
+    if (ic) {
+      gi_phi[i] = p / norm;
+      gi_J[i] = j / norm;
+      gi_K[i] = k / norm;
+    }
     const double normc = A.closure_track ? (A.n_src * dxi * A.dt) : norm;
     gc_phi[i] = scale * cp / normc;
     gc_K[i] = scale * ck / normc;
@@ -187,6 +234,10 @@ __global__ void __launch_bounds__(LOSM_REDUCE_THREADS) losm_reduce_kernel(LosmAr
   losm_reduce_body(A, (int)blockIdx.x);
 }
 
+// kWil: where the working arrays live (0 global scratch, 1 LDS, 2 LDS with
+// the Fourier coefficients too), fixed at compile time so that every access
+// is a plain LDS or global one.
+template <int kWil>
 __device__ __forceinline__ void losm_body(const LosmArgs &A, double *dyn) {
   const int I = A.I;
   const int M = I + 2;
@@ -194,20 +245,23 @@ __device__ __forceinline__ void losm_body(const LosmArgs &A, double *dyn) {
   const int tid = threadIdx.x;
   const int T = blockDim.x;
   double *u = dyn;  // [n] right-hand side, then solution
-  // Working grid functions live in LDS when they fit, else in the global
-  // scratch.
-  double *S = A.work_in_lds ? dyn + n : A.scratch;
-  double *phi_o = S;
-  double *J_o = phi_o + M;
-  double *F_o = J_o + M;
-  double *F_n = F_o + M;
-  double *tmp = F_n + M;
-  const double *gi_phi = A.scratch + 5 * M;
+  double *S = kWil ? dyn + n : A.scratch;
+  // Each thread's rows of the substitutions, loaded now to overlap the
+  // first phases (up to kScanRows rows per thread, else read when used).
+  constexpr int kScanRows = 4;
+  const bool rows_in_regs = (n + T - 1) / T <= kScanRows;
+  ScanRows<kScanRows> R;
+  if (rows_in_regs) losm_scan_prefetch(A.factor, n, R);
+  // Grid functions and two spare buffers; filters write into a spare and
+  // the pointers swap (faces copied along).
+  double *phi_o = S, *J_o = S + M, *F_o = S + 2 * M, *F_n = S + 3 * M, *T1 = S + 4 * M, *T2 = S + 5 * M;
+  const double *gi_phi = losm_sums(A);
   const double *gi_J = gi_phi + I;
   const double *gi_K = gi_J + I;
   const double *gc_phi = gi_K + I;
   const double *gc_K = gc_phi + I;
-  __shared__ double sp[LOSM_THREADS], sq[LOSM_THREADS];
+  const double *gfaces = gc_K + I;
+  __shared__ double sp[64], sq[64];
   __shared__ double face[12];  // ic: phi L/R, P L/R, F L/R; cl: same
   __shared__ double sc[4];     // scale, s, max
   __shared__ int bad;
@@ -227,6 +281,8 @@ __device__ __forceinline__ void losm_body(const LosmArgs &A, double *dyn) {
     // No start weight swept yet: no closures exist, the update is skipped.
     if (A.implicit && !(sc[0] > 0.0)) skip = 1;
   }
+  // 1. batch sums: done by losm_reduce_kernel into gi_*, gc_* and the faces.
+  if (tid < 12) face[tid] = gfaces[tid];
   __syncthreads();
   if (bad) return;
   if (skip) {
@@ -235,44 +291,33 @@ __device__ __forceinline__ void losm_body(const LosmArgs &A, double *dyn) {
     return;
   }
 
-  // 1. batch sums: done by losm_reduce_kernel into gi_* and gc_*.
-  if (tid < 12) face[tid] = A.scratch[5 * M + 5 * I + tid];
-  __syncthreads();
-
-  // 2. grid functions.
+  // 2. grid functions of the initial condition and the closures.
   for (int i = tid; i <= I + 1; i += T) {
+    double fo;
     if (i == 0) {
       phi_o[0] = face[0];
-      F_o[0] = face[4];
+      fo = face[4];
       J_o[0] = -0.5 * face[0] + face[2];
     } else if (i == I + 1) {
       phi_o[I + 1] = face[1];
-      F_o[I + 1] = face[5];
+      fo = face[5];
       J_o[I] = 0.5 * face[1] - face[3];
     } else {
       phi_o[i] = gi_phi[i - 1];
-      F_o[i] = gi_phi[i - 1] / 3.0 - gi_K[i - 1];
+      fo = gi_phi[i - 1] / 3.0 - gi_K[i - 1];
       if (i <= I - 1) {
         const double dl = A.edges[i] - A.edges[i - 1], dr = A.edges[i + 1] - A.edges[i];
         J_o[i] = (dr * gi_J[i - 1] + dl * gi_J[i]) / (dl + dr);
       }
     }
+    F_o[i] = fo;
+    if (!A.implicit) F_n[i] = fo;
+    else if (i == 0) F_n[0] = face[10];
+    else if (i == I + 1) F_n[I + 1] = face[11];
+    else F_n[i] = gc_phi[i - 1] / 3.0 - gc_K[i - 1];
   }
-  __syncthreads();
-  double PL, PR;
-  if (!A.implicit) {
-    for (int i = tid; i <= I + 1; i += T) F_n[i] = F_o[i];
-    PL = face[2];
-    PR = face[3];
-  } else {
-    for (int i = tid; i <= I + 1; i += T) {
-      if (i == 0) F_n[0] = face[10];
-      else if (i == I + 1) F_n[I + 1] = face[11];
-      else F_n[i] = gc_phi[i - 1] / 3.0 - gc_K[i - 1];
-    }
-    PL = face[8];
-    PR = face[9];
-  }
+  const double PL = A.implicit ? face[8] : face[2];
+  const double PR = A.implicit ? face[9] : face[3];
   __syncthreads();
 
   if (A.export_only) {
@@ -296,44 +341,53 @@ __device__ __forceinline__ void losm_body(const LosmArgs &A, double *dyn) {
     for (int i = tid; i <= I; i += T) u[2 * i + 1] = 0.0;
     __syncthreads();
   } else {
-  // 3. filters.
-  if (A.filter == 2) {
-    // Coefficients: after the working grid functions in LDS when they fit
-    // there too, else in the global scratch.
-    double *xc = A.work_in_lds == 2 ? S + 5 * M : A.scratch + 12 * M;
-    double *arrs[3] = {F_n + 1, F_o + 1, phi_o + 1};
-    for (int q = 0; q < 3; ++q) {
-      fourier_filter_dev(arrs[q], tmp, I, A.kappa, xc);
-      for (int i = tid; i < I; i += T) arrs[q][i] = tmp[i];
-      __syncthreads();
-    }
-    fourier_filter_dev(J_o, tmp, I + 1, A.kappa, xc);
-    for (int i = tid; i <= I; i += T) J_o[i] = tmp[i];
-    __syncthreads();
-  }
+  // 3. filters of F^n, F^{n-1}, phi^{n-1} (cell values) and J^{n-1} (edges).
   if (A.filter == 1) {
-    double *arrs[3] = {F_n + 1, F_o + 1, phi_o + 1};
-    for (int q = 0; q < 3; ++q) {
-      ma_filter_dev(arrs[q], tmp, I, A.ma_k);
-      __syncthreads();
-      for (int i = tid; i < I; i += T) arrs[q][i] = tmp[i];
-      __syncthreads();
+    // Moving average, two grid functions per pass.
+    ma_filter_dev(F_n + 1, T1 + 1, I, A.ma_k);
+    ma_filter_dev(F_o + 1, T2 + 1, I, A.ma_k);
+    if (tid == 0) {
+      T1[0] = F_n[0]; T1[I + 1] = F_n[I + 1];
+      T2[0] = F_o[0]; T2[I + 1] = F_o[I + 1];
     }
-    ma_filter_dev(J_o, tmp, I + 1, A.ma_k);
     __syncthreads();
-    for (int i = tid; i <= I; i += T) J_o[i] = tmp[i];
+    double *a = F_n, *b = F_o;
+    F_n = T1; F_o = T2; T1 = a; T2 = b;
+    ma_filter_dev(phi_o + 1, T1 + 1, I, A.ma_k);
+    ma_filter_dev(J_o, T2, I + 1, A.ma_k);
+    if (tid == 0) {
+      T1[0] = phi_o[0]; T1[I + 1] = phi_o[I + 1];
+    }
     __syncthreads();
+    phi_o = T1; J_o = T2;
+  } else if (A.filter == 2) {
+    // Fourier low pass, one grid function at a time.
+    double *xc = kWil == 2 ? S + 6 * M : losm_fourier_scratch(A);
+    fourier_cells_swap(F_n, T1, I, A.kappa, xc);
+    fourier_cells_swap(F_o, T1, I, A.kappa, xc);
+    fourier_cells_swap(phi_o, T1, I, A.kappa, xc);
+    fourier_filter_dev(J_o, T1, I + 1, A.kappa, xc);
+    double *old = J_o;
+    J_o = T1;
+    T1 = old;
   }
 
-  // 4. right-hand side.
+  // 4. right-hand side, 5. substitutions as parallel scans of affine
+  // recurrences.  With the rows in registers each thread assembles the
+  // rows it then scans first, so no barrier sits between the two.
   const double th = A.theta;
-  const double inv_vdt = 1.0 / (A.v * A.dt);
-  for (int r = tid; r < n; r += T)
-    u[r] = losm_rhs(I, A.edges, A.sig_t, A.sig_s, th, inv_vdt, r, phi_o, J_o, F_o, F_n, PL, PR);
-  __syncthreads();
-
-  // 5. substitutions as parallel scans of affine recurrences.
-  losm_solve_scans(u, n, A.factor, sp, sq);
+  if (rows_in_regs) {
+    const int m = (n + T - 1) / T, r0 = tid * m, cnt = min(m, n - r0);
+#pragma unroll
+    for (int k = 0; k < kScanRows; ++k)
+      if (k < cnt) u[r0 + k] = losm_rhs_bb(I, th, r0 + k, R.bb[k], phi_o, J_o, F_o, F_n, PL, PR);
+    losm_solve_scans_rows(u, n, R, sp, sq);
+  } else {
+    for (int r = tid; r < n; r += T)
+      u[r] = losm_rhs_bb(I, th, r, A.factor[3 * n + r], phi_o, J_o, F_o, F_n, PL, PR);
+    __syncthreads();
+    losm_solve_scans(u, n, A.factor, sp, sq);
+  }
   }
   for (int i = tid; i <= I + 1; i += T) A.phi_out[i] = u[2 * i];
   for (int i = tid; i <= I; i += T) A.J_out[i] = u[2 * i + 1];
@@ -386,9 +440,10 @@ __device__ __forceinline__ void losm_body(const LosmArgs &A, double *dyn) {
   }
 }
 
+template <int kWil>
 __global__ void __launch_bounds__(LOSM_THREADS) losm_kernel(LosmArgs A) {
   extern __shared__ double dyn[];
-  losm_body(A, dyn);
+  losm_body<kWil>(A, dyn);
 }
 
 // Batched solves: replica r of the table takes block r (factor, solve) or
@@ -405,7 +460,7 @@ __device__ inline LosmArgs losm_batch_args(const LosmReplica &R, const LosmCall 
   A.next_chunk = c.next_chunk;
   A.theta = c.theta;
   A.implicit = c.implicit; A.filter = c.filter; A.ma_k = c.ma_k;
-  A.kappa = c.kappa; A.lagged = c.lagged;
+  A.kappa = c.kappa; A.lagged = c.lagged; A.ic_cached = c.ic_cached;
   A.closure_track = c.closure_track; A.apply_windows = c.apply_windows;
   A.eps_min = c.eps_min; A.rho = c.rho;
   A.refactor = c.refactor; A.work_in_lds = c.work_in_lds; A.export_only = c.export_only;
@@ -413,9 +468,8 @@ __device__ inline LosmArgs losm_batch_args(const LosmReplica &R, const LosmCall 
 }
 
 __global__ void losm_factor_batch_kernel(const LosmReplica *tab, LosmCall c) {
-  if (threadIdx.x != 0) return;
   const LosmArgs A = losm_batch_args(tab[blockIdx.x], c);
-  *A.status = 0;
+  if (threadIdx.x == 0) *A.status = 0;
   losm_factor_body(A);
 }
 
@@ -425,10 +479,11 @@ __global__ void __launch_bounds__(LOSM_REDUCE_THREADS) losm_reduce_batch_kernel(
   losm_reduce_body(A, (int)blockIdx.x);
 }
 
+template <int kWil>
 __global__ void __launch_bounds__(LOSM_THREADS) losm_batch_kernel(const LosmReplica *tab, LosmCall c) {
   extern __shared__ double dyn[];
   const LosmArgs A = losm_batch_args(tab[blockIdx.x], c);
-  losm_body(A, dyn);
+  losm_body<kWil>(A, dyn);
 }
 
 // Dynamic LDS of a solve of I cells: the unknowns; then, when they fit
@@ -436,9 +491,9 @@ __global__ void __launch_bounds__(LOSM_THREADS) losm_batch_kernel(const LosmRepl
 // 1) and also the Fourier filter's coefficients (2).
 static size_t losm_lds(int I, int *work_in_lds) {
   const size_t lds_min = (size_t)(2 * I + 3) * sizeof(double);
-  const size_t lds_full = lds_min + (size_t)5 * (I + 2) * sizeof(double);
+  const size_t lds_full = lds_min + (size_t)6 * (I + 2) * sizeof(double);
   const size_t lds_four = lds_full + (size_t)((I + 2) + 4) * sizeof(double);
-  const size_t budget = 160 * 1024 - 17 * 1024;
+  const size_t budget = 160 * 1024 - 2 * 1024;  // static LDS of the solve: about 1.3 KB
   *work_in_lds = lds_four <= budget ? 2 : (lds_full <= budget ? 1 : 0);
   return *work_in_lds == 2 ? lds_four : (*work_in_lds == 1 ? lds_full : lds_min);
 }
@@ -468,12 +523,17 @@ hipError_t launch_losm_batch(const LosmReplica *tab, int n, int max_I, const Los
   int wil = 0;
   const size_t lds = losm_lds(max_I, &wil);
   if (wil != c.work_in_lds) return hipErrorInvalidValue;
-  static size_t done = 0;
+  static size_t done[3] = {0, 0, 0};
+  const void *fn = wil == 2 ? reinterpret_cast<const void *>(&losm_batch_kernel<2>)
+                 : wil == 1 ? reinterpret_cast<const void *>(&losm_batch_kernel<1>)
+                            : reinterpret_cast<const void *>(&losm_batch_kernel<0>);
   {
-    const hipError_t e = allow_losm_lds(reinterpret_cast<const void *>(&losm_batch_kernel), lds, &done);
+    const hipError_t e = allow_losm_lds(fn, lds, &done[wil]);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(losm_batch_kernel, dim3(n), dim3(LOSM_THREADS), lds, s, tab, c);
+  if (wil == 2) hipLaunchKernelGGL(losm_batch_kernel<2>, dim3(n), dim3(LOSM_THREADS), lds, s, tab, c);
+  else if (wil == 1) hipLaunchKernelGGL(losm_batch_kernel<1>, dim3(n), dim3(LOSM_THREADS), lds, s, tab, c);
+  else hipLaunchKernelGGL(losm_batch_kernel<0>, dim3(n), dim3(LOSM_THREADS), lds, s, tab, c);
   return hipGetLastError();
 }
 
@@ -490,12 +550,18 @@ hipError_t launch_losm(const LosmArgs &a, hipStream_t s) {
   }
   LosmArgs b = a;
   const size_t lds = losm_lds(a.I, &b.work_in_lds);
-  static size_t done = 0;
+  const int wil = b.work_in_lds;
+  static size_t done[3] = {0, 0, 0};
+  const void *fn = wil == 2 ? reinterpret_cast<const void *>(&losm_kernel<2>)
+                 : wil == 1 ? reinterpret_cast<const void *>(&losm_kernel<1>)
+                            : reinterpret_cast<const void *>(&losm_kernel<0>);
   {
-    const hipError_t e = allow_losm_lds(reinterpret_cast<const void *>(&losm_kernel), lds, &done);
+    const hipError_t e = allow_losm_lds(fn, lds, &done[wil]);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(losm_kernel, dim3(1), dim3(LOSM_THREADS), lds, s, b);
+  if (wil == 2) hipLaunchKernelGGL(losm_kernel<2>, dim3(1), dim3(LOSM_THREADS), lds, s, b);
+  else if (wil == 1) hipLaunchKernelGGL(losm_kernel<1>, dim3(1), dim3(LOSM_THREADS), lds, s, b);
+  else hipLaunchKernelGGL(losm_kernel<0>, dim3(1), dim3(LOSM_THREADS), lds, s, b);
   return hipGetLastError();
 }
 

@@ -92,6 +92,23 @@ __device__ inline double losm_rhs(int I, const double *edges, const double *sig_
        + (th - 1.0) * ((phi_o[j + 1] - phi_o[j]) / 3.0 + sh * dxh * J_o[j] - (F_o[j + 1] - F_o[j]));
 }
 
+// The same right-hand side with the old-time diagonal bb_r of row r (the
+// coefficient of u_r in losm_brow) precomputed: no mesh or cross-section
+// reads in the solve.
+__device__ inline double losm_rhs_bb(int I, double th, int r, double bb, const double *phi_o, const double *J_o,
+                                     const double *F_o, const double *F_n, double PL, double PR) {
+  const int n = 2 * I + 3;
+  if (r == 0) return PL;
+  if (r == n - 1) return -PR;
+  if ((r & 1) == 0) {
+    const int i = r / 2;
+    return bb * phi_o[i] + (th - 1.0) * (J_o[i] - J_o[i - 1]);
+  }
+  const int j = (r - 1) / 2;
+  return bb * J_o[j] + th * (F_n[j + 1] - F_n[j])
+       + (th - 1.0) * ((phi_o[j + 1] - phi_o[j]) / 3.0 - (F_o[j + 1] - F_o[j]));
+}
+
 // Thomas factors of the matrix (or of its transpose) for the forward
 // recurrence d'_r = d_r/den_r + alpha_r d'_{r-1} and the backward one
 // x_r = d'_r + gamma_r x_{r+1}: factor = [alpha | 1/den | gamma], each n long.
@@ -203,6 +220,74 @@ __device__ inline void losm_solve_scans(double *u, int n, const double *factor, 
       y = u[r] + g * y;
       u[r] = y;
     }
+  }
+  __syncthreads();
+}
+
+// losm_solve_scans with each thread's factor entries loaded into registers
+// beforehand (losm_scan_prefetch, at most MR rows per thread): the same
+// arithmetic in the same order, without factor loads on the critical path.
+// The factor array here is [alpha | 1/den | gamma | bb] (bb: the old-time
+// diagonal of losm_rhs_bb).
+template <int MR>
+struct ScanRows {
+  double al[MR], iv[MR], ga[MR], bb[MR];
+};
+
+template <int MR>
+__device__ inline void losm_scan_prefetch(const double *factor, int n, ScanRows<MR> &R) {
+  const int T = blockDim.x, tid = threadIdx.x;
+  const int m = (n + T - 1) / T;
+  const int r0 = tid * m, b0 = (T - 1 - tid) * m;
+#pragma unroll
+  for (int k = 0; k < MR; ++k) {
+    const int r = r0 + k, rb = b0 + k;
+    const bool f = k < m && r < n, b = k < m && rb < n;
+    R.al[k] = f ? factor[r] : 0.0;
+    R.iv[k] = f ? factor[n + r] : 0.0;
+    R.bb[k] = f ? factor[3 * n + r] : 0.0;
+    R.ga[k] = (b && rb != n - 1) ? factor[2 * n + rb] : 0.0;
+  }
+}
+
+template <int MR>
+__device__ inline void losm_solve_scans_rows(double *u, int n, const ScanRows<MR> &R, double *sp, double *sq) {
+  const int T = blockDim.x, tid = threadIdx.x;
+  const int m = (n + T - 1) / T;
+  {
+    const int r0 = tid * m, cnt = min(m, n - r0);
+    double P = 0.0, Q = 1.0;
+#pragma unroll
+    for (int k = 0; k < MR; ++k)
+      if (k < cnt) {
+        P = u[r0 + k] * R.iv[k] + R.al[k] * P;
+        Q = R.al[k] * Q;
+      }
+    double y = affine_scan_excl(sp, sq, P, Q);
+#pragma unroll
+    for (int k = 0; k < MR; ++k)
+      if (k < cnt) {
+        y = u[r0 + k] * R.iv[k] + R.al[k] * y;
+        u[r0 + k] = y;
+      }
+  }
+  __syncthreads();
+  {
+    const int b0 = (T - 1 - tid) * m, cnt = min(m, n - b0);
+    double P = 0.0, Q = 1.0;
+#pragma unroll
+    for (int k = MR - 1; k >= 0; --k)
+      if (k < cnt) {
+        P = u[b0 + k] + R.ga[k] * P;
+        Q = R.ga[k] * Q;
+      }
+    double y = affine_scan_excl(sp, sq, P, Q);
+#pragma unroll
+    for (int k = MR - 1; k >= 0; --k)
+      if (k < cnt) {
+        y = u[b0 + k] + R.ga[k] * y;
+        u[b0 + k] = y;
+      }
   }
   __syncthreads();
 }

@@ -137,7 +137,7 @@ void make_layout(const hww_problem &p, Layout *L, bool member = false) {
   L->off_err = c.take(4);
   L->off_status = c.take(4);
   L->off_scratch = c.take(8 * 24 * (I + 4));
-  L->off_factor = c.take(8 * 3 * (2 * I + 3));
+  L->off_factor = c.take(8 * 4 * (2 * I + 3));
   L->off_phi_out = c.take(8 * (I + 2));
   L->off_J_out = c.take(8 * (I + 1));
   L->off_F_out = c.take(8 * (I + 2));
@@ -225,6 +225,11 @@ struct hww_handle {
   int ww_on = 0;
   int fatal = 0;
   double factor_theta = -1.0;  // theta of the LU factors in the workspace
+  // Writes into each tally set (sweeps, clears) and the set and count whose
+  // batch sums of the initial condition the LOSM scratch holds.
+  uint64_t tal_epoch[2] = {0, 0};
+  int ic_buf = -1;
+  uint64_t ic_epoch = 0;
   size_t lds = 0;
   int block = kBlock, tile = kTile, grid = 0;  // sweep launch shape (grid: batched launches)
   bool cells_lds = false;      // the sweep keeps the per-cell records in LDS
@@ -388,12 +393,14 @@ int launch_chunk(hww_handle *h, int chunk, int k) {
     else a.dq = h->bq32;
     a.dcap = h->bdcap;
     a.err = h->err;
+    ++h->tal_epoch[h->cur_tal];
     HIPCHK(h, launch_sweep_batch<Real>(a, h->cells_lds, h->grid, h->block, h->lds, h->stream));
     return HWW_OK;
   }
   SweepArgs<Real> a = base_args<Real>(h);
   a.chunk = chunk;
   a.tile = h->tile;
+  ++h->tal_epoch[h->cur_tal];
   HIPCHK(h, launch_sweep<Real>(a, h->cells_lds, h->B * h->K, h->block, h->lds, h->stream));
   return HWW_OK;
 }
@@ -486,6 +493,7 @@ int prime_handle(hww_handle *h, const hww_problem &problem) {
   HIPCHK(h, launch_fill_u32(reinterpret_cast<uint32_t *>(h->status), 0u, 1, h->stream));
   h->start_bank = 0;
   h->cur_tal = 0;
+  h->ic_buf = -1;
   SourceArgs sa{};
   sa.I = I; sa.B = h->B; sa.nc = h->nc;
   sa.v = problem.speed; sa.dt = problem.dt; sa.src_x = problem.src_x;
@@ -648,6 +656,7 @@ void flip_banks(hww_handle *h) {
 
 // Queue the clearing of the new step's accumulators (after flip_banks).
 int begin_step(hww_handle *h) {
+  ++h->tal_epoch[h->cur_tal];
   if (h->is_batch) {
     HIPCHK(h, launch_begin_step_batch(h->bs_tab + (size_t)h->start_bank * h->rep.size(), (int)h->rep.size(),
                                       (int64_t)64 * h->max_I * 6, h->stream));
@@ -892,6 +901,19 @@ int hww_read_run_stats(hww_handle *h, hww_step_stats *stats) {
   return HWW_OK;
 }
 
+// The batch sums of the initial-condition set stay in the LOSM scratch from
+// one solve to the next while that tally set is not written: the semi-
+// implicit solve of a step and the implicit solves of the next share them.
+// A replica view of a batch sees no sweeps of its own and never caches.
+static int ic_cached(const hww_handle *h, int buf) {
+  return !h->is_view && h->ic_buf == buf && h->ic_epoch == h->tal_epoch[buf];
+}
+static void note_ic(hww_handle *h, int buf) {
+  if (h->is_view) return;
+  h->ic_buf = buf;
+  h->ic_epoch = h->tal_epoch[buf];
+}
+
 int hww_solve_losm(hww_handle *h, const hww_losm_opts *o, double *phi_out, double *J_out) {
   if (!h || !o) return HWW_E_INVALID_ARG;
   if (h->is_view) return fail(h, HWW_E_STATE, "a replica view is read-only");
@@ -923,7 +945,10 @@ int hww_solve_losm(hww_handle *h, const hww_losm_opts *o, double *phi_out, doubl
     c.refactor = (o->theta != h->factor_theta) ? 1 : 0;
     c.work_in_lds = h->losm_wil;
     c.theta = o->theta; c.eps_min = o->eps_min; c.rho = o->rho;
+    const int ib = o->implicit ? 1 - h->cur_tal : h->cur_tal;
+    c.ic_cached = ic_cached(h, ib);
     HIPCHK(h, launch_losm_batch(h->losm_tab, (int)h->rep.size(), h->max_I, c, h->stream));
+    note_ic(h, ib);
     h->factor_theta = o->theta;
     if (o->apply_windows) h->ww_on = 1;
     sync_replica_state(h);
@@ -956,8 +981,11 @@ int hww_solve_losm(hww_handle *h, const hww_losm_opts *o, double *phi_out, doubl
   a.refactor = (o->theta != h->factor_theta) ? 1 : 0;
   a.win = h->win;
   a.phi_out = h->phi_out; a.J_out = h->J_out; a.err = h->err; a.status = h->status;
+  const int ib = o->implicit ? 1 - h->cur_tal : h->cur_tal;
+  a.ic_cached = ic_cached(h, ib);
   if (a.refactor) HIPCHK(h, launch_fill_u32(reinterpret_cast<uint32_t *>(h->status), 0u, 1, h->stream));
   HIPCHK(h, launch_losm(a, h->stream));
+  note_ic(h, ib);
   h->factor_theta = o->theta;
   if (o->apply_windows) h->ww_on = 1;
   if (phi_out || J_out) {
@@ -989,8 +1017,10 @@ int hww_read_closures(hww_handle *h, double *F, double *P, double *phi, double *
   a.export_only = 1;
   a.F_out = reinterpret_cast<double *>(h->ws + h->L.off_F_out);
   a.P_out = reinterpret_cast<double *>(h->ws + h->L.off_P_out);
+  a.ic_cached = ic_cached(h, h->cur_tal);
   if (a.refactor) HIPCHK(h, launch_fill_u32(reinterpret_cast<uint32_t *>(h->status), 0u, 1, h->stream));
   HIPCHK(h, launch_losm(a, h->stream));
+  note_ic(h, h->cur_tal);
   h->factor_theta = a.theta;
   const int I = h->I;
   HIPCHK(h, hipMemcpyAsync(F, a.F_out, 8 * (size_t)(I + 2), hipMemcpyDeviceToHost, h->stream));
@@ -1427,6 +1457,7 @@ int hww_autotune(hww_handle *h, hww_tune_result *best) {
     HIPCHK(h, launch_fill_u32(reinterpret_cast<uint32_t *>(reps[r]->tracks), 0u, 2 * (int64_t)reps[r]->I, h->stream));
   }
   HIPCHK(h, hipMemcpyAsync(cdev, csave.data(), 8 * ncnt, hipMemcpyHostToDevice, h->stream));
+  h->ic_buf = -1;
   rc = clear_work();
   if (rc != HWW_OK) return rc;
   HIPCHK(h, hipStreamSynchronize(h->stream));
