@@ -5,7 +5,9 @@
  * the hybrid weight-window Monte Carlo method of Shaw & Anistratov (arXiv
  * 2512.19925): flight, collision and census of a 1D slab particle bank with
  * isotropic scattering (transport equation, Sec. 3 Eq. HO_transport),
- * track-length and time-crossing tallies (Sec. 3 Eqs. phi-mc, ct-mc),
+ * and fission (the nu_f Sigma_f term of that equation), track-length and
+ * time-crossing tallies (Sec. 3 Eqs. phi-mc, ct-mc), uniform combing of the
+ * census (the population control of Sec. 5.1),
  * splitting and Russian roulette against weight windows (Sec. 2, Eqs.
  * ww-c&f, ww-center), and the hybrid low-order second-moment (HLOSM)
  * solve that defines the window centres (Sec. 3 Eqs. losm-disc,
@@ -32,6 +34,15 @@
  *                       closed-form moment solutions for 0 < c < 1
  *   split / roulette    exact daughter count and weight sum, unbiased
  *                       roulette, HWW vs analog tallies agree statistically
+ *   fission             nu_f = 1 fission identical to scattering (tallies,
+ *                       counters, solves), exact multiplicity for integer
+ *                       nu_f, closed-form pulse moments and the reference
+ *                       pulse solution at c_eff = 1.1, low-order balance
+ *                       with the nu_f sigma_f production term
+ *   orc_comb            systematic-sampling property (floor/ceil copies of
+ *                       every run, canonical order kept), equal weights
+ *                       summing to the census weight, identities and
+ *                       chunks, uniform offset over seeds
  * Parity unpinned: the variance/FOM benefit of a particular window schedule
  * (the paper shows it only in figures).
  */
@@ -72,7 +83,7 @@ double orc_u53(uint32_t a, uint32_t b) {
 
 /* Random-number slots of the keying contract. */
 enum { SLOT_FLIGHT = 0, SLOT_EVENT = 1, SLOT_START = 2, SLOT_BIRTH = 3,
-       SLOT_LIN_EVENT = 4, SLOT_LIN_START = 5 };
+       SLOT_LIN_EVENT = 4, SLOT_LIN_START = 5, SLOT_FISSION_DIR = 6, SLOT_COMB = 7 };
 
 static void draw(uint32_t seed, uint32_t replica, int slot, uint32_t src, uint64_t lin,
                  uint32_t e, double *ua, double *ub, uint32_t raw[4]) {
@@ -117,6 +128,10 @@ typedef struct {
 struct orc_sim {
   int32_t I;
   double *edges, *sig_t, *sig_s, *cratio, *inv_sig_t;
+  double *cfis;      /* (sigma_s + sigma_f) / sigma_t: collision is scatter below cratio, fission below cfis */
+  double *sig_s_lo;  /* sigma_s + nu_f sigma_f: the production term of the low-order balance */
+  double nu_f;
+  int fission;
   double v, inv_v, dt;
   int32_t n_steps;
   double src_x;
@@ -176,6 +191,7 @@ static int batch_of(const orc_sim *s, uint32_t src) { return (int)(src % (uint32
 void orc_destroy(orc_sim *s) {
   if (!s) return;
   free(s->edges); free(s->sig_t); free(s->sig_s); free(s->cratio); free(s->inv_sig_t); free(s->batch_on);
+  free(s->cfis); free(s->sig_s_lo);
   free(s->centre); free(s->ceil_); free(s->floor_);
   free(s->start); free(s->census); free(s->stack);
   free(s->cur.cells); free(s->cur.bnd); free(s->prev.cells); free(s->prev.bnd);
@@ -206,7 +222,9 @@ int orc_create(const orc_params *p, orc_sim **out) {
   for (int i = 0; i < I; ++i) {
     if (!(p->edges[i + 1] > p->edges[i])) return -1;
     if (!(p->sigma_t[i] > 0.0) || !(p->sigma_s[i] >= 0.0) || p->sigma_s[i] > p->sigma_t[i]) return -1;
+    if (p->sigma_f && (!(p->sigma_f[i] >= 0.0) || p->sigma_s[i] + p->sigma_f[i] > p->sigma_t[i])) return -1;
   }
+  if (p->sigma_f && (!(p->nu_f >= 0.0) || !(p->nu_f < 1.0e6))) return -1;
   if (!(p->src_x >= p->edges[0] && p->src_x <= p->edges[I])) return -1;
 
   orc_sim *s = (orc_sim *)calloc(1, sizeof(orc_sim));
@@ -219,6 +237,8 @@ int orc_create(const orc_params *p, orc_sim **out) {
   s->sig_s = (double *)malloc(sizeof(double) * I);
   s->cratio = (double *)malloc(sizeof(double) * I);
   s->inv_sig_t = (double *)malloc(sizeof(double) * I);
+  s->cfis = (double *)malloc(sizeof(double) * I);
+  s->sig_s_lo = (double *)malloc(sizeof(double) * I);
   s->centre = (double *)malloc(sizeof(double) * I);
   s->ceil_ = (double *)malloc(sizeof(double) * I);
   s->floor_ = (double *)malloc(sizeof(double) * I);
@@ -230,7 +250,8 @@ int orc_create(const orc_params *p, orc_sim **out) {
   s->census = (particle *)malloc(sizeof(particle) * (size_t)(s->cap > 0 ? s->cap : 1));
   s->cap_stack = 1024;
   s->stack = (particle *)malloc(sizeof(particle) * (size_t)s->cap_stack);
-  if (!s->edges || !s->sig_t || !s->sig_s || !s->cratio || !s->inv_sig_t || !s->centre || !s->ceil_ ||
+  if (!s->edges || !s->sig_t || !s->sig_s || !s->cratio || !s->inv_sig_t || !s->cfis || !s->sig_s_lo ||
+      !s->centre || !s->ceil_ ||
       !s->floor_ || !s->batch_on || !s->tracks || !s->w_chunk_start || !s->w_chunk_next ||
       !s->start || !s->census || !s->stack ||
       tally_alloc(&s->cur, s->B, I) || tally_alloc(&s->prev, s->B, I)) {
@@ -240,9 +261,14 @@ int orc_create(const orc_params *p, orc_sim **out) {
   memcpy(s->edges, p->edges, sizeof(double) * (I + 1));
   memcpy(s->sig_t, p->sigma_t, sizeof(double) * I);
   memcpy(s->sig_s, p->sigma_s, sizeof(double) * I);
+  s->fission = p->sigma_f != NULL;
+  s->nu_f = s->fission ? p->nu_f : 0.0;
   for (int i = 0; i < I; ++i) {
     s->cratio[i] = s->sig_s[i] / s->sig_t[i];
     s->inv_sig_t[i] = 1.0 / s->sig_t[i];
+    const double sf = s->fission ? p->sigma_f[i] : 0.0;
+    s->cfis[i] = (s->sig_s[i] + sf) / s->sig_t[i];
+    s->sig_s_lo[i] = s->sig_s[i] + s->nu_f * sf;
   }
   s->inv_v = 1.0 / s->v;
   memset(s->batch_on, 1, s->B);
@@ -458,6 +484,35 @@ static int transport(orc_sim *s, particle *p) {
       if (r == 1) return 0;
       continue;
     }
+    if (s->fission && ub < s->cfis[i]) {
+      /* Fission (Eq. HO_transport, nu_f Sigma_f term): floor(nu_f + xi)
+       * neutrons of the parent's weight, isotropic.  The first continues
+       * the parent's history with the direction of slot 1; the others are
+       * daughters with lineage base + j (base from slot 4) and directions
+       * from slot 6 at their own lineage. */
+      double ua1, xi;
+      draw(s->seed, s->replica, SLOT_EVENT, p->src, p->lin, e, &ua1, &xi, NULL);
+      const int64_t nf = (int64_t)floor(s->nu_f + xi);
+      s->counters[ORC_N_FISSIONS] += 1;
+      s->counters[ORC_N_FISSION_BIRTHS] += (uint64_t)nf;
+      if (nf == 0) return 0;
+      p->mu = 2.0 * ua1 - 1.0;
+      if (nf >= 2) {
+        uint32_t raw[4];
+        draw(s->seed, s->replica, SLOT_LIN_EVENT, p->src, p->lin, e, NULL, NULL, raw);
+        const uint64_t base = (uint64_t)raw[0] | ((uint64_t)raw[1] << 32);
+        for (int64_t j = nf - 1; j >= 1; --j) {
+          particle d = *p;
+          d.lin = base + (uint64_t)j;
+          d.e = p->e;
+          double ud;
+          draw(s->seed, s->replica, SLOT_FISSION_DIR, d.src, d.lin, d.e, &ud, NULL, NULL);
+          d.mu = 2.0 * ud - 1.0;
+          if (push(s, &d)) return -3;
+        }
+      }
+      continue;
+    }
     s->counters[ORC_N_ABSORPTIONS] += 1;
     return 0;
   }
@@ -516,6 +571,95 @@ int orc_sweep_chunk(orc_sim *s, int32_t step, int32_t chunk) {
     }
   }
   s->next_chunk = chunk + 1;
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Uniform combing                                                           */
+/* ------------------------------------------------------------------------ */
+
+/* Canonical order of a bank: source history, then lineage, then event index
+ * (particles of equal keys share their whole random stream from there on). */
+static int canon_cmp(const void *a, const void *b) {
+  const particle *p = (const particle *)a, *q = (const particle *)b;
+  if (p->src != q->src) return p->src < q->src ? -1 : 1;
+  if (p->lin != q->lin) return p->lin < q->lin ? -1 : 1;
+  if (p->e != q->e) return p->e < q->e ? -1 : 1;
+  return 0;
+}
+
+/* Uniform comb (population control of Sec. 5.1): lay the census particles
+ * end to end in canonical order, each an interval as long as its weight, and
+ * put n_target teeth at (k + xi) W / n_target, k = 0 .. n_target-1, with one
+ * uniform xi per comb (slot 7, counter (step, 0, 0, 0)).  Every tooth makes
+ * a copy of the particle whose interval it hits, of weight W / n_target.
+ * The weights are laid out as integers in units of 2^eu, eu chosen so that
+ * n max(w) < 2^(53 + eu): every prefix sum is then exact both as an integer
+ * and as a double, and so is each comparison with a tooth.  Copy k becomes
+ * history k of lineage `step` (event index 0) in batch k mod B and chunk
+ * (k / B) mod n_chunks. */
+int orc_comb(orc_sim *s, int64_t n_target, int64_t *n_before, double *w_total) {
+  if (!s || n_target < 1 || n_target > s->cap || n_target > 0xFFFFFFFFll) return -1;
+  if (s->next_chunk != s->n_chunks || s->step < 1) return -2;
+  for (int b = 0; b < s->B; ++b)
+    if (!s->batch_on[b]) return -2;
+  const int64_t n = s->n_census;
+  if (n_before) *n_before = n;
+  if (w_total) *w_total = 0.0;
+  if (n == 0) return 0;
+  qsort(s->census, (size_t)n, sizeof(particle), canon_cmp);
+  double m = 0.0;
+  for (int64_t j = 0; j < n; ++j)
+    if (s->census[j].w > m) m = s->census[j].w;
+  if (!(m > 0.0) || !isfinite(m)) return -5;
+  int em;
+  frexp(m, &em); /* m < 2^em */
+  int ln = 0;
+  while (((int64_t)1 << ln) < n) ++ln;
+  const int eu = em + ln - 53;
+  uint64_t *q = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
+  if (!q) return -3;
+  uint64_t acc = 0;
+  for (int64_t j = 0; j < n; ++j) {
+    acc += (uint64_t)rint(ldexp(s->census[j].w, -eu));
+    q[j] = acc; /* inclusive prefix sum */
+  }
+  const double W = (double)acc;
+  double xi;
+  draw(s->seed, s->replica, SLOT_COMB, (uint32_t)s->step, 0, 0, &xi, NULL, NULL);
+  const double delta = W / (double)n_target;
+  const double w_out = ldexp(W, eu) / (double)n_target;
+  int64_t *per_chunk = (int64_t *)calloc((size_t)s->n_chunks, sizeof(int64_t));
+  if (!per_chunk) { free(q); return -3; }
+  particle *dst = s->start;
+  for (int64_t k = 0; k < n_target; ++k) {
+    double t = ((double)k + xi) * delta;
+    if (t >= W) t = W - 1.0;
+    /* First particle whose interval ends beyond the tooth. */
+    int64_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+      const int64_t mid = lo + (hi - lo) / 2;
+      if ((double)q[mid] > t) hi = mid; else lo = mid + 1;
+    }
+    particle c = s->census[lo];
+    c.w = w_out;
+    c.src = (uint32_t)k;
+    c.lin = (uint64_t)s->step;
+    c.e = 0;
+    c.chunk = (int32_t)((k / s->B) % s->n_chunks);
+    per_chunk[c.chunk] += 1;
+    dst[k] = c;
+  }
+  s->start = s->census;
+  s->census = dst;
+  s->n_census = n_target;
+  for (int c = 0; c < s->n_chunks; ++c) {
+    s->w_chunk_next[c].s = (double)per_chunk[c] * w_out;
+    s->w_chunk_next[c].c = 0.0;
+  }
+  if (w_total) *w_total = ldexp(W, eu);
+  free(per_chunk);
+  free(q);
   return 0;
 }
 
@@ -814,7 +958,7 @@ int orc_solve_losm(orc_sim *s, const orc_losm_opts *o, double *phi_out, double *
     free(buf);
     return -1;
   }
-  int rc = orc_losm_step(I, s->edges, s->sig_t, s->sig_s, s->v, s->dt, o->theta,
+  int rc = orc_losm_step(I, s->edges, s->sig_t, s->sig_s_lo, s->v, s->dt, o->theta,
                          phi_o, J_o, F_o, F_n, PL, PR, 0.0, 0.0, NULL, NULL, phi_n, J_n);
   if (rc == 0) {
     if (phi_out) memcpy(phi_out, phi_n, sizeof(double) * (I + 2));

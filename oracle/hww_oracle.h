@@ -26,7 +26,8 @@ enum { ORC_B_PHI = 0, ORC_B_P = 1, ORC_B_F = 2 };
 enum {
   ORC_N_SEGMENTS = 0, ORC_N_COLLISIONS, ORC_N_SCATTERS, ORC_N_ABSORPTIONS,
   ORC_N_CROSSINGS, ORC_N_LEAKS, ORC_N_CENSUS, ORC_N_SPLITS, ORC_N_DAUGHTERS,
-  ORC_N_RR_KILL, ORC_N_RR_SURVIVE, ORC_N_HISTORIES, ORC_N_COUNTERS = 16
+  ORC_N_RR_KILL, ORC_N_RR_SURVIVE, ORC_N_HISTORIES, ORC_N_FISSIONS, ORC_N_FISSION_BIRTHS,
+  ORC_N_COUNTERS = 16
 };
 
 typedef struct orc_params {
@@ -42,6 +43,8 @@ typedef struct orc_params {
   uint32_t seed, replica;
   int32_t n_batches;
   int32_t n_chunks;
+  const double *sigma_f;  /* n_cells, or NULL: no fission */
+  double nu_f;            /* mean number of neutrons per fission */
 } orc_params;
 
 typedef struct orc_losm_opts {
@@ -70,6 +73,11 @@ void orc_destroy(orc_sim *s);
 int orc_set_batch_mask(orc_sim *s, const uint8_t *mask);
 int orc_set_windows(orc_sim *s, const double *centre, double rho);
 int orc_sweep_chunk(orc_sim *s, int32_t step, int32_t chunk);
+/* Uniform combing of the census bank of the finished step into n_target
+ * particles of equal weight (population control of the supercritical test
+ * problem, Sec. 5.1).  n_before and w_total (nullable) return the census
+ * size and the total weight that the comb distributes. */
+int orc_comb(orc_sim *s, int64_t n_target, int64_t *n_before, double *w_total);
 int orc_solve_losm(orc_sim *s, const orc_losm_opts *o, double *phi_out, double *J_out);
 /* Unfiltered closures F (I+2), P (2) and initial condition phi (I+2), J (I+1)
  * that the finished step hands to the next. */

@@ -21,7 +21,8 @@ _LIB = os.path.join(_HERE, "liborc_hww.so")
 
 T_PHI, T_J, T_K, C_PHI, C_J, C_K = range(6)
 COUNTER_NAMES = ["segments", "collisions", "scatters", "absorptions", "crossings", "leaks",
-                 "census", "splits", "daughters", "rr_kill", "rr_survive", "histories"]
+                 "census", "splits", "daughters", "rr_kill", "rr_survive", "histories", "fissions",
+                 "fission_births"]
 N_COUNTERS = 16
 
 
@@ -52,6 +53,7 @@ def lib():
         L.orc_set_batch_mask.argtypes = [C.c_void_p, C.c_void_p]
         L.orc_set_windows.argtypes = [C.c_void_p, dp, C.c_double]
         L.orc_sweep_chunk.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
+        L.orc_comb.argtypes = [C.c_void_p, C.c_int64, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
         L.orc_solve_losm.argtypes = [C.c_void_p, C.c_void_p, dp, dp]
         L.orc_get_closures.argtypes = [C.c_void_p, dp, dp, dp, dp]
         L.orc_get_tallies.argtypes = [C.c_void_p, C.c_int32, dp, dp]
@@ -194,7 +196,7 @@ class _Params(C.Structure):
                 ("speed", C.c_double), ("dt", C.c_double), ("n_steps", C.c_int32),
                 ("src_x", C.c_double), ("n_src", C.c_int64), ("bank_capacity", C.c_int64),
                 ("seed", C.c_uint32), ("replica", C.c_uint32), ("n_batches", C.c_int32),
-                ("n_chunks", C.c_int32)]
+                ("n_chunks", C.c_int32), ("sigma_f", C.POINTER(C.c_double)), ("nu_f", C.c_double)]
 
 
 class _Opts(C.Structure):
@@ -220,10 +222,11 @@ class OracleSim:
     """One problem on the oracle.  Arguments are plain numbers and arrays."""
 
     def __init__(self, edges, sigma_t, sigma_s, speed, dt, n_steps, src_x, n_src,
-                 bank_capacity=None, seed=1, replica=0, n_batches=32, n_chunks=4):
+                 bank_capacity=None, seed=1, replica=0, n_batches=32, n_chunks=4, sigma_f=None, nu_f=0.0):
         self.edges = _f64(edges)
         self.sigma_t = _f64(sigma_t)
         self.sigma_s = _f64(sigma_s)
+        self.sigma_f = None if sigma_f is None else _f64(sigma_f)
         self.I = len(self.sigma_t)
         self.B = int(n_batches)
         self.n_chunks = int(n_chunks)
@@ -232,7 +235,7 @@ class OracleSim:
         cap = int(bank_capacity) if bank_capacity is not None else max(4 * self.n_src, 1024)
         p = _Params(self.I, _dp(self.edges), _dp(self.sigma_t), _dp(self.sigma_s), self.speed,
                     self.dt, self.n_steps, float(src_x), self.n_src, cap, int(seed), int(replica),
-                    self.B, self.n_chunks)
+                    self.B, self.n_chunks, _dp(self.sigma_f), float(nu_f))
         h = C.c_void_p()
         _check("create", lib().orc_create(C.byref(p), C.byref(h)))
         self._h = h
@@ -264,6 +267,13 @@ class OracleSim:
 
     def sweep(self, step, chunk):
         _check("sweep", lib().orc_sweep_chunk(self._h, int(step), int(chunk)))
+
+    def comb(self, n_target):
+        """Uniform comb of the finished step's census into n_target particles;
+        returns (census size before, total weight)."""
+        nb, wt = C.c_int64(), C.c_double()
+        _check("comb", lib().orc_comb(self._h, int(n_target), C.byref(nb), C.byref(wt)))
+        return int(nb.value), float(wt.value)
 
     def solve_losm(self, opts: LosmOpts, implicit: bool, apply_windows=True):
         o = _Opts(float(opts.theta), int(implicit), int(opts.filter), int(opts.ma_k),
@@ -323,13 +333,16 @@ class OracleSim:
         return out
 
 
-def run(sim: OracleSim, steps, opts: LosmOpts | None, on_step=None, windows=None):
+def run(sim: OracleSim, steps, opts: LosmOpts | None, on_step=None, windows=None, comb=None):
     """Time loop of the method (Sec. 3): at the start of step n the
     semi-implicit HLOSM solve sets the windows; after each of the first
     n_chunks-1 chunks of histories the fully implicit solve updates them.
     ``opts=None`` runs analog (no windows); ``windows`` (a callable n -> centre
-    array) feeds fixed windows instead of the HLOSM ones."""
+    array) feeds fixed windows instead of the HLOSM ones; ``comb`` (a number
+    of particles) combs every census but the last one to that size."""
     for n in range(1, steps + 1):
+        if comb and n > 1:
+            sim.comb(comb)
         if opts is not None and windows is None:
             sim.solve_losm(opts, implicit=False)
         elif windows is not None:

@@ -6,9 +6,10 @@ path and the CPU oracle may be fed from it.
 
 The physics follows the paper's test (Sec. 5.1: infinite homogeneous slab, an
 isotropic unit pulse at x = 0 and t = 0, one speed) with the scattering ratios,
-meshes and particle counts of the five workloads below.  Every workload is
-pure scattering plus absorption (c < 1, no fission), so no population control
-is needed.
+meshes and particle counts of the workloads below.  Most are pure scattering
+plus absorption (c < 1, no fission), so no population control is needed; the
+paper's own supercritical problem (`paper_fission`) adds fission and combs
+every census back to a fixed population.
 """
 from __future__ import annotations
 
@@ -44,6 +45,9 @@ class Workload:
     lagged: bool = False       # windows from the previous step's track-length flux (no LOSM)
     closure_track: int = 0
     analog: bool = False
+    sigma_f: np.ndarray | None = None  # fission cross sections (None: no fission)
+    nu_f: float = 0.0                  # mean neutrons per fission
+    comb: int = 0                      # comb every census to this many particles (0: never)
 
     @property
     def edges(self) -> np.ndarray:
@@ -79,6 +83,20 @@ def full_scale(c: float = 0.9, rho: float = 5.0, n_src: int = 10_000_000) -> Wor
 
 FULL_SCALE_C = (0.5, 0.9, 0.99)
 FULL_SCALE_RHO = (2.0, 2.5, 5.0, 10.0)
+
+
+def paper_fission(n_src: int = 10_000) -> Workload:
+    """The paper's supercritical test problem (Sec. 5.1): 201 cells on
+    [-20.5, 20.5], sigma_t = 1, sigma_s = sigma_f = 1/3, nu_f = 2.3
+    (c_eff = 1.1), v = 1, 20 steps of 1, H^n = 1e4 histories per step kept by
+    uniform combing, windows of width 1.25 with eps_min = 1e-3, Crank-Nicolson,
+    three window updates per step, moving-average filtered closures (k = 3)."""
+    I = 201
+    st = np.ones(I)
+    return Workload(name="paper-fission-201c", x_lo=-20.5, x_hi=20.5, n_cells=I, sigma_t=st,
+                    sigma_s=st / 3.0, sigma_f=st / 3.0, nu_f=2.3, speed=1.0, dt=1.0, n_steps=20,
+                    n_src=n_src, comb=n_src, rho=1.25, eps_min=1e-3, filter=1, ma_k=3,
+                    bank_capacity=max(40 * n_src, 4096), seed=1)
 
 
 def precision_form(n_src: int = 10_000_000) -> Workload:

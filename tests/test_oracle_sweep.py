@@ -12,7 +12,8 @@ from paper_2512_19925_amd import workloads as W
 
 def _sim(w, **kw):
     return O.OracleSim(w.edges, w.sigma_t, w.sigma_s, w.speed, w.dt, w.n_steps, w.src_x, w.n_src,
-                       w.capacity(), w.seed, w.replica, w.n_batches, w.n_chunks, **kw)
+                       w.capacity(), w.seed, w.replica, w.n_batches, w.n_chunks, sigma_f=w.sigma_f,
+                       nu_f=w.nu_f, **kw)
 
 
 def _opts(w):

@@ -22,7 +22,7 @@ def _cone_integral(f, t, n=600):
     return float(np.sum(w * t * np.cos(th) * f(x)))
 
 
-@pytest.mark.parametrize("c", [0.3, 0.9, 0.99])
+@pytest.mark.parametrize("c", [0.3, 0.9, 0.99, 1.1])
 @pytest.mark.parametrize("t", [0.2, 1.0, 4.0])
 def test_total_weight_and_second_moment(c, t):
     m0, _, _, x2 = CF.moments(c, t)
