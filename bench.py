@@ -403,7 +403,7 @@ def main():
         "kernel_segments_per_s": tim["segments"] / (tim["kernel_ms"] * 1e-3) if tim["kernel_ms"] else None,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "sweep_kernel<double, true>",
+                     "kernel": "sweep_kernel<double, true, false>",
                      "launches": tim["launches"], "avg_launch_ms": tim["kernel_ms"] / max(tim["launches"], 1),
                      "bytes_per_launch": tim["bytes_moved"] / max(tim["launches"], 1)},
     }

@@ -65,6 +65,10 @@ typedef struct hww_problem {
   int32_t n_batches;      /* statistical batches B (history src mod B), 1..64     */
   int32_t precision;      /* HWW_FP64 or HWW_FP32                                 */
   int32_t n_chunks;       /* u_ww + 1 window-update chunks per step, 1..8         */
+  const double *sigma_f;  /* I fission cross sections (host), or NULL: no fission;
+                             0 <= sigma_f, sigma_s + sigma_f <= sigma_t (Eq. HO_transport) */
+  double nu_f;            /* mean neutrons per fission, 0 <= nu_f < 1e6 (with sigma_f) */
+  int32_t comb;           /* 1: reserve the workspace hww_comb needs, 0: none    */
 } hww_problem;
 
 typedef struct hww_handle hww_handle;
@@ -79,6 +83,8 @@ typedef struct hww_step_stats {
   double kernel_ms;       /* summed sweep-kernel time of those launches made with timing
                              on (HIP events; see hww_set_timing)                       */
   uint64_t bytes_moved;   /* algorithmic bank bytes read + written by those launches    */
+  uint64_t fissions;      /* collisions that were fissions                              */
+  uint64_t fission_births;/* neutrons those fissions produced (the continuing one included) */
 } hww_step_stats;
 
 /* Options of an HLOSM solve (Sec. 3 Eqs. losm-disc / losm-disc-semi, Sec. 4). */
@@ -139,6 +145,26 @@ int hww_set_windows(hww_handle *h, const double *centre, double rho);
  * queues one kernel launch; with stats it waits for the GPU and fills the
  * step's counters so far.  Errors: HWW_E_STATE, HWW_E_CAPACITY, HWW_E_DEVICE. */
 int hww_sweep_step(hww_handle *h, int32_t step, int32_t chunk, hww_step_stats *stats);
+
+/* Uniform combing (the population control of the supercritical test problem,
+ * Sec. 5.1) of the census bank of the finished step into n_target particles
+ * of equal weight W / n_target, W the census weight.  The census particles
+ * are laid end to end in (src, lineage, event) order, each as long as its
+ * weight taken as an integer multiple of 2^eu (eu chosen so that
+ * count * max weight < 2^(53 + eu), which keeps every prefix sum exact), and
+ * n_target teeth are placed at (k + xi) W / n_target with one uniform xi per
+ * comb (Philox slot 7, counter (step, 0, 0, 0)).  Tooth k copies the
+ * position, direction and cell of the particle it hits; the copy becomes
+ * history k (lineage = step, event index 0) of batch k mod B and next-step
+ * chunk (k / B) mod n_chunks.  Census tallies are unchanged; the per-chunk
+ * census weights become count * W / n_target.  Call after the last chunk of
+ * a step and before the next step's semi-implicit solve.  n_before and
+ * w_total (nullable host pointers) receive the census size and W.
+ * Synchronises the stream.  Single problems initialised with comb = 1 only.
+ * Errors: HWW_E_INVALID_ARG (n_target outside 1..bank_capacity or > 2^32-1),
+ * HWW_E_STATE (step not finished, no comb workspace, a batch or a view),
+ * HWW_E_CAPACITY (a region of the new bank overflows), HWW_E_DEVICE. */
+int hww_comb(hww_handle *h, int64_t n_target, int64_t *n_before, double *w_total);
 
 /* Counters, kernel time and bank bytes of every sweep since init (same
  * fields as hww_step_stats, summed over all steps; generations is the

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhww.so")
-SOURCES = ["hww_runtime.hip", "hww_sweep.hip", "hww_losm.hip", "hww_adjoint.hip"]
+SOURCES = ["hww_runtime.hip", "hww_sweep.hip", "hww_losm.hip", "hww_adjoint.hip", "hww_comb.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -1,0 +1,387 @@
+// Uniform combing of a census bank (the population control of the paper's
+// supercritical test problem, Sec. 5.1): the census particles are laid end
+// to end in canonical order (src, lineage, event), each as long as its
+// weight, and n_target equally spaced teeth with one random offset pick the
+// particles that are copied, at weight W / n_target.
+//
+// Order on the device: a counting sort by src (histogram, exclusive scan,
+// scatter), then each history's particles sorted by (lineage, event): one
+// lane per history when it has few, one work-group ranking by comparison
+// counts when it has many.  Weights become integers in units of 2^eu
+// (count * max weight < 2^(53 + eu)), so the inclusive prefix sums are exact
+// and identical in any summation order, and each tooth finds its particle
+// by binary search over them.
+#include "hww_internal.h"
+#include "hww_rng_dev.h"
+
+namespace hww {
+
+namespace {
+
+constexpr int kScanThreads = 1024;
+constexpr int kScanPer = 4;                        // elements per thread in a scan tile
+constexpr int kScanTile = kScanThreads * kScanPer;
+constexpr int kSmallBin = 48;                      // histories sorted by one lane up to this size
+
+// Census slot q of the bank: valid when inside its segment's count.
+template <typename Real>
+__device__ inline bool census_slot(const CombArgs<Real> &A, int64_t q) {
+  const BankGeom &G = A.G;
+  const int64_t r = q / G.stride, o = q - r * G.stride;
+  if (o < (int64_t)G.K * G.seg_cap) {
+    const int64_t s = o / G.seg_cap, i = o - s * G.seg_cap;
+    const int64_t n = min((int64_t)A.src_bank.segcnt[r * G.K + s], G.seg_cap);
+    return i < n;
+  }
+  const int64_t i = o - (int64_t)G.K * G.seg_cap;
+  return i < min((int64_t)A.src_bank.ovfcnt[r], G.ovf_cap);
+}
+
+// Histogram by history, census count and largest weight (positive doubles
+// order like their bit patterns).
+template <typename Real>
+__global__ void comb_count_kernel(CombArgs<Real> A) {
+  const int64_t slots = (int64_t)A.R * A.G.stride;
+  unsigned long long mx = 0, n = 0;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < slots; q += (int64_t)gridDim.x * blockDim.x) {
+    if (!census_slot(A, q)) continue;
+    const uint32_t src = A.src_bank.tag[q].src;
+    if ((int64_t)src >= A.n_hist) {
+      atomicOr(A.err, ERR_CAPACITY);
+      continue;
+    }
+    atomicAdd(&A.cnt[src], 1ull);
+    const unsigned long long wb = (unsigned long long)__double_as_longlong(A.src_bank.w[q]);
+    mx = wb > mx ? wb : mx;
+    ++n;
+  }
+  for (int o = 32; o >= 1; o >>= 1) {
+    const unsigned long long t = __shfl_xor(mx, o);
+    mx = t > mx ? t : mx;
+    n += __shfl_xor(n, o);
+  }
+  if ((threadIdx.x & 63) == 0 && n != 0) {
+    atomicMax(&A.misc[0], mx);
+    atomicAdd(&A.misc[1], n);
+  }
+}
+
+// Scan of a[0..n) in tiles of kScanTile: local scan of each tile and its
+// total into blk; then the scan of the totals; then the tile offsets added.
+__device__ inline unsigned long long block_excl_scan(unsigned long long v, unsigned long long *sh,
+                                                     unsigned long long *total) {
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6, nw = blockDim.x >> 6;
+  unsigned long long x = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned long long y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) sh[wv] = x;
+  __syncthreads();
+  if (t == 0) {
+    unsigned long long acc = 0;
+    for (int w = 0; w < nw; ++w) {
+      const unsigned long long s = sh[w];
+      sh[w] = acc;
+      acc += s;
+    }
+    sh[32] = acc;
+  }
+  __syncthreads();
+  const unsigned long long r = sh[wv] + x - v;
+  *total = sh[32];
+  __syncthreads();
+  return r;
+}
+
+__global__ void __launch_bounds__(kScanThreads) scan_tiles_kernel(unsigned long long *a, int64_t n,
+                                                                  unsigned long long *blk, int inclusive) {
+  __shared__ unsigned long long sh[48];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
+  unsigned long long v[kScanPer], s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    v[k] = base + k < n ? a[base + k] : 0ull;
+    s += v[k];
+  }
+  unsigned long long total;
+  unsigned long long run = block_excl_scan(s, sh, &total);
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    const unsigned long long nx = run + v[k];
+    if (base + k < n) a[base + k] = inclusive ? nx : run;
+    run = nx;
+  }
+  if (threadIdx.x == 0) blk[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(kScanThreads) scan_top_kernel(unsigned long long *blk, int64_t nb) {
+  __shared__ unsigned long long sh[48];
+  unsigned long long carry = 0;
+  for (int64_t b0 = 0; b0 < nb; b0 += kScanThreads) {
+    const int64_t i = b0 + threadIdx.x;
+    const unsigned long long v = i < nb ? blk[i] : 0ull;
+    unsigned long long total;
+    const unsigned long long r = block_excl_scan(v, sh, &total);
+    if (i < nb) blk[i] = carry + r;
+    carry += total;
+  }
+}
+
+__global__ void __launch_bounds__(kScanThreads) scan_add_kernel(unsigned long long *a, int64_t n,
+                                                                const unsigned long long *blk) {
+  const unsigned long long off = blk[blockIdx.x];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k)
+    if (base + k < n) a[base + k] += off;
+}
+
+// Each census particle takes the next place of its history's range.
+template <typename Real>
+__global__ void comb_scatter_kernel(CombArgs<Real> A) {
+  const int64_t slots = (int64_t)A.R * A.G.stride;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < slots; q += (int64_t)gridDim.x * blockDim.x) {
+    if (!census_slot(A, q)) continue;
+    const uint32_t src = A.src_bank.tag[q].src;
+    if ((int64_t)src >= A.n_hist) continue;
+    const unsigned long long pos = A.cnt[src] + atomicAdd(&A.cur[src], 1u);
+    A.order[pos] = (unsigned long long)q;
+  }
+}
+
+template <typename Real>
+__device__ inline bool key_less(const CombArgs<Real> &A, unsigned long long qa, unsigned long long qb) {
+  const uint64_t la = A.src_bank.lin[qa], lb = A.src_bank.lin[qb];
+  if (la != lb) return la < lb;
+  return A.src_bank.tag[qa].e < A.src_bank.tag[qb].e;
+}
+
+// Histories with few particles: one lane each, insertion sort in place;
+// the others are listed (misc[4] counts them, their ids go to cur[]).
+template <typename Real>
+__global__ void comb_sort_small_kernel(CombArgs<Real> A) {
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < A.n_hist; s += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t lo = (int64_t)A.cnt[s], hi = (int64_t)A.cnt[s + 1];
+    if (hi - lo <= 1) continue;
+    if (hi - lo > kSmallBin) {
+      const unsigned long long slot = atomicAdd(&A.misc[4], 1ull);
+      A.cur[slot] = (uint32_t)s;  // the cursors are free again after the scatter
+      continue;
+    }
+    for (int64_t i = lo + 1; i < hi; ++i) {
+      const unsigned long long qi = A.order[i];
+      int64_t j = i - 1;
+      while (j >= lo && key_less(A, qi, A.order[j])) {
+        A.order[j + 1] = A.order[j];
+        --j;
+      }
+      A.order[j + 1] = qi;
+    }
+  }
+}
+
+// Histories with many particles: one work-group each; particle i goes to
+// place (number of particles of smaller key, ties by current place), keys
+// staged through LDS a tile at a time; the result goes through wq.
+template <typename Real>
+__global__ void __launch_bounds__(1024) comb_sort_big_kernel(CombArgs<Real> A) {
+  __shared__ uint64_t kl[1024];
+  __shared__ uint32_t ke[1024];
+  const int64_t nbig = (int64_t)A.misc[4];
+  for (int64_t g = blockIdx.x; g < nbig; g += gridDim.x) {
+    const int64_t s = A.cur[g];
+    const int64_t lo = (int64_t)A.cnt[s], m = (int64_t)A.cnt[s + 1] - lo;
+    for (int64_t i0 = 0; i0 < m; i0 += blockDim.x) {
+      const int64_t i = i0 + threadIdx.x;
+      uint64_t li = 0;
+      uint32_t ei = 0;
+      if (i < m) {
+        const unsigned long long q = A.order[lo + i];
+        li = A.src_bank.lin[q];
+        ei = A.src_bank.tag[q].e;
+      }
+      int64_t rank = 0;
+      for (int64_t j0 = 0; j0 < m; j0 += blockDim.x) {
+        __syncthreads();
+        const int64_t j = j0 + threadIdx.x;
+        if (j < m) {
+          const unsigned long long q = A.order[lo + j];
+          kl[threadIdx.x] = A.src_bank.lin[q];
+          ke[threadIdx.x] = A.src_bank.tag[q].e;
+        }
+        __syncthreads();
+        const int64_t jn = min((int64_t)blockDim.x, m - j0);
+        if (i < m)
+          for (int64_t t = 0; t < jn; ++t) {
+            const uint64_t lj = kl[t];
+            const uint32_t ej = ke[t];
+            const bool less = lj < li || (lj == li && (ej < ei || (ej == ei && j0 + t < i)));
+            rank += less ? 1 : 0;
+          }
+      }
+      if (i < m) A.wq[lo + rank] = A.order[lo + i];
+    }
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < m; i += blockDim.x) A.order[lo + i] = A.wq[lo + i];
+    __syncthreads();
+  }
+}
+
+// Integer weights in units of 2^eu, in canonical order.
+template <typename Real>
+__global__ void comb_weights_kernel(CombArgs<Real> A, int64_t n, int eu) {
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+    const double w = A.src_bank.w[A.order[j]];
+    A.wq[j] = (unsigned long long)rint(ldexp(w, -eu));
+  }
+}
+
+// Place of comb copy k in the new bank: region (k mod B, (k / B) mod nc),
+// the region's copies spread over its K segments in runs of `per`, the rest
+// (if a run would pass seg_cap) in the overflow segment.
+struct CombPlace {
+  int64_t slot;
+  bool ok;
+};
+__device__ __host__ inline void comb_region(int64_t H, int B, int nc, int b, int c, int64_t *n_bc) {
+  const int64_t n_b = H > b ? (H - b + B - 1) / B : 0;
+  *n_bc = n_b > c ? (n_b - c + nc - 1) / nc : 0;
+}
+__device__ inline CombPlace comb_place(int64_t k, int64_t H, int B, int nc, const BankGeom &G) {
+  const int b = (int)(k % B);
+  const int64_t t = k / B;
+  const int c = (int)(t % nc);
+  const int64_t q = t / nc;
+  int64_t n_bc;
+  comb_region(H, B, nc, b, c, &n_bc);
+  const int64_t per = min(G.seg_cap, (n_bc + G.K - 1) / G.K);
+  const int64_t r0 = ((int64_t)b * nc + c) * G.stride;
+  CombPlace p{0, true};
+  const int64_t s = q / per;
+  if (s < G.K) {
+    p.slot = r0 + s * G.seg_cap + (q - s * per);
+  } else {
+    const int64_t o = q - (int64_t)G.K * per;
+    p.ok = o < G.ovf_cap;
+    p.slot = r0 + (int64_t)G.K * G.seg_cap + o;
+  }
+  return p;
+}
+
+// Tooth k: the first particle whose inclusive prefix exceeds (k + xi) delta.
+template <typename Real>
+__global__ void comb_teeth_kernel(CombArgs<Real> A, int64_t n, int eu) {
+  uint32_t r[4];
+  draw(A.seed, A.key1, SLOT_COMB, A.step, 0ull, 0u, r);
+  const double xi = u53(r[0], r[1]);
+  const double W = (double)A.wq[n - 1];
+  const double delta = W / (double)A.n_target;
+  const double w_out = ldexp(W, eu) / (double)A.n_target;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < A.n_target;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    double t = ((double)k + xi) * delta;
+    if (t >= W) t = W - 1.0;
+    int64_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+      const int64_t mid = lo + (hi - lo) / 2;
+      if ((double)A.wq[mid] > t) hi = mid;
+      else lo = mid + 1;
+    }
+    const unsigned long long q = A.order[lo];
+    const CombPlace pl = comb_place(k, A.n_target, A.B, A.nc, A.G);
+    if (!pl.ok) {
+      atomicOr(A.err, ERR_CAPACITY);
+      continue;
+    }
+    A.dst_bank.xm[pl.slot] = A.src_bank.xm[q];
+    A.dst_bank.w[pl.slot] = w_out;
+    A.dst_bank.lin[pl.slot] = (uint64_t)A.step;
+    Tag tg;
+    tg.src = (uint32_t)k;
+    tg.e = 0u;
+    tg.cell = A.src_bank.tag[q].cell;
+    A.dst_bank.tag[pl.slot] = tg;
+  }
+}
+
+// Segment counts of the new bank, chunk weights count * W / n_target and
+// the total weight W for the host (misc[2]).
+template <typename Real>
+__global__ void comb_finish_kernel(CombArgs<Real> A, int64_t n, int eu) {
+  const BankGeom &G = A.G;
+  const double W = (double)A.wq[n - 1];
+  const double w_out = ldexp(W, eu) / (double)A.n_target;
+  for (int r = threadIdx.x; r < A.R; r += blockDim.x) {
+    const int b = r / A.nc, c = r % A.nc;
+    int64_t n_bc;
+    comb_region(A.n_target, A.B, A.nc, b, c, &n_bc);
+    const int64_t per = min(G.seg_cap, (n_bc + G.K - 1) / G.K);
+    for (int s = 0; s < G.K; ++s) {
+      const int64_t left = n_bc - (int64_t)s * per;
+      A.dst_bank.segcnt[(int64_t)r * G.K + s] = (uint32_t)(left < 0 ? 0 : (left < per ? left : per));
+    }
+    const int64_t over = n_bc - (int64_t)G.K * per;
+    A.dst_bank.ovfcnt[r] = (uint32_t)(over > 0 ? over : 0);
+  }
+  if (threadIdx.x < (unsigned)A.nc) {
+    int64_t cnt = 0;
+    for (int b = 0; b < A.B; ++b) {
+      int64_t n_bc;
+      comb_region(A.n_target, A.B, A.nc, b, (int)threadIdx.x, &n_bc);
+      cnt += n_bc;
+    }
+    A.wnext[threadIdx.x] = (double)cnt * w_out;
+  }
+  if (threadIdx.x == 0) A.misc[2] = (unsigned long long)__double_as_longlong(ldexp(W, eu));
+}
+
+hipError_t scan(unsigned long long *a, int64_t n, unsigned long long *blk, int inclusive, hipStream_t s) {
+  const int64_t nb = (n + kScanTile - 1) / kScanTile;
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(scan_tiles_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, a, n, blk, inclusive);
+  hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(kScanThreads), 0, s, blk, nb);
+  hipLaunchKernelGGL(scan_add_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, a, n, blk);
+  return hipGetLastError();
+}
+
+unsigned grid_for(int64_t n, int block) {
+  const int64_t g = (n + block - 1) / block;
+  return (unsigned)(g < 1 ? 1 : (g > 8192 ? 8192 : g));
+}
+
+}  // namespace
+
+int64_t comb_scan_blocks(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
+
+template <typename Real>
+hipError_t launch_comb_count(const CombArgs<Real> &a, hipStream_t s) {
+  const int64_t slots = (int64_t)a.R * a.G.stride;
+  hipLaunchKernelGGL(comb_count_kernel<Real>, dim3(grid_for(slots, 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename Real>
+hipError_t launch_comb_rest(const CombArgs<Real> &a, int64_t n, int eu, hipStream_t s) {
+  const int64_t slots = (int64_t)a.R * a.G.stride;
+  hipError_t e = scan(a.cnt, a.n_hist + 1, a.blk, 0, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(comb_scatter_kernel<Real>, dim3(grid_for(slots, 256)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(comb_sort_small_kernel<Real>, dim3(grid_for(a.n_hist, 256)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(comb_sort_big_kernel<Real>, dim3(256), dim3(1024), 0, s, a);
+  hipLaunchKernelGGL(comb_weights_kernel<Real>, dim3(grid_for(n, 256)), dim3(256), 0, s, a, n, eu);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = scan(a.wq, n, a.blk, 1, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(comb_teeth_kernel<Real>, dim3(grid_for(a.n_target, 256)), dim3(256), 0, s, a, n, eu);
+  hipLaunchKernelGGL(comb_finish_kernel<Real>, dim3(1), dim3(256), 0, s, a, n, eu);
+  return hipGetLastError();
+}
+
+template hipError_t launch_comb_count<double>(const CombArgs<double> &, hipStream_t);
+template hipError_t launch_comb_count<float>(const CombArgs<float> &, hipStream_t);
+template hipError_t launch_comb_rest<double>(const CombArgs<double> &, int64_t, int, hipStream_t);
+template hipError_t launch_comb_rest<float>(const CombArgs<float> &, int64_t, int, hipStream_t);
+
+}  // namespace hww

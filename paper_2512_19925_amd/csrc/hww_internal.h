@@ -13,13 +13,14 @@ enum : uint32_t { ERR_CAPACITY = 1u, ERR_NUMERIC = 2u, ERR_SPLIT = 4u, ERR_GENER
 // Counter slots (per step, uint64).
 enum {
   C_SEGMENTS = 0, C_COLLISIONS, C_SCATTERS, C_ABSORPTIONS, C_CROSSINGS, C_LEAKS, C_CENSUS,
-  C_SPLITS, C_DAUGHTERS, C_RR_KILL, C_RR_SURVIVE, C_HISTORIES, C_GENERATIONS, C_NCOUNTERS = 16
+  C_SPLITS, C_DAUGHTERS, C_RR_KILL, C_RR_SURVIVE, C_HISTORIES, C_GENERATIONS, C_FISSIONS, C_FISSION_BIRTHS,
+  C_NCOUNTERS = 16
 };
 
 // Random-number slots of the keying contract: key = (seed, (replica << 4) | slot),
 // counter = (src, lineage lo, lineage hi, event index).
 enum { SLOT_FLIGHT = 0, SLOT_EVENT = 1, SLOT_START = 2, SLOT_BIRTH = 3, SLOT_LIN_EVENT = 4,
-       SLOT_LIN_START = 5 };
+       SLOT_LIN_START = 5, SLOT_FISSION_DIR = 6, SLOT_COMB = 7 };
 
 // Work-group-local daughter generations per launch before giving up.
 constexpr int kMaxGenerations = 4096;
@@ -85,6 +86,8 @@ struct SweepArgs {
   uint32_t seed, key1;  // key1 = replica << 4
   const CellData<Real> *cells;  // [I]
   const Window *win;       // [I]
+  const double *cfis;      // [I] (sigma_s + sigma_f) / sigma_t, or null: no fission
+  double nu_f;             // mean neutrons per fission
   int32_t ww_on;
   int32_t chunk;
   int32_t tile;            // start-bank / daughter tile a wave claims at a time
@@ -131,6 +134,30 @@ struct BatchSweepArgs {
   int32_t chunk, ww_on, tile;
   Queue<Real> dq;      // daughter buffers: 2 per work-group of the grid
   int64_t dcap;
+  uint32_t *err;
+};
+
+// Uniform comb of a census bank (src_bank, geometry G, R = B * nc regions)
+// into dst_bank.  Scratch: per-history counts and offsets (n_hist + 1),
+// cursors (n_hist), the canonical order of the census slots and the
+// integer weights / their prefix sums (cap each), scan block sums, and
+// misc[8] = {max weight bits, census count, W, eu, xi bits, ...}.
+template <typename Real>
+struct CombArgs {
+  Bank<Real> src_bank, dst_bank;
+  BankGeom G;
+  int32_t B, nc, R;
+  int64_t n_hist;              // bound on src values + 1 of the census
+  int64_t cap;                 // bound on census particles
+  int64_t n_target;
+  uint32_t seed, key1, step;
+  unsigned long long *cnt;     // [n_hist + 1] counts, then exclusive offsets
+  uint32_t *cur;               // [n_hist]
+  unsigned long long *order;   // [cap] slot index of the census particle at each canonical position
+  unsigned long long *wq;      // [cap] integer weights, then inclusive prefix sums
+  unsigned long long *blk;     // scan block sums
+  unsigned long long *misc;    // [8]
+  double *wnext;               // [nc]
   uint32_t *err;
 };
 
@@ -234,6 +261,11 @@ hipError_t launch_losm(const LosmArgs &a, hipStream_t s);
 hipError_t launch_losm_batch(const LosmReplica *tab, int n, int max_I, const LosmCall &c, hipStream_t s);
 size_t losm_batch_lds(int max_I, int *work_in_lds);
 hipError_t launch_begin_step_batch(const BeginStepArgs *tab, int n, int64_t max_tal, hipStream_t s);
+template <typename Real>
+hipError_t launch_comb_count(const CombArgs<Real> &a, hipStream_t s);
+template <typename Real>
+hipError_t launch_comb_rest(const CombArgs<Real> &a, int64_t n, int eu, hipStream_t s);
+int64_t comb_scan_blocks(int64_t n);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);
 hipError_t launch_rotate_chunks(double *wstart, double *wnext, int nc, hipStream_t s);

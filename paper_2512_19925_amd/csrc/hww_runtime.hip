@@ -30,7 +30,10 @@ struct Layout {
   BankGeom geom{};
   bool cells_lds = false;  // the sweep keeps the per-cell records in LDS
   int64_t dcap = 0;
-  int64_t off_edges, off_sigt, off_sigs, off_cells, off_win;
+  int64_t off_edges, off_sigt, off_sigs, off_cells, off_win, off_cfis;
+  // Comb scratch (comb = 1): n_hist histories, slots census slots.
+  int64_t n_hist = 0, comb_slots = 0, off_c_cnt = 0, off_c_cur = 0, off_c_order = 0, off_c_wq = 0, off_c_blk = 0,
+          off_c_misc = 0;
   int64_t off_bank[2], off_segcnt[2], off_ovfcnt[2], off_q;
   int64_t off_tal[2], off_bnd[2], off_tracks, off_counters, off_wstart, off_wnext;
   int64_t off_err, off_status, off_scratch, off_factor, off_phi_out, off_J_out;
@@ -111,6 +114,7 @@ void make_layout(const hww_problem &p, Layout *L, bool member = false) {
   L->off_sigs = c.take(8 * I);
   L->off_cells = c.take(4 * rb * I);
   L->off_win = c.take(sizeof(Window) * I);
+  L->off_cfis = c.take(p.sigma_f ? 8 * I : 0);
   for (int k = 0; k < 2; ++k) {
     L->off_bank[k] = c.take(0);
     // (x, mu), w, lin, (src, e, cell) streams
@@ -155,6 +159,16 @@ void make_layout(const hww_problem &p, Layout *L, bool member = false) {
   L->off_m_fact = c.take(8 * 3 * n);
   L->off_m_G = c.take(8);
   L->off_m_g = c.take(8 * 2 * I);
+  if (p.comb && !member) {
+    L->n_hist = std::max<int64_t>(p.n_src, p.bank_capacity);
+    L->comb_slots = slots;
+    L->off_c_cnt = c.take(8 * (L->n_hist + 1));
+    L->off_c_cur = c.take(4 * L->n_hist);
+    L->off_c_order = c.take(8 * slots);
+    L->off_c_wq = c.take(8 * slots);
+    L->off_c_blk = c.take(8 * comb_scan_blocks(std::max<int64_t>(L->n_hist + 1, slots)));
+    L->off_c_misc = c.take(8 * 8);
+  }
   L->total = c.cur;
 }
 
@@ -218,6 +232,8 @@ struct hww_handle {
   uint32_t *err;
   int32_t *status;
   double *scratch, *factor, *phi_out, *J_out;
+  double *cfis = nullptr;  // (sigma_s + sigma_f) / sigma_t, fission problems only
+  double nu_f = 0.0;
 
   int start_bank = 0;  // census bank = 1 - start_bank
   int cur_tal = 0;
@@ -299,7 +315,12 @@ int validate(const hww_problem *p, std::string *why) {
     if (!(p->edges[i + 1] > p->edges[i])) { *why = "edges must ascend"; return HWW_E_INVALID_ARG; }
     if (!(p->sigma_t[i] > 0.0) || !(p->sigma_s[i] >= 0.0) || p->sigma_s[i] > p->sigma_t[i] ||
         !std::isfinite(p->sigma_t[i])) { *why = "need 0 < sigma_t, 0 <= sigma_s <= sigma_t"; return HWW_E_INVALID_ARG; }
+    if (p->sigma_f && (!(p->sigma_f[i] >= 0.0) || p->sigma_s[i] + p->sigma_f[i] > p->sigma_t[i])) {
+      *why = "need 0 <= sigma_f, sigma_s + sigma_f <= sigma_t"; return HWW_E_INVALID_ARG;
+    }
   }
+  if (p->sigma_f && (!(p->nu_f >= 0.0) || !(p->nu_f < 1.0e6))) { *why = "nu_f must be in [0, 1e6)"; return HWW_E_INVALID_ARG; }
+  if (p->comb != 0 && p->comb != 1) { *why = "comb must be 0 or 1"; return HWW_E_INVALID_ARG; }
   if (!(p->src_x >= p->edges[0] && p->src_x <= p->edges[p->n_cells])) { *why = "src_x outside the mesh"; return HWW_E_INVALID_ARG; }
   if (sweep_lds_bytes(p->n_cells, p->n_chunks, 64) > 160 * 1024) { *why = "too many cells for the LDS histogram (I <= 3300)"; return HWW_E_INVALID_ARG; }
   return HWW_OK;
@@ -353,6 +374,8 @@ SweepArgs<Real> base_args(hww_handle *h) {
   a.v = h->p.speed; a.inv_v = 1.0 / h->p.speed; a.dt = h->p.dt;
   a.seed = h->p.seed; a.key1 = h->p.replica << 4;
   a.win = h->win;
+  a.cfis = h->cfis;
+  a.nu_f = h->nu_f;
   a.ww_on = h->ww_on;
   a.geom = h->L.geom;
   if constexpr (sizeof(Real) == 8) {
@@ -414,7 +437,9 @@ int zero_counts(hww_handle *h, int k) {
 // Point the handle's arrays into its part of the workspace.
 void carve_handle(hww_handle *h, const hww_problem &problem, char *ws, const Layout &L, hipStream_t stream) {
   h->p = problem;
-  h->p.edges = h->p.sigma_t = h->p.sigma_s = nullptr;
+  h->p.edges = h->p.sigma_t = h->p.sigma_s = h->p.sigma_f = nullptr;
+  h->cfis = problem.sigma_f ? reinterpret_cast<double *>(ws + L.off_cfis) : nullptr;
+  h->nu_f = problem.sigma_f ? problem.nu_f : 0.0;
   h->I = problem.n_cells;
   h->B = problem.n_batches;
   h->nc = problem.n_chunks;
@@ -474,7 +499,19 @@ int prime_handle(hww_handle *h, const hww_problem &problem) {
   }
   HIPCHK(h, hipMemcpyAsync(h->edges, problem.edges, 8 * (I + 1), hipMemcpyHostToDevice, h->stream));
   HIPCHK(h, hipMemcpyAsync(h->sig_t, problem.sigma_t, 8 * I, hipMemcpyHostToDevice, h->stream));
-  HIPCHK(h, hipMemcpyAsync(h->sig_s, problem.sigma_s, 8 * I, hipMemcpyHostToDevice, h->stream));
+  // The low-order balance takes sigma_s + nu_f sigma_f (Eq. balance); a
+  // collision below (sigma_s + sigma_f) / sigma_t and above the scattering
+  // ratio is a fission.
+  std::vector<double> sig_lo(problem.sigma_s, problem.sigma_s + I), cfis_h;
+  if (problem.sigma_f) {
+    cfis_h.resize(I);
+    for (int i = 0; i < I; ++i) {
+      sig_lo[i] = problem.sigma_s[i] + problem.nu_f * problem.sigma_f[i];
+      cfis_h[i] = (problem.sigma_s[i] + problem.sigma_f[i]) / problem.sigma_t[i];
+    }
+    HIPCHK(h, hipMemcpyAsync(h->cfis, cfis_h.data(), 8 * I, hipMemcpyHostToDevice, h->stream));
+  }
+  HIPCHK(h, hipMemcpyAsync(h->sig_s, sig_lo.data(), 8 * I, hipMemcpyHostToDevice, h->stream));
   if (h->fp32)
     HIPCHK(h, hipMemcpyAsync(h->cells32, cf.data(), sizeof(CellData<float>) * I, hipMemcpyHostToDevice, h->stream));
   else
@@ -536,6 +573,10 @@ int make_batch_layout(const hww_problem *probs, int n, BatchLayout *BL, std::str
   for (int r = 0; r < n; ++r) {
     const int rc = validate(&probs[r], why);
     if (rc != HWW_OK) { *why = "replica " + std::to_string(r) + ": " + *why; return rc; }
+    if (probs[r].sigma_f || probs[r].comb) {
+      *why = "replica " + std::to_string(r) + ": fission and combing need a single problem";
+      return HWW_E_INVALID_ARG;
+    }
     if (probs[r].precision != probs[0].precision || probs[r].n_chunks != probs[0].n_chunks ||
         probs[r].n_steps != probs[0].n_steps) {
       *why = "replicas must share precision, n_chunks and n_steps";
@@ -740,6 +781,8 @@ void fill_stats(hww_handle *h, const unsigned long long *cnt, hww_step_stats *st
   stats->rr_survive = cnt[C_RR_SURVIVE];
   stats->histories = cnt[C_HISTORIES];
   stats->generations = cnt[C_GENERATIONS];
+  stats->fissions = cnt[C_FISSIONS];
+  stats->fission_births = cnt[C_FISSION_BIRTHS];
   const uint64_t rec = h->fp32 ? 36 : 44, drec = h->fp32 ? 44 : 52;
   stats->bytes_moved = cnt[C_HISTORIES] * rec + cnt[C_CENSUS] * rec + cnt[C_DAUGHTERS] * 2 * drec;
 }
@@ -880,6 +923,86 @@ int hww_sweep_step(hww_handle *h, int32_t step, int32_t chunk, hww_step_stats *s
     ms += t;
   }
   stats->kernel_ms = ms;
+  return HWW_OK;
+}
+
+int hww_comb(hww_handle *h, int64_t n_target, int64_t *n_before, double *w_total) {
+  if (!h) return HWW_E_INVALID_ARG;
+  if (h->is_batch || h->is_view) return fail(h, HWW_E_STATE, "combing needs a single problem");
+  if (h->fatal) return fail(h, h->fatal, "an earlier error left the problem invalid");
+  if (!h->p.comb) return fail(h, HWW_E_STATE, "the problem was initialised without comb workspace");
+  if (n_target < 1 || n_target > h->p.bank_capacity || n_target > 0xFFFFFFFFll)
+    return fail(h, HWW_E_INVALID_ARG, "n_target must be in 1..bank_capacity and < 2^32");
+  if (h->step < 1 || h->next_chunk != h->nc) return fail(h, HWW_E_STATE, "combing needs a finished step");
+  const Layout &L = h->L;
+  const BankGeom &G = L.geom;
+  // Every region of the new bank must fit its segments and overflow.
+  for (int b = 0; b < h->B; ++b)
+    for (int c = 0; c < h->nc; ++c) {
+      const int64_t n_b = n_target > b ? (n_target - b + h->B - 1) / h->B : 0;
+      const int64_t n_bc = n_b > c ? (n_b - c + h->nc - 1) / h->nc : 0;
+      const int64_t per = std::min<int64_t>(G.seg_cap, (n_bc + G.K - 1) / G.K);
+      if (n_bc - (int64_t)G.K * per > G.ovf_cap) return fail(h, HWW_E_CAPACITY, "a region of the combed bank overflows");
+    }
+  auto fill = [&](CombArgs<double> &a) {
+    a.G = G;
+    a.B = h->B; a.nc = h->nc; a.R = h->R;
+    a.n_hist = L.n_hist;
+    a.cap = L.comb_slots;
+    a.n_target = n_target;
+    a.seed = h->p.seed; a.key1 = h->p.replica << 4; a.step = (uint32_t)h->step;
+    a.cnt = reinterpret_cast<unsigned long long *>(h->ws + L.off_c_cnt);
+    a.cur = reinterpret_cast<uint32_t *>(h->ws + L.off_c_cur);
+    a.order = reinterpret_cast<unsigned long long *>(h->ws + L.off_c_order);
+    a.wq = reinterpret_cast<unsigned long long *>(h->ws + L.off_c_wq);
+    a.blk = reinterpret_cast<unsigned long long *>(h->ws + L.off_c_blk);
+    a.misc = reinterpret_cast<unsigned long long *>(h->ws + L.off_c_misc);
+    a.wnext = h->wnext;
+    a.err = h->err;
+  };
+  CombArgs<double> a{};
+  CombArgs<float> a32{};
+  fill(a);
+  a.src_bank = h->bank[1 - h->start_bank];
+  a.dst_bank = h->bank[h->start_bank];
+  if (h->fp32) {
+    a32.src_bank = h->bank32[1 - h->start_bank];
+    a32.dst_bank = h->bank32[h->start_bank];
+    a32.G = a.G; a32.B = a.B; a32.nc = a.nc; a32.R = a.R; a32.n_hist = a.n_hist; a32.cap = a.cap;
+    a32.n_target = a.n_target; a32.seed = a.seed; a32.key1 = a.key1; a32.step = a.step;
+    a32.cnt = a.cnt; a32.cur = a.cur; a32.order = a.order; a32.wq = a.wq; a32.blk = a.blk; a32.misc = a.misc;
+    a32.wnext = a.wnext; a32.err = a.err;
+  }
+  HIPCHK(h, launch_fill_u32(reinterpret_cast<uint32_t *>(a.cnt), 0u, 2 * (L.n_hist + 1), h->stream));
+  HIPCHK(h, launch_fill_u32(a.cur, 0u, L.n_hist, h->stream));
+  HIPCHK(h, launch_fill_u32(reinterpret_cast<uint32_t *>(a.misc), 0u, 16, h->stream));
+  HIPCHK(h, h->fp32 ? launch_comb_count<float>(a32, h->stream) : launch_comb_count<double>(a, h->stream));
+  unsigned long long misc[8];
+  HIPCHK(h, hipMemcpyAsync(misc, a.misc, sizeof misc, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  int rc = poll_errors(h);
+  if (rc != HWW_OK) return rc;
+  const int64_t n = (int64_t)misc[1];
+  if (n_before) *n_before = n;
+  if (w_total) *w_total = 0.0;
+  if (n == 0) return HWW_OK;  // an empty census stays empty
+  double m;
+  std::memcpy(&m, &misc[0], 8);
+  if (!(m > 0.0) || !std::isfinite(m)) return fail(h, HWW_E_NUMERIC, "census weights must be positive and finite");
+  // Unit 2^eu of the integer weights: n * max weight < 2^(53 + eu).
+  int em;
+  std::frexp(m, &em);
+  int ln = 0;
+  while (((int64_t)1 << ln) < n) ++ln;
+  const int eu = em + ln - 53;
+  HIPCHK(h, h->fp32 ? launch_comb_rest<float>(a32, n, eu, h->stream) : launch_comb_rest<double>(a, n, eu, h->stream));
+  HIPCHK(h, hipMemcpyAsync(misc, a.misc, sizeof misc, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  // The combed bank becomes the census bank.
+  h->start_bank = 1 - h->start_bank;
+  rc = poll_errors(h);
+  if (rc != HWW_OK) return rc;
+  if (w_total) std::memcpy(w_total, &misc[2], 8);
   return HWW_OK;
 }
 

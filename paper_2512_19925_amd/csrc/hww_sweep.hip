@@ -17,72 +17,14 @@
 // Each wave keeps its 64 lanes busy: a lane whose particle ends (census,
 // leak, absorption, roulette) refills from the wave's current tile.
 #include "hww_internal.h"
+#include "hww_rng_dev.h"
 
 namespace hww {
 
-// Philox4x32-10 (Salmon et al., SC'11): ten rounds of the two published
-// 32x32 -> 64 multiplies; key bumped by the Weyl constants between rounds.
-__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
-    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
-    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
-    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
-    c[1] = (uint32_t)p1;
-    c[3] = (uint32_t)p0;
-    c[0] = n0;
-    c[2] = n2;
-    k0 += 0x9E3779B9u;
-    k1 += 0xBB67AE85u;
-  }
-}
-
-__device__ __forceinline__ void draw(uint32_t seed, uint32_t key1, int slot, uint32_t src,
-                                     uint64_t lin, uint32_t e, uint32_t r[4]) {
-  r[0] = src;
-  r[1] = (uint32_t)lin;
-  r[2] = (uint32_t)(lin >> 32);
-  r[3] = e;
-  uint32_t k0 = seed, k1 = key1 | (uint32_t)slot;
-  // Keep the round-key schedule local to each draw: otherwise it is hoisted
-  // out of the particle loop for every slot and exhausts the scalar registers.
-  asm volatile("" : "+s"(k0), "+s"(k1));
-  philox4x32_10(r, k0, k1);
-}
-
-// Same draw with a slot that differs between lanes (the key's second word
-// then lives in a vector register).
-__device__ __forceinline__ void draw_lane(uint32_t seed, uint32_t key1, int slot, uint32_t src,
-                                          uint64_t lin, uint32_t e, uint32_t r[4]) {
-  r[0] = src;
-  r[1] = (uint32_t)lin;
-  r[2] = (uint32_t)(lin >> 32);
-  r[3] = e;
-  uint32_t k0 = seed, k1 = key1 | (uint32_t)slot;
-  asm volatile("" : "+s"(k0), "+v"(k1));
-  philox4x32_10(r, k0, k1);
-}
-
 // Window and event actions of a lane (bit flags).
-enum : uint32_t { WW_ROULETTE = 1u, WW_SPLIT = 2u, EV_DRAW = 4u, EV_SCATTER = 8u };
+enum : uint32_t { WW_ROULETTE = 1u, WW_SPLIT = 2u, EV_DRAW = 4u, EV_SCATTER = 8u, EV_FISSION = 16u,
+                  FIS_BIRTHS = 32u };
 
-// 53-bit uniform on [0,1) from the high bits of two words.
-__device__ __forceinline__ double u53(uint32_t a, uint32_t b) {
-  const double k = (double)(a >> 5) * 67108864.0 + (double)(b >> 6);
-  return k * (1.0 / 9007199254740992.0);
-}
-
-// Uniform on [0,1) in the flight precision: 53 bits (FP64) or the 24 high
-// bits of the first word (FP32); 1 - u is exact in both.
-template <typename Real>
-__device__ __forceinline__ Real uflight(uint32_t a, uint32_t b);
-template <>
-__device__ __forceinline__ double uflight<double>(uint32_t a, uint32_t b) { return u53(a, b); }
-template <>
-__device__ __forceinline__ float uflight<float>(uint32_t a, uint32_t) {
-  return (float)(a >> 8) * (1.0f / 16777216.0f);
-}
 __device__ __forceinline__ double log_r(double v) { return log(v); }
 __device__ __forceinline__ float log_r(float v) { return logf(v); }
 
@@ -111,11 +53,13 @@ __device__ __forceinline__ int32_t find_cell(const double *edges, int I, double 
 // start-of-step outcomes that leave it alive have bits of their own.
 enum : uint32_t {
   EVB_CENSUS = 1u, EVB_LEAK = 2u, EVB_CROSS = 4u, EVB_SCATTER = 8u, EVB_ABSORB = 16u,
-  EVB_RR_SURVIVE = 32u, EVB_RR_KILL = 64u, EVB_SPLIT = 128u, EVB_START_SURVIVE = 256u, EVB_START_SPLIT = 512u
+  EVB_RR_SURVIVE = 32u, EVB_RR_KILL = 64u, EVB_SPLIT = 128u, EVB_START_SURVIVE = 256u, EVB_START_SPLIT = 512u,
+  EVB_FISSION = 1024u
 };
-constexpr int kEventKinds = 10;
+constexpr int kEventKinds = 11;
 __device__ constexpr int kEventSlot[kEventKinds] = {C_CENSUS, C_LEAKS, C_CROSSINGS, C_SCATTERS, C_ABSORPTIONS,
-                                                    C_RR_SURVIVE, C_RR_KILL, C_SPLITS, C_RR_SURVIVE, C_SPLITS};
+                                                    C_RR_SURVIVE, C_RR_KILL, C_SPLITS, C_RR_SURVIVE, C_SPLITS,
+                                                    C_FISSIONS};
 
 // Shared-memory carve-up common to the sweep and source kernels.
 struct Lds {
@@ -252,8 +196,9 @@ __device__ inline void census_append(const Bank<Real> &bk, const BankGeom &G, ui
 // appends into segment jseg of the batch's regions.  The work-group's
 // daughter buffers are number qslot of nq.  With kCellsLds the per-cell
 // records are copied into LDS first.  Starts and ends with the LDS free for
-// reuse.
-template <typename Real, bool kCellsLds>
+// reuse.  kFission compiles the fission branch of collisions in (problems
+// with fission cross sections); without it the kernel is the plain sweep.
+template <typename Real, bool kCellsLds, bool kFission>
 __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int jseg, int qslot, int nq,
                                            double *lds_raw) {
   const int I = A.I, nc = A.nc;
@@ -308,10 +253,12 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
   uint64_t lin = 0;
   bool active = false;
   uint32_t start_act = 0u;  // start-of-step window action of a lane just loaded
-  // Pending split of this lane: the daughters copy the lane state.
+  // Pending split or fission of this lane: the daughters copy the lane
+  // state (a fission daughter draws its own direction).
   uint32_t nd = 0;
   uint64_t lin_base = 0;
   uint32_t e_d = 0;
+  bool fis = false;
   uint32_t evb = 0u;  // EVB_* events not yet counted
   int out_buf = 0;
 
@@ -337,7 +284,14 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
     }
     const uint32_t total = __shfl(incl, 63);
     if (total != 0) {
-      if (lane == 0) atomicAdd(&L.cnt[C_DAUGHTERS], total);
+      // Split daughters are counted here; fission neutrons at the fission.
+      uint32_t nsplit = (kFission && fis) ? 0u : cntd;
+      if (kFission && __ballot(fis && cntd != 0) != 0) {
+        for (int o = 32; o >= 1; o >>= 1) nsplit += __shfl_xor(nsplit, o);
+      } else {
+        nsplit = total;
+      }
+      if (lane == 0 && nsplit != 0) atomicAdd(&L.cnt[C_DAUGHTERS], nsplit);
       uint32_t base = 0;
       if (lane == 0) base = atomicAdd(&L.dcnt[out_buf], total);
       base = __shfl(base, 0);
@@ -351,6 +305,11 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
         XMu<Real> xm;
         xm.x = x;
         xm.mu = mu;
+        if (kFission && fis) {
+          uint32_t rd[4];
+          draw(A.seed, A.key1, SLOT_FISSION_DIR, src, lin_base + q, e_d, rd);
+          xm.mu = (Real)2 * uflight<Real>(rd[0], rd[1]) - (Real)1;
+        }
         A.dq.xm[k] = xm;
         WTau wt;
         wt.w = w;
@@ -601,6 +560,9 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
             if (ub < cd.c) {
               evb |= EVB_SCATTER;
               act = classify() | EV_DRAW | EV_SCATTER;
+            } else if (kFission && (double)ub < A.cfis[i]) {
+              evb |= EVB_FISSION;
+              act = EV_DRAW | EV_FISSION;
             } else {
               evb |= EVB_ABSORB;
               active = false;
@@ -613,19 +575,36 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
       // scattering direction (first variate) and the roulette uniform
       // (second); slot 4 gives the lineage base of a split.  The window
       // check follows the new direction, as in the serial order.
+      // A fission makes floor(nu_f + xi) neutrons (xi: second variate of
+      // slot 1): the lane continues as the first with the direction of the
+      // first variate, the others become daughters (lineage base of slot 4).
+      uint32_t nf = 0;
       if (__ballot((act & EV_DRAW) != 0u) != 0) {
         if ((act & EV_DRAW) != 0u) {
           uint32_t r1[4];
           draw(A.seed, A.key1, SLOT_EVENT, src, lin, e_ev, r1);
-          if (act & EV_SCATTER) mu = (Real)2 * uflight<Real>(r1[0], r1[1]) - (Real)1;
+          if (act & (EV_SCATTER | EV_FISSION)) mu = (Real)2 * uflight<Real>(r1[0], r1[1]) - (Real)1;
           if (act & WW_ROULETTE) roulette(u53(r1[2], r1[3]), false);
+          if (kFission && (act & EV_FISSION)) {
+            nf = (uint32_t)floor(A.nu_f + u53(r1[2], r1[3]));
+            atomicAdd(&L.cnt[C_FISSION_BIRTHS], nf);
+            if (nf == 0) active = false;
+            else if (nf >= 2) act |= FIS_BIRTHS;
+          }
         }
       }
-      if (__ballot((act & WW_SPLIT) != 0u) != 0) {
-        if ((act & WW_SPLIT) != 0u) {
+      if (__ballot((act & (WW_SPLIT | FIS_BIRTHS)) != 0u) != 0) {
+        if ((act & (WW_SPLIT | FIS_BIRTHS)) != 0u) {
           uint32_t r2[4];
           draw(A.seed, A.key1, SLOT_LIN_EVENT, src, lin, e_ev, r2);
-          split(r2, e, false);
+          if (!kFission || (act & WW_SPLIT)) {
+            split(r2, e, false);
+          } else {
+            lin_base = (uint64_t)r2[0] | ((uint64_t)r2[1] << 32);
+            nd = nf;
+            e_d = e;
+            fis = true;
+          }
         }
       }
 
@@ -639,6 +618,7 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
       nd = 0;
       lin_base = 0;
       e_d = 0;
+      fis = false;
     }
 
     // ------------------------------------------- next daughter generation --
@@ -660,10 +640,10 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
   }
 
   // Every segment ends in exactly one of census, leak, crossing or collision
-  // (scatter or absorption).
+  // (scatter, fission or absorption).
   __syncthreads();
   if (tid == 0) {
-    L.cnt[C_COLLISIONS] = L.cnt[C_SCATTERS] + L.cnt[C_ABSORPTIONS];
+    L.cnt[C_COLLISIONS] = L.cnt[C_SCATTERS] + L.cnt[C_ABSORPTIONS] + L.cnt[C_FISSIONS];
     L.cnt[C_SEGMENTS] = L.cnt[C_CENSUS] + L.cnt[C_LEAKS] + L.cnt[C_CROSSINGS] + L.cnt[C_COLLISIONS];
   }
   __syncthreads();
@@ -671,7 +651,7 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
     const uint32_t cc = L.ccnt[tid];
     A.census.segcnt[(b * nc + tid) * K + jseg] = cc < (uint32_t)G.seg_cap ? cc : (uint32_t)G.seg_cap;
   }
-  if (tid < 12) {
+  if (tid < C_NCOUNTERS && tid != C_GENERATIONS) {
     const uint32_t t = L.cnt[tid];
     if (t != 0) {
       atomicAdd(&A.counters[tid], (unsigned long long)t);                // this step
@@ -687,10 +667,10 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
 
 // One problem: grid = B * K work-groups; work-group g is the unit
 // (batch g mod B, segment g / B).
-template <typename Real, bool kCellsLds>
+template <typename Real, bool kCellsLds, bool kFission>
 __global__ void __launch_bounds__(1024) sweep_kernel(SweepArgs<Real> A) {
   extern __shared__ double lds_raw[];
-  sweep_unit<Real, kCellsLds>(A, (int)(blockIdx.x % A.B), (int)(blockIdx.x / A.B), (int)blockIdx.x,
+  sweep_unit<Real, kCellsLds, kFission>(A, (int)(blockIdx.x % A.B), (int)(blockIdx.x / A.B), (int)blockIdx.x,
                               (int)gridDim.x, lds_raw);
 }
 
@@ -721,6 +701,7 @@ __global__ void __launch_bounds__(1024) sweep_batch_kernel(BatchSweepArgs<Real> 
     A.seed = __builtin_amdgcn_readfirstlane(D.seed);
     A.key1 = __builtin_amdgcn_readfirstlane(D.key1);
     A.cells = D.cells; A.win = D.win;
+    A.cfis = nullptr; A.nu_f = 0.0;  // batches have no fission (kFission = false)
     A.ww_on = P.ww_on; A.chunk = P.chunk; A.tile = P.tile;
     A.geom = D.geom;
     A.in_bank = D.bank[P.start_bank];
@@ -729,7 +710,7 @@ __global__ void __launch_bounds__(1024) sweep_batch_kernel(BatchSweepArgs<Real> 
     A.tal = D.tal[P.start_bank]; A.bnd = D.bnd[P.start_bank];
     A.tracks = D.tracks; A.counters = D.counters; A.wnext = D.wnext;
     A.err = P.err;
-    sweep_unit<Real, kCellsLds>(A, b, jseg, (int)blockIdx.x, (int)gridDim.x, lds_raw);
+    sweep_unit<Real, kCellsLds, false>(A, b, jseg, (int)blockIdx.x, (int)gridDim.x, lds_raw);
     __syncthreads();
   }
 }
@@ -834,13 +815,21 @@ static hipError_t allow_lds(const void *fn, size_t lds, size_t *done) {
 
 template <typename Real>
 hipError_t launch_sweep(const SweepArgs<Real> &a, bool cells_lds, int grid, int block, size_t lds, hipStream_t s) {
-  static size_t done[2] = {64 * 1024, 64 * 1024};
-  const void *fn = cells_lds ? reinterpret_cast<const void *>(&sweep_kernel<Real, true>)
-                             : reinterpret_cast<const void *>(&sweep_kernel<Real, false>);
-  hipError_t e = allow_lds(fn, lds, &done[cells_lds ? 1 : 0]);
+  static size_t done[4] = {64 * 1024, 64 * 1024, 64 * 1024, 64 * 1024};
+  const bool fis = a.cfis != nullptr;
+  const void *fn = fis ? (cells_lds ? reinterpret_cast<const void *>(&sweep_kernel<Real, true, true>)
+                                    : reinterpret_cast<const void *>(&sweep_kernel<Real, false, true>))
+                       : (cells_lds ? reinterpret_cast<const void *>(&sweep_kernel<Real, true, false>)
+                                    : reinterpret_cast<const void *>(&sweep_kernel<Real, false, false>));
+  hipError_t e = allow_lds(fn, lds, &done[(fis ? 2 : 0) + (cells_lds ? 1 : 0)]);
   if (e != hipSuccess) return e;
-  if (cells_lds) hipLaunchKernelGGL((sweep_kernel<Real, true>), dim3(grid), dim3(block), lds, s, a);
-  else hipLaunchKernelGGL((sweep_kernel<Real, false>), dim3(grid), dim3(block), lds, s, a);
+  if (fis) {
+    if (cells_lds) hipLaunchKernelGGL((sweep_kernel<Real, true, true>), dim3(grid), dim3(block), lds, s, a);
+    else hipLaunchKernelGGL((sweep_kernel<Real, false, true>), dim3(grid), dim3(block), lds, s, a);
+  } else {
+    if (cells_lds) hipLaunchKernelGGL((sweep_kernel<Real, true, false>), dim3(grid), dim3(block), lds, s, a);
+    else hipLaunchKernelGGL((sweep_kernel<Real, false, false>), dim3(grid), dim3(block), lds, s, a);
+  }
   return hipGetLastError();
 }
 

@@ -25,7 +25,7 @@ TALLY_CELLS, TALLY_BOUNDARY, TALLY_TRACKS, TALLY_PREV_CELLS, TALLY_PREV_BOUNDARY
 
 # Every symbol include/hww.h declares.
 EXPORTS = ["hww_workspace_bytes", "hww_init_problem", "hww_set_windows", "hww_sweep_step",
-           "hww_read_run_stats", "hww_solve_losm", "hww_read_closures", "hww_losm_march", "hww_losm_adjoint",
+           "hww_read_run_stats", "hww_comb", "hww_solve_losm", "hww_read_closures", "hww_losm_march", "hww_losm_adjoint",
            "hww_read_tallies", "hww_read_bank", "hww_batch_workspace_bytes", "hww_init_batch",
            "hww_batch_replica", "hww_autotune", "hww_set_timing", "hww_sync", "hww_last_error", "hww_destroy"]
 
@@ -42,7 +42,8 @@ class Problem(C.Structure):
                 ("speed", C.c_double), ("dt", C.c_double), ("n_steps", C.c_int32),
                 ("src_x", C.c_double), ("n_src", C.c_int64), ("bank_capacity", C.c_int64),
                 ("seed", C.c_uint32), ("replica", C.c_uint32), ("n_batches", C.c_int32),
-                ("precision", C.c_int32), ("n_chunks", C.c_int32)]
+                ("precision", C.c_int32), ("n_chunks", C.c_int32), ("sigma_f", C.POINTER(C.c_double)),
+                ("nu_f", C.c_double), ("comb", C.c_int32)]
 
 
 class StepStats(C.Structure):
@@ -50,7 +51,8 @@ class StepStats(C.Structure):
                                           "crossings", "leaks", "census", "splits", "daughters",
                                           "rr_kill", "rr_survive", "histories", "generations",
                                           "launches")] + \
-               [("kernel_ms", C.c_double), ("bytes_moved", C.c_uint64)]
+               [("kernel_ms", C.c_double), ("bytes_moved", C.c_uint64), ("fissions", C.c_uint64),
+                ("fission_births", C.c_uint64)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -89,6 +91,7 @@ def lib():
         L.hww_set_windows.argtypes = [vp, dp, C.c_double]
         L.hww_sweep_step.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(StepStats)]
         L.hww_read_run_stats.argtypes = [vp, C.POINTER(StepStats)]
+        L.hww_comb.argtypes = [vp, C.c_int64, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
         L.hww_solve_losm.argtypes = [vp, C.POINTER(LosmOpts), dp, dp]
         L.hww_read_tallies.argtypes = [vp, C.c_int32, vp, C.c_int64]
         L.hww_read_closures.argtypes = [vp, dp, dp, dp, dp]
@@ -134,14 +137,18 @@ class ProblemSpec:
     n_batches: int = 32
     precision: int = HWW_FP64
     n_chunks: int = 4
+    sigma_f: np.ndarray | None = None
+    nu_f: float = 0.0
+    comb: int = 0
 
     def to_c(self):
-        self._keep = [_f64(self.edges), _f64(self.sigma_t), _f64(self.sigma_s)]
-        e, st, ss = self._keep
+        self._keep = [_f64(self.edges), _f64(self.sigma_t), _f64(self.sigma_s),
+                      None if self.sigma_f is None else _f64(self.sigma_f)]
+        e, st, ss, sf = self._keep
         return Problem(len(st), _dp(e), _dp(st), _dp(ss), float(self.speed), float(self.dt),
                        int(self.n_steps), float(self.src_x), int(self.n_src), int(self.bank_capacity),
                        int(self.seed), int(self.replica), int(self.n_batches), int(self.precision),
-                       int(self.n_chunks))
+                       int(self.n_chunks), _dp(sf), float(self.nu_f), int(self.comb))
 
 
 def workspace_bytes(spec: ProblemSpec) -> int:
@@ -232,6 +239,13 @@ class Handle:
         st = StepStats()
         self._check("hww_read_run_stats", lib().hww_read_run_stats(self._h, C.byref(st)))
         return st.as_dict()
+
+    def comb(self, n_target):
+        """Uniform comb of the finished step's census into n_target particles;
+        returns (census size before, total weight)."""
+        nb, wt = C.c_int64(), C.c_double()
+        self._check("hww_comb", lib().hww_comb(self._h, int(n_target), C.byref(nb), C.byref(wt)))
+        return int(nb.value), float(wt.value)
 
     def solve_losm(self, theta=0.5, implicit=False, filter=0, ma_k=3, eps_min=1e-3, rho=5.0,
                    closure_track=0, apply_windows=True, want_solution=False, kappa=30, lagged=0):
@@ -412,7 +426,7 @@ def spec_from_workload(w, precision=HWW_FP64) -> ProblemSpec:
     return ProblemSpec(edges=w.edges, sigma_t=w.sigma_t, sigma_s=w.sigma_s, speed=w.speed, dt=w.dt,
                        n_steps=w.n_steps, src_x=w.src_x, n_src=w.n_src, bank_capacity=w.capacity(),
                        seed=w.seed, replica=w.replica, n_batches=w.n_batches, precision=precision,
-                       n_chunks=w.n_chunks)
+                       n_chunks=w.n_chunks, sigma_f=w.sigma_f, nu_f=w.nu_f, comb=int(w.comb > 0))
 
 
 def losm_kwargs(w):
@@ -424,11 +438,14 @@ def losm_kwargs(w):
 def run(h: Handle, w, steps=None, on_step=None, analog=None, stats=True):
     """Time loop of the method (Sec. 3): semi-implicit solve at the start of
     each step, then the chunks of histories with a fully implicit solve after
-    each chunk but the last.  Calls only the C ABI."""
+    each chunk but the last; with w.comb, every census but the last is
+    combed to that many particles first.  Calls only the C ABI."""
     analog = w.analog if analog is None else analog
     steps = w.n_steps if steps is None else steps
     kw = losm_kwargs(w)
     for n in range(1, steps + 1):
+        if w.comb and n > 1:
+            h.comb(w.comb)
         if not analog:
             h.solve_losm(implicit=False, **kw)
         chunk_stats = []

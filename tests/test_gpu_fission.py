@@ -1,0 +1,106 @@
+"""GPU parity of the paper's supercritical test problem (Sec. 5.1): fission
+collisions in the HIP sweep and the uniform comb of every census, called
+through the C ABI, against the CPU oracle on the same seeded inputs.  FP64
+tallies agree to 1e-12 relative per batch and cell, counters exactly, and
+census banks as multisets both before and after each comb."""
+import numpy as np
+import pytest
+
+from gpu_common import (assert_bank_match, assert_bnd_match, assert_tallies_match, need_gpu,
+                        oracle_opts, oracle_sim, say)
+from paper_2512_19925_amd import hww as H
+from paper_2512_19925_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+COUNTERS = ["segments", "collisions", "scatters", "absorptions", "crossings", "leaks", "census",
+            "splits", "daughters", "rr_kill", "rr_survive", "histories", "fissions", "fission_births"]
+
+
+def _run_pair(w, steps=None, analog=False):
+    need_gpu()
+    steps = w.n_steps if steps is None else steps
+    say(f"case {w.name}: n_src={w.n_src} I={w.n_cells} nu={w.nu_f} comb={w.comb} steps={steps} analog={analog}")
+    h = H.Handle(H.spec_from_workload(w))
+    sim = oracle_sim(w)
+    opts = oracle_opts(w)
+    kw = H.losm_kwargs(w)
+    worst = 0.0
+    for n in range(1, steps + 1):
+        if w.comb and n > 1:
+            gn, gw = h.comb(w.comb)
+            on, ow = sim.comb(w.comb)
+            assert gn == on, f"step {n}: census sizes before the comb {gn} vs {on}"
+            assert abs(gw / ow - 1.0) < 1e-15, f"step {n}: comb weight {gw} vs {ow}"
+            assert_bank_match(h.read_bank(1), sim.bank(1), what=f"{w.name} comb before step {n}")
+        if not analog:
+            h.solve_losm(implicit=False, **kw)
+            sim.solve_losm(opts, implicit=False)
+        for p in range(w.n_chunks):
+            st = h.sweep_step(n, p, stats=(p == w.n_chunks - 1))
+            sim.sweep(n, p)
+            if not analog and p < w.n_chunks - 1:
+                h.solve_losm(implicit=True, **kw)
+                sim.solve_losm(opts, implicit=True)
+        oc = sim.counters()
+        assert {k: st[k] for k in COUNTERS} == {k: oc[k] for k in COUNTERS}, f"step {n}: counters"
+        g = h.read_tallies(H.TALLY_CELLS)
+        o, ob = sim.tallies()
+        worst = max(worst, assert_tallies_match(g, o, what=f"{w.name} step {n}"))
+        assert_bnd_match(h.read_tallies(H.TALLY_BOUNDARY), ob, what=f"{w.name} step {n}")
+        assert np.array_equal(h.read_tallies(H.TALLY_TRACKS), sim.tracks()), f"step {n}: tracks"
+        assert_bank_match(h.read_bank(1), sim.bank(1), what=f"{w.name} step {n}")
+        if not analog:
+            np.testing.assert_allclose(h.read_tallies(H.TALLY_WINDOWS)[0], sim.windows()[0], rtol=1e-12)
+    say(f"  max relative tally difference {worst:.2e}; fissions in the last step {st['fissions']}")
+    h.close()
+    return worst
+
+
+def test_paper_problem_end_to_end():
+    # The paper's problem as specified: 201 cells, c_eff = 1.1, 20 steps of
+    # dt = 1, 1e4 histories per step kept by combing, rho = 1.25.
+    _run_pair(W.paper_fission())
+
+
+def test_fission_analog_without_comb():
+    # Integer multiplicity (every fission makes exactly two), no windows, no
+    # comb: the population grows freely for a few steps.
+    w = W.paper_fission(n_src=3000).with_(name="fis-analog", nu_f=2.0, comb=0, n_steps=4,
+                                           bank_capacity=200_000)
+    _run_pair(w, analog=True)
+
+
+def test_fission_with_splitting_daughters():
+    # Wide windows of the small problem's kind: splits and fission daughters
+    # in the same work-group buffers.
+    w = W.paper_fission(n_src=4000).with_(name="fis-split", rho=2.0, eps_min=1e-2, n_steps=6, n_batches=8)
+    _run_pair(w)
+
+
+def test_comb_errors():
+    need_gpu()
+    w = W.paper_fission(n_src=2000).with_(n_steps=3)
+    h = H.Handle(H.spec_from_workload(w))
+    with pytest.raises(H.HwwError) as e:       # step 0 is not a finished step of the sweep
+        h.comb(2000)
+    assert e.value.code == -2
+    for p in range(w.n_chunks):
+        h.sweep_step(1, p, stats=False)
+    with pytest.raises(H.HwwError) as e:
+        h.comb(w.capacity() + 1)
+    assert e.value.code == -1
+    n, W_tot = h.comb(500)
+    assert n > 0 and W_tot > 0
+    assert len(h.read_bank(1)["w"]) == 500
+    h.close()
+    plain = H.Handle(H.spec_from_workload(W.plain_small().with_(n_steps=2)))
+    for p in range(4):
+        plain.sweep_step(1, p, stats=False)
+    with pytest.raises(H.HwwError) as e:       # no comb workspace
+        plain.comb(100)
+    assert e.value.code == -2
+    plain.close()
+    with pytest.raises(H.HwwError) as e:       # batches take no fission
+        H.Batch([H.spec_from_workload(W.paper_fission(n_src=500))])
+    assert e.value.code == -1
