@@ -10,9 +10,11 @@ Prints one JSON line: particle segments/s over the timed steps (inputs
 resident in HBM), the sweep kernel's HBM-roofline figures measured with HIP
 events on the library's stream, the figure-of-merit gain over the plain
 (analog) FP64 sweep of the same problem, the CPU oracle timed on a bounded
-sample of the same workload, and two side figures: the batched form (256
+sample of the same workload, and three side figures: the batched form (256
 uneven replicas, one persistent launch per chunk) against one handle per
-replica, and the FP32 flight arithmetic against FP64 on the precision form.
+replica, the FP32 flight arithmetic against FP64 on the precision form, and
+the paper's own supercritical problem (fission, uniform combing) for the
+paper's methods against analog.
 """
 from __future__ import annotations
 
@@ -51,6 +53,7 @@ def parse():
     ap.add_argument("--sweep", action="store_true", help="also run every (c, rho) pair of the workload")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-form figures")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 figures")
+    ap.add_argument("--no-paper", action="store_true", help="skip the paper's supercritical problem")
     ap.add_argument("--batch-steps", type=int, default=50)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--out", default=None, help="also write per-step records (JSON) here")
@@ -328,6 +331,86 @@ def run_sweep(total, warmup, n_src):
     return out
 
 
+def run_paper_problem(seeds=5):
+    """The paper's own supercritical problem (Sec. 5.1: c_eff = 1.1 with
+    fission, 201 cells, 20 steps of dt = 1, 1e4 histories per step kept by
+    uniform combing, rho = 1.25, eps_min = 1e-3) for the paper's methods:
+    analog, HWW, HWW-MA, HWW-F and lagged windows.  Per step: tau^n is the
+    wall time of the step (comb, solves, sweeps and the wait for them),
+    FOM_sigma^n from the batch spread of the track flux and FOM_Error^n
+    against the reference pulse solution at c = 1.1; each FOM is averaged
+    over `seeds` seeds before the ratio to analog is taken."""
+    import torch
+    from paper_2512_19925_amd import hww as H
+    from paper_2512_19925_amd import pulse_reference as P
+    from paper_2512_19925_amd import workloads as W
+    w0 = W.paper_fission()
+    ref = P.cell_step_averages(w0.edges, w0.dt, w0.n_steps, 1.1)
+    dx = np.diff(w0.edges)
+    methods = (("analog", w0.with_(analog=True)), ("HWW", w0.with_(filter=0)), ("HWW-MA", w0),
+               ("HWW-F", w0.with_(filter=2, kappa=30)), ("LWW", w0.with_(filter=0, lagged=True)))
+    res = {}
+    for name, w in methods:
+        sig = np.zeros((seeds, w.n_steps))
+        err = np.zeros((seeds, w.n_steps))
+        sig_w = np.zeros((seeds, w.n_steps))  # cost = segments of the step instead of its wall time
+        err_w = np.zeros((seeds, w.n_steps))
+        segs, wall, fis = 0, 0.0, 0
+        try:
+            for sd in range(seeds):
+                ws = w.with_(seed=1 + sd)
+                h = H.Handle(H.spec_from_workload(ws))
+                h.set_timing(False)
+                kw = H.losm_kwargs(ws)
+                torch.cuda.synchronize()
+                for n in range(1, ws.n_steps + 1):
+                    t0 = time.perf_counter()
+                    if n > 1:
+                        h.comb(ws.comb)
+                    st = _step(h, ws, n, ws.analog, kw, stats=True)
+                    tau = time.perf_counter() - t0
+                    wall += tau
+                    segs += st["segments"]
+                    fis += st["fissions"]
+                    cells = h.read_tallies(H.TALLY_CELLS)
+                    fs = fom_sigma(cells, ws.n_src, dx, ws.dt)
+                    fe = fom_error(cells, ws.n_src, dx, ws.dt, ref[n - 1])
+                    sig[sd, n - 1], err[sd, n - 1] = fs / tau, fe / tau
+                    sig_w[sd, n - 1], err_w[sd, n - 1] = fs / st["segments"], fe / st["segments"]
+                h.close()
+        except H.HwwError as e:
+            res[name] = {"error": str(e)}
+            continue
+        res[name] = {"sig": sig.mean(0), "err": err.mean(0), "sig_w": sig_w.mean(0), "err_w": err_w.mean(0),
+                     "segments_per_s": segs / wall,
+                     "ms_per_step": wall * 1e3 / (seeds * w.n_steps), "fissions_per_step": fis / (seeds * w.n_steps)}
+    out = {"workload": f"{w0.name}: {w0.n_cells} cells on [{w0.x_lo},{w0.x_hi}], sigma_t=1, sigma_s=sigma_f=1/3, "
+                       f"nu_f={w0.nu_f} (c_eff=1.1), v=1, dt={w0.dt}, {w0.n_steps} steps, H={w0.comb} histories "
+                       f"per step (uniform comb), rho={w0.rho}, eps_min={w0.eps_min}, CN, 3 window updates per "
+                       f"step, {seeds} seeds",
+           "fom": "per step, tau = step wall time (work_fom: tau = segments of the step); FOM averaged over "
+                  "the seeds, ratio to analog averaged over the 20 steps"}
+    a = res.get("analog")
+    for name, r in res.items():
+        if "error" in r:
+            out[name] = r
+            continue
+        rec = {"segments_per_s": r["segments_per_s"], "ms_per_step": r["ms_per_step"],
+               "fissions_per_step": r["fissions_per_step"]}
+        if a is not None and "error" not in a and name != "analog":
+            rec["fom_sigma_over_analog_mean"] = float(np.mean(r["sig"] / a["sig"]))
+            rec["fom_error_over_analog_mean"] = float(np.mean(r["err"] / a["err"]))
+            rec["fom_sigma_over_analog_steps_4_19"] = [float(r["sig"][3] / a["sig"][3]),
+                                                      float(r["sig"][18] / a["sig"][18])]
+            # With the cost of a step taken as its segments (a serial code's
+            # runtime), not the GPU wall time that launch latency dominates at
+            # 1e4 histories.
+            rec["work_fom_sigma_over_analog_mean"] = float(np.mean(r["sig_w"] / a["sig_w"]))
+            rec["work_fom_error_over_analog_mean"] = float(np.mean(r["err_w"] / a["err_w"]))
+        out[name] = rec
+    return out
+
+
 def cpu_baseline(w, budget_s):
     """The oracle, as it stands, on a bounded sample: the same problem with
     fewer source particles, as many steps as fit in about budget_s."""
@@ -430,6 +513,8 @@ def main():
         line["batched"] = run_batched(args.batch_steps)
     if not args.no_fp32:
         line["fp32"] = run_fp32_pair()
+    if not args.no_paper:
+        line["paper_problem"] = run_paper_problem()
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     if args.out:

@@ -8,7 +8,7 @@
 namespace hww {
 
 // Device error bits (ORed into one word of the workspace).
-enum : uint32_t { ERR_CAPACITY = 1u, ERR_NUMERIC = 2u, ERR_SPLIT = 4u, ERR_GENERATIONS = 8u };
+enum : uint32_t { ERR_CAPACITY = 1u, ERR_NUMERIC = 2u, ERR_SPLIT = 4u, ERR_GENERATIONS = 8u, ERR_DAUGHTERS = 16u };
 
 // Counter slots (per step, uint64).
 enum {

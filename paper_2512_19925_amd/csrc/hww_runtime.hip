@@ -105,7 +105,10 @@ void make_layout(const hww_problem &p, Layout *L, bool member = false) {
   G.seg_cap = (int64_t)std::ceil(kSegSlack * share / K) + 64;
   G.ovf_cap = (int64_t)std::ceil(kOvfShare * share) + 1024;
   G.stride = (int64_t)K * G.seg_cap + G.ovf_cap;
-  L->dcap = std::max<int64_t>(4096, (p.bank_capacity + B * K - 1) / (B * K));
+  // Daughter slots per work-group buffer: its share of the bank, four times
+  // that for combed (supercritical) problems, whose windows split whole
+  // generations at the wave front.
+  L->dcap = std::max<int64_t>(4096, (p.comb ? 4 : 1) * ((p.bank_capacity + B * K - 1) / (B * K)));
   const int64_t slots = R * G.stride;
   const int64_t dslots = member ? 0 : 2 * B * K * L->dcap;
   Carver c;
@@ -350,11 +353,12 @@ int poll_errors(hww_handle *h) {
   uint64_t cen = 0;
   int rc = census_total(h, 1 - h->start_bank, &cen);
   if (rc != HWW_OK) return rc;
-  if (e & (ERR_CAPACITY | ERR_SPLIT | ERR_GENERATIONS)) {
+  if (e & (ERR_CAPACITY | ERR_SPLIT | ERR_GENERATIONS | ERR_DAUGHTERS)) {
     h->fatal = HWW_E_CAPACITY;
     return fail(h, HWW_E_CAPACITY, (e & ERR_SPLIT) ? "a split exceeded 1e9 daughters"
                                    : (e & ERR_GENERATIONS) ? "too many daughter generations"
-                                                           : "bank segment or daughter buffer overflow");
+                                   : (e & ERR_DAUGHTERS) ? "a work-group's daughter buffer overflowed"
+                                                         : "bank segment overflow");
   }
   if (cen > (uint64_t)h->p.bank_capacity) {
     h->fatal = HWW_E_CAPACITY;
@@ -726,11 +730,12 @@ int poll_batch(hww_handle *h) {
   HIPCHK(h, hipMemcpyAsync(seg.data(), h->segcnt_all[cb], 4 * seg.size(), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipMemcpyAsync(ovf.data(), h->ovfcnt_all[cb], 4 * ovf.size(), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
-  if (e & (ERR_CAPACITY | ERR_SPLIT | ERR_GENERATIONS)) {
+  if (e & (ERR_CAPACITY | ERR_SPLIT | ERR_GENERATIONS | ERR_DAUGHTERS)) {
     h->fatal = HWW_E_CAPACITY;
     return fail(h, HWW_E_CAPACITY, (e & ERR_SPLIT) ? "a split exceeded 1e9 daughters"
                                    : (e & ERR_GENERATIONS) ? "too many daughter generations"
-                                                           : "bank segment or daughter buffer overflow");
+                                   : (e & ERR_DAUGHTERS) ? "a work-group's daughter buffer overflowed"
+                                                         : "bank segment overflow");
   }
   for (size_t q = 0; q < h->rep.size(); ++q) {
     hww_handle *r = h->rep[q];

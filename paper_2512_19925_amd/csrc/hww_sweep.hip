@@ -295,7 +295,7 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
       uint32_t base = 0;
       if (lane == 0) base = atomicAdd(&L.dcnt[out_buf], total);
       base = __shfl(base, 0);
-      if ((uint64_t)base + total > (uint64_t)A.dcap && lane == 0) atomicOr(A.err, ERR_CAPACITY);
+      if ((uint64_t)base + total > (uint64_t)A.dcap && lane == 0) atomicOr(A.err, ERR_DAUGHTERS);
       const int64_t qb = ((int64_t)out_buf * nq + qslot) * dstride;
       const uint32_t start = base + incl - cntd;
       for (uint32_t q = 1; q <= cntd; ++q) {
@@ -342,7 +342,7 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
         return 0u;
       }
       if (ndf - 1.0 > (double)A.dcap) {
-        atomicOr(A.err, ERR_CAPACITY);
+        atomicOr(A.err, ERR_DAUGHTERS);
         active = false;
         return 0u;
       }

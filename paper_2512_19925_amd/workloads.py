@@ -90,13 +90,15 @@ def paper_fission(n_src: int = 10_000) -> Workload:
     [-20.5, 20.5], sigma_t = 1, sigma_s = sigma_f = 1/3, nu_f = 2.3
     (c_eff = 1.1), v = 1, 20 steps of 1, H^n = 1e4 histories per step kept by
     uniform combing, windows of width 1.25 with eps_min = 1e-3, Crank-Nicolson,
-    three window updates per step, moving-average filtered closures (k = 3)."""
+    three window updates per step, moving-average filtered closures (k = 3).
+    The bank holds 400 H: unfiltered closures and lagged windows split the
+    census at the wave front to about 3e6 particles."""
     I = 201
     st = np.ones(I)
     return Workload(name="paper-fission-201c", x_lo=-20.5, x_hi=20.5, n_cells=I, sigma_t=st,
                     sigma_s=st / 3.0, sigma_f=st / 3.0, nu_f=2.3, speed=1.0, dt=1.0, n_steps=20,
                     n_src=n_src, comb=n_src, rho=1.25, eps_min=1e-3, filter=1, ma_k=3,
-                    bank_capacity=max(40 * n_src, 4096), seed=1)
+                    bank_capacity=max(400 * n_src, 4096), seed=1)
 
 
 def precision_form(n_src: int = 10_000_000) -> Workload:
