@@ -108,6 +108,9 @@ typedef struct hww_losm_opts {
                              shape is the Monte Carlo track-length flux of the previous step
                              (semi-implicit calls only; a step with no track flux, such as
                              the source, leaves the windows as they are)          */
+  int32_t window_scale;   /* 0: centres of Eq. ww-center times s^n, the start (semi-implicit: census)
+                                weight of the step per source particle;
+                             1: Eq. ww-center as printed, largest centre 1      */
 } hww_losm_opts;
 
 /* Tally kinds for hww_read_tallies. */

@@ -902,7 +902,7 @@ int orc_solve_losm(orc_sim *s, const orc_losm_opts *o, double *phi_out, double *
     const double sc = nval(&wtot) / (double)s->n_src;
     int rc = 0;
     if (mx > 0.0 && sc > 0.0) {
-      rc = orc_ww_centres(I, g.phi, o->eps_min, sc, buf + 3 * I);
+      rc = orc_ww_centres(I, g.phi, o->eps_min, o->window_scale ? 1.0 : sc, buf + 3 * I);
       if (rc == 0) rc = orc_set_windows(s, buf + 3 * I, o->rho);
     }
     free(buf);
@@ -966,7 +966,9 @@ int orc_solve_losm(orc_sim *s, const orc_losm_opts *o, double *phi_out, double *
     double sc = nval(&wtot) / (double)s->n_src;
     /* An empty bank has nothing to window: the windows stay as they are. */
     if (o->apply_windows && sc > 0.0) {
-      rc = orc_ww_centres(I, phi_n + 1, o->eps_min, sc, tmp);
+      /* Eq. ww-center as printed has its largest centre at 1; window_scale 0
+       * multiplies it by the bank's mean weight per source particle. */
+      rc = orc_ww_centres(I, phi_n + 1, o->eps_min, o->window_scale ? 1.0 : sc, tmp);
       if (rc == 0) rc = orc_set_windows(s, tmp, o->rho);
     }
   }

@@ -58,6 +58,7 @@ typedef struct orc_losm_opts {
   int32_t apply_windows;
   int32_t kappa;         /* Fourier cutoff */
   int32_t lagged;        /* 1: windows from the previous step's track-length flux, no solve */
+  int32_t window_scale;  /* 0: centres times s^n = start weight / N_src; 1: as printed (max centre 1) */
 } orc_losm_opts;
 
 typedef struct orc_sim orc_sim;

@@ -203,7 +203,7 @@ class _Opts(C.Structure):
     _fields_ = [("theta", C.c_double), ("implicit", C.c_int32), ("filter", C.c_int32),
                 ("ma_k", C.c_int32), ("eps_min", C.c_double), ("rho", C.c_double),
                 ("closure_track", C.c_int32), ("apply_windows", C.c_int32), ("kappa", C.c_int32),
-                ("lagged", C.c_int32)]
+                ("lagged", C.c_int32), ("window_scale", C.c_int32)]
 
 
 @dataclass
@@ -216,6 +216,7 @@ class LosmOpts:
     closure_track: int = 0
     kappa: int = 30
     lagged: int = 0
+    window_scale: int = 0
 
 
 class OracleSim:
@@ -278,7 +279,7 @@ class OracleSim:
     def solve_losm(self, opts: LosmOpts, implicit: bool, apply_windows=True):
         o = _Opts(float(opts.theta), int(implicit), int(opts.filter), int(opts.ma_k),
                   float(opts.eps_min), float(opts.rho), int(opts.closure_track), int(apply_windows),
-                  int(opts.kappa), int(opts.lagged))
+                  int(opts.kappa), int(opts.lagged), int(opts.window_scale))
         phi = np.zeros(self.I + 2)
         J = np.zeros(self.I + 1)
         _check("solve_losm", lib().orc_solve_losm(self._h, C.byref(o), _dp(phi), _dp(J)))

@@ -193,6 +193,7 @@ struct LosmArgs {
   double theta;
   int32_t implicit, filter, ma_k, closure_track, apply_windows;
   int32_t kappa, lagged;          // Fourier cutoff; windows from the previous step's track flux
+  int32_t window_scale;           // 1: centres as printed (max 1), 0: times start weight / n_src
   double eps_min, rho;
   double *scratch;                // >= 24 * (I + 4) doubles
   double *factor;                 // [4][2I+3] LU factors of the system for `theta`, old-time diagonal
@@ -216,7 +217,7 @@ struct LosmReplica {
 struct LosmCall {
   int32_t cur;  // current tally set
   int32_t implicit, next_chunk, filter, ma_k, closure_track, apply_windows, export_only, refactor, work_in_lds;
-  int32_t kappa, lagged, ic_cached;
+  int32_t kappa, lagged, ic_cached, window_scale;
   double theta, eps_min, rho;
 };
 

@@ -425,7 +425,7 @@ __device__ __forceinline__ void losm_body(const LosmArgs &A, double *dyn) {
       if (tid == 0) atomicOr(A.err, ERR_NUMERIC);
       return;
     }
-    const double mm = sc[2], s = sc[1];
+    const double mm = sc[2], s = A.window_scale ? 1.0 : sc[1];
     for (int i = tid; i < I; i += T) {
       const double p = u[2 * (i + 1)];
       const double rr = p > 0.0 ? p / mm : 0.0;
@@ -460,7 +460,7 @@ __device__ inline LosmArgs losm_batch_args(const LosmReplica &R, const LosmCall 
   A.next_chunk = c.next_chunk;
   A.theta = c.theta;
   A.implicit = c.implicit; A.filter = c.filter; A.ma_k = c.ma_k;
-  A.kappa = c.kappa; A.lagged = c.lagged; A.ic_cached = c.ic_cached;
+  A.kappa = c.kappa; A.lagged = c.lagged; A.ic_cached = c.ic_cached; A.window_scale = c.window_scale;
   A.closure_track = c.closure_track; A.apply_windows = c.apply_windows;
   A.eps_min = c.eps_min; A.rho = c.rho;
   A.refactor = c.refactor; A.work_in_lds = c.work_in_lds; A.export_only = c.export_only;

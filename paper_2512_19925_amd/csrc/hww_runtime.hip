@@ -1069,7 +1069,7 @@ int hww_solve_losm(hww_handle *h, const hww_losm_opts *o, double *phi_out, doubl
     c.cur = h->cur_tal;
     c.implicit = o->implicit; c.next_chunk = h->next_chunk; c.filter = o->filter; c.ma_k = o->ma_k;
     c.closure_track = o->lagged ? 1 : o->closure_track; c.apply_windows = o->apply_windows; c.export_only = 0;
-    c.kappa = o->kappa; c.lagged = o->lagged;
+    c.kappa = o->kappa; c.lagged = o->lagged; c.window_scale = o->window_scale ? 1 : 0;
     c.refactor = (o->theta != h->factor_theta) ? 1 : 0;
     c.work_in_lds = h->losm_wil;
     c.theta = o->theta; c.eps_min = o->eps_min; c.rho = o->rho;
@@ -1103,7 +1103,7 @@ int hww_solve_losm(hww_handle *h, const hww_losm_opts *o, double *phi_out, doubl
   a.wstart = h->wstart; a.wnext = h->wnext; a.next_chunk = h->next_chunk;
   a.theta = o->theta; a.implicit = o->implicit; a.filter = o->filter; a.ma_k = o->ma_k;
   a.closure_track = o->lagged ? 1 : o->closure_track; a.apply_windows = o->apply_windows;
-  a.kappa = o->kappa; a.lagged = o->lagged;
+  a.kappa = o->kappa; a.lagged = o->lagged; a.window_scale = o->window_scale ? 1 : 0;
   a.eps_min = o->eps_min; a.rho = o->rho;
   a.scratch = h->scratch; a.factor = h->factor;
   a.refactor = (o->theta != h->factor_theta) ? 1 : 0;

@@ -62,7 +62,7 @@ class LosmOpts(C.Structure):
     _fields_ = [("theta", C.c_double), ("implicit", C.c_int32), ("filter", C.c_int32),
                 ("ma_k", C.c_int32), ("eps_min", C.c_double), ("rho", C.c_double),
                 ("closure_track", C.c_int32), ("apply_windows", C.c_int32), ("kappa", C.c_int32),
-                ("lagged", C.c_int32)]
+                ("lagged", C.c_int32), ("window_scale", C.c_int32)]
 
 
 class TuneResult(C.Structure):
@@ -248,9 +248,10 @@ class Handle:
         return int(nb.value), float(wt.value)
 
     def solve_losm(self, theta=0.5, implicit=False, filter=0, ma_k=3, eps_min=1e-3, rho=5.0,
-                   closure_track=0, apply_windows=True, want_solution=False, kappa=30, lagged=0):
+                   closure_track=0, apply_windows=True, want_solution=False, kappa=30, lagged=0,
+                   window_scale=0):
         o = LosmOpts(float(theta), int(implicit), int(filter), int(ma_k), float(eps_min), float(rho),
-                     int(closure_track), int(apply_windows), int(kappa), int(lagged))
+                     int(closure_track), int(apply_windows), int(kappa), int(lagged), int(window_scale))
         phi = np.zeros(self.I + 2) if want_solution else None
         J = np.zeros(self.I + 1) if want_solution else None
         self._check("hww_solve_losm", lib().hww_solve_losm(self._h, C.byref(o), _dp(phi), _dp(J)))
@@ -378,9 +379,10 @@ class Batch:
         return st.as_dict()
 
     def solve_losm(self, theta=0.5, implicit=False, filter=0, ma_k=3, eps_min=1e-3, rho=5.0,
-                   closure_track=0, apply_windows=True, want_solution=False, kappa=30, lagged=0):
+                   closure_track=0, apply_windows=True, want_solution=False, kappa=30, lagged=0,
+                   window_scale=0):
         o = LosmOpts(float(theta), int(implicit), int(filter), int(ma_k), float(eps_min), float(rho),
-                     int(closure_track), int(apply_windows), int(kappa), int(lagged))
+                     int(closure_track), int(apply_windows), int(kappa), int(lagged), int(window_scale))
         phi = np.zeros(sum(i + 2 for i in self.I)) if want_solution else None
         J = np.zeros(sum(i + 1 for i in self.I)) if want_solution else None
         self._check("hww_solve_losm", lib().hww_solve_losm(self._h, C.byref(o), _dp(phi), _dp(J)))
@@ -432,7 +434,8 @@ def spec_from_workload(w, precision=HWW_FP64) -> ProblemSpec:
 def losm_kwargs(w):
     """solve_losm keywords of a Workload."""
     return dict(theta=w.theta, filter=w.filter, ma_k=w.ma_k, eps_min=w.eps_min, rho=w.rho,
-                closure_track=w.closure_track, kappa=w.kappa, lagged=int(w.lagged))
+                closure_track=w.closure_track, kappa=w.kappa, lagged=int(w.lagged),
+                window_scale=int(w.window_scale))
 
 
 def run(h: Handle, w, steps=None, on_step=None, analog=None, stats=True):

@@ -48,6 +48,7 @@ class Workload:
     sigma_f: np.ndarray | None = None  # fission cross sections (None: no fission)
     nu_f: float = 0.0                  # mean neutrons per fission
     comb: int = 0                      # comb every census to this many particles (0: never)
+    window_scale: int = 0              # 1: window centres as printed (largest 1), 0: times s^n
 
     @property
     def edges(self) -> np.ndarray:

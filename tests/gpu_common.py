@@ -23,7 +23,8 @@ def oracle_sim(w):
 
 def oracle_opts(w):
     return O.LosmOpts(theta=w.theta, filter=w.filter, ma_k=w.ma_k, eps_min=w.eps_min, rho=w.rho,
-                      closure_track=w.closure_track, kappa=w.kappa, lagged=int(w.lagged))
+                      closure_track=w.closure_track, kappa=w.kappa, lagged=int(w.lagged),
+                      window_scale=int(w.window_scale))
 
 
 def say(*a):

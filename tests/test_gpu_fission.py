@@ -63,6 +63,12 @@ def test_paper_problem_end_to_end():
     _run_pair(W.paper_fission())
 
 
+def test_paper_problem_windows_as_printed():
+    # Eq. ww-center as printed (largest centre 1 while the mean weight grows
+    # with fission): many more splits at every step start.
+    _run_pair(W.paper_fission().with_(name="paper-printed-ww", window_scale=1, n_steps=10))
+
+
 def test_fission_analog_without_comb():
     # Integer multiplicity (every fission makes exactly two), no windows, no
     # comb: the population grows freely for a few steps.

@@ -262,3 +262,25 @@ def test_comb_keeps_the_paper_problem_bounded():
     sim.comb(w.comb)
     assert len(sim.bank(1)["w"]) == w.comb
     assert tot[-1] > tot[0]
+
+
+@pytest.mark.parametrize("window_scale", [0, 1])
+def test_window_scale_readings(window_scale):
+    # Eq. ww-center as printed puts the largest centre at exactly 1 and the
+    # smallest at eps_min or above; window_scale 0 multiplies the centres by
+    # s^n, the census weight per source particle (here grown by fission).
+    w = W.paper_fission(n_src=2000).with_(n_steps=4, window_scale=window_scale)
+    sim = oracle_sim(w)
+    opts = O.LosmOpts(theta=0.5, rho=w.rho, eps_min=w.eps_min, filter=1, window_scale=window_scale)
+    for n in (1, 2):
+        _sweep_step(sim, n)
+    sim.comb(w.comb)
+    sim.solve_losm(opts, implicit=False)
+    c, u, f = sim.windows()
+    s_n = sim.state()[3].sum() / w.n_src
+    assert s_n > 1.05            # the population grew
+    top = 1.0 if window_scale else s_n
+    assert c.max() == pytest.approx(top, rel=1e-15)
+    assert c.min() >= w.eps_min * top * (1 - 1e-15)
+    np.testing.assert_allclose(u, c * w.rho, rtol=1e-15)
+    np.testing.assert_allclose(f, c / w.rho, rtol=1e-15)
