@@ -279,7 +279,10 @@ def run_methods(total, warmup, n_src, c, rho, ref):
     # them split the bank past its capacity of 4e7 unless eps_min is raised
     # (eps_min = 0.05 peaks at 7e7 particles, 0.2 at 2.5e7), so LWW runs with
     # eps_min = 0.2.
-    for name, w in (("HWW", w0.with_(filter=0)), ("HWW-MA", w0), ("HWW-F", w0.with_(filter=2, kappa=30)),
+    # "HWW-MA phi-only": the cheaper closure tallies of census closures, the
+    # track-length phi alone per segment instead of phi, J and K.
+    for name, w in (("HWW", w0.with_(filter=0)), ("HWW-MA", w0), ("HWW-MA phi-only", w0.with_(track_moments=1)),
+                    ("HWW-F", w0.with_(filter=2, kappa=30)),
                     ("LWW eps_min=0.2", w0.with_(filter=0, lagged=True, eps_min=0.2))):
         rec = {}
         try:

@@ -69,6 +69,10 @@ typedef struct hww_problem {
                              0 <= sigma_f, sigma_s + sigma_f <= sigma_t (Eq. HO_transport) */
   double nu_f;            /* mean neutrons per fission, 0 <= nu_f < 1e6 (with sigma_f) */
   int32_t comb;           /* 1: reserve the workspace hww_comb needs, 0: none    */
+  int32_t track_moments;  /* track-length moments scored per segment (Eq. phi-mc and its mu, mu^2
+                             moments): 0 or 3 phi, J and K; 2 phi and K (enough for track-length
+                             closures); 1 phi only (census closures need no more); the
+                             tallies not scored read as zero                      */
 } hww_problem;
 
 typedef struct hww_handle hww_handle;

@@ -132,6 +132,7 @@ struct orc_sim {
   double *sig_s_lo;  /* sigma_s + nu_f sigma_f: the production term of the low-order balance */
   double nu_f;
   int fission;
+  int track_moments;  /* 3: phi, J, K; 2: phi, K; 1: phi */
   double v, inv_v, dt;
   int32_t n_steps;
   double src_x;
@@ -225,6 +226,7 @@ int orc_create(const orc_params *p, orc_sim **out) {
     if (p->sigma_f && (!(p->sigma_f[i] >= 0.0) || p->sigma_s[i] + p->sigma_f[i] > p->sigma_t[i])) return -1;
   }
   if (p->sigma_f && (!(p->nu_f >= 0.0) || !(p->nu_f < 1.0e6))) return -1;
+  if (p->track_moments < 0 || p->track_moments > 3) return -1;
   if (!(p->src_x >= p->edges[0] && p->src_x <= p->edges[I])) return -1;
 
   orc_sim *s = (orc_sim *)calloc(1, sizeof(orc_sim));
@@ -262,6 +264,7 @@ int orc_create(const orc_params *p, orc_sim **out) {
   memcpy(s->sig_t, p->sigma_t, sizeof(double) * I);
   memcpy(s->sig_s, p->sigma_s, sizeof(double) * I);
   s->fission = p->sigma_f != NULL;
+  s->track_moments = p->track_moments == 0 ? 3 : p->track_moments;
   s->nu_f = s->fission ? p->nu_f : 0.0;
   for (int i = 0; i < I; ++i) {
     s->cratio[i] = s->sig_s[i] / s->sig_t[i];
@@ -421,8 +424,8 @@ static int transport(orc_sim *s, particle *p) {
     double wl = p->w * l;
     double t1 = wl * p->mu;
     nadd(&cells[i * 6 + ORC_T_PHI], wl);
-    nadd(&cells[i * 6 + ORC_T_J], t1);
-    nadd(&cells[i * 6 + ORC_T_K], t1 * p->mu);
+    if (s->track_moments == 3) nadd(&cells[i * 6 + ORC_T_J], t1);
+    if (s->track_moments >= 2) nadd(&cells[i * 6 + ORC_T_K], t1 * p->mu);
     s->tracks[i] += 1;
     s->counters[ORC_N_SEGMENTS] += 1;
     uint32_t e = p->e;
@@ -858,6 +861,7 @@ int orc_solve_losm(orc_sim *s, const orc_losm_opts *o, double *phi_out, double *
   if (!s || !o) return -1;
   if (!(o->theta > 0.0 && o->theta <= 1.0) || o->ma_k < 0 || o->kappa < 0) return -1;
   if (o->apply_windows && (!(o->rho >= 1.0) || !(o->eps_min > 0.0 && o->eps_min <= 1.0))) return -1;
+  if (o->closure_track && !o->lagged && s->track_moments < 2) return -1; /* track closures need K */
   if (o->lagged && (o->implicit || !o->apply_windows)) return -1;
   const int I = s->I;
   const tally_set *ic, *cl;

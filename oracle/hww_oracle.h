@@ -45,6 +45,7 @@ typedef struct orc_params {
   int32_t n_chunks;
   const double *sigma_f;  /* n_cells, or NULL: no fission */
   double nu_f;            /* mean number of neutrons per fission */
+  int32_t track_moments;  /* track-length moments scored per segment: 0 or 3 phi, J, K; 2 phi, K; 1 phi */
 } orc_params;
 
 typedef struct orc_losm_opts {

@@ -196,7 +196,8 @@ class _Params(C.Structure):
                 ("speed", C.c_double), ("dt", C.c_double), ("n_steps", C.c_int32),
                 ("src_x", C.c_double), ("n_src", C.c_int64), ("bank_capacity", C.c_int64),
                 ("seed", C.c_uint32), ("replica", C.c_uint32), ("n_batches", C.c_int32),
-                ("n_chunks", C.c_int32), ("sigma_f", C.POINTER(C.c_double)), ("nu_f", C.c_double)]
+                ("n_chunks", C.c_int32), ("sigma_f", C.POINTER(C.c_double)), ("nu_f", C.c_double),
+                ("track_moments", C.c_int32)]
 
 
 class _Opts(C.Structure):
@@ -223,7 +224,8 @@ class OracleSim:
     """One problem on the oracle.  Arguments are plain numbers and arrays."""
 
     def __init__(self, edges, sigma_t, sigma_s, speed, dt, n_steps, src_x, n_src,
-                 bank_capacity=None, seed=1, replica=0, n_batches=32, n_chunks=4, sigma_f=None, nu_f=0.0):
+                 bank_capacity=None, seed=1, replica=0, n_batches=32, n_chunks=4, sigma_f=None, nu_f=0.0,
+                 track_moments=0):
         self.edges = _f64(edges)
         self.sigma_t = _f64(sigma_t)
         self.sigma_s = _f64(sigma_s)
@@ -236,7 +238,7 @@ class OracleSim:
         cap = int(bank_capacity) if bank_capacity is not None else max(4 * self.n_src, 1024)
         p = _Params(self.I, _dp(self.edges), _dp(self.sigma_t), _dp(self.sigma_s), self.speed,
                     self.dt, self.n_steps, float(src_x), self.n_src, cap, int(seed), int(replica),
-                    self.B, self.n_chunks, _dp(self.sigma_f), float(nu_f))
+                    self.B, self.n_chunks, _dp(self.sigma_f), float(nu_f), int(track_moments))
         h = C.c_void_p()
         _check("create", lib().orc_create(C.byref(p), C.byref(h)))
         self._h = h

@@ -88,6 +88,7 @@ struct SweepArgs {
   const Window *win;       // [I]
   const double *cfis;      // [I] (sigma_s + sigma_f) / sigma_t, or null: no fission
   double nu_f;             // mean neutrons per fission
+  int32_t track_moments;   // 3: phi, J, K per segment; 2: phi, K; 1: phi
   int32_t ww_on;
   int32_t chunk;
   int32_t tile;            // start-bank / daughter tile a wave claims at a time
@@ -114,6 +115,7 @@ struct ReplicaDesc {
   uint32_t seed, key1;
   const CellData<Real> *cells;
   const Window *win;
+  int32_t track_moments;
   BankGeom geom;
   Bank<Real> bank[2];
   double *tal[2], *bnd[2];

@@ -237,6 +237,7 @@ struct hww_handle {
   double *scratch, *factor, *phi_out, *J_out;
   double *cfis = nullptr;  // (sigma_s + sigma_f) / sigma_t, fission problems only
   double nu_f = 0.0;
+  int track_moments = 3;   // track-length moments scored per segment
 
   int start_bank = 0;  // census bank = 1 - start_bank
   int cur_tal = 0;
@@ -324,6 +325,7 @@ int validate(const hww_problem *p, std::string *why) {
   }
   if (p->sigma_f && (!(p->nu_f >= 0.0) || !(p->nu_f < 1.0e6))) { *why = "nu_f must be in [0, 1e6)"; return HWW_E_INVALID_ARG; }
   if (p->comb != 0 && p->comb != 1) { *why = "comb must be 0 or 1"; return HWW_E_INVALID_ARG; }
+  if (p->track_moments < 0 || p->track_moments > 3) { *why = "track_moments must be 0..3"; return HWW_E_INVALID_ARG; }
   if (!(p->src_x >= p->edges[0] && p->src_x <= p->edges[p->n_cells])) { *why = "src_x outside the mesh"; return HWW_E_INVALID_ARG; }
   if (sweep_lds_bytes(p->n_cells, p->n_chunks, 64) > 160 * 1024) { *why = "too many cells for the LDS histogram (I <= 3300)"; return HWW_E_INVALID_ARG; }
   return HWW_OK;
@@ -380,6 +382,7 @@ SweepArgs<Real> base_args(hww_handle *h) {
   a.win = h->win;
   a.cfis = h->cfis;
   a.nu_f = h->nu_f;
+  a.track_moments = h->track_moments;
   a.ww_on = h->ww_on;
   a.geom = h->L.geom;
   if constexpr (sizeof(Real) == 8) {
@@ -444,6 +447,7 @@ void carve_handle(hww_handle *h, const hww_problem &problem, char *ws, const Lay
   h->p.edges = h->p.sigma_t = h->p.sigma_s = h->p.sigma_f = nullptr;
   h->cfis = problem.sigma_f ? reinterpret_cast<double *>(ws + L.off_cfis) : nullptr;
   h->nu_f = problem.sigma_f ? problem.nu_f : 0.0;
+  h->track_moments = problem.track_moments == 0 ? 3 : problem.track_moments;
   h->I = problem.n_cells;
   h->B = problem.n_batches;
   h->nc = problem.n_chunks;
@@ -647,6 +651,7 @@ ReplicaDesc<Real> replica_desc(hww_handle *r) {
   d.v = r->p.speed; d.inv_v = 1.0 / r->p.speed; d.dt = r->p.dt;
   d.seed = r->p.seed; d.key1 = r->p.replica << 4;
   d.win = r->win;
+  d.track_moments = r->track_moments;
   d.geom = r->L.geom;
   for (int k = 0; k < 2; ++k) {
     if constexpr (sizeof(Real) == 8) d.bank[k] = r->bank[k];
@@ -1050,6 +1055,8 @@ int hww_solve_losm(hww_handle *h, const hww_losm_opts *o, double *phi_out, doubl
     return fail(h, HWW_E_INVALID_ARG, "bad LOSM options");
   if (o->lagged && (o->implicit || !o->apply_windows))
     return fail(h, HWW_E_INVALID_ARG, "lagged windows are set at the start of a step");
+  if (o->closure_track && !o->lagged && h->track_moments < 2)
+    return fail(h, HWW_E_INVALID_ARG, "track-length closures need the K tally (track_moments 0, 2 or 3)");
   if (o->lagged && h->step == 0 && h->next_chunk == h->nc) {
     // The source has no track-length flux: the first step runs with the
     // windows as they are (none unless set).

@@ -505,8 +505,8 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
         const double wl = w * (double)l;
         const double t1 = wl * (double)mu;
         atomicAdd(&L.hist[i * 6 + 0], wl);
-        atomicAdd(&L.hist[i * 6 + 1], t1);
-        atomicAdd(&L.hist[i * 6 + 2], t1 * (double)mu);
+        if (A.track_moments == 3) atomicAdd(&L.hist[i * 6 + 1], t1);
+        if (A.track_moments >= 2) atomicAdd(&L.hist[i * 6 + 2], t1 * (double)mu);
         atomicAdd(&L.trk[i], 1u);
         e_ev = e;
         e = e_ev + 1;
@@ -701,6 +701,7 @@ __global__ void __launch_bounds__(1024) sweep_batch_kernel(BatchSweepArgs<Real> 
     A.seed = __builtin_amdgcn_readfirstlane(D.seed);
     A.key1 = __builtin_amdgcn_readfirstlane(D.key1);
     A.cells = D.cells; A.win = D.win;
+    A.track_moments = D.track_moments;
     A.cfis = nullptr; A.nu_f = 0.0;  // batches have no fission (kFission = false)
     A.ww_on = P.ww_on; A.chunk = P.chunk; A.tile = P.tile;
     A.geom = D.geom;

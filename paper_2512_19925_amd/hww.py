@@ -43,7 +43,7 @@ class Problem(C.Structure):
                 ("src_x", C.c_double), ("n_src", C.c_int64), ("bank_capacity", C.c_int64),
                 ("seed", C.c_uint32), ("replica", C.c_uint32), ("n_batches", C.c_int32),
                 ("precision", C.c_int32), ("n_chunks", C.c_int32), ("sigma_f", C.POINTER(C.c_double)),
-                ("nu_f", C.c_double), ("comb", C.c_int32)]
+                ("nu_f", C.c_double), ("comb", C.c_int32), ("track_moments", C.c_int32)]
 
 
 class StepStats(C.Structure):
@@ -140,6 +140,7 @@ class ProblemSpec:
     sigma_f: np.ndarray | None = None
     nu_f: float = 0.0
     comb: int = 0
+    track_moments: int = 0
 
     def to_c(self):
         self._keep = [_f64(self.edges), _f64(self.sigma_t), _f64(self.sigma_s),
@@ -148,7 +149,7 @@ class ProblemSpec:
         return Problem(len(st), _dp(e), _dp(st), _dp(ss), float(self.speed), float(self.dt),
                        int(self.n_steps), float(self.src_x), int(self.n_src), int(self.bank_capacity),
                        int(self.seed), int(self.replica), int(self.n_batches), int(self.precision),
-                       int(self.n_chunks), _dp(sf), float(self.nu_f), int(self.comb))
+                       int(self.n_chunks), _dp(sf), float(self.nu_f), int(self.comb), int(self.track_moments))
 
 
 def workspace_bytes(spec: ProblemSpec) -> int:
@@ -428,7 +429,8 @@ def spec_from_workload(w, precision=HWW_FP64) -> ProblemSpec:
     return ProblemSpec(edges=w.edges, sigma_t=w.sigma_t, sigma_s=w.sigma_s, speed=w.speed, dt=w.dt,
                        n_steps=w.n_steps, src_x=w.src_x, n_src=w.n_src, bank_capacity=w.capacity(),
                        seed=w.seed, replica=w.replica, n_batches=w.n_batches, precision=precision,
-                       n_chunks=w.n_chunks, sigma_f=w.sigma_f, nu_f=w.nu_f, comb=int(w.comb > 0))
+                       n_chunks=w.n_chunks, sigma_f=w.sigma_f, nu_f=w.nu_f, comb=int(w.comb > 0),
+                       track_moments=w.track_moments)
 
 
 def losm_kwargs(w):

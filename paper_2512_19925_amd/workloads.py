@@ -49,6 +49,7 @@ class Workload:
     nu_f: float = 0.0                  # mean neutrons per fission
     comb: int = 0                      # comb every census to this many particles (0: never)
     window_scale: int = 0              # 1: window centres as printed (largest 1), 0: times s^n
+    track_moments: int = 0             # track moments per segment: 0/3 phi, J, K; 2 phi, K; 1 phi
 
     @property
     def edges(self) -> np.ndarray:

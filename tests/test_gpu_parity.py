@@ -81,6 +81,26 @@ def test_backward_euler_and_track_closures():
     _run_pair(W.plain_small().with_(name="be-track", theta=1.0, closure_track=1, n_src=4000, n_steps=8))
 
 
+@pytest.mark.parametrize("tm", [1, 2])
+def test_fewer_track_moments(tm):
+    # Census closures need only the track-length phi; track_moments 2 keeps
+    # K for track-length closures.
+    w = W.plain_small().with_(name=f"track-moments-{tm}", n_src=4000, n_steps=6, track_moments=tm,
+                              closure_track=1 if tm == 2 else 0)
+    _run_pair(w)
+
+
+def test_track_closures_need_k():
+    need_gpu()
+    h = H.Handle(H.spec_from_workload(W.plain_small().with_(n_steps=2, track_moments=1)))
+    for p in range(4):
+        h.sweep_step(1, p, stats=False)
+    with pytest.raises(H.HwwError) as e:
+        h.solve_losm(implicit=False, closure_track=1)
+    assert e.value.code == -1
+    h.close()
+
+
 def test_fourier_filtered_end_to_end():
     # Fourier low pass (kappa = 30 of 200 cells) on the closures and the
     # initial condition of every solve.

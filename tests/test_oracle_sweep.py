@@ -13,7 +13,7 @@ from paper_2512_19925_amd import workloads as W
 def _sim(w, **kw):
     return O.OracleSim(w.edges, w.sigma_t, w.sigma_s, w.speed, w.dt, w.n_steps, w.src_x, w.n_src,
                        w.capacity(), w.seed, w.replica, w.n_batches, w.n_chunks, sigma_f=w.sigma_f,
-                       nu_f=w.nu_f, **kw)
+                       nu_f=w.nu_f, track_moments=w.track_moments, **kw)
 
 
 def _opts(w):
@@ -260,3 +260,26 @@ def test_lagged_windows_are_the_previous_track_flux():
             np.testing.assert_allclose(sim.windows()[1], expect * w.rho, rtol=1e-13)
         for p in range(w.n_chunks):
             sim.sweep(n, p)
+
+
+@pytest.mark.parametrize("tm", [1, 2])
+def test_fewer_track_moments_change_nothing_else(tm):
+    # Scoring fewer track-length moments per segment (census closures need
+    # only phi) leaves every other tally, counter, bank and window as they
+    # are; the moments not scored read as zero.
+    w = W.plain_small().with_(n_src=3000, n_steps=4)
+    a, b = _sim(w), _sim(w.with_(track_moments=tm))
+    O.run(a, 3, _opts(w))
+    O.run(b, 3, _opts(w))
+    ta, ba = a.tallies()
+    tb, bb = b.tallies()
+    keep = [O.T_PHI, O.C_PHI, O.C_J, O.C_K] + ([O.T_K] if tm == 2 else [])
+    assert np.array_equal(ta[..., keep], tb[..., keep]) and np.array_equal(ba, bb)
+    assert not np.any(tb[..., O.T_J])
+    if tm == 1:
+        assert not np.any(tb[..., O.T_K])
+    assert a.counters() == b.counters()
+    np.testing.assert_array_equal(a.windows()[0], b.windows()[0])
+    if tm == 1:
+        with pytest.raises(O.OracleError):
+            b.solve_losm(O.LosmOpts(closure_track=1), implicit=False)
