@@ -57,6 +57,8 @@ enum : uint32_t {
   EVB_FISSION = 1024u
 };
 constexpr int kEventKinds = 11;
+constexpr uint32_t kRareEvents = EVB_LEAK | EVB_RR_SURVIVE | EVB_RR_KILL | EVB_SPLIT | EVB_START_SURVIVE |
+                                 EVB_START_SPLIT | EVB_FISSION;
 __device__ constexpr int kEventSlot[kEventKinds] = {C_CENSUS, C_LEAKS, C_CROSSINGS, C_SCATTERS, C_ABSORPTIONS,
                                                     C_RR_SURVIVE, C_RR_KILL, C_SPLITS, C_RR_SURVIVE, C_SPLITS,
                                                     C_FISSIONS};
@@ -262,12 +264,22 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
   uint32_t evb = 0u;  // EVB_* events not yet counted
   int out_buf = 0;
 
-  // Add the wave's pending events to the work-group counters (converged).
+  // Add the wave's pending events to the work-group counters (converged):
+  // the common kinds every pass, the rare ones behind a single ballot.
+  // Crossings are not counted here; every segment adds one to its cell's
+  // track counter, so they follow from the segment total at the end.
+  auto count_kind = [&](int q) {
+    const uint64_t m = __ballot(((evb >> q) & 1u) != 0u);
+    if (m != 0 && lane == 0) atomicAdd(&L.cnt[kEventSlot[q]], (uint32_t)__popcll(m));
+  };
   auto count_events = [&]() {
+    count_kind(0);  // census
+    count_kind(3);  // scatter
+    count_kind(4);  // absorption
+    if (__ballot((evb & kRareEvents) != 0u) != 0) {
+      count_kind(1);
 #pragma unroll
-    for (int q = 0; q < kEventKinds; ++q) {
-      const uint64_t m = __ballot(((evb >> q) & 1u) != 0u);
-      if (m != 0 && lane == 0) atomicAdd(&L.cnt[kEventSlot[q]], (uint32_t)__popcll(m));
+      for (int q = 5; q < kEventKinds; ++q) count_kind(q);
     }
     evb = 0u;
   };
@@ -548,7 +560,6 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
             } else {
               if (mu > (Real)0) { x = xr; cell = i + 1; }
               else { x = xl; cell = i - 1; }
-              evb |= EVB_CROSS;
               act = classify();
               if (act == WW_ROULETTE) act |= EV_DRAW;
             }
@@ -639,12 +650,20 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
     ++gen;
   }
 
-  // Every segment ends in exactly one of census, leak, crossing or collision
-  // (scatter, fission or absorption).
+  // Segments: the sum of the per-cell track counters.  Every segment ends
+  // in exactly one of census, leak, crossing or collision (scatter, fission
+  // or absorption), which gives the crossings.
+  __syncthreads();
+  {
+    uint32_t part = 0;
+    for (int j = tid; j < I; j += blockDim.x) part += L.trk[j];
+    for (int o = 32; o >= 1; o >>= 1) part += __shfl_xor(part, o);
+    if ((tid & 63) == 0 && part != 0) atomicAdd(&L.cnt[C_SEGMENTS], part);
+  }
   __syncthreads();
   if (tid == 0) {
     L.cnt[C_COLLISIONS] = L.cnt[C_SCATTERS] + L.cnt[C_ABSORPTIONS] + L.cnt[C_FISSIONS];
-    L.cnt[C_SEGMENTS] = L.cnt[C_CENSUS] + L.cnt[C_LEAKS] + L.cnt[C_CROSSINGS] + L.cnt[C_COLLISIONS];
+    L.cnt[C_CROSSINGS] = L.cnt[C_SEGMENTS] - L.cnt[C_CENSUS] - L.cnt[C_LEAKS] - L.cnt[C_COLLISIONS];
   }
   __syncthreads();
   if (tid < nc) {
