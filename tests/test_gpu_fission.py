@@ -110,3 +110,87 @@ def test_comb_errors():
     with pytest.raises(H.HwwError) as e:       # batches take no fission
         H.Batch([H.spec_from_workload(W.paper_fission(n_src=500))])
     assert e.value.code == -1
+
+
+def _comb_by_definition(bank, n_target, step, seed, replica, B, nc):
+    """The comb from its definition, on the host: canonical order, integer
+    weights in units of 2^eu, prefix sums, teeth (k + xi) W / n_target.
+    Returns (x, mu, cell) of each copy and the copy weight."""
+    from oracle import oracle as O
+    order = np.lexsort((bank["e"], bank["lin"], bank["src"]))
+    w = bank["w"][order]
+    n = len(w)
+    em = int(np.frexp(w.max())[1])
+    ln = int(np.ceil(np.log2(n))) if n > 1 else 0
+    eu = em + ln - 53
+    wi = np.rint(np.ldexp(w, -eu)).astype(np.uint64)
+    q = np.cumsum(wi, dtype=np.uint64)
+    W = float(q[-1])
+    r = O.philox4x32_10([step, 0, 0, 0], [seed, (replica << 4) | 7])
+    xi = O.u53(r[0], r[1])
+    delta = W / float(n_target)
+    t = (np.arange(n_target, dtype=np.float64) + xi) * delta
+    t = np.where(t >= W, W - 1.0, t)
+    j = np.searchsorted(q.astype(np.float64), t, side="right")
+    par = order[j]
+    return bank["x"][par], bank["mu"][par], bank["cell"][par], np.ldexp(W, eu) / n_target
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_comb_matches_its_definition(precision):
+    # The device comb against the comb written out on the host from the
+    # census it combs (FP32 banks included): every copy k, its weight, its
+    # identity and its chunk.
+    need_gpu()
+    w = W.paper_fission(n_src=5000).with_(n_steps=4, n_batches=16)
+    prec = H.HWW_FP32 if precision == "fp32" else H.HWW_FP64
+    h = H.Handle(H.spec_from_workload(w, precision=prec))
+    kw = H.losm_kwargs(w)
+    for n in (1, 2):
+        if n > 1:
+            h.comb(w.comb)
+        h.solve_losm(implicit=False, **kw)
+        for p in range(w.n_chunks):
+            h.sweep_step(n, p, stats=False)
+            if p < w.n_chunks - 1:
+                h.solve_losm(implicit=True, **kw)
+    census = h.read_bank(1)
+    for H_t in (3000, 12345):             # fewer and more copies than particles
+        before = {k: v.copy() for k, v in census.items()}
+        n_b, W_tot = h.comb(H_t)
+        assert n_b == len(before["w"])
+        x, mu, cell, w_out = _comb_by_definition(before, H_t, 2, w.seed, w.replica, w.n_batches, w.n_chunks)
+        after = h.read_bank(1)
+        o = np.argsort(after["src"])
+        after = {k: v[o] for k, v in after.items()}
+        assert np.array_equal(after["src"], np.arange(H_t, dtype=np.uint32))
+        assert np.all(after["lin"] == 2) and np.all(after["e"] == 0)
+        assert np.array_equal(after["chunk"], (np.arange(H_t) // w.n_batches) % w.n_chunks)
+        assert np.all(after["w"] == w_out) and abs(W_tot - w_out * H_t) <= 1e-12 * W_tot
+        assert np.array_equal(after["x"], x) and np.array_equal(after["mu"], mu)
+        assert np.array_equal(after["cell"], cell)
+        census = after  # the second comb combs the combed bank
+    h.close()
+
+
+def test_comb_of_an_empty_census():
+    # A pure absorber of 100 mean free paths per step: nothing reaches the
+    # census (survival e^-100), the comb finds nothing, the census stays
+    # empty and the next step sweeps nothing, as in the oracle.
+    need_gpu()
+    st = np.ones(10)
+    w = W.Workload(name="absorb-all", x_lo=-0.5, x_hi=0.5, n_cells=10, sigma_t=st * 100.0, sigma_s=st * 0.0,
+                   sigma_f=st * 0.0, nu_f=2.0, speed=1.0, dt=1.0, n_steps=3, n_src=500, comb=500,
+                   bank_capacity=20000, n_batches=4)
+    h = H.Handle(H.spec_from_workload(w))
+    sim = oracle_sim(w)
+    for p in range(w.n_chunks):
+        h.sweep_step(1, p, stats=False)
+        sim.sweep(1, p)
+    assert h.comb(500) == (0, 0.0) == sim.comb(500)
+    assert len(h.read_bank(1)["w"]) == 0
+    for p in range(w.n_chunks):
+        st_g = h.sweep_step(2, p)
+        sim.sweep(2, p)
+    assert st_g["segments"] == 0 == sim.counters()["segments"]
+    h.close()
