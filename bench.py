@@ -415,6 +415,42 @@ def run_paper_problem(seeds=5, window_scale=1):
     return out
 
 
+def _oracle_replica(args):
+    """One process of the aggregate CPU figure: the bounded oracle sample of
+    cpu_baseline with its own replica key."""
+    w, n, k, budget_s = args
+    from oracle import oracle as O
+    ws = w.with_(n_src=n, bank_capacity=4 * n + 4096, replica=k)
+    sim = O.OracleSim(ws.edges, ws.sigma_t, ws.sigma_s, ws.speed, ws.dt, ws.n_steps, ws.src_x, ws.n_src,
+                      ws.capacity(), ws.seed, ws.replica, ws.n_batches, ws.n_chunks)
+    opts = O.LosmOpts(theta=ws.theta, filter=ws.filter, ma_k=ws.ma_k, eps_min=ws.eps_min, rho=ws.rho)
+    seg, t0 = 0, time.perf_counter()
+    for step in range(1, ws.n_steps + 1):
+        sim.solve_losm(opts, implicit=False)
+        for p in range(ws.n_chunks):
+            sim.sweep(step, p)
+            if p < ws.n_chunks - 1:
+                sim.solve_losm(opts, implicit=True)
+        seg += sim.counters()["segments"]
+        if time.perf_counter() - t0 > budget_s:
+            break
+    return seg, time.perf_counter() - t0
+
+
+def cpu_aggregate(w, budget_s, procs=None):
+    """The oracle in P independent processes at once, each the bounded
+    sample of cpu_baseline under its own replica key, P = the host's CPU
+    count (at most 16): summed segments/s."""
+    import multiprocessing as mp
+    P = procs or min(os.cpu_count() or 1, 16)
+    n = max(w.n_src // 4, 1000)
+    with mp.get_context("spawn").Pool(P) as pool:
+        res = pool.map(_oracle_replica, [(w, n, k, budget_s) for k in range(P)])
+    return {"value": sum(s / t for s, t in res), "unit": "segments/s", "processes": P,
+            "sample": f"{P} processes at once, each the single-core sample under replica key k = 0..{P - 1}, "
+                      f"about {budget_s:.0f} s each"}
+
+
 def cpu_baseline(w, budget_s):
     """The oracle, as it stands, on a bounded sample: the same problem with
     fewer source particles, as many steps as fit in about budget_s."""
@@ -522,6 +558,7 @@ def main():
                                  "windows_as_printed": run_paper_problem(window_scale=1)}
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+        line["cpu_baseline"]["aggregate"] = cpu_aggregate(w, args.cpu_seconds)
     if args.out:
         with open(args.out, "w") as f:
             json.dump({"hww": hww, "timed": tim, "line": line}, f, default=float)
