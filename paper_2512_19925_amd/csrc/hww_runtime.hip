@@ -22,7 +22,7 @@ constexpr double kSegSlack = 2.0;   // segment capacity / fair share of a work-g
 constexpr double kOvfShare = 0.5;   // overflow capacity / fair share of a region
 constexpr int kBlock = 512;         // threads per sweep work-group (default; see hww_autotune)
 constexpr int kTile = 256;          // particles a wave claims per tile (default)
-constexpr int64_t kUnitParticles = 2048;  // start particles per batched work unit and launch
+constexpr int64_t kUnitParticles = 8192;  // start particles per batched work unit and launch
 constexpr int kGridMax = 1024;      // work-groups of a batched launch at most
 
 struct Layout {
