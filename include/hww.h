@@ -229,8 +229,9 @@ int hww_losm_adjoint(hww_handle *h, double *grad_sigma_t, double *grad_sigma_s);
 int hww_read_tallies(hww_handle *h, int32_t kind, void *out, int64_t out_bytes);
 
 /* Copy one bank to host memory (for checks): which = 0 start bank of the
- * current step, 1 census bank.  Arrays hold up to `cap` particles; *count
- * receives the number of particles.  Any array pointer may be NULL. */
+ * current step, 1 census bank.  After hww_comb, 1 is the combed bank and 0
+ * the census as it was before the comb.  Arrays hold up to `cap` particles;
+ * *count receives the number of particles.  Any array pointer may be NULL. */
 int hww_read_bank(hww_handle *h, int32_t which, int64_t cap, int64_t *count, double *x, double *mu,
                   double *w, uint32_t *src, uint64_t *lin, uint32_t *e, int32_t *cell, int32_t *chunk);
 
