@@ -73,3 +73,30 @@ def test_batch_workspace_bytes_and_validation():
     bad[3].n_batches = 0
     assert _batch_bytes(bad) == -1
     assert _batch_bytes([]) == -1
+
+
+def test_fission_comb_and_tally_options_validation():
+    w = W.paper_fission(n_src=2000)
+    base = H.workspace_bytes(H.spec_from_workload(w))
+    plain = H.workspace_bytes(H.spec_from_workload(w.with_(comb=0)))
+    assert base > plain      # the comb's scratch and the wider daughter buffers
+    bad = [
+        dict(sigma_f=w.sigma_t * 0.9),                 # sigma_s + sigma_f > sigma_t
+        dict(sigma_f=-w.sigma_f),                      # negative fission cross section
+        dict(nu_f=-1.0), dict(nu_f=float("nan")),
+        dict(comb=2), dict(track_moments=4), dict(track_moments=-1),
+    ]
+    for kw in bad:
+        spec = H.spec_from_workload(w)
+        for k, v in kw.items():
+            setattr(spec, k, v)
+        with pytest.raises(H.HwwError) as ei:
+            H.workspace_bytes(spec)
+        assert ei.value.code == -1
+    # Batches take neither fission nor combing.
+    ws = W.batched_replicas(n_replicas=4)
+    specs = [H.spec_from_workload(x) for x in ws]
+    specs[2] = H.spec_from_workload(ws[2].with_(sigma_f=ws[2].sigma_t * 0.01, nu_f=2.0))
+    assert _batch_bytes(specs) == -1
+    specs[2] = H.spec_from_workload(ws[2].with_(comb=100))
+    assert _batch_bytes(specs) == -1
