@@ -101,6 +101,16 @@ def test_track_closures_need_k():
     h.close()
 
 
+def test_large_mesh_fallback_paths():
+    # 3000 cells: the cell records no longer fit in LDS beside the histogram
+    # (global-memory flights), the LOSM working arrays (6 x 3002 doubles
+    # beside 6003 unknowns) leave LDS, and each thread has more substitution
+    # rows (6) than it keeps in registers (4).
+    w = W.homogeneous("large-mesh-3000c", -30.0, 30.0, 3000, 1.0, 0.9, dt=0.1, n_steps=5, n_src=6000,
+                      rho=5.0, filter=1, ma_k=3)
+    _run_pair(w)
+
+
 def test_fourier_filtered_end_to_end():
     # Fourier low pass (kappa = 30 of 200 cells) on the closures and the
     # initial condition of every solve.
