@@ -116,6 +116,7 @@ struct ReplicaDesc {
   const CellData<Real> *cells;
   const Window *win;
   int32_t track_moments;
+  int32_t cells_lds;   // the replica's cell records fit in LDS beside its histogram
   BankGeom geom;
   Bank<Real> bank[2];
   double *tal[2], *bnd[2];
@@ -258,7 +259,7 @@ template <typename Real>
 hipError_t launch_source(const SourceArgs &a, const Bank<Real> &bank, int grid, int block, size_t lds,
                          hipStream_t s);
 template <typename Real>
-hipError_t launch_sweep_batch(const BatchSweepArgs<Real> &a, bool cells_lds, int grid, int block, size_t lds,
+hipError_t launch_sweep_batch(const BatchSweepArgs<Real> &a, int cells_mode, int grid, int block, size_t lds,
                               hipStream_t s);
 hipError_t launch_losm(const LosmArgs &a, hipStream_t s);
 hipError_t launch_losm_batch(const LosmReplica *tab, int n, int max_I, const LosmCall &c, hipStream_t s);

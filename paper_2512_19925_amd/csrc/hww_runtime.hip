@@ -253,6 +253,7 @@ struct hww_handle {
   size_t lds = 0;
   int block = kBlock, tile = kTile, grid = 0;  // sweep launch shape (grid: batched launches)
   bool cells_lds = false;      // the sweep keeps the per-cell records in LDS
+  int cells_mode = 0;          // batches: 0 no replica, 1 every replica, 2 some keep cell records in LDS
   int is_view = 0;             // a replica of a batch, for reads only
   // Batch of replicas (is_batch): the replicas are handles of their own
   // whose small per-replica arrays live in shared arrays of the batch.
@@ -424,7 +425,7 @@ int launch_chunk(hww_handle *h, int chunk, int k) {
     a.dcap = h->bdcap;
     a.err = h->err;
     ++h->tal_epoch[h->cur_tal];
-    HIPCHK(h, launch_sweep_batch<Real>(a, h->cells_lds, h->grid, h->block, h->lds, h->stream));
+    HIPCHK(h, launch_sweep_batch<Real>(a, h->cells_mode, h->grid, h->block, h->lds, h->stream));
     return HWW_OK;
   }
   SweepArgs<Real> a = base_args<Real>(h);
@@ -644,6 +645,13 @@ int make_batch_layout(const hww_problem *probs, int n, BatchLayout *BL, std::str
   return HWW_OK;
 }
 
+size_t replica_cell_bytes(const hww_handle *r) {
+  return r->fp32 ? lds_cell_bytes<float>() : lds_cell_bytes<double>();
+}
+bool replica_cells_lds(const hww_handle *r) {
+  return sweep_lds_bytes(r->I, r->nc, r->K, replica_cell_bytes(r)) <= kLdsBytes;
+}
+
 template <typename Real>
 ReplicaDesc<Real> replica_desc(hww_handle *r) {
   ReplicaDesc<Real> d{};
@@ -652,6 +660,7 @@ ReplicaDesc<Real> replica_desc(hww_handle *r) {
   d.seed = r->p.seed; d.key1 = r->p.replica << 4;
   d.win = r->win;
   d.track_moments = r->track_moments;
+  d.cells_lds = replica_cells_lds(r) ? 1 : 0;
   d.geom = r->L.geom;
   for (int k = 0; k < 2; ++k) {
     if constexpr (sizeof(Real) == 8) d.bank[k] = r->bank[k];
@@ -1401,9 +1410,19 @@ int hww_init_batch(const hww_problem *problems, int32_t n, void *dev_workspace, 
   h->max_I = BL.max_I;
   h->max_K = BL.max_K;
   {
+    // Each replica keeps its cell records in LDS when they fit beside its
+    // histogram; the launch's LDS holds the largest need.
+    h->lds = 0;
+    int fit = 0;
     const size_t cb = h->fp32 ? lds_cell_bytes<float>() : lds_cell_bytes<double>();
-    h->cells_lds = sweep_lds_bytes(BL.max_I, h->nc, BL.max_K, cb) <= kLdsBytes;
-    h->lds = sweep_lds_bytes(BL.max_I, h->nc, BL.max_K, h->cells_lds ? cb : 0);
+    for (int r = 0; r < n; ++r) {
+      const int I = problems[r].n_cells, K = BL.L[r].geom.K;
+      const bool f = sweep_lds_bytes(I, h->nc, K, cb) <= kLdsBytes;
+      fit += f ? 1 : 0;
+      h->lds = std::max(h->lds, sweep_lds_bytes(I, h->nc, K, f ? cb : 0));
+    }
+    h->cells_mode = fit == 0 ? 0 : (fit == n ? 1 : 2);
+    h->cells_lds = fit > 0;
     // One work-group per compute unit when the LDS allows no more: make it wide.
     h->block = h->lds > kLdsBytes / 2 ? 1024 : kBlock;
   }

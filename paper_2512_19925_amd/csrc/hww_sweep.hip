@@ -696,8 +696,10 @@ __global__ void __launch_bounds__(1024) sweep_kernel(SweepArgs<Real> A) {
 // Many problems (replicas) in one persistent launch: each work-group claims
 // units from the launch's counter until none is left.  The unit table lists
 // the biggest replicas first and the units of one batch next to each other,
-// so the units that share a batch's tiles run at the same time.
-template <typename Real, bool kCellsLds>
+// so the units that share a batch's tiles run at the same time.  kCells:
+// 0 no replica keeps its cell records in LDS, 1 all do, 2 each as its
+// descriptor says (the launch's LDS holds the largest need).
+template <typename Real, int kCells>
 __global__ void __launch_bounds__(1024) sweep_batch_kernel(BatchSweepArgs<Real> P,
                                                            const ReplicaDesc<Real> *__restrict__ desc,
                                                            const uint32_t *__restrict__ units) {
@@ -730,7 +732,10 @@ __global__ void __launch_bounds__(1024) sweep_batch_kernel(BatchSweepArgs<Real> 
     A.tal = D.tal[P.start_bank]; A.bnd = D.bnd[P.start_bank];
     A.tracks = D.tracks; A.counters = D.counters; A.wnext = D.wnext;
     A.err = P.err;
-    sweep_unit<Real, kCellsLds, false>(A, b, jseg, (int)blockIdx.x, (int)gridDim.x, lds_raw);
+    if (kCells == 1 || (kCells == 2 && D.cells_lds))
+      sweep_unit<Real, true, false>(A, b, jseg, (int)blockIdx.x, (int)gridDim.x, lds_raw);
+    else
+      sweep_unit<Real, false, false>(A, b, jseg, (int)blockIdx.x, (int)gridDim.x, lds_raw);
     __syncthreads();
   }
 }
@@ -864,22 +869,25 @@ hipError_t launch_source(const SourceArgs &a, const Bank<Real> &bank, int grid, 
 }
 
 template <typename Real>
-hipError_t launch_sweep_batch(const BatchSweepArgs<Real> &a, bool cells_lds, int grid, int block, size_t lds,
+hipError_t launch_sweep_batch(const BatchSweepArgs<Real> &a, int cells_mode, int grid, int block, size_t lds,
                               hipStream_t s) {
-  static size_t done[2] = {64 * 1024, 64 * 1024};
-  const void *fn = cells_lds ? reinterpret_cast<const void *>(&sweep_batch_kernel<Real, true>)
-                             : reinterpret_cast<const void *>(&sweep_batch_kernel<Real, false>);
-  hipError_t e = allow_lds(fn, lds, &done[cells_lds ? 1 : 0]);
+  static size_t done[3] = {64 * 1024, 64 * 1024, 64 * 1024};
+  const void *fn = cells_mode == 1   ? reinterpret_cast<const void *>(&sweep_batch_kernel<Real, 1>)
+                   : cells_mode == 2 ? reinterpret_cast<const void *>(&sweep_batch_kernel<Real, 2>)
+                                     : reinterpret_cast<const void *>(&sweep_batch_kernel<Real, 0>);
+  hipError_t e = allow_lds(fn, lds, &done[cells_mode]);
   if (e != hipSuccess) return e;
-  if (cells_lds)
-    hipLaunchKernelGGL((sweep_batch_kernel<Real, true>), dim3(grid), dim3(block), lds, s, a, a.desc, a.units);
+  if (cells_mode == 1)
+    hipLaunchKernelGGL((sweep_batch_kernel<Real, 1>), dim3(grid), dim3(block), lds, s, a, a.desc, a.units);
+  else if (cells_mode == 2)
+    hipLaunchKernelGGL((sweep_batch_kernel<Real, 2>), dim3(grid), dim3(block), lds, s, a, a.desc, a.units);
   else
-    hipLaunchKernelGGL((sweep_batch_kernel<Real, false>), dim3(grid), dim3(block), lds, s, a, a.desc, a.units);
+    hipLaunchKernelGGL((sweep_batch_kernel<Real, 0>), dim3(grid), dim3(block), lds, s, a, a.desc, a.units);
   return hipGetLastError();
 }
 
-template hipError_t launch_sweep_batch<double>(const BatchSweepArgs<double> &, bool, int, int, size_t, hipStream_t);
-template hipError_t launch_sweep_batch<float>(const BatchSweepArgs<float> &, bool, int, int, size_t, hipStream_t);
+template hipError_t launch_sweep_batch<double>(const BatchSweepArgs<double> &, int, int, int, size_t, hipStream_t);
+template hipError_t launch_sweep_batch<float>(const BatchSweepArgs<float> &, int, int, int, size_t, hipStream_t);
 template hipError_t launch_sweep<double>(const SweepArgs<double> &, bool, int, int, size_t, hipStream_t);
 template hipError_t launch_sweep<float>(const SweepArgs<float> &, bool, int, int, size_t, hipStream_t);
 template hipError_t launch_source<double>(const SourceArgs &, const Bank<double> &, int, int, size_t, hipStream_t);
