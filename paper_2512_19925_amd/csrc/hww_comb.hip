@@ -11,6 +11,8 @@
 // (count * max weight < 2^(53 + eu)), so the inclusive prefix sums are exact
 // and identical in any summation order, and each tooth finds its particle
 // by binary search over them.
+#include <algorithm>
+
 #include "hww_internal.h"
 #include "hww_rng_dev.h"
 
@@ -23,38 +25,39 @@ constexpr int kScanPer = 4;                        // elements per thread in a s
 constexpr int kScanTile = kScanThreads * kScanPer;
 constexpr int kSmallBin = 48;                      // histories sorted by one lane up to this size
 
-// Census slot q of the bank: valid when inside its segment's count.
-template <typename Real>
-__device__ inline bool census_slot(const CombArgs<Real> &A, int64_t q) {
+// The occupied slots of the census bank: each work-group takes whole
+// segments (K per region plus the overflow segment) and its threads the
+// slots below the segment's count, so the walk costs the census, not the
+// bank's capacity.  f(q) is called for every occupied slot q.
+template <typename Real, typename F>
+__device__ inline void for_each_census_slot(const CombArgs<Real> &A, F &&f) {
   const BankGeom &G = A.G;
-  const int64_t r = q / G.stride, o = q - r * G.stride;
-  if (o < (int64_t)G.K * G.seg_cap) {
-    const int64_t s = o / G.seg_cap, i = o - s * G.seg_cap;
-    const int64_t n = min((int64_t)A.src_bank.segcnt[r * G.K + s], G.seg_cap);
-    return i < n;
+  const int64_t nseg = (int64_t)A.R * (G.K + 1);
+  for (int64_t sg = blockIdx.x; sg < nseg; sg += gridDim.x) {
+    const int64_t r = sg / (G.K + 1), sidx = sg - r * (G.K + 1);
+    const int64_t n = sidx < G.K ? min((int64_t)A.src_bank.segcnt[r * G.K + sidx], G.seg_cap)
+                                 : min((int64_t)A.src_bank.ovfcnt[r], G.ovf_cap);
+    const int64_t base = r * G.stride + sidx * G.seg_cap;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) f(base + i);
   }
-  const int64_t i = o - (int64_t)G.K * G.seg_cap;
-  return i < min((int64_t)A.src_bank.ovfcnt[r], G.ovf_cap);
 }
 
 // Histogram by history, census count and largest weight (positive doubles
 // order like their bit patterns).
 template <typename Real>
 __global__ void comb_count_kernel(CombArgs<Real> A) {
-  const int64_t slots = (int64_t)A.R * A.G.stride;
   unsigned long long mx = 0, n = 0;
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < slots; q += (int64_t)gridDim.x * blockDim.x) {
-    if (!census_slot(A, q)) continue;
+  for_each_census_slot(A, [&](int64_t q) {
     const uint32_t src = A.src_bank.tag[q].src;
     if ((int64_t)src >= A.n_hist) {
       atomicOr(A.err, ERR_CAPACITY);
-      continue;
+      return;
     }
     atomicAdd(&A.cnt[src], 1ull);
     const unsigned long long wb = (unsigned long long)__double_as_longlong(A.src_bank.w[q]);
     mx = wb > mx ? wb : mx;
     ++n;
-  }
+  });
   for (int o = 32; o >= 1; o >>= 1) {
     const unsigned long long t = __shfl_xor(mx, o);
     mx = t > mx ? t : mx;
@@ -140,14 +143,12 @@ __global__ void __launch_bounds__(kScanThreads) scan_add_kernel(unsigned long lo
 // Each census particle takes the next place of its history's range.
 template <typename Real>
 __global__ void comb_scatter_kernel(CombArgs<Real> A) {
-  const int64_t slots = (int64_t)A.R * A.G.stride;
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < slots; q += (int64_t)gridDim.x * blockDim.x) {
-    if (!census_slot(A, q)) continue;
+  for_each_census_slot(A, [&](int64_t q) {
     const uint32_t src = A.src_bank.tag[q].src;
-    if ((int64_t)src >= A.n_hist) continue;
+    if ((int64_t)src >= A.n_hist) return;
     const unsigned long long pos = A.cnt[src] + atomicAdd(&A.cur[src], 1u);
     A.order[pos] = (unsigned long long)q;
-  }
+  });
 }
 
 template <typename Real>
@@ -356,17 +357,17 @@ int64_t comb_scan_blocks(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1
 
 template <typename Real>
 hipError_t launch_comb_count(const CombArgs<Real> &a, hipStream_t s) {
-  const int64_t slots = (int64_t)a.R * a.G.stride;
-  hipLaunchKernelGGL(comb_count_kernel<Real>, dim3(grid_for(slots, 256)), dim3(256), 0, s, a);
+  const int64_t nseg = (int64_t)a.R * (a.G.K + 1);
+  hipLaunchKernelGGL(comb_count_kernel<Real>, dim3((unsigned)std::min<int64_t>(nseg, 8192)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
 template <typename Real>
 hipError_t launch_comb_rest(const CombArgs<Real> &a, int64_t n, int eu, hipStream_t s) {
-  const int64_t slots = (int64_t)a.R * a.G.stride;
+  const int64_t nseg = (int64_t)a.R * (a.G.K + 1);
   hipError_t e = scan(a.cnt, a.n_hist + 1, a.blk, 0, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(comb_scatter_kernel<Real>, dim3(grid_for(slots, 256)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(comb_scatter_kernel<Real>, dim3((unsigned)std::min<int64_t>(nseg, 8192)), dim3(256), 0, s, a);
   hipLaunchKernelGGL(comb_sort_small_kernel<Real>, dim3(grid_for(a.n_hist, 256)), dim3(256), 0, s, a);
   hipLaunchKernelGGL(comb_sort_big_kernel<Real>, dim3(256), dim3(1024), 0, s, a);
   hipLaunchKernelGGL(comb_weights_kernel<Real>, dim3(grid_for(n, 256)), dim3(256), 0, s, a, n, eu);

@@ -236,6 +236,7 @@ struct hww_handle {
   int32_t *status;
   double *scratch, *factor, *phi_out, *J_out;
   double *cfis = nullptr;  // (sigma_s + sigma_f) / sigma_t, fission problems only
+  int64_t src_bound = 0;   // history ids of the start and census banks are below this
   double nu_f = 0.0;
   int track_moments = 3;   // track-length moments scored per segment
 
@@ -448,6 +449,7 @@ void carve_handle(hww_handle *h, const hww_problem &problem, char *ws, const Lay
   h->p.edges = h->p.sigma_t = h->p.sigma_s = h->p.sigma_f = nullptr;
   h->cfis = problem.sigma_f ? reinterpret_cast<double *>(ws + L.off_cfis) : nullptr;
   h->nu_f = problem.sigma_f ? problem.nu_f : 0.0;
+  h->src_bound = problem.n_src;
   h->track_moments = problem.track_moments == 0 ? 3 : problem.track_moments;
   h->I = problem.n_cells;
   h->B = problem.n_batches;
@@ -966,7 +968,7 @@ int hww_comb(hww_handle *h, int64_t n_target, int64_t *n_before, double *w_total
   auto fill = [&](CombArgs<double> &a) {
     a.G = G;
     a.B = h->B; a.nc = h->nc; a.R = h->R;
-    a.n_hist = L.n_hist;
+    a.n_hist = h->src_bound;
     a.cap = L.comb_slots;
     a.n_target = n_target;
     a.seed = h->p.seed; a.key1 = h->p.replica << 4; a.step = (uint32_t)h->step;
@@ -992,8 +994,8 @@ int hww_comb(hww_handle *h, int64_t n_target, int64_t *n_before, double *w_total
     a32.cnt = a.cnt; a32.cur = a.cur; a32.order = a.order; a32.wq = a.wq; a32.blk = a.blk; a32.misc = a.misc;
     a32.wnext = a.wnext; a32.err = a.err;
   }
-  HIPCHK(h, launch_fill_u32(reinterpret_cast<uint32_t *>(a.cnt), 0u, 2 * (L.n_hist + 1), h->stream));
-  HIPCHK(h, launch_fill_u32(a.cur, 0u, L.n_hist, h->stream));
+  HIPCHK(h, launch_fill_u32(reinterpret_cast<uint32_t *>(a.cnt), 0u, 2 * (a.n_hist + 1), h->stream));
+  HIPCHK(h, launch_fill_u32(a.cur, 0u, a.n_hist, h->stream));
   HIPCHK(h, launch_fill_u32(reinterpret_cast<uint32_t *>(a.misc), 0u, 16, h->stream));
   HIPCHK(h, h->fp32 ? launch_comb_count<float>(a32, h->stream) : launch_comb_count<double>(a, h->stream));
   unsigned long long misc[8];
@@ -1017,8 +1019,9 @@ int hww_comb(hww_handle *h, int64_t n_target, int64_t *n_before, double *w_total
   HIPCHK(h, h->fp32 ? launch_comb_rest<float>(a32, n, eu, h->stream) : launch_comb_rest<double>(a, n, eu, h->stream));
   HIPCHK(h, hipMemcpyAsync(misc, a.misc, sizeof misc, hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
-  // The combed bank becomes the census bank.
+  // The combed bank becomes the census bank; its histories are 0..n_target-1.
   h->start_bank = 1 - h->start_bank;
+  h->src_bound = std::max<int64_t>(h->src_bound, n_target);
   rc = poll_errors(h);
   if (rc != HWW_OK) return rc;
   if (w_total) std::memcpy(w_total, &misc[2], 8);
