@@ -5,12 +5,14 @@
 // particles that are copied, at weight W / n_target.
 //
 // Order on the device: a counting sort by src (histogram, exclusive scan,
-// scatter), then each history's particles sorted by (lineage, event): one
-// lane per history when it has few, one work-group ranking by comparison
-// counts when it has many.  Weights become integers in units of 2^eu
-// (count * max weight < 2^(53 + eu)), so the inclusive prefix sums are exact
-// and identical in any summation order, and each tooth finds its particle
-// by binary search over them.
+// scatter), then each history's particles ranked by (lineage, event): one
+// lane per particle comparing its key with the rest of its history when the
+// history has few, one work-group ranking through LDS tiles when it has many.
+// Weights become integers in units of 2^eu (count * max weight < 2^(53 +
+// eu)), so the inclusive prefix sums are exact and identical in any
+// summation order, and each tooth finds its particle by binary search over
+// them.  The census count and eu are read on the device, so the whole comb
+// is one sequence of launches with one wait at its end.
 #include <algorithm>
 
 #include "hww_internal.h"
@@ -23,29 +25,63 @@ namespace {
 constexpr int kScanThreads = 1024;
 constexpr int kScanPer = 4;                        // elements per thread in a scan tile
 constexpr int kScanTile = kScanThreads * kScanPer;
-constexpr int kSmallBin = 48;                      // histories sorted by one lane up to this size
+constexpr int kSmallBin = 64;                      // histories ranked lane by lane up to this size
 
-// The occupied slots of the census bank: each work-group takes whole
-// segments (K per region plus the overflow segment) and its threads the
-// slots below the segment's count, so the walk costs the census, not the
-// bank's capacity.  f(q) is called for every occupied slot q.
+// The occupied slots of the census bank: each wavefront takes whole
+// segments (K per region plus the overflow segment) and its lanes the slots
+// below the segment's count, so the walk costs the census, not the bank's
+// capacity.  f(q) is called for every occupied slot q.
 template <typename Real, typename F>
 __device__ inline void for_each_census_slot(const CombArgs<Real> &A, F &&f) {
   const BankGeom &G = A.G;
   const int64_t nseg = (int64_t)A.R * (G.K + 1);
-  for (int64_t sg = blockIdx.x; sg < nseg; sg += gridDim.x) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nwave = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t sg = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; sg < nseg; sg += nwave) {
     const int64_t r = sg / (G.K + 1), sidx = sg - r * (G.K + 1);
     const int64_t n = sidx < G.K ? min((int64_t)A.src_bank.segcnt[r * G.K + sidx], G.seg_cap)
                                  : min((int64_t)A.src_bank.ovfcnt[r], G.ovf_cap);
     const int64_t base = r * G.stride + sidx * G.seg_cap;
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) f(base + i);
+    for (int64_t i = lane; i < n; i += 64) f(base + i);
   }
+}
+
+// Clears the history counts and cursors and the reduction cells.
+template <typename Real>
+__global__ void comb_clear_kernel(CombArgs<Real> A) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= A.n_hist; i += (int64_t)gridDim.x * blockDim.x) {
+    A.cnt[i] = 0ull;
+    if (i < A.n_hist) A.cur[i] = 0u;
+    if (i < 8) A.misc[i] = 0ull;
+  }
+}
+
+// Census count n, unit exponent eu and whether the largest weight is
+// positive and finite, from the reduction cells (misc[0] largest weight's
+// bits, misc[1] count): every kernel after the count derives them alike.
+struct CombScale {
+  int64_t n;
+  int eu;
+  bool ok;
+};
+__device__ inline CombScale comb_scale(const unsigned long long *misc) {
+  CombScale c;
+  c.n = (int64_t)misc[1];
+  const double m = __longlong_as_double((long long)misc[0]);
+  c.ok = c.n > 0 && m > 0.0 && m <= 1.7976931348623157e308;
+  int em = 0;
+  if (c.ok) frexp(m, &em);
+  int ln = 0;
+  while (((int64_t)1 << ln) < c.n) ++ln;
+  c.eu = em + ln - 53;
+  return c;
 }
 
 // Histogram by history, census count and largest weight (positive doubles
 // order like their bit patterns).
 template <typename Real>
-__global__ void comb_count_kernel(CombArgs<Real> A) {
+__global__ void __launch_bounds__(256) comb_count_kernel(CombArgs<Real> A) {
+  __shared__ unsigned long long red[2][4];
   unsigned long long mx = 0, n = 0;
   for_each_census_slot(A, [&](int64_t q) {
     const uint32_t src = A.src_bank.tag[q].src;
@@ -63,9 +99,21 @@ __global__ void comb_count_kernel(CombArgs<Real> A) {
     mx = t > mx ? t : mx;
     n += __shfl_xor(n, o);
   }
-  if ((threadIdx.x & 63) == 0 && n != 0) {
-    atomicMax(&A.misc[0], mx);
-    atomicAdd(&A.misc[1], n);
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[0][wv] = mx;
+    red[1][wv] = n;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < 4; ++k) {
+      mx = red[0][k] > mx ? red[0][k] : mx;
+      n += red[1][k];
+    }
+    if (n != 0) {
+      atomicMax(&A.misc[0], mx);
+      atomicAdd(&A.misc[1], n);
+    }
   }
 }
 
@@ -97,9 +145,21 @@ __device__ inline unsigned long long block_excl_scan(unsigned long long v, unsig
   return r;
 }
 
-__global__ void __launch_bounds__(kScanThreads) scan_tiles_kernel(unsigned long long *a, int64_t n,
+// The length is n, or the device value *n_dev when that is smaller (the
+// host launches tiles for the bound; the tiles past the end do nothing).
+__device__ inline int64_t scan_len(int64_t n, const unsigned long long *n_dev) {
+  return n_dev ? min(n, (int64_t)*n_dev) : n;
+}
+
+__global__ void __launch_bounds__(kScanThreads) scan_tiles_kernel(unsigned long long *a, int64_t n_bound,
+                                                                  const unsigned long long *n_dev,
                                                                   unsigned long long *blk, int inclusive) {
   __shared__ unsigned long long sh[48];
+  const int64_t n = scan_len(n_bound, n_dev);
+  if ((int64_t)blockIdx.x * kScanTile >= n) {
+    if (threadIdx.x == 0) blk[blockIdx.x] = 0ull;
+    return;
+  }
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
   unsigned long long v[kScanPer], s = 0;
 #pragma unroll
@@ -118,21 +178,27 @@ __global__ void __launch_bounds__(kScanThreads) scan_tiles_kernel(unsigned long 
   if (threadIdx.x == 0) blk[blockIdx.x] = total;
 }
 
-__global__ void __launch_bounds__(kScanThreads) scan_top_kernel(unsigned long long *blk, int64_t nb) {
+// One work-group scans a[0..n) a block of kScanThreads at a time, carrying
+// the running total: the top level of the tiled scan, and the whole scan of
+// a short array.
+__global__ void __launch_bounds__(kScanThreads) scan_one_kernel(unsigned long long *a, int64_t n, int inclusive) {
   __shared__ unsigned long long sh[48];
   unsigned long long carry = 0;
-  for (int64_t b0 = 0; b0 < nb; b0 += kScanThreads) {
+  for (int64_t b0 = 0; b0 < n; b0 += kScanThreads) {
     const int64_t i = b0 + threadIdx.x;
-    const unsigned long long v = i < nb ? blk[i] : 0ull;
+    const unsigned long long v = i < n ? a[i] : 0ull;
     unsigned long long total;
     const unsigned long long r = block_excl_scan(v, sh, &total);
-    if (i < nb) blk[i] = carry + r;
+    if (i < n) a[i] = carry + r + (inclusive ? v : 0ull);
     carry += total;
   }
 }
 
-__global__ void __launch_bounds__(kScanThreads) scan_add_kernel(unsigned long long *a, int64_t n,
+__global__ void __launch_bounds__(kScanThreads) scan_add_kernel(unsigned long long *a, int64_t n_bound,
+                                                                const unsigned long long *n_dev,
                                                                 const unsigned long long *blk) {
+  const int64_t n = scan_len(n_bound, n_dev);
+  if ((int64_t)blockIdx.x * kScanTile >= n) return;
   const unsigned long long off = blk[blockIdx.x];
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
 #pragma unroll
@@ -158,33 +224,43 @@ __device__ inline bool key_less(const CombArgs<Real> &A, unsigned long long qa, 
   return A.src_bank.tag[qa].e < A.src_bank.tag[qb].e;
 }
 
-// Histories with few particles: one lane each, insertion sort in place;
-// the others are listed (misc[4] counts them, their ids go to cur[]).
+// Canonical position of every census particle of a history with at most
+// kSmallBin particles: its history's start plus the number of the history's
+// particles of smaller (lineage, event), ties by current place.  The sorted
+// slot indices go to wq.  Longer histories are listed for the work-group
+// sort: misc[4] counts them, their ids go to cur[] (the cursors are free
+// again after the scatter).
 template <typename Real>
-__global__ void comb_sort_small_kernel(CombArgs<Real> A) {
-  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < A.n_hist; s += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t lo = (int64_t)A.cnt[s], hi = (int64_t)A.cnt[s + 1];
-    if (hi - lo <= 1) continue;
-    if (hi - lo > kSmallBin) {
-      const unsigned long long slot = atomicAdd(&A.misc[4], 1ull);
-      A.cur[slot] = (uint32_t)s;  // the cursors are free again after the scatter
+__global__ void comb_rank_small_kernel(CombArgs<Real> A) {
+  const CombScale c = comb_scale(A.misc);
+  if (!c.ok) return;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < c.n; p += (int64_t)gridDim.x * blockDim.x) {
+    const unsigned long long q = A.order[p];
+    const uint32_t s = A.src_bank.tag[q].src;
+    const int64_t lo = (int64_t)A.cnt[s], m = (int64_t)A.cnt[s + 1] - lo;
+    if (m > kSmallBin) {
+      if (p == lo) {
+        const unsigned long long slot = atomicAdd(&A.misc[4], 1ull);
+        A.cur[slot] = s;
+      }
       continue;
     }
-    for (int64_t i = lo + 1; i < hi; ++i) {
-      const unsigned long long qi = A.order[i];
-      int64_t j = i - 1;
-      while (j >= lo && key_less(A, qi, A.order[j])) {
-        A.order[j + 1] = A.order[j];
-        --j;
-      }
-      A.order[j + 1] = qi;
+    const uint64_t li = A.src_bank.lin[q];
+    const uint32_t ei = A.src_bank.tag[q].e;
+    int64_t rank = 0;
+    for (int64_t j = lo; j < lo + m; ++j) {
+      const unsigned long long qj = A.order[j];
+      const uint64_t lj = A.src_bank.lin[qj];
+      const uint32_t ej = A.src_bank.tag[qj].e;
+      rank += (lj < li || (lj == li && (ej < ei || (ej == ei && j < p)))) ? 1 : 0;
     }
+    A.wq[lo + rank] = q;
   }
 }
 
 // Histories with many particles: one work-group each; particle i goes to
 // place (number of particles of smaller key, ties by current place), keys
-// staged through LDS a tile at a time; the result goes through wq.
+// staged through LDS a tile at a time; the sorted slot indices go to wq.
 template <typename Real>
 __global__ void __launch_bounds__(1024) comb_sort_big_kernel(CombArgs<Real> A) {
   __shared__ uint64_t kl[1024];
@@ -224,17 +300,19 @@ __global__ void __launch_bounds__(1024) comb_sort_big_kernel(CombArgs<Real> A) {
       if (i < m) A.wq[lo + rank] = A.order[lo + i];
     }
     __syncthreads();
-    for (int64_t i = threadIdx.x; i < m; i += blockDim.x) A.order[lo + i] = A.wq[lo + i];
-    __syncthreads();
   }
 }
 
-// Integer weights in units of 2^eu, in canonical order.
+// The sorted slot indices move from wq to order, and wq takes the integer
+// weights in units of 2^eu, in canonical order.
 template <typename Real>
-__global__ void comb_weights_kernel(CombArgs<Real> A, int64_t n, int eu) {
-  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
-    const double w = A.src_bank.w[A.order[j]];
-    A.wq[j] = (unsigned long long)rint(ldexp(w, -eu));
+__global__ void comb_weights_kernel(CombArgs<Real> A) {
+  const CombScale c = comb_scale(A.misc);
+  if (!c.ok) return;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < c.n; j += (int64_t)gridDim.x * blockDim.x) {
+    const unsigned long long q = A.wq[j];
+    A.order[j] = q;
+    A.wq[j] = (unsigned long long)rint(ldexp(A.src_bank.w[q], -c.eu));
   }
 }
 
@@ -272,7 +350,11 @@ __device__ inline CombPlace comb_place(int64_t k, int64_t H, int B, int nc, cons
 
 // Tooth k: the first particle whose inclusive prefix exceeds (k + xi) delta.
 template <typename Real>
-__global__ void comb_teeth_kernel(CombArgs<Real> A, int64_t n, int eu) {
+__global__ void comb_teeth_kernel(CombArgs<Real> A) {
+  const CombScale c = comb_scale(A.misc);
+  if (!c.ok) return;
+  const int64_t n = c.n;
+  const int eu = c.eu;
   uint32_t r[4];
   draw(A.seed, A.key1, SLOT_COMB, A.step, 0ull, 0u, r);
   const double xi = u53(r[0], r[1]);
@@ -307,42 +389,52 @@ __global__ void comb_teeth_kernel(CombArgs<Real> A, int64_t n, int eu) {
 }
 
 // Segment counts of the new bank, chunk weights count * W / n_target and
-// the total weight W for the host (misc[2]).
+// the total weight W for the host (misc[2]).  One work-group: a thread per
+// segment, the chunk counts summed in LDS.
 template <typename Real>
-__global__ void comb_finish_kernel(CombArgs<Real> A, int64_t n, int eu) {
+__global__ void __launch_bounds__(1024) comb_finish_kernel(CombArgs<Real> A) {
+  __shared__ unsigned long long chunk[8];
+  const CombScale cs = comb_scale(A.misc);
+  if (!cs.ok) return;
   const BankGeom &G = A.G;
-  const double W = (double)A.wq[n - 1];
-  const double w_out = ldexp(W, eu) / (double)A.n_target;
-  for (int r = threadIdx.x; r < A.R; r += blockDim.x) {
+  if (threadIdx.x < 8) chunk[threadIdx.x] = 0ull;
+  __syncthreads();
+  const int64_t nseg = (int64_t)A.R * (G.K + 1);
+  for (int64_t t = threadIdx.x; t < nseg; t += blockDim.x) {
+    const int r = (int)(t / (G.K + 1)), s = (int)(t - (int64_t)r * (G.K + 1));
     const int b = r / A.nc, c = r % A.nc;
     int64_t n_bc;
     comb_region(A.n_target, A.B, A.nc, b, c, &n_bc);
     const int64_t per = min(G.seg_cap, (n_bc + G.K - 1) / G.K);
-    for (int s = 0; s < G.K; ++s) {
+    if (s < G.K) {
       const int64_t left = n_bc - (int64_t)s * per;
       A.dst_bank.segcnt[(int64_t)r * G.K + s] = (uint32_t)(left < 0 ? 0 : (left < per ? left : per));
+    } else {
+      const int64_t over = n_bc - (int64_t)G.K * per;
+      A.dst_bank.ovfcnt[r] = (uint32_t)(over > 0 ? over : 0);
+      atomicAdd(&chunk[c], (unsigned long long)n_bc);
     }
-    const int64_t over = n_bc - (int64_t)G.K * per;
-    A.dst_bank.ovfcnt[r] = (uint32_t)(over > 0 ? over : 0);
   }
-  if (threadIdx.x < (unsigned)A.nc) {
-    int64_t cnt = 0;
-    for (int b = 0; b < A.B; ++b) {
-      int64_t n_bc;
-      comb_region(A.n_target, A.B, A.nc, b, (int)threadIdx.x, &n_bc);
-      cnt += n_bc;
-    }
-    A.wnext[threadIdx.x] = (double)cnt * w_out;
-  }
-  if (threadIdx.x == 0) A.misc[2] = (unsigned long long)__double_as_longlong(ldexp(W, eu));
+  __syncthreads();
+  const double W = (double)A.wq[cs.n - 1];
+  const double w_out = ldexp(W, cs.eu) / (double)A.n_target;
+  if (threadIdx.x < (unsigned)A.nc) A.wnext[threadIdx.x] = (double)chunk[threadIdx.x] * w_out;
+  if (threadIdx.x == 0) A.misc[2] = (unsigned long long)__double_as_longlong(ldexp(W, cs.eu));
 }
 
-hipError_t scan(unsigned long long *a, int64_t n, unsigned long long *blk, int inclusive, hipStream_t s) {
+// Scan of a[0..n) (n bounded by *n_dev when given): one work-group for a
+// short array, else tiles, their totals, and the tile offsets added.
+hipError_t scan(unsigned long long *a, int64_t n, const unsigned long long *n_dev, unsigned long long *blk,
+                int inclusive, hipStream_t s) {
   const int64_t nb = (n + kScanTile - 1) / kScanTile;
   if (nb == 0) return hipSuccess;
-  hipLaunchKernelGGL(scan_tiles_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, a, n, blk, inclusive);
-  hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(kScanThreads), 0, s, blk, nb);
-  hipLaunchKernelGGL(scan_add_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, a, n, blk);
+  if (!n_dev && nb <= 4) {
+    hipLaunchKernelGGL(scan_one_kernel, dim3(1), dim3(kScanThreads), 0, s, a, n, inclusive);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(scan_tiles_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, a, n, n_dev, blk, inclusive);
+  hipLaunchKernelGGL(scan_one_kernel, dim3(1), dim3(kScanThreads), 0, s, blk, nb, 0);
+  hipLaunchKernelGGL(scan_add_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, a, n, n_dev, blk);
   return hipGetLastError();
 }
 
@@ -356,33 +448,28 @@ unsigned grid_for(int64_t n, int block) {
 int64_t comb_scan_blocks(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
 
 template <typename Real>
-hipError_t launch_comb_count(const CombArgs<Real> &a, hipStream_t s) {
+hipError_t launch_comb(const CombArgs<Real> &a, hipStream_t s) {
   const int64_t nseg = (int64_t)a.R * (a.G.K + 1);
-  hipLaunchKernelGGL(comb_count_kernel<Real>, dim3((unsigned)std::min<int64_t>(nseg, 8192)), dim3(256), 0, s, a);
-  return hipGetLastError();
-}
-
-template <typename Real>
-hipError_t launch_comb_rest(const CombArgs<Real> &a, int64_t n, int eu, hipStream_t s) {
-  const int64_t nseg = (int64_t)a.R * (a.G.K + 1);
-  hipError_t e = scan(a.cnt, a.n_hist + 1, a.blk, 0, s);
+  const unsigned seg_grid = grid_for(nseg, 4);  // four wavefronts of 64 per work-group
+  hipLaunchKernelGGL(comb_clear_kernel<Real>, dim3(grid_for(a.n_hist + 1, 256)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(comb_count_kernel<Real>, dim3(seg_grid), dim3(256), 0, s, a);
+  hipError_t e = scan(a.cnt, a.n_hist + 1, nullptr, a.blk, 0, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(comb_scatter_kernel<Real>, dim3((unsigned)std::min<int64_t>(nseg, 8192)), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(comb_sort_small_kernel<Real>, dim3(grid_for(a.n_hist, 256)), dim3(256), 0, s, a);
+  const unsigned cen_grid = grid_for(a.cap, 256);
+  hipLaunchKernelGGL(comb_scatter_kernel<Real>, dim3(seg_grid), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(comb_rank_small_kernel<Real>, dim3(cen_grid), dim3(256), 0, s, a);
   hipLaunchKernelGGL(comb_sort_big_kernel<Real>, dim3(256), dim3(1024), 0, s, a);
-  hipLaunchKernelGGL(comb_weights_kernel<Real>, dim3(grid_for(n, 256)), dim3(256), 0, s, a, n, eu);
+  hipLaunchKernelGGL(comb_weights_kernel<Real>, dim3(cen_grid), dim3(256), 0, s, a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  e = scan(a.wq, n, a.blk, 1, s);
+  e = scan(a.wq, a.cap, a.misc + 1, a.blk, 1, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(comb_teeth_kernel<Real>, dim3(grid_for(a.n_target, 256)), dim3(256), 0, s, a, n, eu);
-  hipLaunchKernelGGL(comb_finish_kernel<Real>, dim3(1), dim3(256), 0, s, a, n, eu);
+  hipLaunchKernelGGL(comb_teeth_kernel<Real>, dim3(grid_for(a.n_target, 256)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(comb_finish_kernel<Real>, dim3(1), dim3(1024), 0, s, a);
   return hipGetLastError();
 }
 
-template hipError_t launch_comb_count<double>(const CombArgs<double> &, hipStream_t);
-template hipError_t launch_comb_count<float>(const CombArgs<float> &, hipStream_t);
-template hipError_t launch_comb_rest<double>(const CombArgs<double> &, int64_t, int, hipStream_t);
-template hipError_t launch_comb_rest<float>(const CombArgs<float> &, int64_t, int, hipStream_t);
+template hipError_t launch_comb<double>(const CombArgs<double> &, hipStream_t);
+template hipError_t launch_comb<float>(const CombArgs<float> &, hipStream_t);
 
 }  // namespace hww

@@ -159,7 +159,7 @@ struct CombArgs {
   unsigned long long *order;   // [cap] slot index of the census particle at each canonical position
   unsigned long long *wq;      // [cap] integer weights, then inclusive prefix sums
   unsigned long long *blk;     // scan block sums
-  unsigned long long *misc;    // [8]
+  unsigned long long *misc;    // [8]: largest weight's bits, count, total weight, -, long histories
   double *wnext;               // [nc]
   uint32_t *err;
 };
@@ -266,9 +266,7 @@ hipError_t launch_losm_batch(const LosmReplica *tab, int n, int max_I, const Los
 size_t losm_batch_lds(int max_I, int *work_in_lds);
 hipError_t launch_begin_step_batch(const BeginStepArgs *tab, int n, int64_t max_tal, hipStream_t s);
 template <typename Real>
-hipError_t launch_comb_count(const CombArgs<Real> &a, hipStream_t s);
-template <typename Real>
-hipError_t launch_comb_rest(const CombArgs<Real> &a, int64_t n, int eu, hipStream_t s);
+hipError_t launch_comb(const CombArgs<Real> &a, hipStream_t s);
 int64_t comb_scan_blocks(int64_t n);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);

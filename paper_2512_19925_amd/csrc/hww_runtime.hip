@@ -994,36 +994,26 @@ int hww_comb(hww_handle *h, int64_t n_target, int64_t *n_before, double *w_total
     a32.cnt = a.cnt; a32.cur = a.cur; a32.order = a.order; a32.wq = a.wq; a32.blk = a.blk; a32.misc = a.misc;
     a32.wnext = a.wnext; a32.err = a.err;
   }
-  HIPCHK(h, launch_fill_u32(reinterpret_cast<uint32_t *>(a.cnt), 0u, 2 * (a.n_hist + 1), h->stream));
-  HIPCHK(h, launch_fill_u32(a.cur, 0u, a.n_hist, h->stream));
-  HIPCHK(h, launch_fill_u32(reinterpret_cast<uint32_t *>(a.misc), 0u, 16, h->stream));
-  HIPCHK(h, h->fp32 ? launch_comb_count<float>(a32, h->stream) : launch_comb_count<double>(a, h->stream));
+  HIPCHK(h, h->fp32 ? launch_comb<float>(a32, h->stream) : launch_comb<double>(a, h->stream));
   unsigned long long misc[8];
   HIPCHK(h, hipMemcpyAsync(misc, a.misc, sizeof misc, hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
-  int rc = poll_errors(h);
-  if (rc != HWW_OK) return rc;
   const int64_t n = (int64_t)misc[1];
   if (n_before) *n_before = n;
   if (w_total) *w_total = 0.0;
-  if (n == 0) return HWW_OK;  // an empty census stays empty
-  double m;
-  std::memcpy(&m, &misc[0], 8);
-  if (!(m > 0.0) || !std::isfinite(m)) return fail(h, HWW_E_NUMERIC, "census weights must be positive and finite");
-  // Unit 2^eu of the integer weights: n * max weight < 2^(53 + eu).
-  int em;
-  std::frexp(m, &em);
-  int ln = 0;
-  while (((int64_t)1 << ln) < n) ++ln;
-  const int eu = em + ln - 53;
-  HIPCHK(h, h->fp32 ? launch_comb_rest<float>(a32, n, eu, h->stream) : launch_comb_rest<double>(a, n, eu, h->stream));
-  HIPCHK(h, hipMemcpyAsync(misc, a.misc, sizeof misc, hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(h, hipStreamSynchronize(h->stream));
-  // The combed bank becomes the census bank; its histories are 0..n_target-1.
-  h->start_bank = 1 - h->start_bank;
-  h->src_bound = std::max<int64_t>(h->src_bound, n_target);
-  rc = poll_errors(h);
+  if (n > 0) {
+    // The kernels after the count do nothing unless the largest weight is
+    // positive and finite; an empty census stays empty.
+    double m;
+    std::memcpy(&m, &misc[0], 8);
+    if (!(m > 0.0) || !std::isfinite(m)) return fail(h, HWW_E_NUMERIC, "census weights must be positive and finite");
+    // The combed bank becomes the census bank; its histories are 0..n_target-1.
+    h->start_bank = 1 - h->start_bank;
+    h->src_bound = std::max<int64_t>(h->src_bound, n_target);
+  }
+  const int rc = poll_errors(h);
   if (rc != HWW_OK) return rc;
+  if (n == 0) return HWW_OK;
   if (w_total) std::memcpy(w_total, &misc[2], 8);
   return HWW_OK;
 }
