@@ -350,6 +350,8 @@ int census_total(hww_handle *h, int bank_idx, uint64_t *total) {
 // code.  Errors are sticky: the problem must be re-initialised.
 int poll_batch(hww_handle *h);
 
+int error_status(hww_handle *h, uint32_t e, uint64_t cen);
+
 int poll_errors(hww_handle *h) {
   if (h->is_batch) return poll_batch(h);
   uint32_t e = 0;
@@ -357,6 +359,11 @@ int poll_errors(hww_handle *h) {
   uint64_t cen = 0;
   int rc = census_total(h, 1 - h->start_bank, &cen);
   if (rc != HWW_OK) return rc;
+  return error_status(h, e, cen);
+}
+
+// The ABI code of an error word read from the device and a census size.
+int error_status(hww_handle *h, uint32_t e, uint64_t cen) {
   if (e & (ERR_CAPACITY | ERR_SPLIT | ERR_GENERATIONS | ERR_DAUGHTERS)) {
     h->fatal = HWW_E_CAPACITY;
     return fail(h, HWW_E_CAPACITY, (e & ERR_SPLIT) ? "a split exceeded 1e9 daughters"
@@ -996,7 +1003,9 @@ int hww_comb(hww_handle *h, int64_t n_target, int64_t *n_before, double *w_total
   }
   HIPCHK(h, h->fp32 ? launch_comb<float>(a32, h->stream) : launch_comb<double>(a, h->stream));
   unsigned long long misc[8];
+  uint32_t e = 0;
   HIPCHK(h, hipMemcpyAsync(misc, a.misc, sizeof misc, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipMemcpyAsync(&e, h->err, 4, hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
   const int64_t n = (int64_t)misc[1];
   if (n_before) *n_before = n;
@@ -1011,7 +1020,8 @@ int hww_comb(hww_handle *h, int64_t n_target, int64_t *n_before, double *w_total
     h->start_bank = 1 - h->start_bank;
     h->src_bound = std::max<int64_t>(h->src_bound, n_target);
   }
-  const int rc = poll_errors(h);
+  // The census is the n_target copies after a comb, still empty otherwise.
+  const int rc = error_status(h, e, n > 0 ? (uint64_t)n_target : 0u);
   if (rc != HWW_OK) return rc;
   if (n == 0) return HWW_OK;
   if (w_total) std::memcpy(w_total, &misc[2], 8);
