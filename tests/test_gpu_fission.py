@@ -155,7 +155,9 @@ def test_comb_matches_its_definition(precision):
             if p < w.n_chunks - 1:
                 h.solve_losm(implicit=True, **kw)
     census = h.read_bank(1)
-    for H_t in (3000, 12345):             # fewer and more copies than particles
+    # Fewer and more copies than particles; the last comb orders 40000
+    # histories, so its history counts take the tiled scan.
+    for H_t in (3000, 12345, 40000, 7000):
         before = {k: v.copy() for k, v in census.items()}
         n_b, W_tot = h.comb(H_t)
         assert n_b == len(before["w"])
@@ -169,7 +171,7 @@ def test_comb_matches_its_definition(precision):
         assert np.all(after["w"] == w_out) and abs(W_tot - w_out * H_t) <= 1e-12 * W_tot
         assert np.array_equal(after["x"], x) and np.array_equal(after["mu"], mu)
         assert np.array_equal(after["cell"], cell)
-        census = after  # the second comb combs the combed bank
+        census = after  # each further comb combs the combed bank
     h.close()
 
 
