@@ -264,18 +264,21 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
   uint32_t evb = 0u;  // EVB_* events not yet counted
   int out_buf = 0;
 
-  // Add the wave's pending events to the work-group counters (converged):
-  // the common kinds every pass, the rare ones behind a single ballot.
-  // Crossings are not counted here; every segment adds one to its cell's
-  // track counter, so they follow from the segment total at the end.
+  // Count the wave's pending events (converged): the common kinds into
+  // wave-uniform totals (scalar registers) added to the work-group counters
+  // once, at the end of the unit; the rare ones into the work-group
+  // counters behind a single ballot.  Crossings are not counted here; every
+  // segment adds one to its cell's track counter, so they follow from the
+  // segment total at the end.
   auto count_kind = [&](int q) {
     const uint64_t m = __ballot(((evb >> q) & 1u) != 0u);
     if (m != 0 && lane == 0) atomicAdd(&L.cnt[kEventSlot[q]], (uint32_t)__popcll(m));
   };
+  uint32_t n_census = 0, n_scatter = 0, n_absorb = 0, n_hist = 0;  // n_hist: start particles taken
   auto count_events = [&]() {
-    count_kind(0);  // census
-    count_kind(3);  // scatter
-    count_kind(4);  // absorption
+    n_census += (uint32_t)__popcll(__ballot((evb & EVB_CENSUS) != 0u));
+    n_scatter += (uint32_t)__popcll(__ballot((evb & EVB_SCATTER) != 0u));
+    n_absorb += (uint32_t)__popcll(__ballot((evb & EVB_ABSORB) != 0u));
     if (__ballot((evb & kRareEvents) != 0u) != 0) {
       count_kind(1);
 #pragma unroll
@@ -465,7 +468,7 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
               active = true;
             }
           }
-          if (from_bank && lane == 0) atomicAdd(&L.cnt[C_HISTORIES], take);
+          if (from_bank) n_hist += take;
           tile_next += take;
         }
         // Start-of-step checks of the lanes just loaded: one draw, from
@@ -479,7 +482,7 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
           }
         }
         start_act = 0u;
-        flush_daughters();
+        if (__ballot(nd > 1) != 0) flush_daughters();
       }
       if (__ballot(active) == 0) {
         count_events();
@@ -650,6 +653,12 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
     ++gen;
   }
 
+  if (lane == 0) {
+    if (n_census) atomicAdd(&L.cnt[C_CENSUS], n_census);
+    if (n_scatter) atomicAdd(&L.cnt[C_SCATTERS], n_scatter);
+    if (n_absorb) atomicAdd(&L.cnt[C_ABSORPTIONS], n_absorb);
+    if (n_hist) atomicAdd(&L.cnt[C_HISTORIES], n_hist);
+  }
   // Segments: the sum of the per-cell track counters.  Every segment ends
   // in exactly one of census, leak, crossing or collision (scatter, fission
   // or absorption), which gives the crossings.
