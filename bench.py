@@ -37,7 +37,9 @@ HBM_PEAK_GBS = 8000.0
 # (FETCH_SIZE and WRITE_SIZE, scaled by a plain-copy calibration); valid only
 # for the kernel sources it was measured on.
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "sweep_full-1000c-c0.9-rho5_hbm_traffic.md")
-SWEEP_SOURCES = [os.path.join(ROOT, "paper_2512_19925_amd", "csrc", f) for f in ("hww_sweep.hip", "hww_internal.h")]
+# The sweep kernel's sources and the compiler flags it is built with.
+SWEEP_SOURCES = [os.path.join(ROOT, "paper_2512_19925_amd", "csrc", f) for f in ("hww_sweep.hip", "hww_internal.h")] + \
+    [os.path.join(ROOT, "paper_2512_19925_amd", "build.py")]
 
 
 def parse():
