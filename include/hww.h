@@ -166,11 +166,14 @@ int hww_sweep_step(hww_handle *h, int32_t step, int32_t chunk, hww_step_stats *s
  * chunk (k / B) mod n_chunks.  Census tallies are unchanged; the per-chunk
  * census weights become count * W / n_target.  Call after the last chunk of
  * a step and before the next step's semi-implicit solve.  n_before and
- * w_total (nullable host pointers) receive the census size and W.
- * Synchronises the stream.  Single problems initialised with comb = 1 only.
+ * w_total (nullable host pointers) receive the census size and W; an empty
+ * census stays empty (both 0).  Synchronises the stream once.  Single
+ * problems initialised with comb = 1 only.
  * Errors: HWW_E_INVALID_ARG (n_target outside 1..bank_capacity or > 2^32-1),
  * HWW_E_STATE (step not finished, no comb workspace, a batch or a view),
- * HWW_E_CAPACITY (a region of the new bank overflows), HWW_E_DEVICE. */
+ * HWW_E_CAPACITY (a region of the new bank overflows), HWW_E_NUMERIC (a
+ * census weight not positive and finite; the census is left as it was),
+ * HWW_E_DEVICE. */
 int hww_comb(hww_handle *h, int64_t n_target, int64_t *n_before, double *w_total);
 
 /* Counters, kernel time and bank bytes of every sweep since init (same
