@@ -82,7 +82,8 @@ typedef struct hww_handle hww_handle;
 typedef struct hww_step_stats {
   uint64_t segments, collisions, scatters, absorptions, crossings, leaks, census;
   uint64_t splits, daughters, rr_kill, rr_survive, histories;
-  uint64_t generations;   /* most daughter generations of any work-group in one launch, + 1 */
+  uint64_t generations;   /* most daughter rounds (barrier-separated passes over a daughter
+                             buffer) of any work-group in one launch, + 1            */
   uint64_t launches;      /* sweep-kernel launches of the step so far                   */
   double kernel_ms;       /* summed sweep-kernel time of those launches made with timing
                              on (HIP events; see hww_set_timing)                       */

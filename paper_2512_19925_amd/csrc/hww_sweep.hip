@@ -71,7 +71,9 @@ struct Lds {
   uint32_t *trk;    // [I]
   uint32_t *cnt;    // [16]
   uint32_t *ccnt;   // [8]   census appends of this work-group per chunk
-  uint32_t *dcnt;   // [2]   daughters per buffer
+  uint32_t *dcnt;   // [2]   daughter slots taken in each buffer
+  uint32_t *dready; // [2]   daughters of each buffer written (visible to the work-group)
+  uint32_t *dtake;  // [2]   daughters taken from a buffer while it is still written
   uint32_t *dcur;   // [1]   tile counter: start-bank tiles (generation 0), then daughter slots
   uint32_t *tstart; // [K+2] first tile of each start-bank segment
   uint32_t *nseg;   // [K+1] particles of each start-bank segment
@@ -87,7 +89,9 @@ __device__ inline Lds carve(double *raw, int I, int nc, int K) {
   L.cnt = L.trk + I;
   L.ccnt = L.cnt + 16;
   L.dcnt = L.ccnt + 8;
-  L.dcur = L.dcnt + 2;
+  L.dready = L.dcnt + 2;
+  L.dtake = L.dready + 2;
+  L.dcur = L.dtake + 2;
   L.tstart = L.dcur + 1;
   L.nseg = L.tstart + (K + 2);
   return L;
@@ -337,6 +341,10 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
         tg.cell = cell;
         A.dq.tag[k] = tg;
       }
+      // Publish: the records are visible to the work-group before the count
+      // that lets other waves take them.
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      if (lane == 0) atomicAdd(&L.dready[out_buf], total);
     }
     nd = 0;
   };
@@ -394,18 +402,20 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
     const int in_buf = (gen + 1) & 1;  // buffer written by the previous generation
     out_buf = gen & 1;
     const int64_t in_qbase = ((int64_t)in_buf * nq + qslot) * dstride;
+    const int64_t out_qbase = ((int64_t)out_buf * nq + qslot) * dstride;
 
     int64_t tile_base = 0;
     uint32_t tile_next = 0, tile_end = 0;
-    bool exhausted = false;
+    bool tile_bank = false;  // the current tile is of start particles (else daughters)
+    bool exhausted = false;  // this generation's own tiles are all taken
     for (;;) {
       // ---------------------------------------------------------- refill --
       const uint64_t need_m = __ballot(!active);
       if (need_m != 0) {
-        if (tile_next == tile_end && !exhausted) {
+        if (tile_next == tile_end) {
           int64_t tb = -1;
           uint32_t tl = 0;
-          if (lane == 0) {
+          if (lane == 0 && !exhausted) {
             if (from_bank) {
               // Tiles of this unit: jseg, jseg + K, ... of the region.
               const uint32_t t = (uint32_t)jseg + (uint32_t)K * atomicAdd(L.dcur, 1u);
@@ -424,14 +434,38 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
               }
             }
           }
+          const bool own = __shfl(tb, 0) >= 0;
+          if (!own) exhausted = true;
+          // With its own tiles gone, the wave takes daughters that this
+          // generation has already written to its output buffer, when every
+          // slot reserved so far is written (then all slots below the count
+          // are); what is left goes to the next generation.
+          if (lane == 0 && !own) {
+            const uint32_t r = __hip_atomic_load(&L.dready[out_buf], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            const uint32_t c = __hip_atomic_load(&L.dcnt[out_buf], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (r == c) {
+              const uint32_t lim = min(r, (uint32_t)A.dcap);
+              uint32_t t = __hip_atomic_load(&L.dtake[out_buf], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+              while (t < lim) {
+                const uint32_t nt = min(t + TILE, lim);
+                const uint32_t old = atomicCAS(&L.dtake[out_buf], t, nt);
+                if (old == t) {
+                  tb = out_qbase + t;
+                  tl = nt - t;
+                  break;
+                }
+                t = old;
+              }
+            }
+          }
           tb = __shfl(tb, 0);
           tl = __shfl(tl, 0);
-          if (tb < 0) {
-            exhausted = true;
-          } else {
+          if (!own && tb >= 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+          if (tb >= 0) {
             tile_base = tb;
             tile_next = 0;
             tile_end = tl;
+            tile_bank = own && from_bank;
           }
         }
         const uint32_t avail = tile_end - tile_next;
@@ -440,7 +474,7 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
           const uint32_t rk = rank_below(need_m);
           if (!active && rk < take) {
             const int64_t k = tile_base + (int64_t)(tile_next + rk);
-            if (from_bank) {
+            if (tile_bank) {
               const XMu<Real> xm = A.in_bank.xm[k];
               const Tag tg = A.in_bank.tag[k];
               x = xm.x;
@@ -468,7 +502,7 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
               active = true;
             }
           }
-          if (from_bank) n_hist += take;
+          if (tile_bank) n_hist += take;
           tile_next += take;
         }
         // Start-of-step checks of the lanes just loaded: one draw, from
@@ -636,9 +670,12 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
     }
 
     // ------------------------------------------- next daughter generation --
+    // The daughters of this generation not taken while it ran: slots
+    // taken .. n_list of its output buffer.
     __syncthreads();
-    const uint32_t produced = L.dcnt[gen & 1];
-    if (produced == 0) break;
+    const uint32_t produced = L.dcnt[gen & 1], taken = L.dtake[gen & 1];
+    const uint32_t next_list = produced < (uint32_t)A.dcap ? produced : (uint32_t)A.dcap;
+    if (next_list <= taken) break;
     if (gen + 1 >= kMaxGenerations) {
       if (tid == 0) atomicOr(A.err, ERR_GENERATIONS);
       break;
@@ -646,10 +683,12 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
     __syncthreads();
     if (tid == 0) {
       L.dcnt[(gen + 1) & 1] = 0u;
-      L.dcur[0] = 0u;
+      L.dready[(gen + 1) & 1] = 0u;
+      L.dtake[(gen + 1) & 1] = 0u;
+      L.dcur[0] = taken;
     }
     __syncthreads();
-    n_list = produced < (uint32_t)A.dcap ? produced : (uint32_t)A.dcap;
+    n_list = next_list;
     ++gen;
   }
 
