@@ -244,7 +244,7 @@ struct MarchArgs {
 // the start-bank tile table.  A sweep that keeps the per-cell records in
 // LDS puts them first (cell_bytes per cell: CellData and Window).
 __host__ __device__ inline size_t lds_doubles(int I, int nc) { return (size_t)I * 6 + nc + 6; }
-__host__ __device__ inline size_t lds_words(int I, int K) { return (size_t)I + 16 + 8 + 2 + 2 + 2 + 1 + (K + 2) + (K + 1); }
+__host__ __device__ inline size_t lds_words(int I, int K) { return (size_t)I + 16 + 8 + 2 + 2 + 2 + 1 + 1 + (K + 2) + (K + 1); }
 inline size_t sweep_lds_bytes(int I, int nc, int K, size_t cell_bytes = 0) {
   return (size_t)I * cell_bytes + lds_doubles(I, nc) * 8 + lds_words(I, K) * 4;
 }

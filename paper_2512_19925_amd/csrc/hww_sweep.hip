@@ -21,6 +21,10 @@
 
 namespace hww {
 
+// Daughters of a generation that waves out of their own tiles take early
+// even when no wave has tiles of its own left.
+constexpr uint32_t kDrainSmall = 256;
+
 // Window and event actions of a lane (bit flags).
 enum : uint32_t { WW_ROULETTE = 1u, WW_SPLIT = 2u, EV_DRAW = 4u, EV_SCATTER = 8u, EV_FISSION = 16u,
                   FIS_BIRTHS = 32u };
@@ -74,6 +78,7 @@ struct Lds {
   uint32_t *dcnt;   // [2]   daughter slots taken in each buffer
   uint32_t *dready; // [2]   daughters of each buffer written (visible to the work-group)
   uint32_t *dtake;  // [2]   daughters taken from a buffer while it is still written
+  uint32_t *obusy;  // [1]   waves still taking tiles of their own in this generation
   uint32_t *dcur;   // [1]   tile counter: start-bank tiles (generation 0), then daughter slots
   uint32_t *tstart; // [K+2] first tile of each start-bank segment
   uint32_t *nseg;   // [K+1] particles of each start-bank segment
@@ -91,7 +96,8 @@ __device__ inline Lds carve(double *raw, int I, int nc, int K) {
   L.dcnt = L.ccnt + 8;
   L.dready = L.dcnt + 2;
   L.dtake = L.dready + 2;
-  L.dcur = L.dtake + 2;
+  L.obusy = L.dtake + 2;
+  L.dcur = L.obusy + 1;
   L.tstart = L.dcur + 1;
   L.nseg = L.tstart + (K + 2);
   return L;
@@ -242,6 +248,7 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
       acc += (n + TILE - 1u) / TILE;
     }
     L.tstart[K + 1] = acc;
+    L.obusy[0] = blockDim.x >> 6;
   }
   __syncthreads();
 
@@ -266,6 +273,7 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
   uint32_t e_d = 0;
   bool fis = false;
   uint32_t evb = 0u;  // EVB_* events not yet counted
+  uint32_t pub = 0u;  // daughters the wave has written but not yet counted as written
   int out_buf = 0;
 
   // Count the wave's pending events (converged): the common kinds into
@@ -289,6 +297,15 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
       for (int q = 5; q < kEventKinds; ++q) count_kind(q);
     }
     evb = 0u;
+  };
+
+  // Count the wave's written daughters as written (for the waves that take
+  // daughters early) once the release fence has made the records visible
+  // to the work-group.
+  auto publish = [&]() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    if (lane == 0) atomicAdd(&L.dready[out_buf], pub);
+    pub = 0u;
   };
 
   // Write the pending daughters of all lanes of the wave into the work-
@@ -341,10 +358,8 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
         tg.cell = cell;
         A.dq.tag[k] = tg;
       }
-      // Publish: the records are visible to the work-group before the count
-      // that lets other waves take them.
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-      if (lane == 0) atomicAdd(&L.dready[out_buf], total);
+      pub += total;
+      publish();
     }
     nd = 0;
   };
@@ -435,15 +450,23 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
             }
           }
           const bool own = __shfl(tb, 0) >= 0;
-          if (!own) exhausted = true;
+          if (!own && !exhausted) {
+            exhausted = true;
+            if (lane == 0) atomicSub(L.obusy, 1u);
+          }
           // With its own tiles gone, the wave takes daughters that this
           // generation has already written to its output buffer, when every
           // slot reserved so far is written (then all slots below the count
-          // are); what is left goes to the next generation.
+          // are): while another wave still has tiles of its own, or while
+          // the generation has made few daughters.  A wave that finds none
+          // leaves the generation, so a long cascade of daughters would be
+          // left to the last waves; past kDrainSmall daughters it goes to the
+          // next generation instead, which all waves share.
           if (lane == 0 && !own) {
+            const bool busy = __hip_atomic_load(L.obusy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0u;
             const uint32_t r = __hip_atomic_load(&L.dready[out_buf], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
             const uint32_t c = __hip_atomic_load(&L.dcnt[out_buf], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (r == c) {
+            if (r == c && (busy || c <= kDrainSmall)) {
               const uint32_t lim = min(r, (uint32_t)A.dcap);
               uint32_t t = __hip_atomic_load(&L.dtake[out_buf], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
               while (t < lim) {
@@ -685,6 +708,7 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
       L.dcnt[(gen + 1) & 1] = 0u;
       L.dready[(gen + 1) & 1] = 0u;
       L.dtake[(gen + 1) & 1] = 0u;
+      L.obusy[0] = blockDim.x >> 6;
       L.dcur[0] = taken;
     }
     __syncthreads();
