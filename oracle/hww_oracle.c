@@ -19,6 +19,8 @@
  * Pins (tests/test_oracle_*.py):
  *   orc_philox4x32_10   published Philox4x32-10 known-answer vectors
  *   orc_u53             exact integer construction, range and moments
+ *   orc_log             libm's log within one ulp over the flight range
+ *                       (0, 1], 0 at 1, log identities at powers of two
  *   orc_thomas          dense LAPACK solve on random well-posed systems
  *   orc_losm_step       manufactured smooth solution: 2nd-order convergence
  *                       for theta = 1/2, 1st order for theta = 1; discrete
@@ -79,6 +81,44 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
 double orc_u53(uint32_t a, uint32_t b) {
   double k = (double)(a >> 5) * 67108864.0 + (double)(b >> 6);
   return k * (1.0 / 9007199254740992.0);
+}
+
+/* Natural logarithm of a positive normal x, as the flight distance uses it.
+ * x = (1 + f) 2^k with 1 + f in [sqrt(1/2), sqrt(2)) (f exact).  With
+ * s = f / (2 + f), ln(1 + f) = 2 atanh(s) = 2s + s R, R the rest of the
+ * atanh series, and 2s = f - s f = f - h + s h (h = f^2 / 2), so
+ * ln(1 + f) = f - (h - s (h + R)): the rounding of s only touches the small
+ * s (h + R) term.  R = sum_{j=1..9} 2 z^j / (2j + 1), z = s^2 <= 0.0295 (the
+ * first term left out is below 2^-54 relatively).  k ln 2 is added with
+ * ln 2 split in two doubles.  Within one ulp of ln x.  The steps are fixed
+ * (every product and sum named, fused multiply-adds where written), so any
+ * implementation of the same steps in IEEE double gives the same bits;
+ * libm's log differs from it in the last bit now and then. */
+double orc_log(double x) {
+  int k;
+  double m = frexp(x, &k);
+  if (m < 0.70710678118654752440) {
+    m = m * 2.0;
+    k = k - 1;
+  }
+  const double f = m - 1.0;
+  const double s = f / (2.0 + f);
+  const double z = s * s;
+  double q = 2.0 / 19.0;
+  q = fma(q, z, 2.0 / 17.0);
+  q = fma(q, z, 2.0 / 15.0);
+  q = fma(q, z, 2.0 / 13.0);
+  q = fma(q, z, 2.0 / 11.0);
+  q = fma(q, z, 2.0 / 9.0);
+  q = fma(q, z, 2.0 / 7.0);
+  q = fma(q, z, 2.0 / 5.0);
+  q = fma(q, z, 2.0 / 3.0);
+  const double R = z * q;
+  const double h = 0.5 * f * f;
+  const double kd = (double)k;
+  const double c = fma(kd, 2.3190468138462996e-17, s * (h + R));
+  const double u = f - (h - c);
+  return fma(kd, 0.69314718055994528623, u);
 }
 
 /* Random-number slots of the keying contract. */
@@ -407,7 +447,7 @@ static int transport(orc_sim *s, particle *p) {
     double ua, ub;
     draw(s->seed, s->replica, SLOT_FLIGHT, p->src, p->lin, p->e, &ua, &ub, NULL);
     /* Exponential flight distance with mean free path 1/sigma_t. */
-    double d_coll = -log(1.0 - ua) * s->inv_sig_t[i];
+    double d_coll = -orc_log(1.0 - ua) * s->inv_sig_t[i];
     double xl = s->edges[i], xr = s->edges[i + 1];
     double d_bnd;
     if (p->mu > 0.0) d_bnd = (xr - p->x) / p->mu;

@@ -68,6 +68,9 @@ typedef struct orc_sim orc_sim;
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 /* 53-bit uniform in [0,1) from two 32-bit words. */
 double orc_u53(uint32_t a, uint32_t b);
+/* ln x for a positive normal x by fixed steps (atanh series); the flight
+ * distance -ln(1 - u) / sigma_t uses it. */
+double orc_log(double x);
 
 int orc_create(const orc_params *p, orc_sim **out);
 void orc_destroy(orc_sim *s);

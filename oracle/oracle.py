@@ -48,6 +48,8 @@ def lib():
         L.orc_philox4x32_10.argtypes = [C.POINTER(C.c_uint32)] * 3
         L.orc_u53.argtypes = [C.c_uint32, C.c_uint32]
         L.orc_u53.restype = C.c_double
+        L.orc_log.argtypes = [C.c_double]
+        L.orc_log.restype = C.c_double
         L.orc_create.argtypes = [C.c_void_p, C.POINTER(C.c_void_p)]
         L.orc_destroy.argtypes = [C.c_void_p]
         L.orc_set_batch_mask.argtypes = [C.c_void_p, C.c_void_p]
@@ -112,6 +114,11 @@ def philox4x32_10(ctr, key):
 
 def u53(a, b):
     return lib().orc_u53(int(a) & 0xFFFFFFFF, int(b) & 0xFFFFFFFF)
+
+
+def log(x):
+    """ln x by the oracle's fixed steps (the flight distance's logarithm)."""
+    return lib().orc_log(float(x))
 
 
 def thomas(a, b, c, d):
