@@ -395,8 +395,17 @@ template <typename Real>
 __global__ void __launch_bounds__(1024) comb_finish_kernel(CombArgs<Real> A) {
   __shared__ unsigned long long chunk[8];
   const CombScale cs = comb_scale(A.misc);
-  if (!cs.ok) return;
   const BankGeom &G = A.G;
+  if (!cs.ok) {
+    // Nothing combed.  When the host does not wait for the census size, it
+    // takes the new bank as the census anyway: make that bank empty.
+    if (!A.no_wait) return;
+    for (int64_t t = threadIdx.x; t < (int64_t)A.R * G.K; t += blockDim.x) A.dst_bank.segcnt[t] = 0u;
+    for (int t = threadIdx.x; t < A.R; t += blockDim.x) A.dst_bank.ovfcnt[t] = 0u;
+    if (threadIdx.x < (unsigned)A.nc) A.wnext[threadIdx.x] = 0.0;
+    if (threadIdx.x == 0 && cs.n > 0) atomicOr(A.err, ERR_COMB_WEIGHT);
+    return;
+  }
   if (threadIdx.x < 8) chunk[threadIdx.x] = 0ull;
   __syncthreads();
   const int64_t nseg = (int64_t)A.R * (G.K + 1);

@@ -8,7 +8,8 @@
 namespace hww {
 
 // Device error bits (ORed into one word of the workspace).
-enum : uint32_t { ERR_CAPACITY = 1u, ERR_NUMERIC = 2u, ERR_SPLIT = 4u, ERR_GENERATIONS = 8u, ERR_DAUGHTERS = 16u };
+enum : uint32_t { ERR_CAPACITY = 1u, ERR_NUMERIC = 2u, ERR_SPLIT = 4u, ERR_GENERATIONS = 8u, ERR_DAUGHTERS = 16u,
+                  ERR_COMB_WEIGHT = 32u };
 
 // Counter slots (per step, uint64).
 enum {
@@ -153,6 +154,9 @@ struct CombArgs {
   int64_t n_hist;              // bound on src values + 1 of the census
   int64_t cap;                 // bound on census particles
   int64_t n_target;
+  int32_t no_wait;             // 1: the host will not read the census size, so an empty or
+                               // invalid census leaves an empty combed bank (and, if
+                               // invalid, ERR_COMB_WEIGHT) for it to take as the census
   uint32_t seed, key1, step;
   unsigned long long *cnt;     // [n_hist + 1] counts, then exclusive offsets
   uint32_t *cur;               // [n_hist]

@@ -379,6 +379,10 @@ int error_status(hww_handle *h, uint32_t e, uint64_t cen) {
     h->fatal = HWW_E_NUMERIC;
     return fail(h, HWW_E_NUMERIC, "non-finite or non-positive window, or zero pivot in the LOSM solve");
   }
+  if (e & ERR_COMB_WEIGHT) {
+    h->fatal = HWW_E_NUMERIC;
+    return fail(h, HWW_E_NUMERIC, "a census combed without waiting had a weight that was not positive and finite");
+  }
   return HWW_OK;
 }
 
@@ -978,6 +982,7 @@ int hww_comb(hww_handle *h, int64_t n_target, int64_t *n_before, double *w_total
     a.n_hist = h->src_bound;
     a.cap = L.comb_slots;
     a.n_target = n_target;
+    a.no_wait = (!n_before && !w_total) ? 1 : 0;
     a.seed = h->p.seed; a.key1 = h->p.replica << 4; a.step = (uint32_t)h->step;
     a.cnt = reinterpret_cast<unsigned long long *>(h->ws + L.off_c_cnt);
     a.cur = reinterpret_cast<uint32_t *>(h->ws + L.off_c_cur);
@@ -997,11 +1002,18 @@ int hww_comb(hww_handle *h, int64_t n_target, int64_t *n_before, double *w_total
     a32.src_bank = h->bank32[1 - h->start_bank];
     a32.dst_bank = h->bank32[h->start_bank];
     a32.G = a.G; a32.B = a.B; a32.nc = a.nc; a32.R = a.R; a32.n_hist = a.n_hist; a32.cap = a.cap;
-    a32.n_target = a.n_target; a32.seed = a.seed; a32.key1 = a.key1; a32.step = a.step;
+    a32.n_target = a.n_target; a32.no_wait = a.no_wait; a32.seed = a.seed; a32.key1 = a.key1; a32.step = a.step;
     a32.cnt = a.cnt; a32.cur = a.cur; a32.order = a.order; a32.wq = a.wq; a32.blk = a.blk; a32.misc = a.misc;
     a32.wnext = a.wnext; a32.err = a.err;
   }
   HIPCHK(h, h->fp32 ? launch_comb<float>(a32, h->stream) : launch_comb<double>(a, h->stream));
+  if (a.no_wait) {
+    // The combed bank (empty if the census was) becomes the census bank;
+    // errors reach the error word, read at the next synchronising call.
+    h->start_bank = 1 - h->start_bank;
+    h->src_bound = std::max<int64_t>(h->src_bound, n_target);
+    return HWW_OK;
+  }
   unsigned long long misc[8];
   uint32_t e = 0;
   HIPCHK(h, hipMemcpyAsync(misc, a.misc, sizeof misc, hipMemcpyDeviceToHost, h->stream));

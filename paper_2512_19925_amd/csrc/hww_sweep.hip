@@ -29,7 +29,39 @@ constexpr uint32_t kDrainSmall = 256;
 enum : uint32_t { WW_ROULETTE = 1u, WW_SPLIT = 2u, EV_DRAW = 4u, EV_SCATTER = 8u, EV_FISSION = 16u,
                   FIS_BIRTHS = 32u };
 
-__device__ __forceinline__ double log_r(double v) { return log(v); }
+// ln v of a positive normal v by fixed steps, so that every IEEE-double
+// implementation of the same steps (the CPU check of this sweep has one)
+// gives the same bits: v = (1 + f) 2^k with 1 + f in [sqrt(1/2), sqrt(2)),
+// s = f / (2 + f), ln(1 + f) = 2 atanh(s) = f - (h - s (h + R)) with
+// h = f^2 / 2 and R = sum_{j=1..9} 2 z^j / (2j + 1), z = s^2 (the rounding
+// of s only touches the small s (h + R) term), plus k ln 2 with ln 2 split
+// in two doubles.  Within one ulp of ln v.
+__device__ __forceinline__ double log_r(double v) {
+  int k;
+  double m = frexp(v, &k);
+  if (m < 0.70710678118654752440) {
+    m = m * 2.0;
+    k = k - 1;
+  }
+  const double f = m - 1.0;
+  const double s = f / (2.0 + f);
+  const double z = s * s;
+  double q = 2.0 / 19.0;
+  q = __builtin_fma(q, z, 2.0 / 17.0);
+  q = __builtin_fma(q, z, 2.0 / 15.0);
+  q = __builtin_fma(q, z, 2.0 / 13.0);
+  q = __builtin_fma(q, z, 2.0 / 11.0);
+  q = __builtin_fma(q, z, 2.0 / 9.0);
+  q = __builtin_fma(q, z, 2.0 / 7.0);
+  q = __builtin_fma(q, z, 2.0 / 5.0);
+  q = __builtin_fma(q, z, 2.0 / 3.0);
+  const double R = z * q;
+  const double h = 0.5 * f * f;
+  const double kd = (double)k;
+  const double c = __builtin_fma(kd, 2.3190468138462996e-17, s * (h + R));
+  const double u = f - (h - c);
+  return __builtin_fma(kd, 0.69314718055994528623, u);
+}
 __device__ __forceinline__ float log_r(float v) { return logf(v); }
 
 __device__ __forceinline__ uint32_t rank_below(uint64_t m) {
