@@ -371,7 +371,7 @@ def run_paper_problem(seeds=5, window_scale=1):
                 for n in range(1, ws.n_steps + 1):
                     t0 = time.perf_counter()
                     if n > 1:
-                        h.comb(ws.comb)
+                        h.comb(ws.comb, wait=False)
                     st = _step(h, ws, n, ws.analog, kw, stats=True)
                     tau = time.perf_counter() - t0
                     wall += tau

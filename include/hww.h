@@ -168,7 +168,11 @@ int hww_sweep_step(hww_handle *h, int32_t step, int32_t chunk, hww_step_stats *s
  * census weights become count * W / n_target.  Call after the last chunk of
  * a step and before the next step's semi-implicit solve.  n_before and
  * w_total (nullable host pointers) receive the census size and W; an empty
- * census stays empty (both 0).  Synchronises the stream once.  Single
+ * census stays empty (both 0).  With either pointer given the call
+ * synchronises the stream once; with both NULL it only queues the comb and
+ * returns: an empty census then leaves an empty combed bank, and a weight
+ * that is not positive and finite leaves an empty bank and an error that
+ * the next synchronising call reports (HWW_E_NUMERIC, fatal).  Single
  * problems initialised with comb = 1 only.
  * Errors: HWW_E_INVALID_ARG (n_target outside 1..bank_capacity or > 2^32-1),
  * HWW_E_STATE (step not finished, no comb workspace, a batch or a view),

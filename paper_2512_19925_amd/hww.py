@@ -241,9 +241,14 @@ class Handle:
         self._check("hww_read_run_stats", lib().hww_read_run_stats(self._h, C.byref(st)))
         return st.as_dict()
 
-    def comb(self, n_target):
+    def comb(self, n_target, wait=True):
         """Uniform comb of the finished step's census into n_target particles;
-        returns (census size before, total weight)."""
+        returns (census size before, total weight).  With wait=False the
+        call only queues the comb (no output, nothing returned; errors show
+        at the next call that synchronises)."""
+        if not wait:
+            self._check("hww_comb", lib().hww_comb(self._h, int(n_target), None, None))
+            return None
         nb, wt = C.c_int64(), C.c_double()
         self._check("hww_comb", lib().hww_comb(self._h, int(n_target), C.byref(nb), C.byref(wt)))
         return int(nb.value), float(wt.value)
@@ -450,7 +455,7 @@ def run(h: Handle, w, steps=None, on_step=None, analog=None, stats=True):
     kw = losm_kwargs(w)
     for n in range(1, steps + 1):
         if w.comb and n > 1:
-            h.comb(w.comb)
+            h.comb(w.comb, wait=False)
         if not analog:
             h.solve_losm(implicit=False, **kw)
         chunk_stats = []

@@ -17,10 +17,11 @@ COUNTERS = ["segments", "collisions", "scatters", "absorptions", "crossings", "l
             "splits", "daughters", "rr_kill", "rr_survive", "histories", "fissions", "fission_births"]
 
 
-def _run_pair(w, steps=None, analog=False):
+def _run_pair(w, steps=None, analog=False, wait=True):
     need_gpu()
     steps = w.n_steps if steps is None else steps
-    say(f"case {w.name}: n_src={w.n_src} I={w.n_cells} nu={w.nu_f} comb={w.comb} steps={steps} analog={analog}")
+    say(f"case {w.name}: n_src={w.n_src} I={w.n_cells} nu={w.nu_f} comb={w.comb} steps={steps} analog={analog} "
+        f"wait={wait}")
     h = H.Handle(H.spec_from_workload(w))
     sim = oracle_sim(w)
     opts = oracle_opts(w)
@@ -28,10 +29,13 @@ def _run_pair(w, steps=None, analog=False):
     worst = 0.0
     for n in range(1, steps + 1):
         if w.comb and n > 1:
-            gn, gw = h.comb(w.comb)
             on, ow = sim.comb(w.comb)
-            assert gn == on, f"step {n}: census sizes before the comb {gn} vs {on}"
-            assert abs(gw / ow - 1.0) < 1e-15, f"step {n}: comb weight {gw} vs {ow}"
+            if wait:
+                gn, gw = h.comb(w.comb)
+                assert gn == on, f"step {n}: census sizes before the comb {gn} vs {on}"
+                assert abs(gw / ow - 1.0) < 1e-15, f"step {n}: comb weight {gw} vs {ow}"
+            else:
+                assert h.comb(w.comb, wait=False) is None
             assert_bank_match(h.read_bank(1), sim.bank(1), what=f"{w.name} comb before step {n}")
         if not analog:
             h.solve_losm(implicit=False, **kw)
@@ -61,6 +65,12 @@ def test_paper_problem_end_to_end():
     # The paper's problem as specified: 201 cells, c_eff = 1.1, 20 steps of
     # dt = 1, 1e4 histories per step kept by combing, rho = 1.25.
     _run_pair(W.paper_fission())
+
+
+def test_paper_problem_comb_without_wait():
+    # The comb only queued (no census size read back): the same realisation
+    # as the oracle's, bank for bank and tally for tally.
+    _run_pair(W.paper_fission(n_src=4000).with_(name="paper-no-wait", n_steps=8), wait=False)
 
 
 def test_paper_problem_windows_as_printed():
@@ -195,4 +205,10 @@ def test_comb_of_an_empty_census():
         st_g = h.sweep_step(2, p)
         sim.sweep(2, p)
     assert st_g["segments"] == 0 == sim.counters()["segments"]
+    # Combed without waiting, the empty census leaves an empty combed bank.
+    assert h.comb(500, wait=False) is None
+    assert len(h.read_bank(1)["w"]) == 0
+    for p in range(w.n_chunks):
+        st_g = h.sweep_step(3, p)
+    assert st_g["segments"] == 0 and st_g["census"] == 0
     h.close()
