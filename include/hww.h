@@ -50,7 +50,8 @@ extern "C" {
 /* Problem of one replica (Sec. 3 Eqs. HO_transport, t-eq-bc, t-eq-ic with
  * q = 0, vacuum boundaries and an isotropic unit-weight pulse at src_x, t = 0). */
 typedef struct hww_problem {
-  int32_t n_cells;        /* I >= 1                                               */
+  int32_t n_cells;        /* 1 <= I <= 3136 (3137 with one chunk): the work-group's
+                             LDS histogram of the sweep holds [I][6] doubles       */
   const double *edges;    /* I+1 ascending cell edges (host)                      */
   const double *sigma_t;  /* I total cross sections, > 0 (host)                   */
   const double *sigma_s;  /* I scattering cross sections, 0 <= sigma_s <= sigma_t */

@@ -329,7 +329,7 @@ int validate(const hww_problem *p, std::string *why) {
   if (p->comb != 0 && p->comb != 1) { *why = "comb must be 0 or 1"; return HWW_E_INVALID_ARG; }
   if (p->track_moments < 0 || p->track_moments > 3) { *why = "track_moments must be 0..3"; return HWW_E_INVALID_ARG; }
   if (!(p->src_x >= p->edges[0] && p->src_x <= p->edges[p->n_cells])) { *why = "src_x outside the mesh"; return HWW_E_INVALID_ARG; }
-  if (sweep_lds_bytes(p->n_cells, p->n_chunks, 64) > 160 * 1024) { *why = "too many cells for the LDS histogram (I <= 3300)"; return HWW_E_INVALID_ARG; }
+  if (sweep_lds_bytes(p->n_cells, p->n_chunks, 64) > 160 * 1024) { *why = "too many cells for the LDS histogram (I <= 3136 with 2..8 chunks, 3137 with 1)"; return HWW_E_INVALID_ARG; }
   return HWW_OK;
 }
 

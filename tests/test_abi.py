@@ -48,6 +48,19 @@ def test_workspace_bytes_and_validation():
         assert ei.value.code == -1
 
 
+def test_largest_mesh_is_accepted_and_one_more_cell_is_not():
+    # The sweep keeps each work-group's tallies in LDS ([I][6] doubles):
+    # 3136 cells fit with 2..8 chunks, 3137 do not.
+    for I, ok in ((3136, True), (3137, False)):
+        w = W.homogeneous(f"mesh-{I}", -1.0, 1.0, I, 1.0, 0.5, n_src=1000)
+        if ok:
+            assert H.workspace_bytes(H.spec_from_workload(w)) > 0
+        else:
+            with pytest.raises(H.HwwError) as ei:
+                H.workspace_bytes(H.spec_from_workload(w))
+            assert ei.value.code == -1
+
+
 def _batch_bytes(specs):
     probs = (H.Problem * len(specs))(*[s.to_c() for s in specs])
     return H.lib().hww_batch_workspace_bytes(probs, len(specs))

@@ -111,6 +111,15 @@ def test_large_mesh_fallback_paths():
     _run_pair(w)
 
 
+def test_largest_mesh():
+    # The largest mesh the LDS histogram takes (3136 cells, 4 chunks), with
+    # MA-filtered windows: the maximum size of the sweep's per-work-group
+    # state.
+    w = W.homogeneous("mesh-3136c", -31.36, 31.36, 3136, 1.0, 0.9, dt=0.1, n_steps=4, n_src=5000,
+                      rho=5.0, filter=1, ma_k=3)
+    _run_pair(w)
+
+
 def test_fourier_filtered_end_to_end():
     # Fourier low pass (kappa = 30 of 200 cells) on the closures and the
     # initial condition of every solve.
