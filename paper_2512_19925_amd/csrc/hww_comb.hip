@@ -49,10 +49,10 @@ __device__ inline void for_each_census_slot(const CombArgs<Real> &A, F &&f) {
 // Clears the history counts and cursors and the reduction cells.
 template <typename Real>
 __global__ void comb_clear_kernel(CombArgs<Real> A) {
+  if (blockIdx.x == 0 && threadIdx.x < 8) A.misc[threadIdx.x] = 0ull;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= A.n_hist; i += (int64_t)gridDim.x * blockDim.x) {
     A.cnt[i] = 0ull;
     if (i < A.n_hist) A.cur[i] = 0u;
-    if (i < 8) A.misc[i] = 0ull;
   }
 }
 

@@ -79,6 +79,16 @@ def test_paper_problem_windows_as_printed():
     _run_pair(W.paper_fission().with_(name="paper-printed-ww", window_scale=1, n_steps=10))
 
 
+def test_comb_of_three_histories_after_a_long_one():
+    # Three histories: at step 4 one of them has 215 census particles (the
+    # work-group sort), and every comb orders fewer histories than the
+    # comb's reduction cells: each comb must start from cleared cells.
+    w = W.paper_fission(n_src=3).with_(name="three-histories", n_batches=1, n_steps=6, rho=1.25, eps_min=1e-3,
+                                       bank_capacity=200_000)
+    _run_pair(w)
+    _run_pair(w.with_(name="three-histories-no-wait"), wait=False)
+
+
 def test_fission_analog_without_comb():
     # Integer multiplicity (every fission makes exactly two), no windows, no
     # comb: the population grows freely for a few steps.
