@@ -251,6 +251,20 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
   const uint32_t TILE = (uint32_t)A.tile;
   const CellData<Real> *cellp = A.cells;
   const Window *winp = A.win;
+  const int tid = threadIdx.x;
+  const int r_in = b * nc + A.chunk;
+  const int64_t in_region = (int64_t)r_in * G.stride;
+  // Sizes of the start region's segments (lane s of wave 0 takes segment s,
+  // the overflow segment at s = K; with K = 64 lane 0 takes the overflow
+  // segment as well) and this unit's census counts, loaded before the LDS
+  // set-up so that their latency overlaps it.
+  uint32_t n_s = 0, n_ovf64 = 0, cen = 0;
+  if (tid < 64) {
+    if (tid < K) n_s = (uint32_t)min((int64_t)A.in_bank.segcnt[r_in * K + tid], G.seg_cap);
+    else if (tid == K) n_s = (uint32_t)min((int64_t)A.in_bank.ovfcnt[r_in], G.ovf_cap);
+    if (K == 64 && tid == 0) n_ovf64 = (uint32_t)min((int64_t)A.in_bank.ovfcnt[r_in], G.ovf_cap);
+  }
+  if (tid < nc) cen = A.census.segcnt[(b * nc + tid) * K + jseg];
   if constexpr (kCellsLds) {
     CellData<Real> *sc = reinterpret_cast<CellData<Real> *>(lds_raw);
     Window *sw = reinterpret_cast<Window *>(sc + I);
@@ -264,24 +278,34 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
   }
   Lds L = carve(lds_raw, I, nc, K);
   zero_lds(lds_raw, I, nc, K);
-  const int tid = threadIdx.x;
-  const int r_in = b * nc + A.chunk;
-  const int64_t in_region = (int64_t)r_in * G.stride;
   __syncthreads();
-  if (tid < nc) L.ccnt[tid] = A.census.segcnt[(b * nc + tid) * K + jseg];
-  if (tid == 0) {
-    uint32_t acc = 0;
-    for (int s = 0; s <= K; ++s) {
-      uint32_t n = (s < K) ? A.in_bank.segcnt[r_in * K + s] : A.in_bank.ovfcnt[r_in];
-      const uint32_t cap = (uint32_t)((s < K) ? G.seg_cap : G.ovf_cap);
-      if (n > cap) n = cap;
-      L.nseg[s] = n;
-      L.tstart[s] = acc;
-      acc += (n + TILE - 1u) / TILE;
+  // Tile table: first tile of each start segment (a wave-wide prefix sum of
+  // the segments' tile counts) and the total.
+  if (tid < 64) {
+    const uint32_t t_s = (n_s + TILE - 1u) / TILE;
+    uint32_t incl = t_s;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(incl, o);
+      if (tid >= o) incl += y;
     }
-    L.tstart[K + 1] = acc;
-    L.obusy[0] = blockDim.x >> 6;
+    if (tid <= K) {
+      L.nseg[tid] = n_s;
+      L.tstart[tid] = incl - t_s;
+    }
+    const uint32_t total = __shfl(incl, 63);
+    if (tid == 0) {
+      if (K == 64) {
+        L.nseg[64] = n_ovf64;
+        L.tstart[64] = total;
+        L.tstart[65] = total + (n_ovf64 + TILE - 1u) / TILE;
+      } else {
+        L.tstart[K + 1] = total;
+      }
+      L.obusy[0] = blockDim.x >> 6;
+    }
   }
+  if (tid < nc) L.ccnt[tid] = cen;
   __syncthreads();
 
   const uint32_t lane = __lane_id();
