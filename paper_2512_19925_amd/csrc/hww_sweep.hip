@@ -607,6 +607,7 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
       bool at_census = false;
       int32_t next_chunk = 0;
       uint32_t act = 0u;  // EV_DRAW | EV_SCATTER | WW_ROULETTE | WW_SPLIT
+      bool chk = false;   // window check due after a crossing or a scatter
       uint32_t e_ev = 0u;
       if (active) {
         const int i = cell;
@@ -638,12 +639,15 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
         atomicAdd(&L.trk[i], 1u);
         e_ev = e;
         e = e_ev + 1;
-
-        if (ev == 0) {
+        // Census and collision move the particle by mu l, kept in the cell.
+        if (ev != 1) {
           Real xn = x + mu * l;
           if (xn < xl) xn = xl;
           if (xn > xr) xn = xr;
           x = xn;
+        }
+
+        if (ev == 0) {
           // The flight draw's second variate is unused at census: it picks
           // the chunk of the next step.
           next_chunk = (int32_t)(ub * (Real)nc);
@@ -676,17 +680,13 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
             } else {
               if (mu > (Real)0) { x = xr; cell = i + 1; }
               else { x = xl; cell = i - 1; }
-              act = classify();
-              if (act == WW_ROULETTE) act |= EV_DRAW;
+              chk = true;
             }
           } else {
-            Real xn = x + mu * l;
-            if (xn < xl) xn = xl;
-            if (xn > xr) xn = xr;
-            x = xn;
             if (ub < cd.c) {
               evb |= EVB_SCATTER;
-              act = classify() | EV_DRAW | EV_SCATTER;
+              act = EV_DRAW | EV_SCATTER;
+              chk = true;
             } else if (kFission && (double)ub < A.cfis[i]) {
               evb |= EVB_FISSION;
               act = EV_DRAW | EV_FISSION;
@@ -696,6 +696,14 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
             }
           }
         }
+      }
+
+      // Window check after a crossing or a scatter (one call for both kinds
+      // of lane); a roulette needs the event draw.
+      if (chk) {
+        const uint32_t c = classify();
+        act |= c;
+        if (c == WW_ROULETTE) act |= EV_DRAW;
       }
 
       // Post-event draws, one converged call per kind: slot 1 gives the
