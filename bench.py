@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 figures")
     ap.add_argument("--no-paper", action="store_true", help="skip the paper's supercritical problem")
     ap.add_argument("--batch-steps", type=int, default=50)
+    ap.add_argument("--batch-compare-steps", type=int, default=10,
+                    help="steps of the one-handle-per-replica comparison of the batched form (0: skip it)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--out", default=None, help="also write per-step records (JSON) here")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -213,7 +215,7 @@ def run_batched(steps, compare_steps=10):
     torch.cuda.empty_cache()
     # One handle per replica, same steps.
     seg_single, wall_single = 0, 0.0
-    for w in ws:
+    for w in (ws if compare_steps > 0 else []):
         h = H.Handle(H.spec_from_workload(w))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -239,7 +241,7 @@ def run_batched(steps, compare_steps=10):
             "steps_1_to_%d" % compare_steps: {
                 "batched_segments_per_s": seg_cmp / wall_cmp,
                 "one_handle_per_replica_segments_per_s": seg_single / wall_single,
-                "speedup": (seg_cmp / wall_cmp) / (seg_single / wall_single)}}
+                "speedup": (seg_cmp / wall_cmp) / (seg_single / wall_single)} if compare_steps > 0 else None}
 
 
 def run_fp32_pair(steps=20, n_src=10_000_000):
@@ -552,7 +554,7 @@ def main():
     if args.sweep:
         line["sweep"] = run_sweep(total, args.warmup, args.n_src)
     if not args.no_batch:
-        line["batched"] = run_batched(args.batch_steps)
+        line["batched"] = run_batched(args.batch_steps, args.batch_compare_steps)
     if not args.no_fp32:
         line["fp32"] = run_fp32_pair()
     if not args.no_paper:

@@ -30,6 +30,16 @@
  *                       the mean for kappa = 0, single cosine modes kept or
  *                       removed exactly
  *   orc_ww_centres      max cell = scale exactly, floor eps*scale, shape
+ *   orc_losm_inputs     closed-form uncollided (c = 0) time-layer cell
+ *                       averages, edge currents (exact where J is linear),
+ *                       face values and P_L, P_R on an unequal leaking mesh,
+ *                       for the semi-implicit inputs and the scaled partial
+ *                       closures of the implicit updates; orc_solve_losm is
+ *                       the pinned LOSM step of the (filtered) inputs
+ *   orc_losm_march      source-free manufactured solution with time-dependent
+ *                       closures: 2nd order (CN), 1st order (BE)
+ *   (tests/test_oracle_mutations.py plants ten plausible mistakes in these
+ *   two and checks that each fails a pin)
  *   sweep (uncollided)  closed-form c = 0 pulse solution for all six tallies
  *   sweep (streaming)   exact geometric track lengths, single particles
  *   sweep (scattering)  exact weight/track conservation at c = 1 (analog),
@@ -897,72 +907,58 @@ static void grid_from(const orc_sim *s, const tally_set *t, int track, double sc
   }
 }
 
-int orc_solve_losm(orc_sim *s, const orc_losm_opts *o, double *phi_out, double *J_out) {
-  if (!s || !o) return -1;
-  if (!(o->theta > 0.0 && o->theta <= 1.0) || o->ma_k < 0 || o->kappa < 0) return -1;
-  if (o->apply_windows && (!(o->rho >= 1.0) || !(o->eps_min > 0.0 && o->eps_min <= 1.0))) return -1;
-  if (o->closure_track && !o->lagged && s->track_moments < 2) return -1; /* track closures need K */
-  if (o->lagged && (o->implicit || !o->apply_windows)) return -1;
+/* Start weight of the bank that a solve's windows act on: at the start of
+ * a step (semi-implicit) the census of the finished step, inside a step
+ * (fully implicit) the start bank of the step. */
+static double bank_weight(const orc_sim *s, int implicit) {
+  nsum wtot = {0, 0};
+  for (int c = 0; c < s->n_chunks; ++c)
+    nadd(&wtot, nval(implicit ? &s->w_chunk_start[c] : &s->w_chunk_next[c]));
+  return nval(&wtot);
+}
+
+/* Initial condition and closures of an HLOSM solve (Sec. 3), before any
+ * filter, from the tallies.
+ *  - Initial condition at the old time level: cell averages phi_i of the
+ *    time-layer tally (Eq. ct-mc), face values phi_0, phi_{I+1} from the
+ *    edge-crossing tallies (reading: step averages at the faces stand for
+ *    the point values); interior edge currents by linear interpolation of
+ *    the two neighbouring cell averages, weighted by the opposite cell's
+ *    width; J_0 and J_I from the vacuum boundary relations of Eq.
+ *    losm-disc-bc, J_0 = -phi_0/2 + P_L and J_I = phi_{I+1}/2 - P_R.
+ *  - Closures F = phi/3 - K (Eq. F) in every cell, face values of F and
+ *    P_L, P_R from the edge-crossing tallies (Eq. F_i-n, losm-disc-bc).
+ * implicit = 0 (start of the next step, Eq. losm-disc-semi): everything
+ * from the finished step; the new-time closures are the lagged ones, so
+ * F_n = F_o.  implicit = 1 (inside a step, Eq. losm-disc): the initial
+ * condition from the previous step's time layer, the new-time closures
+ * from the chunks swept so far (time-layer or, with closure_track, track-
+ * length moments), scaled by W_start / W_done, the start weight of the
+ * step over the start weight swept.
+ * Returns 0; 1 when no start weight has been swept yet (no closures exist,
+ * outputs untouched); -2 in the wrong state. */
+int orc_losm_inputs(const orc_sim *s, int32_t implicit, int32_t closure_track, double *phi_o, double *J_o,
+                    double *F_o, double *F_n, double *P) {
+  if (!s || !phi_o || !J_o || !F_o || !F_n || !P) return -1;
   const int I = s->I;
   const tally_set *ic, *cl;
   double scale = 1.0;
-  nsum wtot = {0, 0};
-  if (!o->implicit) {
-    /* Start of step n = step+1: lagged closures of the finished step; the
-     * weight scale is that of the bank the step starts from. */
-    if (s->next_chunk != s->n_chunks || s->step >= s->n_steps) return -2;
+  if (!implicit) {
+    if (s->next_chunk != s->n_chunks) return -2;
     ic = &s->cur; cl = &s->cur;
-    for (int c = 0; c < s->n_chunks; ++c) nadd(&wtot, nval(&s->w_chunk_next[c]));
   } else {
     if (s->step < 1 || s->next_chunk < 1 || s->next_chunk >= s->n_chunks) return -2;
     ic = &s->prev; cl = &s->cur;
-    for (int c = 0; c < s->n_chunks; ++c) nadd(&wtot, nval(&s->w_chunk_start[c]));
     nsum done = {0, 0};
     for (int c = 0; c < s->next_chunk; ++c) nadd(&done, nval(&s->w_chunk_start[c]));
-    if (!(nval(&done) > 0.0)) {
-      /* No start weight swept yet: no closures exist, the update is skipped. */
-      if (phi_out) memset(phi_out, 0, sizeof(double) * (I + 2));
-      if (J_out) memset(J_out, 0, sizeof(double) * (I + 1));
-      return 0;
-    }
-    scale = nval(&wtot) / nval(&done);
+    if (!(nval(&done) > 0.0)) return 1;
+    scale = bank_weight(s, 1) / nval(&done);
   }
-
-  if (o->lagged) {
-    /* Lagged weight windows (Sec. 5): the window shape is the Monte Carlo
-     * track-length flux of the finished step; no LOSM solve.  A step without
-     * track flux (the source) leaves the windows as they are. */
-    double *buf = (double *)calloc((size_t)4 * I, sizeof(double));
-    if (!buf) return -1;
-    grid_fns g = {buf, buf + I, buf + 2 * I, {0}, {0}, {0}};
-    grid_from(s, ic, 1, 1.0, &g);
-    if (phi_out) {
-      phi_out[0] = phi_out[I + 1] = 0.0;
-      memcpy(phi_out + 1, g.phi, sizeof(double) * I);
-    }
-    if (J_out) memset(J_out, 0, sizeof(double) * (I + 1));
-    double mx = 0.0;
-    for (int i = 0; i < I; ++i) mx = g.phi[i] > mx ? g.phi[i] : mx;
-    const double sc = nval(&wtot) / (double)s->n_src;
-    int rc = 0;
-    if (mx > 0.0 && sc > 0.0) {
-      rc = orc_ww_centres(I, g.phi, o->eps_min, o->window_scale ? 1.0 : sc, buf + 3 * I);
-      if (rc == 0) rc = orc_set_windows(s, buf + 3 * I, o->rho);
-    }
-    free(buf);
-    return rc;
-  }
-
-  double *buf = (double *)calloc((size_t)20 * (I + 2), sizeof(double));
+  double *buf = (double *)calloc((size_t)6 * I, sizeof(double));
   if (!buf) return -1;
-  grid_fns gi = {buf, buf + (I + 2), buf + 2 * (I + 2), {0}, {0}, {0}};
-  grid_fns gc = {buf + 3 * (I + 2), buf + 4 * (I + 2), buf + 5 * (I + 2), {0}, {0}, {0}};
-  double *phi_o = buf + 6 * (I + 2), *J_o = buf + 7 * (I + 2), *F_o = buf + 8 * (I + 2);
-  double *F_n = buf + 9 * (I + 2), *phi_n = buf + 10 * (I + 2), *J_n = buf + 11 * (I + 2);
-  double *tmp = buf + 12 * (I + 2), *tmp2 = buf + 13 * (I + 2);
+  grid_fns gi = {buf, buf + I, buf + 2 * I, {0}, {0}, {0}};
+  grid_fns gc = {buf + 3 * I, buf + 4 * I, buf + 5 * I, {0}, {0}, {0}};
 
-  /* Initial condition at t^{n-1}: census cell averages, face values from the
-   * edge-crossing tallies of the previous step. */
   grid_from(s, ic, 0, 1.0, &gi);
   phi_o[0] = gi.fphi[0];
   phi_o[I + 1] = gi.fphi[1];
@@ -977,17 +973,73 @@ int orc_solve_losm(orc_sim *s, const orc_losm_opts *o, double *phi_out, double *
   F_o[I + 1] = gi.fF[1];
   for (int i = 1; i <= I; ++i) F_o[i] = gi.phi[i - 1] / 3.0 - gi.K[i - 1];
 
-  double PL, PR;
-  if (!o->implicit) {
+  if (!implicit) {
     memcpy(F_n, F_o, sizeof(double) * (I + 2));
-    PL = gi.fP[0]; PR = gi.fP[1];
+    P[0] = gi.fP[0]; P[1] = gi.fP[1];
   } else {
-    grid_from(s, cl, o->closure_track, scale, &gc);
+    grid_from(s, cl, closure_track, scale, &gc);
     F_n[0] = gc.fF[0];
     F_n[I + 1] = gc.fF[1];
     for (int i = 1; i <= I; ++i) F_n[i] = gc.phi[i - 1] / 3.0 - gc.K[i - 1];
-    PL = gc.fP[0]; PR = gc.fP[1];
+    P[0] = gc.fP[0]; P[1] = gc.fP[1];
   }
+  free(buf);
+  return 0;
+}
+
+int orc_solve_losm(orc_sim *s, const orc_losm_opts *o, double *phi_out, double *J_out) {
+  if (!s || !o) return -1;
+  if (!(o->theta > 0.0 && o->theta <= 1.0) || o->ma_k < 0 || o->kappa < 0) return -1;
+  if (o->apply_windows && (!(o->rho >= 1.0) || !(o->eps_min > 0.0 && o->eps_min <= 1.0))) return -1;
+  if (o->closure_track && !o->lagged && s->track_moments < 2) return -1; /* track closures need K */
+  if (o->lagged && (o->implicit || !o->apply_windows)) return -1;
+  const int I = s->I;
+  if (!o->implicit && s->step >= s->n_steps) return -2;
+  /* The windows scale with the weight of the bank they act on. */
+  const double sc = bank_weight(s, o->implicit) / (double)s->n_src;
+
+  if (o->lagged) {
+    /* Lagged weight windows (Sec. 5): the window shape is the Monte Carlo
+     * track-length flux of the finished step; no LOSM solve.  A step without
+     * track flux (the source) leaves the windows as they are. */
+    if (s->next_chunk != s->n_chunks) return -2;
+    double *buf = (double *)calloc((size_t)4 * I, sizeof(double));
+    if (!buf) return -1;
+    grid_fns g = {buf, buf + I, buf + 2 * I, {0}, {0}, {0}};
+    grid_from(s, &s->cur, 1, 1.0, &g);
+    if (phi_out) {
+      phi_out[0] = phi_out[I + 1] = 0.0;
+      memcpy(phi_out + 1, g.phi, sizeof(double) * I);
+    }
+    if (J_out) memset(J_out, 0, sizeof(double) * (I + 1));
+    double mx = 0.0;
+    for (int i = 0; i < I; ++i) mx = g.phi[i] > mx ? g.phi[i] : mx;
+    int rc = 0;
+    if (mx > 0.0 && sc > 0.0) {
+      rc = orc_ww_centres(I, g.phi, o->eps_min, o->window_scale ? 1.0 : sc, buf + 3 * I);
+      if (rc == 0) rc = orc_set_windows(s, buf + 3 * I, o->rho);
+    }
+    free(buf);
+    return rc;
+  }
+
+  double *buf = (double *)calloc((size_t)8 * (I + 2), sizeof(double));
+  if (!buf) return -1;
+  double *phi_o = buf, *J_o = buf + (I + 2), *F_o = buf + 2 * (I + 2);
+  double *F_n = buf + 3 * (I + 2), *phi_n = buf + 4 * (I + 2), *J_n = buf + 5 * (I + 2);
+  double *tmp = buf + 6 * (I + 2), *tmp2 = buf + 7 * (I + 2);
+  double P[2];
+  int rc = orc_losm_inputs(s, o->implicit, o->closure_track, phi_o, J_o, F_o, F_n, P);
+  if (rc == 1) {
+    /* No start weight swept yet: no closures exist, the update is skipped. */
+    if (phi_out) memset(phi_out, 0, sizeof(double) * (I + 2));
+    if (J_out) memset(J_out, 0, sizeof(double) * (I + 1));
+    free(buf);
+    return 0;
+  }
+  if (rc != 0) { free(buf); return rc; }
+  /* The filter of Sec. 4 acts on the cell values of F at both time levels
+   * and on the initial condition (phi in the cells, J at every edge). */
   if (o->filter == 1) {
     orc_ma_filter(F_n + 1, I, o->ma_k, tmp); memcpy(F_n + 1, tmp, sizeof(double) * I);
     orc_ma_filter(F_o + 1, I, o->ma_k, tmp); memcpy(F_o + 1, tmp, sizeof(double) * I);
@@ -1002,12 +1054,11 @@ int orc_solve_losm(orc_sim *s, const orc_losm_opts *o, double *phi_out, double *
     free(buf);
     return -1;
   }
-  int rc = orc_losm_step(I, s->edges, s->sig_t, s->sig_s_lo, s->v, s->dt, o->theta,
-                         phi_o, J_o, F_o, F_n, PL, PR, 0.0, 0.0, NULL, NULL, phi_n, J_n);
+  rc = orc_losm_step(I, s->edges, s->sig_t, s->sig_s_lo, s->v, s->dt, o->theta,
+                     phi_o, J_o, F_o, F_n, P[0], P[1], 0.0, 0.0, NULL, NULL, phi_n, J_n);
   if (rc == 0) {
     if (phi_out) memcpy(phi_out, phi_n, sizeof(double) * (I + 2));
     if (J_out) memcpy(J_out, J_n, sizeof(double) * (I + 1));
-    double sc = nval(&wtot) / (double)s->n_src;
     /* An empty bank has nothing to window: the windows stay as they are. */
     if (o->apply_windows && sc > 0.0) {
       /* Eq. ww-center as printed has its largest centre at 1; window_scale 0
@@ -1021,32 +1072,14 @@ int orc_solve_losm(orc_sim *s, const orc_losm_opts *o, double *phi_out, double *
 }
 
 /* Closures and initial condition that the finished step hands to the next
- * (Sec. 3): unfiltered F, P_L, P_R, phi, J from the census and face tallies
- * of the step, exactly as the semi-implicit solve forms them. */
+ * (Sec. 3): the unfiltered inputs of the next step's semi-implicit solve. */
 int orc_get_closures(const orc_sim *s, double *F, double *P, double *phi, double *J) {
   if (!s || !F || !P || !phi || !J) return -1;
-  if (s->next_chunk != s->n_chunks) return -2;
-  const int I = s->I;
-  double *buf = (double *)calloc((size_t)3 * I, sizeof(double));
-  if (!buf) return -1;
-  grid_fns g = {buf, buf + I, buf + 2 * I, {0}, {0}, {0}};
-  grid_from(s, &s->cur, 0, 1.0, &g);
-  phi[0] = g.fphi[0];
-  phi[I + 1] = g.fphi[1];
-  for (int i = 1; i <= I; ++i) phi[i] = g.phi[i - 1];
-  for (int i = 1; i <= I - 1; ++i) {
-    double dl = s->edges[i] - s->edges[i - 1], dr = s->edges[i + 1] - s->edges[i];
-    J[i] = (dr * g.J[i - 1] + dl * g.J[i]) / (dl + dr);
-  }
-  J[0] = -0.5 * phi[0] + g.fP[0];
-  J[I] = 0.5 * phi[I + 1] - g.fP[1];
-  F[0] = g.fF[0];
-  F[I + 1] = g.fF[1];
-  for (int i = 1; i <= I; ++i) F[i] = g.phi[i - 1] / 3.0 - g.K[i - 1];
-  P[0] = g.fP[0];
-  P[1] = g.fP[1];
-  free(buf);
-  return 0;
+  double *Fn = (double *)calloc((size_t)s->I + 2, sizeof(double));
+  if (!Fn) return -1;
+  int rc = orc_losm_inputs(s, 0, 0, phi, J, F, Fn, P);
+  free(Fn);
+  return rc;
 }
 
 /* ------------------------------------------------------------------------ */

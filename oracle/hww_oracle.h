@@ -84,6 +84,14 @@ int orc_sweep_chunk(orc_sim *s, int32_t step, int32_t chunk);
  * size and the total weight that the comb distributes. */
 int orc_comb(orc_sim *s, int64_t n_target, int64_t *n_before, double *w_total);
 int orc_solve_losm(orc_sim *s, const orc_losm_opts *o, double *phi_out, double *J_out);
+/* Initial condition phi_o (I+2), J_o (I+1), F_o (I+2) and closures F_n
+ * (I+2), P (2: P_L, P_R) of an HLOSM solve, before any filter:
+ * implicit = 0 the semi-implicit solve at the start of the next step
+ * (F_n = F_o, the lagged closures), 1 the fully implicit solve inside the
+ * step after the chunks swept so far.  Returns 1 when no start weight has
+ * been swept yet (no closures), -2 in the wrong state. */
+int orc_losm_inputs(const orc_sim *s, int32_t implicit, int32_t closure_track, double *phi_o, double *J_o,
+                    double *F_o, double *F_n, double *P);
 /* Unfiltered closures F (I+2), P (2) and initial condition phi (I+2), J (I+1)
  * that the finished step hands to the next. */
 int orc_get_closures(const orc_sim *s, double *F, double *P, double *phi, double *J);

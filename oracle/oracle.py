@@ -36,14 +36,20 @@ def build() -> str:
 
 
 _lib = None
+# A copy of the oracle built elsewhere (tests that plant a mistake in the
+# oracle's source load their mutated build through this variable).
+_LIB_OVERRIDE = os.environ.get("HWW_ORACLE_LIB")
 
 
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build()
-        L = C.CDLL(_LIB)
+        if _LIB_OVERRIDE:
+            L = C.CDLL(_LIB_OVERRIDE)
+        else:
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build()
+            L = C.CDLL(_LIB)
         dp = C.POINTER(C.c_double)
         L.orc_philox4x32_10.argtypes = [C.POINTER(C.c_uint32)] * 3
         L.orc_u53.argtypes = [C.c_uint32, C.c_uint32]
@@ -58,6 +64,7 @@ def lib():
         L.orc_comb.argtypes = [C.c_void_p, C.c_int64, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
         L.orc_solve_losm.argtypes = [C.c_void_p, C.c_void_p, dp, dp]
         L.orc_get_closures.argtypes = [C.c_void_p, dp, dp, dp, dp]
+        L.orc_losm_inputs.argtypes = [C.c_void_p, C.c_int32, C.c_int32, dp, dp, dp, dp, dp]
         L.orc_get_tallies.argtypes = [C.c_void_p, C.c_int32, dp, dp]
         L.orc_get_counters.argtypes = [C.c_void_p, C.POINTER(C.c_uint64)]
         L.orc_get_tracks.argtypes = [C.c_void_p, C.POINTER(C.c_uint64)]
@@ -293,6 +300,19 @@ class OracleSim:
         J = np.zeros(self.I + 1)
         _check("solve_losm", lib().orc_solve_losm(self._h, C.byref(o), _dp(phi), _dp(J)))
         return phi, J
+
+    def losm_inputs(self, implicit, closure_track=0):
+        """Unfiltered initial condition and closures of the next HLOSM solve:
+        (phi_o, J_o, F_o, F_n, P), or None when no start weight has been swept
+        yet in the step (implicit solve without closures)."""
+        phi_o, J_o = np.zeros(self.I + 2), np.zeros(self.I + 1)
+        F_o, F_n, P = np.zeros(self.I + 2), np.zeros(self.I + 2), np.zeros(2)
+        rc = lib().orc_losm_inputs(self._h, int(bool(implicit)), int(closure_track), _dp(phi_o), _dp(J_o),
+                                   _dp(F_o), _dp(F_n), _dp(P))
+        if rc == 1:
+            return None
+        _check("losm_inputs", rc)
+        return phi_o, J_o, F_o, F_n, P
 
     def closures(self):
         F, P = np.zeros(self.I + 2), np.zeros(2)
