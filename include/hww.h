@@ -226,16 +226,27 @@ int hww_losm_march(hww_handle *h, const double *sigma_t, const double *sigma_s, 
                    const double *F, const double *P, const double *phi0, const double *J0, const double *weights,
                    double *phi_hist, double *J_hist, double *G);
 
-/* Gradient of the G of the last hww_losm_march with respect to sigma_t and
- * sigma_s of every cell (I host doubles each), by the adjoint of the
- * discretised march: transposed solves backward in time.  I <= 4096.
+/* Gradient, with respect to sigma_t and sigma_s of every cell (I host
+ * doubles each), of a functional of the last hww_losm_march's flux history,
+ * by the adjoint of the discretised march (Sec. 3 Eq. losm-disc): transposed
+ * solves backward in time, A^T lambda^n = dG/dphi^n + B^T lambda^{n+1}, then
+ * dG/dp = -sum_n lambda^n . (dA/dp u^n - dB/dp u^{n-1}).  dG_dphi gives
+ * dG/dphi_i^n ((n_steps+1) x (I+2) host doubles, rows n = 0..n_steps of the
+ * march); NULL takes the march's weights, i.e. the gradient of its G.  The
+ * entry for n = 0 is not used (phi^0 is an input).  I <= 4096.
  * Errors: HWW_E_STATE without a preceding march.  Synchronises. */
-int hww_losm_adjoint(hww_handle *h, double *grad_sigma_t, double *grad_sigma_s);
+int hww_losm_adjoint(hww_handle *h, const double *dG_dphi, double *grad_sigma_t, double *grad_sigma_s);
 
-/* Copy a tally array of the current step to host memory (raw per-batch sums,
- * not normalised: track sums are w*l, census sums v*w, face sums w f(mu)/|mu|).
- * out_bytes must equal the size of the kind.  Synchronises the stream. */
-int hww_read_tallies(hww_handle *h, int32_t kind, void *out, int64_t out_bytes);
+/* Copy a tally array of the current step to host memory.  raw = 1: per-batch
+ * sums as scored (track sums w*l, time-layer sums v*w, face sums
+ * w f(mu)/|mu|).  raw = 0: the same per-batch arrays normalised per source
+ * particle, so that their sum over batches is the estimate: track-length
+ * moments over N_src dx_i dt (Eq. phi-mc, step average), time-layer moments
+ * over N_src dx_i (Eq. ct-mc, at t^n), face tallies over N_src dt (step
+ * averages at the faces); the other kinds (tracks, windows, bank counts)
+ * are the same either way.  out_bytes must equal the size of the kind.
+ * Synchronises the stream. */
+int hww_read_tallies(hww_handle *h, int32_t kind, int32_t raw, void *out, int64_t out_bytes);
 
 /* Copy one bank to host memory (for checks): which = 0 start bank of the
  * current step, 1 census bank.  After hww_comb, 1 is the combed bank and 0

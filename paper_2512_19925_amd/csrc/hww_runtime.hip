@@ -39,7 +39,7 @@ struct Layout {
   int64_t off_err, off_status, off_scratch, off_factor, off_phi_out, off_J_out;
   int64_t off_F_out, off_P_out;
   int64_t off_m_sig, off_m_F, off_m_P, off_m_phi0, off_m_J0, off_m_w, off_m_hist, off_m_fac, off_m_fact, off_m_G,
-      off_m_g;
+      off_m_g, off_m_dw;
 };
 
 int64_t align_up(int64_t v) { return (v + 255) & ~int64_t(255); }
@@ -162,6 +162,7 @@ void make_layout(const hww_problem &p, Layout *L, bool member = false) {
   L->off_m_fact = c.take(8 * 3 * n);
   L->off_m_G = c.take(8);
   L->off_m_g = c.take(8 * 2 * I);
+  L->off_m_dw = c.take(8 * N1 * (I + 2));
   if (p.comb && !member) {
     L->n_hist = std::max<int64_t>(p.n_src, p.bank_capacity);
     L->comb_slots = slots;
@@ -279,6 +280,7 @@ struct hww_handle {
   int64_t launch_count = 0;    // sweep launches since init (timed or not)
   int step_ev0 = 0;            // first event pair of the current step
   std::vector<hipEvent_t> ev;  // start/stop pairs of every sweep launch since init
+  std::vector<double> dx_host;  // cell widths (normalised tally reads)
   MarchArgs march{};           // last deterministic march (its state stays in the workspace)
   int march_ok = 0;
   int ev_used = 0;             // pairs recorded
@@ -457,6 +459,8 @@ int zero_counts(hww_handle *h, int k) {
 // Point the handle's arrays into its part of the workspace.
 void carve_handle(hww_handle *h, const hww_problem &problem, char *ws, const Layout &L, hipStream_t stream) {
   h->p = problem;
+  h->dx_host.resize(problem.n_cells);
+  for (int i = 0; i < problem.n_cells; ++i) h->dx_host[i] = problem.edges[i + 1] - problem.edges[i];
   h->p.edges = h->p.sigma_t = h->p.sigma_s = h->p.sigma_f = nullptr;
   h->cfis = problem.sigma_f ? reinterpret_cast<double *>(ws + L.off_cfis) : nullptr;
   h->nu_f = problem.sigma_f ? problem.nu_f : 0.0;
@@ -1247,17 +1251,43 @@ int hww_losm_march(hww_handle *h, const double *sigma_t, const double *sigma_s, 
   return HWW_OK;
 }
 
-int hww_losm_adjoint(hww_handle *h, double *grad_sigma_t, double *grad_sigma_s) {
+int hww_losm_adjoint(hww_handle *h, const double *dG_dphi, double *grad_sigma_t, double *grad_sigma_s) {
   if (!h || !grad_sigma_t || !grad_sigma_s) return HWW_E_INVALID_ARG;
   if (h->is_batch || h->is_view || !h->march_ok) return fail(h, HWW_E_STATE, "the adjoint needs a preceding hww_losm_march");
   if (h->I > 4 * 1024) return fail(h, HWW_E_INVALID_ARG, "the adjoint handles I <= 4096");
-  HIPCHK(h, launch_adjoint(h->march, h->stream));
-  HIPCHK(h, hipMemcpyAsync(grad_sigma_t, h->march.g_t, 8 * (size_t)h->I, hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(h, hipMemcpyAsync(grad_sigma_s, h->march.g_s, 8 * (size_t)h->I, hipMemcpyDeviceToHost, h->stream));
+  MarchArgs a = h->march;
+  if (dG_dphi) {
+    double *dw = reinterpret_cast<double *>(h->ws + h->L.off_m_dw);
+    const size_t N1 = (size_t)a.n_steps + 1, M = (size_t)h->I + 2;
+    HIPCHK(h, hipMemcpyAsync(dw, dG_dphi, 8 * N1 * M, hipMemcpyHostToDevice, h->stream));
+    a.w = dw;
+  }
+  HIPCHK(h, launch_adjoint(a, h->stream));
+  HIPCHK(h, hipMemcpyAsync(grad_sigma_t, a.g_t, 8 * (size_t)h->I, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipMemcpyAsync(grad_sigma_s, a.g_s, 8 * (size_t)h->I, hipMemcpyDeviceToHost, h->stream));
   return poll_errors(h);
 }
 
-int hww_read_tallies(hww_handle *h, int32_t kind, void *out, int64_t out_bytes) {
+// Normalise a tally array of handle h in place (Eqs. phi-mc, ct-mc): track
+// sums w*l over N_src dx dt, time-layer sums v*w over N_src dx, face sums
+// w f(mu)/|mu| over N_src dt; other kinds are left as they are.
+static void normalise_tallies(const hww_handle *h, int32_t kind, double *o) {
+  const double N = (double)h->p.n_src, dt = h->p.dt;
+  const int64_t I = h->I, B = h->B;
+  if (kind == HWW_TALLY_CELLS || kind == HWW_TALLY_PREV_CELLS) {
+    for (int64_t b = 0; b < B; ++b)
+      for (int64_t i = 0; i < I; ++i) {
+        double *c = o + (b * I + i) * 6;
+        const double nt = N * h->dx_host[i] * dt, nc = N * h->dx_host[i];
+        for (int k = 0; k < 3; ++k) c[k] /= nt;
+        for (int k = 3; k < 6; ++k) c[k] /= nc;
+      }
+  } else if (kind == HWW_TALLY_BOUNDARY || kind == HWW_TALLY_PREV_BOUNDARY) {
+    for (int64_t k = 0; k < B * 6; ++k) o[k] /= N * dt;
+  }
+}
+
+int hww_read_tallies(hww_handle *h, int32_t kind, int32_t raw, void *out, int64_t out_bytes) {
   if (!h || !out) return HWW_E_INVALID_ARG;
   if (h->is_batch) {
     int64_t need = 0;
@@ -1283,7 +1313,7 @@ int hww_read_tallies(hww_handle *h, int32_t kind, void *out, int64_t out_bytes) 
         case HWW_TALLY_WINDOWS: sz = 8 * 3 * (int64_t)r->I; break;
         default: sz = 16; break;
       }
-      const int rc = hww_read_tallies(r, kind, o, sz);
+      const int rc = hww_read_tallies(r, kind, raw, o, sz);
       if (rc != HWW_OK) return fail(h, rc, r->msg);
       o += sz;
     }
@@ -1327,7 +1357,9 @@ int hww_read_tallies(hww_handle *h, int32_t kind, void *out, int64_t out_bytes) 
     return poll_errors(h);
   }
   HIPCHK(h, hipMemcpyAsync(out, src, bytes, hipMemcpyDeviceToHost, h->stream));
-  return poll_errors(h);
+  const int rc = poll_errors(h);
+  if (rc == HWW_OK && !raw) normalise_tallies(h, kind, static_cast<double *>(out));
+  return rc;
 }
 
 int hww_read_bank(hww_handle *h, int32_t which, int64_t cap, int64_t *count, double *x, double *mu, double *w,

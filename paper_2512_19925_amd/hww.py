@@ -93,10 +93,10 @@ def lib():
         L.hww_read_run_stats.argtypes = [vp, C.POINTER(StepStats)]
         L.hww_comb.argtypes = [vp, C.c_int64, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
         L.hww_solve_losm.argtypes = [vp, C.POINTER(LosmOpts), dp, dp]
-        L.hww_read_tallies.argtypes = [vp, C.c_int32, vp, C.c_int64]
+        L.hww_read_tallies.argtypes = [vp, C.c_int32, C.c_int32, vp, C.c_int64]
         L.hww_read_closures.argtypes = [vp, dp, dp, dp, dp]
         L.hww_losm_march.argtypes = [vp, dp, dp, C.c_double, C.c_int32] + [dp] * 8
-        L.hww_losm_adjoint.argtypes = [vp, dp, dp]
+        L.hww_losm_adjoint.argtypes = [vp, dp, dp, dp]
         L.hww_read_bank.argtypes = [vp, C.c_int32, C.c_int64, C.POINTER(C.c_int64)] + [vp] * 8
         L.hww_batch_workspace_bytes.argtypes = [C.POINTER(Problem), C.c_int32]
         L.hww_batch_workspace_bytes.restype = C.c_int64
@@ -263,7 +263,8 @@ class Handle:
         self._check("hww_solve_losm", lib().hww_solve_losm(self._h, C.byref(o), _dp(phi), _dp(J)))
         return (phi, J) if want_solution else None
 
-    def read_tallies(self, kind=TALLY_CELLS):
+    def read_tallies(self, kind=TALLY_CELLS, raw=True):
+        """Per-batch tally array; raw=False normalises it per source particle."""
         I, B = self.I, self.B
         shapes = {TALLY_CELLS: ((B, I, 6), np.float64), TALLY_BOUNDARY: ((B, 2, 3), np.float64),
                   TALLY_TRACKS: ((I,), np.uint64), TALLY_PREV_CELLS: ((B, I, 6), np.float64),
@@ -271,7 +272,8 @@ class Handle:
                   TALLY_BANK_COUNTS: ((2,), np.uint64)}
         shape, dt = shapes[kind]
         out = np.zeros(shape, dtype=dt)
-        self._check("hww_read_tallies", lib().hww_read_tallies(self._h, int(kind), out.ctypes.data, out.nbytes))
+        self._check("hww_read_tallies", lib().hww_read_tallies(self._h, int(kind), int(bool(raw)), out.ctypes.data,
+                                                               out.nbytes))
         return out
 
     def read_bank(self, which):
@@ -306,9 +308,12 @@ class Handle:
             _dp(ph), _dp(jh), C.byref(G)))
         return (G.value, ph, jh) if histories else G.value
 
-    def losm_adjoint(self):
+    def losm_adjoint(self, dG_dphi=None):
+        """Gradient of the last march's G (or of the functional whose
+        derivative with respect to the flux history is dG_dphi)."""
         gt, gs = np.zeros(self.I), np.zeros(self.I)
-        self._check("hww_losm_adjoint", lib().hww_losm_adjoint(self._h, _dp(gt), _dp(gs)))
+        d = None if dG_dphi is None else _f64(dG_dphi)
+        self._check("hww_losm_adjoint", lib().hww_losm_adjoint(self._h, _dp(d), _dp(gt), _dp(gs)))
         return gt, gs
 
     def sync(self):
@@ -398,7 +403,7 @@ class Batch:
         js = np.split(J, np.cumsum([i + 1 for i in self.I])[:-1])
         return ps, js
 
-    def read_tallies(self, kind=TALLY_CELLS):
+    def read_tallies(self, kind=TALLY_CELLS, raw=True):
         """List of per-replica arrays (same shapes as Handle.read_tallies)."""
         def shape(I, B):
             return {TALLY_CELLS: ((B, I, 6), np.float64), TALLY_BOUNDARY: ((B, 2, 3), np.float64),
@@ -408,7 +413,8 @@ class Batch:
         shapes = [shape(I, B) for I, B in zip(self.I, self.B)]
         sizes = [int(np.prod(sh)) * 8 for sh, _ in shapes]
         buf = np.zeros(sum(sizes), dtype=np.uint8)
-        self._check("hww_read_tallies", lib().hww_read_tallies(self._h, int(kind), buf.ctypes.data, buf.nbytes))
+        self._check("hww_read_tallies", lib().hww_read_tallies(self._h, int(kind), int(bool(raw)), buf.ctypes.data,
+                                                               buf.nbytes))
         out, o = [], 0
         for (sh, dt), sz in zip(shapes, sizes):
             out.append(buf[o:o + sz].view(dt).reshape(sh).copy())
