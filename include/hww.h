@@ -140,6 +140,25 @@ int64_t hww_workspace_bytes(const hww_problem *problem);
 int hww_init_problem(const hww_problem *problem, void *dev_workspace, int64_t ws_bytes,
                      void *hip_stream, hww_handle **out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): hww_init_problem
+ * with the library's own fixed workspace in place of dev_workspace.  Each
+ * GPU the library runs on holds one static array of
+ * HWW_STATIC_WORKSPACE_BYTES bytes until the process ends; the handle works
+ * in the copy of the device that is current at this call (hip_stream, if not
+ * NULL, must belong to that device).  The call allocates no device memory.
+ * Every handle made this way on one GPU shares that GPU's array, so at most
+ * one may be live per GPU at a time: a second call before hww_destroy of the
+ * first returns HWW_E_STATE (two processes, or handles that overlap in any
+ * other way, would race).  The array keeps the last handle's contents; this
+ * call clears every accumulator the sweep and the solves start from.
+ * Errors: as hww_init_problem; HWW_E_INVALID_ARG also when the problem needs
+ * more than HWW_STATIC_WORKSPACE_BYTES (hww_workspace_bytes tells), or the
+ * stream belongs to another device; HWW_E_DEVICE when the array's address
+ * cannot be looked up. */
+#define HWW_STATIC_WORKSPACE_BYTES (160ll << 20)
+int hww_init_problem_static(const hww_problem *problem, void *hip_stream, hww_handle **out);
+
 /* Set absolute window centres ww_i (Sec. 2): ceiling = ww*rho, floor = ww/rho.
  * centre: I positive finite host doubles, or NULL for analog (no windows).
  * Errors: HWW_E_INVALID_ARG (rho < 1), HWW_E_NUMERIC (a centre <= 0 or not finite). */

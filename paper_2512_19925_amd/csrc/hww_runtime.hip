@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -214,6 +215,39 @@ std::string g_init_error;
 
 }  // namespace
 
+// Fixed device workspace of hww_init_problem_static, for callers that cannot
+// allocate device memory.  Every GPU the library runs on holds one copy of
+// it until the process ends.  Host code never passes this name to a kernel
+// or a copy: it stands in for the array on the host only.  The device
+// address of each GPU's copy comes from hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[HWW_STATIC_WORKSPACE_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+char *g_static_ptr[kMaxDevices];   // device address of each GPU's `scratch` (null until looked up)
+bool g_static_busy[kMaxDevices];   // a live handle works in that GPU's copy
+
+// Device address of the current device's copy of the static workspace.
+// Looked up once per device, with that device current.  Caller holds
+// g_static_mu.
+int static_workspace(int dev, char **ptr, std::string *why) {
+  if (!g_static_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      *why = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+      return HWW_E_DEVICE;
+    }
+    g_static_ptr[dev] = static_cast<char *>(p);
+  }
+  *ptr = g_static_ptr[dev];
+  return HWW_OK;
+}
+
+}  // namespace
+
 struct hww_handle {
   hww_problem p{};
   int I = 0, B = 0, nc = 0, R = 0, K = 1;
@@ -257,6 +291,7 @@ struct hww_handle {
   bool cells_lds = false;      // the sweep keeps the per-cell records in LDS
   int cells_mode = 0;          // batches: 0 no replica, 1 every replica, 2 some keep cell records in LDS
   int is_view = 0;             // a replica of a batch, for reads only
+  int static_dev = -1;        // device whose static workspace the handle uses (-1: caller's)
   // Batch of replicas (is_batch): the replicas are handles of their own
   // whose small per-replica arrays live in shared arrays of the batch.
   int is_batch = 0;
@@ -863,6 +898,50 @@ int hww_init_problem(const hww_problem *problem, void *dev_workspace, int64_t ws
     g_init_error = h->msg;
     destroy_events(h);
     delete h;
+    return rc;
+  }
+  *out = h;
+  return HWW_OK;
+}
+
+int hww_init_problem_static(const hww_problem *problem, void *hip_stream, hww_handle **out) {
+  std::string why;
+  if (!out) return fail(nullptr, HWW_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  int rc = validate(problem, &why);
+  if (rc != HWW_OK) return fail(nullptr, rc, why);
+  Layout L;
+  make_layout(*problem, &L);
+  if (L.total > (int64_t)HWW_STATIC_WORKSPACE_BYTES)
+    return fail(nullptr, HWW_E_INVALID_ARG,
+                "problem needs " + std::to_string(L.total) + " workspace bytes; the static workspace holds " +
+                    std::to_string((int64_t)HWW_STATIC_WORKSPACE_BYTES));
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+    return fail(nullptr, HWW_E_DEVICE, "no current device (or its ordinal is >= 64)");
+  if (hip_stream) {
+    hipDevice_t sdev = -1;
+    if (hipStreamGetDevice(reinterpret_cast<hipStream_t>(hip_stream), &sdev) != hipSuccess || sdev != dev)
+      return fail(nullptr, HWW_E_INVALID_ARG, "the stream does not belong to the current device");
+  }
+  char *ws = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (g_static_busy[dev]) return fail(nullptr, HWW_E_STATE, "a live handle already uses this device's static workspace");
+    rc = static_workspace(dev, &ws, &why);
+    if (rc != HWW_OK) return fail(nullptr, rc, why);
+    g_static_busy[dev] = true;
+  }
+  hww_handle *h = new hww_handle();
+  h->static_dev = dev;
+  // prime_handle clears every accumulator the previous user of the array
+  // left behind; the banks and queues are read only below their counts.
+  carve_handle(h, *problem, ws, L, reinterpret_cast<hipStream_t>(hip_stream));
+  rc = prime_handle(h, *problem);
+  if (rc == HWW_OK) rc = poll_errors(h);
+  if (rc != HWW_OK) {
+    g_init_error = h->msg;
+    hww_destroy(h);
     return rc;
   }
   *out = h;
@@ -1696,6 +1775,10 @@ void hww_destroy(hww_handle *h) {
   (void)hipStreamSynchronize(h->stream);
   destroy_events(h);
   for (hww_handle *r : h->rep) delete r;
+  if (h->static_dev >= 0) {
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    g_static_busy[h->static_dev] = false;
+  }
   delete h;
 }
 

@@ -24,7 +24,7 @@ TALLY_CELLS, TALLY_BOUNDARY, TALLY_TRACKS, TALLY_PREV_CELLS, TALLY_PREV_BOUNDARY
     TALLY_BANK_COUNTS = range(7)
 
 # Every symbol include/hww.h declares.
-EXPORTS = ["hww_workspace_bytes", "hww_init_problem", "hww_set_windows", "hww_sweep_step",
+EXPORTS = ["hww_workspace_bytes", "hww_init_problem", "hww_init_problem_static", "hww_set_windows", "hww_sweep_step",
            "hww_read_run_stats", "hww_comb", "hww_solve_losm", "hww_read_closures", "hww_losm_march", "hww_losm_adjoint",
            "hww_read_tallies", "hww_read_bank", "hww_batch_workspace_bytes", "hww_init_batch",
            "hww_batch_replica", "hww_autotune", "hww_set_timing", "hww_sync", "hww_last_error", "hww_destroy"]
@@ -88,6 +88,7 @@ def lib():
         L.hww_workspace_bytes.argtypes = [C.POINTER(Problem)]
         L.hww_workspace_bytes.restype = C.c_int64
         L.hww_init_problem.argtypes = [C.POINTER(Problem), vp, C.c_int64, vp, C.POINTER(vp)]
+        L.hww_init_problem_static.argtypes = [C.POINTER(Problem), vp, C.POINTER(vp)]
         L.hww_set_windows.argtypes = [vp, dp, C.c_double]
         L.hww_sweep_step.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(StepStats)]
         L.hww_read_run_stats.argtypes = [vp, C.POINTER(StepStats)]
@@ -175,17 +176,30 @@ class Handle:
         v._owner = owner
         return v
 
-    def __init__(self, spec: ProblemSpec, device="cuda", stream=None):
+    def __init__(self, spec: ProblemSpec, device="cuda", stream=None, static_workspace=False):
+        """static_workspace=True: hww_init_problem_static (the library's
+        fixed per-GPU workspace; no device allocation here or there)."""
         import torch
         self.spec = spec
         self.I = len(spec.sigma_t)
         self.B = int(spec.n_batches)
         self.n_chunks = int(spec.n_chunks)
         nbytes = workspace_bytes(spec)
-        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.workspace.device)
         p = spec.to_c()
         h = C.c_void_p()
+        if static_workspace:
+            dev = torch.device(device)
+            dev = torch.device("cuda", torch.cuda.current_device() if dev.index is None else dev.index)
+            self.workspace = None
+            self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+            with torch.cuda.device(dev):
+                rc = lib().hww_init_problem_static(C.byref(p), C.c_void_p(self.stream.cuda_stream), C.byref(h))
+            if rc != HWW_OK:
+                raise HwwError("hww_init_problem_static", rc, lib().hww_last_error(None).decode())
+            self._h = h
+            return
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.workspace.device)
         rc = lib().hww_init_problem(C.byref(p), C.c_void_p(self.workspace.data_ptr()), nbytes,
                                     C.c_void_p(self.stream.cuda_stream), C.byref(h))
         if rc != HWW_OK:

@@ -113,3 +113,19 @@ def test_fission_comb_and_tally_options_validation():
     assert _batch_bytes(specs) == -1
     specs[2] = H.spec_from_workload(ws[2].with_(comb=100))
     assert _batch_bytes(specs) == -1
+
+
+def test_static_workspace_rejects_a_problem_too_big_for_it():
+    # The size check comes before any device call, so it runs without a GPU.
+    import ctypes as C
+    L = H.lib()
+    limit = 160 << 20
+    for n_src, ok in ((10_000, True), (1_000_000, False)):
+        spec = H.spec_from_workload(W.plain_small().with_(n_src=n_src))
+        assert (H.workspace_bytes(spec) <= limit) == ok
+    spec = H.spec_from_workload(W.plain_small().with_(n_src=1_000_000))
+    p = spec.to_c()  # spec keeps the arrays p points into
+    h = C.c_void_p()
+    rc = L.hww_init_problem_static(C.byref(p), None, C.byref(h))
+    assert rc == -1 and not h.value
+    assert b"static workspace holds" in L.hww_last_error(None)
