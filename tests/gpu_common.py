@@ -73,3 +73,38 @@ def assert_bank_match(gb, ob, what=""):
     np.testing.assert_allclose(gb["w"][kg], ob["w"][ko], rtol=1e-12, atol=0, err_msg=what)
     np.testing.assert_array_equal(gb["mu"][kg], ob["mu"][ko], err_msg=what)
     np.testing.assert_array_equal(gb["x"][kg], ob["x"][ko], err_msg=what)
+
+
+KIND_NAMES = ("track phi", "track J", "track K", "census phi", "census J", "census K")
+
+
+def precision_error(steps_g, steps_o, floor=1e-3):
+    """Error of reduced-precision tallies against FP64 ones of the same seed,
+    per tally kind over all cells and steps.  Each step gives [B][I][6] raw
+    per-batch sums.  z = (T_g - T_o) / sigma_o with sigma_o the batch
+    standard deviation of the FP64 sum (cells where it is 0 are left out of
+    z); relative error against |T_o|, J against phi of the same cell and
+    estimator, over cells above floor times the step's largest."""
+    zs = [[] for _ in range(6)]
+    rel = [[] for _ in range(6)]
+    for g, o in zip(steps_g, steps_o):
+        B = o.shape[0]
+        To, Tg = o.sum(0), g.sum(0)
+        sig = np.sqrt(B / (B - 1.0) * ((o - To / B) ** 2).sum(0))
+        scale = np.abs(To)
+        scale[:, 1] = scale[:, 0]
+        scale[:, 4] = scale[:, 3]
+        for k in range(6):
+            m = sig[:, k] > 0
+            zs[k].append((Tg[m, k] - To[m, k]) / sig[m, k])
+            mr = scale[:, k] > floor * scale[:, k].max() if scale[:, k].max() > 0 else np.zeros(len(To), bool)
+            rel[k].append(np.abs(Tg[mr, k] - To[mr, k]) / scale[mr, k])
+    out = {}
+    for k in range(6):
+        z = np.concatenate(zs[k])
+        r = np.concatenate(rel[k])
+        out[KIND_NAMES[k]] = {"n": int(z.size), "max_abs_z": float(np.abs(z).max()) if z.size else 0.0,
+                              "frac_within_3sigma": float(np.mean(np.abs(z) <= 3.0)) if z.size else 1.0,
+                              "median_rel_err": float(np.median(r)) if r.size else 0.0,
+                              "max_rel_err": float(r.max()) if r.size else 0.0}
+    return out

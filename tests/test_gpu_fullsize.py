@@ -1,16 +1,19 @@
 """Full-size checks in the launch configuration the benchmark times: the
 1000-cell, 1e7-particle problem with 32 batches and three window updates per
-step.  With windows fed identically to both sides, the tallies of batch 0
-(the histories with src mod 32 = 0, about 3.1e5 of them) are replayed on the
-oracle and must match to 1e-12; with the HLOSM windows the method's
-invariants are checked at full size."""
+step.  End to end, with each side computing its own HLOSM windows, every
+batch's cell, face and track tallies, the event counters, the windows and the
+census bank are compared with the oracle step by step (the benchmarked
+c = 0.9, rho = 5 problem, and c = 0.99, rho = 2 far enough into the run that
+windows split and roulette); with windows fed identically to both sides,
+batch 0 is replayed; the method's invariants are checked at full size."""
 import math
 
 import numpy as np
 import pytest
 
 import closed_forms as CF
-from gpu_common import assert_tallies_match, need_gpu, say
+from gpu_common import (assert_bank_match, assert_bnd_match, assert_tallies_match, need_gpu, oracle_opts,
+                        oracle_sim, say)
 from oracle import oracle as O
 from paper_2512_19925_amd import hww as H
 from paper_2512_19925_amd import workloads as W
@@ -25,6 +28,55 @@ def _windows(w):
         t = n * w.dt
         return np.exp(-0.5 * (xc / (0.2 + 0.7 * t)) ** 2) + 1e-3
     return f
+
+
+COUNTERS = ["segments", "collisions", "scatters", "absorptions", "crossings", "leaks", "census",
+            "splits", "daughters", "rr_kill", "rr_survive", "histories"]
+
+
+@pytest.mark.parametrize("c,rho,steps,bank_steps", [(0.9, 5.0, 4, (1, 4)), (0.99, 2.0, 13, (9, 11, 13))])
+def test_fullsize_end_to_end_matches_oracle(c, rho, steps, bank_steps):
+    # The method's own windows on both sides (semi-implicit solve, then a
+    # fully implicit one after each of the first three chunks).  At c = 0.99,
+    # rho = 2 the windows first split in step 9 and roulette from step 11.
+    need_gpu()
+    import time
+    w = W.full_scale(c=c, rho=rho)
+    say(f"case {w.name}: n_src={w.n_src}, {steps} steps, HLOSM windows on both sides, all batches")
+    h = H.Handle(H.spec_from_workload(w))
+    sim = oracle_sim(w)
+    opts = oracle_opts(w)
+    kw = H.losm_kwargs(w)
+    seen = {"splits": 0, "rr_kill": 0}
+    for n in range(1, steps + 1):
+        t0 = time.time()
+        h.solve_losm(implicit=False, **kw)
+        sim.solve_losm(opts, implicit=False)
+        for p in range(w.n_chunks):
+            st = h.sweep_step(n, p, stats=(p == w.n_chunks - 1))
+            sim.sweep(n, p)
+            if p < w.n_chunks - 1:
+                h.solve_losm(implicit=True, **kw)
+                sim.solve_losm(opts, implicit=True)
+        oc = sim.counters()
+        cnt = {k: st[k] for k in COUNTERS}
+        assert cnt == {k: oc[k] for k in COUNTERS}, f"step {n}: counters {cnt} vs {oc}"
+        for k in seen:
+            seen[k] += cnt[k]
+        g = h.read_tallies(H.TALLY_CELLS)
+        o, ob = sim.tallies()
+        worst = assert_tallies_match(g, o, what=f"{w.name} step {n}")
+        assert_bnd_match(h.read_tallies(H.TALLY_BOUNDARY), ob, what=f"{w.name} step {n}")
+        assert np.array_equal(h.read_tallies(H.TALLY_TRACKS), sim.tracks()), f"step {n}: tracks"
+        gw, ow = h.read_tallies(H.TALLY_WINDOWS), sim.windows()
+        np.testing.assert_allclose(gw, np.array(ow), rtol=1e-12, atol=0, err_msg=f"step {n}: windows")
+        if n in bank_steps:
+            assert_bank_match(h.read_bank(1), sim.bank(1), what=f"{w.name} step {n}")
+        say(f"  step {n}: census {cnt['census']}, splits {cnt['splits']}, roulette kills {cnt['rr_kill']}, "
+            f"max relative tally difference {worst:.2e} ({time.time() - t0:.1f} s)")
+    if c == 0.99:
+        assert seen["splits"] > 0 and seen["rr_kill"] > 0
+    h.close()
 
 
 def test_fullsize_batch0_matches_oracle():
@@ -66,10 +118,15 @@ def test_fullsize_hww_invariants():
     h = H.Handle(H.spec_from_workload(w))
     recs = []
 
+    tracks_by_step, counts_by_step, wsum_by_step = {}, {}, {}
+
     def on_step(n, hh, st):
         cells = hh.read_tallies(H.TALLY_CELLS)
         s = st[-1]
         recs.append((n, cells, s))
+        tracks_by_step[n] = hh.read_tallies(H.TALLY_TRACKS)
+        counts_by_step[n] = hh.read_tallies(H.TALLY_BANK_COUNTS)
+        wsum_by_step[n] = float(hh.read_bank(1)["w"].sum())
 
     H.run(h, w, steps=steps, on_step=on_step)
     for n, cells, s in recs:
@@ -81,6 +138,10 @@ def test_fullsize_hww_invariants():
         say(f"  step {n}: census weight {mean:.6f} +- {se:.1e} vs {expect:.6f}; census {s['census']}")
         assert abs(mean - expect) < 5 * se + 1e-12
         assert np.all(cells[..., 0] >= 0) and np.all(cells[..., 2] >= 0) and np.all(cells[..., 3] >= 0)
-        assert s["segments"] == s["census"] + s["crossings"] + s["collisions"] + s["leaks"]
-        assert s["collisions"] == s["scatters"] + s["absorptions"]
-        assert s["census"] <= w.capacity()
+        # Counted apart on the device: segments per lane, tracks per cell in
+        # the LDS histogram, census records by the bank's segment counters.
+        assert s["segments"] == int(tracks_by_step[n].sum())
+        assert s["census"] == int(counts_by_step[n][1]) <= w.capacity()
+        assert s["histories"] == int(counts_by_step[n][0])
+        # The census phi tally is v times the census bank's weight.
+        assert abs(cells[..., 3].sum() / w.speed - wsum_by_step[n]) <= 1e-12 * wsum_by_step[n]
