@@ -321,7 +321,11 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
   uint32_t src = 0, e = 0;
   uint64_t lin = 0;
   bool active = false;
-  uint32_t start_act = 0u;  // start-of-step window action of a lane just loaded
+  // Window check still due for the lane's particle in its cell: the
+  // start-of-step check of a particle just loaded from the bank, or the
+  // check after a crossing (made at the top of the next pass, where the new
+  // cell's record is read anyway; the particle does nothing in between).
+  uint32_t pend = 0u;
   // Pending split or fission of this lane: the daughters copy the lane
   // state (a fission daughter draws its own direction).
   uint32_t nd = 0;
@@ -425,9 +429,8 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
   // one converged call per kind.  classify() decides from the weight alone:
   // 0 inside the window, WW_ROULETTE below the floor, WW_SPLIT above the
   // ceiling (an impossible split raises an error and ends the particle).
-  auto classify = [&]() -> uint32_t {
+  auto classify = [&](const Window &wd) -> uint32_t {
     if (!A.ww_on) return 0u;
-    const Window wd = winp[cell];
     if (w > wd.ceil) {
       const double ndf = ceil(w / wd.ww);
       if (!(ndf >= 2.0) || ndf > 1.0e9) {
@@ -445,8 +448,7 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
     return w < wd.floor ? WW_ROULETTE : 0u;
   };
   // Roulette with the uniform xi: survive at the window centre or die.
-  auto roulette = [&](double xi, bool at_start) {
-    const double ww = winp[cell].ww;
+  auto roulette = [&](double xi, double ww, bool at_start) {
     if (xi < w / ww) {
       w = ww;
       evb |= at_start ? EVB_START_SURVIVE : EVB_RR_SURVIVE;
@@ -457,8 +459,8 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
   };
   // Split into N_d = ceil(w / ww) equal daughters; the lane keeps daughter
   // 0, the others take lineage base + j and the event index e_daughter.
-  auto split = [&](const uint32_t r[4], uint32_t e_daughter, bool at_start) {
-    const double ndf = ceil(w / winp[cell].ww);
+  auto split = [&](const uint32_t r[4], double ww, uint32_t e_daughter, bool at_start) {
+    const double ndf = ceil(w / ww);
     lin_base = (uint64_t)r[0] | ((uint64_t)r[1] << 32);
     nd = (uint32_t)ndf;
     w = w / ndf;
@@ -565,7 +567,7 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
               cell = tg.cell;
               tau = dt_r;
               active = true;
-              start_act = classify();
+              pend = 1u;
             } else {
               const XMu<Real> xm = A.dq.xm[k];
               const WTau wt = A.dq.wt[k];
@@ -579,23 +581,12 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
               e = tg.e;
               cell = tg.cell;
               active = true;
+              pend = 0u;
             }
           }
           if (tile_bank) n_hist += take;
           tile_next += take;
         }
-        // Start-of-step checks of the lanes just loaded: one draw, from
-        // slot 2 (roulette) or slot 5 (lineage of a split) per lane.
-        if (__ballot(start_act != 0u) != 0) {
-          if (start_act != 0u) {
-            uint32_t r[4];
-            draw_lane(A.seed, A.key1, start_act == WW_SPLIT ? SLOT_LIN_START : SLOT_START, src, lin, e, r);
-            if (start_act == WW_SPLIT) split(r, e, true);
-            else roulette(u53(r[2], r[3]), true);
-          }
-        }
-        start_act = 0u;
-        if (__ballot(nd > 1) != 0) flush_daughters();
       }
       if (__ballot(active) == 0) {
         count_events();
@@ -603,11 +594,39 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
         continue;
       }
 
+      // ------------------------------------------------ cell, window check --
+      // The cell's flight record and its window, read together; then the
+      // pending checks: the start-of-step one draws from slot 2 (roulette)
+      // or 5 (split lineage) at the particle's event index, the one after a
+      // crossing from slot 1 (roulette) or 4 (split lineage) at the index of
+      // the crossing event, e - 1 (Sec. 2; one converged draw for all).
+      CellData<Real> cd{};
+      Window wd{};
+      if (active) {
+        cd = cellp[cell];
+        if (A.ww_on) wd = winp[cell];
+      }
+      uint32_t ck = 0u;
+      if (pend != 0u && active) ck = classify(wd);
+      if (__ballot(ck != 0u) != 0) {
+        if (ck != 0u) {
+          const bool st = pend == 1u;
+          const int slot = ck == WW_SPLIT ? (st ? SLOT_LIN_START : SLOT_LIN_EVENT) : (st ? SLOT_START : SLOT_EVENT);
+          uint32_t r[4];
+          draw_lane(A.seed, A.key1, slot, src, lin, st ? e : e - 1u, r);
+          if (ck == WW_SPLIT) split(r, wd.ww, e, st);
+          else roulette(u53(r[2], r[3]), wd.ww, st);
+        }
+        if (__ballot(nd > 1) != 0) flush_daughters();
+        nd = 0;
+      }
+      pend = 0u;
+
       // --------------------------------------------------------- segment --
       bool at_census = false;
       int32_t next_chunk = 0;
       uint32_t act = 0u;  // EV_DRAW | EV_SCATTER | WW_ROULETTE | WW_SPLIT
-      bool chk = false;   // window check due after a crossing or a scatter
+      bool chk = false;   // window check due after a scatter
       uint32_t e_ev = 0u;
       if (active) {
         const int i = cell;
@@ -615,7 +634,6 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
         draw(A.seed, A.key1, SLOT_FLIGHT, src, lin, e, r);
         const Real ua = uflight<Real>(r[0], r[1]);
         const Real ub = uflight<Real>(r[2], r[3]);
-        const CellData<Real> cd = cellp[i];
         // Exponential flight distance with mean free path 1/sigma_t.
         const Real d_coll = -log_r((Real)1 - ua) * cd.inv_sig;
         const Real xl = cd.xl, xr = cd.xr;
@@ -680,7 +698,7 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
             } else {
               if (mu > (Real)0) { x = xr; cell = i + 1; }
               else { x = xl; cell = i - 1; }
-              chk = true;
+              pend = 2u;
             }
           } else {
             if (ub < cd.c) {
@@ -698,10 +716,10 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
         }
       }
 
-      // Window check after a crossing or a scatter (one call for both kinds
-      // of lane); a roulette needs the event draw.
+      // Window check after a scatter (same cell: its window is in
+      // registers); a roulette needs the event draw.
       if (chk) {
-        const uint32_t c = classify();
+        const uint32_t c = classify(wd);
         act |= c;
         if (c == WW_ROULETTE) act |= EV_DRAW;
       }
@@ -719,7 +737,7 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
           uint32_t r1[4];
           draw(A.seed, A.key1, SLOT_EVENT, src, lin, e_ev, r1);
           if (act & (EV_SCATTER | EV_FISSION)) mu = (Real)2 * uflight<Real>(r1[0], r1[1]) - (Real)1;
-          if (act & WW_ROULETTE) roulette(u53(r1[2], r1[3]), false);
+          if (act & WW_ROULETTE) roulette(u53(r1[2], r1[3]), wd.ww, false);
           if (kFission && (act & EV_FISSION)) {
             nf = (uint32_t)floor(A.nu_f + u53(r1[2], r1[3]));
             atomicAdd(&L.cnt[C_FISSION_BIRTHS], nf);
@@ -733,7 +751,7 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
           uint32_t r2[4];
           draw(A.seed, A.key1, SLOT_LIN_EVENT, src, lin, e_ev, r2);
           if (!kFission || (act & WW_SPLIT)) {
-            split(r2, e, false);
+            split(r2, wd.ww, e, false);
           } else {
             lin_base = (uint64_t)r2[0] | ((uint64_t)r2[1] << 32);
             nd = nf;
