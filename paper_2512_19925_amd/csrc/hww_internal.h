@@ -26,6 +26,12 @@ enum { SLOT_FLIGHT = 0, SLOT_EVENT = 1, SLOT_START = 2, SLOT_BIRTH = 3, SLOT_LIN
 // Work-group-local daughter generations per launch before giving up.
 constexpr int kMaxGenerations = 4096;
 
+// Batch-summed tallies: every sweep work-group adds its histogram into copy
+// (work-group index mod kSumCopies) of [copy][6][I] (column-major), besides
+// its batch's row of [B][I][6]; an LOSM solve adds the copies up.  More copies
+// spread the atomics of the flush over more addresses.
+constexpr int kSumCopies = 4;
+
 // Position and direction of a particle (one 16-byte load in FP64).
 template <typename Real>
 struct alignas(2 * sizeof(Real)) XMu {
@@ -99,6 +105,7 @@ struct SweepArgs {
   Queue<Real> dq;
   int64_t dcap;
   double *tal;                     // [B][I][6]
+  double *tsum;                    // [kSumCopies][6][I] batch sums of tal
   double *bnd;                     // [B][2][3]
   unsigned long long *tracks;      // [I]
   unsigned long long *counters;    // [2][C_NCOUNTERS]: this step, since init
@@ -120,7 +127,7 @@ struct ReplicaDesc {
   int32_t cells_lds;   // the replica's cell records fit in LDS beside its histogram
   BankGeom geom;
   Bank<Real> bank[2];
-  double *tal[2], *bnd[2];
+  double *tal[2], *tsum[2], *bnd[2];
   unsigned long long *tracks, *counters;
   double *wnext;
 };
@@ -170,10 +177,10 @@ struct CombArgs {
 
 struct BeginStepArgs {
   uint32_t *segcnt, *ovfcnt;
-  double *tal, *bnd;
+  double *tal, *tsum, *bnd;
   unsigned long long *tracks, *counters;
   double *wstart, *wnext;
-  int64_t n_seg, n_ovf, n_tal, n_bnd, n_tracks;
+  int64_t n_seg, n_ovf, n_tal, n_tsum, n_bnd, n_tracks;
   int32_t nc;
 };
 
@@ -184,7 +191,8 @@ struct SourceArgs {
   uint32_t seed, key1;
   const double *edges;
   BankGeom geom;
-  double *tal;  // census part of [B][I][6]
+  double *tal;   // census part of [B][I][6]
+  double *tsum;  // and of its batch sums
   double *wnext;
   uint32_t *err;
 };
@@ -193,8 +201,10 @@ struct LosmArgs {
   int32_t I, B, nc;
   double v, dt, n_src;
   const double *edges, *sig_t, *sig_s;
-  const double *tal_ic, *bnd_ic;  // tally set of the initial condition (census at t^{n-1})
-  const double *tal_cl, *bnd_cl;  // tally set of the closures (same as tal_ic when semi-implicit)
+  const double *tsum_ic, *bnd_ic;  // tally set of the initial condition (census at t^{n-1}):
+                                   // batch-sum copies [kSumCopies][6][I], faces [B][2][3]
+  const double *tsum_cl, *bnd_cl;  // tally set of the closures (same as the initial condition's
+                                   // when semi-implicit)
   const double *wstart, *wnext;   // [nc] chunk weights of the start bank / census bank
   int32_t next_chunk;             // chunks already swept in the step (implicit solve)
   double theta;
@@ -206,7 +216,7 @@ struct LosmArgs {
   double *factor;                 // [4][2I+3] LU factors of the system for `theta`, old-time diagonal
   int32_t refactor;               // 1: (re)compute the factors first
   int32_t work_in_lds;            // set by the launcher: grid functions fit in LDS
-  int32_t ic_cached;              // 1: the batch sums of tal_ic/bnd_ic are already in the scratch
+  int32_t ic_cached;              // 1: the initial condition's sums are already in the scratch
   int32_t export_only;            // 1: write phi^{n-1}, J^{n-1}, F^{n-1}, P^{n-1} and stop
   double *F_out, *P_out;          // I+2, 2 (device) for export_only
   Window *win;                    // [I] window centres, ceilings, floors
@@ -219,7 +229,7 @@ struct LosmArgs {
 // the per-call options come from LosmCall.
 struct LosmReplica {
   LosmArgs a;
-  const double *tal[2], *bnd[2];
+  const double *tsum[2], *bnd[2];
 };
 struct LosmCall {
   int32_t cur;  // current tally set

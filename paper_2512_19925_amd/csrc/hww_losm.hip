@@ -8,8 +8,9 @@
 // (Gaussian elimination without pivoting, the Thomas algorithm) are computed
 // once per theta by losm_factor_kernel.  Each solve (losm_kernel, one
 // work-group) then
-//   1. sums the per-batch tallies of the initial-condition set (census at
-//      t^{n-1}, face tallies of step n-1) and of the closure set
+//   1. adds up the batch-sum copies that the sweep's work-groups flushed, of
+//      the initial-condition set (census at t^{n-1}) and of the closure set,
+//      and the per-batch face tallies
 //   2. forms phi^{n-1}, J^{n-1} at edges (linear interpolation of
 //      cell-average currents), F^{n-1}, F^n, P_L, P_R
 //   3. optionally moving-average filters F^n, F^{n-1}, phi^{n-1}, J^{n-1}
@@ -23,7 +24,6 @@
 namespace hww {
 
 static constexpr int LOSM_THREADS = 1024;
-static constexpr int LOSM_REDUCE_THREADS = 512;
 
 // Thomas factors of the solve matrix for A.theta, then the old-time
 // diagonal of every row: factor = [alpha | 1/den | gamma | bb], each 2I+3
@@ -139,100 +139,11 @@ __device__ inline double closure_scale(const LosmArgs &A) {
 
 // Layout of a solve's working arrays (M = I + 2 doubles each): six grid
 // functions, in LDS when they fit (work_in_lds) else at the start of the
-// global scratch; the batch sums of the reduction after them; the Fourier
+// global scratch; the normalised batch sums after them (those of the
+// initial condition are kept for the later solves of the step); the Fourier
 // coefficients after those.
 __device__ inline double *losm_sums(const LosmArgs &A) { return A.scratch + 6 * (A.I + 2); }
 __device__ inline double *losm_fourier_scratch(const LosmArgs &A) { return A.scratch + 12 * (A.I + 2) + 16; }
-
-// Phase 1 over many work-groups: per cell, sum the B batch tallies of the
-// initial-condition set (census phi, J, K) and of the closure set, and
-// normalise per source particle.  A work-group takes 64 cells; its waves
-// each sum a share of the batches and combine through LDS.  With ic_cached
-// the sums of the initial-condition set are still in the scratch from an
-// earlier solve of the same step and only the closure set is read.
-__device__ inline void losm_reduce_body(const LosmArgs &A, int blk) {
-  const int I = A.I;
-  double *gi_phi = losm_sums(A);
-  double *gi_J = gi_phi + I;
-  double *gi_K = gi_J + I;
-  double *gc_phi = gi_K + I;
-  double *gc_K = gc_phi + I;
-  double *faces = gc_K + I;
-  constexpr int NG = LOSM_REDUCE_THREADS / 64;  // wave groups, each summing a share of the batches
-  __shared__ double part[NG][5][64];
-  const double scale = closure_scale(A);
-  const bool ic = !A.ic_cached;
-  if (blk == 0 && threadIdx.x < 12) {
-    // Face values: q = (phi L, phi R, P L, P R, F L, F R) of the initial-
-    // condition set (t < 6) and of the closure set (t >= 6).
-    const int t = threadIdx.x;
-    const int set = t / 6, q = t % 6;
-    const int f = q & 1, kind = q >> 1;
-    if (set == 1 || ic) {
-      const double *bs = set == 0 ? A.bnd_ic : A.bnd_cl;
-      double acc = 0.0;
-#pragma unroll 8
-      for (int b = 0; b < A.B; ++b) acc += bs[(b * 2 + f) * 3 + kind];
-      faces[t] = (set == 0 ? 1.0 : scale) * acc / (A.n_src * A.dt);
-    }
-  }
-  const int kc = A.closure_track ? 0 : 3;
-  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
-  const int i = blk * 64 + lane;
-  double p = 0.0, j = 0.0, k = 0.0, cp = 0.0, ck = 0.0;
-  if (i < I) {
-    if (ic) {
-#pragma unroll 4
-      for (int b = grp; b < A.B; b += NG) {
-        const double *t = A.tal_ic + ((size_t)b * I + i) * 6;
-        p += t[3];
-        j += t[4];
-        k += t[5];
-        const double *tc = A.tal_cl + ((size_t)b * I + i) * 6;
-        cp += tc[kc];
-        ck += tc[kc + 2];
-      }
-    } else {
-#pragma unroll 4
-      for (int b = grp; b < A.B; b += NG) {
-        const double *tc = A.tal_cl + ((size_t)b * I + i) * 6;
-        cp += tc[kc];
-        ck += tc[kc + 2];
-      }
-    }
-  }
-  part[grp][0][lane] = p;
-  part[grp][1][lane] = j;
-  part[grp][2][lane] = k;
-  part[grp][3][lane] = cp;
-  part[grp][4][lane] = ck;
-  __syncthreads();
-  if (grp == 0 && i < I) {
-    p = j = k = cp = ck = 0.0;
-#pragma unroll
-    for (int g = 0; g < NG; ++g) {
-      p += part[g][0][lane];
-      j += part[g][1][lane];
-      k += part[g][2][lane];
-      cp += part[g][3][lane];
-      ck += part[g][4][lane];
-    }
-    const double dxi = A.edges[i + 1] - A.edges[i];
-    const double norm = A.n_src * dxi;
-    if (ic) {
-      gi_phi[i] = p / norm;
-      gi_J[i] = j / norm;
-      gi_K[i] = k / norm;
-    }
-    const double normc = A.closure_track ? (A.n_src * dxi * A.dt) : norm;
-    gc_phi[i] = scale * cp / normc;
-    gc_K[i] = scale * ck / normc;
-  }
-}
-
-__global__ void __launch_bounds__(LOSM_REDUCE_THREADS) losm_reduce_kernel(LosmArgs A) {
-  losm_reduce_body(A, (int)blockIdx.x);
-}
 
 // kWil: where the working arrays live (0 global scratch, 1 LDS, 2 LDS with
 // the Fourier coefficients too), fixed at compile time so that every access
@@ -255,12 +166,11 @@ __device__ __forceinline__ void losm_body(const LosmArgs &A, double *dyn) {
   // Grid functions and two spare buffers; filters write into a spare and
   // the pointers swap (faces copied along).
   double *phi_o = S, *J_o = S + M, *F_o = S + 2 * M, *F_n = S + 3 * M, *T1 = S + 4 * M, *T2 = S + 5 * M;
-  const double *gi_phi = losm_sums(A);
-  const double *gi_J = gi_phi + I;
-  const double *gi_K = gi_J + I;
-  const double *gc_phi = gi_K + I;
-  const double *gc_K = gc_phi + I;
-  const double *gfaces = gc_K + I;
+  double *gi_phi = losm_sums(A);
+  double *gi_J = gi_phi + I;
+  double *gi_K = gi_J + I;
+  double *gc_phi = gi_K + I;
+  double *gc_K = gc_phi + I;
   __shared__ double sp[64], sq[64];
   __shared__ double face[12];  // ic: phi L/R, P L/R, F L/R; cl: same
   __shared__ double sc[4];     // scale, s, max
@@ -281,14 +191,60 @@ __device__ __forceinline__ void losm_body(const LosmArgs &A, double *dyn) {
     // No start weight swept yet: no closures exist, the update is skipped.
     if (A.implicit && !(sc[0] > 0.0)) skip = 1;
   }
-  // 1. batch sums: done by losm_reduce_kernel into gi_*, gc_* and the faces.
-  if (tid < 12) face[tid] = gfaces[tid];
   __syncthreads();
   if (bad) return;
   if (skip) {
     for (int i = tid; i <= I + 1; i += T) A.phi_out[i] = 0.0;
     for (int i = tid; i <= I; i += T) A.J_out[i] = 0.0;
     return;
+  }
+
+  // 1. batch sums of the cell tallies, normalised per source particle and
+  // cell width (and step for track-length closures; the closure set scaled
+  // by W_start / W_done), and of the face tallies.
+  {
+    const double scale = sc[0];
+    if (tid < 12 * 64) {
+      // Face values, one wave each (lane = batch, B <= 64): t = (phi L,
+      // phi R, P L, P R, F L, F R) of the initial-condition set (t < 6) and
+      // of the closure set (t >= 6).
+      const int t = tid >> 6, bl = tid & 63;
+      const int set = t / 6, q = t % 6;
+      const int f = q & 1, kind = q >> 1;
+      const double *bs = set == 0 ? A.bnd_ic : A.bnd_cl;
+      double acc = bl < A.B ? bs[(bl * 2 + f) * 3 + kind] : 0.0;
+      for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
+      if (bl == 0) face[t] = (set == 0 ? 1.0 : scale) * acc / (A.n_src * A.dt);
+    }
+    const int kc = A.closure_track ? 0 : 3;
+    for (int i = tid; i < I; i += T) {
+      const double dxi = A.edges[i + 1] - A.edges[i];
+      const double norm = A.n_src * dxi;
+      if (!A.ic_cached) {
+        double p = 0.0, j = 0.0, k = 0.0;
+#pragma unroll
+        for (int c = 0; c < kSumCopies; ++c) {
+          const double *t = A.tsum_ic + (size_t)c * 6 * I;
+          p += t[3 * I + i];
+          j += t[4 * I + i];
+          k += t[5 * I + i];
+        }
+        gi_phi[i] = p / norm;
+        gi_J[i] = j / norm;
+        gi_K[i] = k / norm;
+      }
+      double cp = 0.0, ck = 0.0;
+#pragma unroll
+      for (int c = 0; c < kSumCopies; ++c) {
+        const double *t = A.tsum_cl + (size_t)c * 6 * I;
+        cp += t[kc * I + i];
+        ck += t[(kc + 2) * I + i];
+      }
+      const double normc = A.closure_track ? norm * A.dt : norm;
+      gc_phi[i] = scale * cp / normc;
+      gc_K[i] = scale * ck / normc;
+    }
+    __syncthreads();
   }
 
   // 2. grid functions of the initial condition and the closures.
@@ -451,11 +407,11 @@ __global__ void __launch_bounds__(LOSM_THREADS) losm_kernel(LosmArgs A) {
 __device__ inline LosmArgs losm_batch_args(const LosmReplica &R, const LosmCall &c) {
   LosmArgs A = R.a;
   if (!c.implicit) {
-    A.tal_ic = R.tal[c.cur]; A.bnd_ic = R.bnd[c.cur];
-    A.tal_cl = A.tal_ic; A.bnd_cl = A.bnd_ic;
+    A.tsum_ic = R.tsum[c.cur]; A.bnd_ic = R.bnd[c.cur];
+    A.tsum_cl = A.tsum_ic; A.bnd_cl = A.bnd_ic;
   } else {
-    A.tal_ic = R.tal[1 - c.cur]; A.bnd_ic = R.bnd[1 - c.cur];
-    A.tal_cl = R.tal[c.cur]; A.bnd_cl = R.bnd[c.cur];
+    A.tsum_ic = R.tsum[1 - c.cur]; A.bnd_ic = R.bnd[1 - c.cur];
+    A.tsum_cl = R.tsum[c.cur]; A.bnd_cl = R.bnd[c.cur];
   }
   A.next_chunk = c.next_chunk;
   A.theta = c.theta;
@@ -471,12 +427,6 @@ __global__ void losm_factor_batch_kernel(const LosmReplica *tab, LosmCall c) {
   const LosmArgs A = losm_batch_args(tab[blockIdx.x], c);
   if (threadIdx.x == 0) *A.status = 0;
   losm_factor_body(A);
-}
-
-__global__ void __launch_bounds__(LOSM_REDUCE_THREADS) losm_reduce_batch_kernel(const LosmReplica *tab, LosmCall c) {
-  const LosmArgs A = losm_batch_args(tab[blockIdx.y], c);
-  if ((int)blockIdx.x * 64 >= A.I && blockIdx.x != 0) return;
-  losm_reduce_body(A, (int)blockIdx.x);
 }
 
 template <int kWil>
@@ -515,11 +465,6 @@ hipError_t launch_losm_batch(const LosmReplica *tab, int n, int max_I, const Los
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(losm_reduce_batch_kernel, dim3((max_I + 63) / 64, n), dim3(LOSM_REDUCE_THREADS), 0, s, tab, c);
-  {
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
   int wil = 0;
   const size_t lds = losm_lds(max_I, &wil);
   if (wil != c.work_in_lds) return hipErrorInvalidValue;
@@ -540,11 +485,6 @@ hipError_t launch_losm_batch(const LosmReplica *tab, int n, int max_I, const Los
 hipError_t launch_losm(const LosmArgs &a, hipStream_t s) {
   if (a.refactor) {
     hipLaunchKernelGGL(losm_factor_kernel, dim3(1), dim3(64), 0, s, a);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  hipLaunchKernelGGL(losm_reduce_kernel, dim3((a.I + 63) / 64), dim3(LOSM_REDUCE_THREADS), 0, s, a);
-  {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

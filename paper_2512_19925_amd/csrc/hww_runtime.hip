@@ -36,7 +36,7 @@ struct Layout {
   int64_t n_hist = 0, comb_slots = 0, off_c_cnt = 0, off_c_cur = 0, off_c_order = 0, off_c_wq = 0, off_c_blk = 0,
           off_c_misc = 0;
   int64_t off_bank[2], off_segcnt[2], off_ovfcnt[2], off_q;
-  int64_t off_tal[2], off_bnd[2], off_tracks, off_counters, off_wstart, off_wnext;
+  int64_t off_tal[2], off_tsum[2], off_bnd[2], off_tracks, off_counters, off_wstart, off_wnext;
   int64_t off_err, off_status, off_scratch, off_factor, off_phi_out, off_J_out;
   int64_t off_F_out, off_P_out;
   int64_t off_m_sig, off_m_F, off_m_P, off_m_phi0, off_m_J0, off_m_w, off_m_hist, off_m_fac, off_m_fact, off_m_G,
@@ -136,6 +136,7 @@ void make_layout(const hww_problem &p, Layout *L, bool member = false) {
   c.take(sizeof(Tag) * dslots);
   for (int k = 0; k < 2; ++k) {
     L->off_tal[k] = c.take(8 * B * I * 6);
+    L->off_tsum[k] = c.take(8 * kSumCopies * 6 * I);
     L->off_bnd[k] = c.take(8 * B * 6);
   }
   L->off_tracks = c.take(8 * I);
@@ -264,7 +265,7 @@ struct hww_handle {
   Bank<float> bank32[2];
   Queue<float> dq32;
   CellData<float> *cells32;
-  double *tal[2], *bnd[2];
+  double *tal[2], *tsum[2], *bnd[2];
   unsigned long long *tracks, *counters;
   double *wstart, *wnext;
   uint32_t *err;
@@ -448,6 +449,7 @@ SweepArgs<Real> base_args(hww_handle *h) {
   }
   a.dcap = h->L.dcap;
   a.tal = h->tal[h->cur_tal];
+  a.tsum = h->tsum[h->cur_tal];
   a.bnd = h->bnd[h->cur_tal];
   a.tracks = h->tracks;
   a.counters = h->counters;
@@ -523,6 +525,7 @@ void carve_handle(hww_handle *h, const hww_problem &problem, char *ws, const Lay
     h->bank[k] = bank_view<double>(ws, L.off_bank[k], L.off_segcnt[k], L.off_ovfcnt[k], slots);
     h->bank32[k] = bank_view<float>(ws, L.off_bank[k], L.off_segcnt[k], L.off_ovfcnt[k], slots);
     h->tal[k] = reinterpret_cast<double *>(ws + L.off_tal[k]);
+    h->tsum[k] = reinterpret_cast<double *>(ws + L.off_tsum[k]);
     h->bnd[k] = reinterpret_cast<double *>(ws + L.off_bnd[k]);
   }
   h->fp32 = problem.precision == HWW_FP32;
@@ -580,6 +583,7 @@ int prime_handle(hww_handle *h, const hww_problem &problem) {
   for (int k = 0; k < 2; ++k) {
     if (zero_counts(h, k) != HWW_OK) return HWW_E_DEVICE;
     HIPCHK(h, launch_fill_f64(h->tal[k], 0.0, (int64_t)h->B * I * 6, h->stream));
+    HIPCHK(h, launch_fill_f64(h->tsum[k], 0.0, (int64_t)kSumCopies * 6 * I, h->stream));
     HIPCHK(h, launch_fill_f64(h->bnd[k], 0.0, (int64_t)h->B * 6, h->stream));
   }
   HIPCHK(h, launch_fill_u32(reinterpret_cast<uint32_t *>(h->tracks), 0u, 2 * (int64_t)I, h->stream));
@@ -597,7 +601,7 @@ int prime_handle(hww_handle *h, const hww_problem &problem) {
   sa.v = problem.speed; sa.dt = problem.dt; sa.src_x = problem.src_x;
   sa.n_src = problem.n_src; sa.seed = problem.seed; sa.key1 = problem.replica << 4;
   sa.edges = h->edges; sa.geom = h->L.geom;
-  sa.tal = h->tal[0]; sa.wnext = h->wnext; sa.err = h->err;
+  sa.tal = h->tal[0]; sa.tsum = h->tsum[0]; sa.wnext = h->wnext; sa.err = h->err;
   if (h->fp32)
     HIPCHK(h, launch_source<float>(sa, h->bank32[1], h->B * h->K, 256, h->lds, h->stream));
   else
@@ -718,6 +722,7 @@ ReplicaDesc<Real> replica_desc(hww_handle *r) {
     if constexpr (sizeof(Real) == 8) d.bank[k] = r->bank[k];
     else d.bank[k] = r->bank32[k];
     d.tal[k] = r->tal[k];
+    d.tsum[k] = r->tsum[k];
     d.bnd[k] = r->bnd[k];
   }
   if constexpr (sizeof(Real) == 8) d.cells = r->cells;
@@ -746,11 +751,11 @@ BeginStepArgs begin_args(hww_handle *h) {
   BeginStepArgs bs{};
   bs.segcnt = h->bank[1 - h->start_bank].segcnt;
   bs.ovfcnt = h->bank[1 - h->start_bank].ovfcnt;
-  bs.tal = h->tal[h->cur_tal]; bs.bnd = h->bnd[h->cur_tal];
+  bs.tal = h->tal[h->cur_tal]; bs.tsum = h->tsum[h->cur_tal]; bs.bnd = h->bnd[h->cur_tal];
   bs.tracks = h->tracks; bs.counters = h->counters;
   bs.wstart = h->wstart; bs.wnext = h->wnext;
   bs.n_seg = (int64_t)h->R * h->K; bs.n_ovf = h->R;
-  bs.n_tal = (int64_t)h->B * h->I * 6; bs.n_bnd = (int64_t)h->B * 6; bs.n_tracks = h->I;
+  bs.n_tal = (int64_t)h->B * h->I * 6; bs.n_tsum = (int64_t)kSumCopies * 6 * h->I; bs.n_bnd = (int64_t)h->B * 6; bs.n_tracks = h->I;
   bs.nc = h->nc;
   return bs;
 }
@@ -1207,12 +1212,12 @@ int hww_solve_losm(hww_handle *h, const hww_losm_opts *o, double *phi_out, doubl
   a.edges = h->edges; a.sig_t = h->sig_t; a.sig_s = h->sig_s;
   if (!o->implicit) {
     if (h->next_chunk != h->nc || h->step >= h->p.n_steps) return fail(h, HWW_E_STATE, "semi-implicit solve needs a finished step");
-    a.tal_ic = h->tal[h->cur_tal]; a.bnd_ic = h->bnd[h->cur_tal];
-    a.tal_cl = a.tal_ic; a.bnd_cl = a.bnd_ic;
+    a.tsum_ic = h->tsum[h->cur_tal]; a.bnd_ic = h->bnd[h->cur_tal];
+    a.tsum_cl = a.tsum_ic; a.bnd_cl = a.bnd_ic;
   } else {
     if (h->step < 1 || h->next_chunk < 1 || h->next_chunk >= h->nc) return fail(h, HWW_E_STATE, "implicit solve needs a step in progress");
-    a.tal_ic = h->tal[1 - h->cur_tal]; a.bnd_ic = h->bnd[1 - h->cur_tal];
-    a.tal_cl = h->tal[h->cur_tal]; a.bnd_cl = h->bnd[h->cur_tal];
+    a.tsum_ic = h->tsum[1 - h->cur_tal]; a.bnd_ic = h->bnd[1 - h->cur_tal];
+    a.tsum_cl = h->tsum[h->cur_tal]; a.bnd_cl = h->bnd[h->cur_tal];
   }
   a.wstart = h->wstart; a.wnext = h->wnext; a.next_chunk = h->next_chunk;
   a.theta = o->theta; a.implicit = o->implicit; a.filter = o->filter; a.ma_k = o->ma_k;
@@ -1247,8 +1252,8 @@ int hww_read_closures(hww_handle *h, double *F, double *P, double *phi, double *
   a.I = h->I; a.B = h->B; a.nc = h->nc;
   a.v = h->p.speed; a.dt = h->p.dt; a.n_src = (double)h->p.n_src;
   a.edges = h->edges; a.sig_t = h->sig_t; a.sig_s = h->sig_s;
-  a.tal_ic = h->tal[h->cur_tal]; a.bnd_ic = h->bnd[h->cur_tal];
-  a.tal_cl = a.tal_ic; a.bnd_cl = a.bnd_ic;
+  a.tsum_ic = h->tsum[h->cur_tal]; a.bnd_ic = h->bnd[h->cur_tal];
+  a.tsum_cl = a.tsum_ic; a.bnd_cl = a.bnd_ic;
   a.wstart = h->wstart; a.wnext = h->wnext; a.next_chunk = h->next_chunk;
   a.theta = h->factor_theta > 0.0 ? h->factor_theta : 0.5;
   a.implicit = 0; a.filter = 0; a.apply_windows = 0;
@@ -1621,7 +1626,7 @@ int hww_init_batch(const hww_problem *problems, int32_t n, void *dev_workspace, 
     else d64[r] = replica_desc<double>(m);
     lt[r].a = replica_losm_args(m);
     for (int k = 0; k < 2; ++k) {
-      lt[r].tal[k] = m->tal[k];
+      lt[r].tsum[k] = m->tsum[k];
       lt[r].bnd[k] = m->bnd[k];
       m->start_bank = m->cur_tal = k;
       bs[(size_t)k * n + r] = begin_args(m);
@@ -1733,6 +1738,7 @@ int hww_autotune(hww_handle *h, hww_tune_result *best) {
   for (size_t r = 0; r < reps.size(); ++r) {
     HIPCHK(h, hipMemcpyAsync(reps[r]->wnext, wsave.data() + r * h->nc, 8 * h->nc, hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, launch_fill_f64(reps[r]->tal[1], 0.0, (int64_t)reps[r]->B * reps[r]->I * 6, h->stream));
+    HIPCHK(h, launch_fill_f64(reps[r]->tsum[1], 0.0, (int64_t)kSumCopies * 6 * reps[r]->I, h->stream));
     HIPCHK(h, launch_fill_f64(reps[r]->bnd[1], 0.0, (int64_t)reps[r]->B * 6, h->stream));
     HIPCHK(h, launch_fill_u32(reinterpret_cast<uint32_t *>(reps[r]->tracks), 0u, 2 * (int64_t)reps[r]->I, h->stream));
   }

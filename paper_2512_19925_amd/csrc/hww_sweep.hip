@@ -143,13 +143,19 @@ __device__ inline void zero_lds(double *raw, int I, int nc, int K) {
   for (size_t t = threadIdx.x; t < nw; t += blockDim.x) w[t] = 0u;
 }
 
-// Flush the work-group histogram of batch b (nonzero entries only).
-__device__ inline void flush_tallies(const Lds &L, int I, int nc, int b, double *tal, double *bnd,
-                                     unsigned long long *tracks, double *wnext) {
+// Flush the work-group histogram of batch b (nonzero entries only) into
+// the batch's row and into copy `copy` of the batch sums.
+__device__ inline void flush_tallies(const Lds &L, int I, int nc, int b, double *tal, double *tsum, int copy,
+                                     double *bnd, unsigned long long *tracks, double *wnext) {
   double *tal_b = tal + (size_t)b * I * 6;
+  double *sum_c = tsum + (size_t)copy * 6 * I;
   for (int j = threadIdx.x; j < I * 6; j += blockDim.x) {
     const double val = L.hist[j];
-    if (val != 0.0) unsafeAtomicAdd(&tal_b[j], val);
+    if (val != 0.0) {
+      unsafeAtomicAdd(&tal_b[j], val);
+      const int i = j / 6, k = j - 6 * i;
+      unsafeAtomicAdd(&sum_c[k * I + i], val);
+    }
   }
   if (tracks) {
     for (int j = threadIdx.x; j < I; j += blockDim.x) {
@@ -835,7 +841,7 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
     atomicMax(&A.counters[C_GENERATIONS], (unsigned long long)(gen + 1));
     atomicMax(&A.counters[C_NCOUNTERS + C_GENERATIONS], (unsigned long long)(gen + 1));
   }
-  flush_tallies(L, I, nc, b, A.tal, A.bnd, A.tracks, A.wnext);
+  flush_tallies(L, I, nc, b, A.tal, A.tsum, qslot % kSumCopies, A.bnd, A.tracks, A.wnext);
 }
 
 // One problem: grid = B * K work-groups; work-group g is the unit
@@ -883,7 +889,7 @@ __global__ void __launch_bounds__(1024) sweep_batch_kernel(BatchSweepArgs<Real> 
     A.in_bank = D.bank[P.start_bank];
     A.census = D.bank[1 - P.start_bank];
     A.dq = P.dq; A.dcap = P.dcap;
-    A.tal = D.tal[P.start_bank]; A.bnd = D.bnd[P.start_bank];
+    A.tal = D.tal[P.start_bank]; A.tsum = D.tsum[P.start_bank]; A.bnd = D.bnd[P.start_bank];
     A.tracks = D.tracks; A.counters = D.counters; A.wnext = D.wnext;
     A.err = P.err;
     if (kCells == 1 || (kCells == 2 && D.cells_lds))
@@ -942,7 +948,7 @@ __global__ void __launch_bounds__(1024) source_kernel(SourceArgs A, Bank<Real> b
     const uint32_t cc = L.ccnt[threadIdx.x];
     bank.segcnt[(b * nc + threadIdx.x) * K + jseg] = cc < (uint32_t)G.seg_cap ? cc : (uint32_t)G.seg_cap;
   }
-  flush_tallies(L, I, nc, b, A.tal, nullptr, nullptr, A.wnext);
+  flush_tallies(L, I, nc, b, A.tal, A.tsum, (int)(blockIdx.x % kSumCopies), nullptr, nullptr, A.wnext);
 }
 
 // Clear the accumulators of a new time step and hand the census chunk
@@ -953,6 +959,7 @@ __device__ inline void begin_step_body(const BeginStepArgs &A) {
   for (int64_t j = t0; j < A.n_seg; j += st) A.segcnt[j] = 0u;
   for (int64_t j = t0; j < A.n_ovf; j += st) A.ovfcnt[j] = 0u;
   for (int64_t j = t0; j < A.n_tal; j += st) A.tal[j] = 0.0;
+  for (int64_t j = t0; j < A.n_tsum; j += st) A.tsum[j] = 0.0;
   for (int64_t j = t0; j < A.n_bnd; j += st) A.bnd[j] = 0.0;
   for (int64_t j = t0; j < A.n_tracks; j += st) A.tracks[j] = 0ull;
   for (int64_t j = t0; j < C_NCOUNTERS; j += st) A.counters[j] = 0ull;
