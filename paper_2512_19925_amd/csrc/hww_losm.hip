@@ -357,10 +357,7 @@ __device__ __forceinline__ void losm_body(const LosmArgs &A, double *dyn) {
       if (!isfinite(p)) nonfinite = 1;
       if (p > mx) mx = p;
     }
-    for (int o = 32; o >= 1; o >>= 1) {
-      const double t = __shfl_xor(mx, o);
-      mx = t > mx ? t : mx;
-    }
+    mx = wave_max_f64(mx);
     if ((tid & 63) == 0) red[tid >> 6] = mx;
     if (nonfinite) atomicOr(&bad, 1);
     __syncthreads();

@@ -138,41 +138,79 @@ __device__ inline bool losm_factor_seq(int I, const double *edges, const double 
   return true;
 }
 
+// Cross-lane moves by DPP (no LDS round trip): the value of another lane of
+// the wave, chosen by the DPP control kCtrl, in the rows of kRowMask; lanes
+// whose source lane lies outside their row, and lanes of other rows, get
+// `old`.  Doubles move as two 32-bit halves.
+enum : int { kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118,
+             kDppWaveShr1 = 0x138, kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143 };
+
+template <int kCtrl, int kRowMask = 0xF>
+__device__ __forceinline__ double dpp_f64(double old, double v) {
+  const uint64_t o = (uint64_t)__double_as_longlong(old), x = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)o, (int)(uint32_t)x, kCtrl, kRowMask, 0xF, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(o >> 32), (int)(uint32_t)(x >> 32), kCtrl,
+                                                            kRowMask, 0xF, false);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// One step of the affine-map scan: compose the lane's map with the map
+// (pp, qq) of the lanes before it (identity (0, 1) where there are none).
+template <int kCtrl, int kRowMask = 0xF>
+__device__ __forceinline__ void affine_step(double &P, double &Q) {
+  const double pp = dpp_f64<kCtrl, kRowMask>(0.0, P), qq = dpp_f64<kCtrl, kRowMask>(1.0, Q);
+  P = P + Q * pp;
+  Q = Q * qq;
+}
+
+// Inclusive scan of affine maps over the 64 lanes of a wave (Hillis-Steele
+// within rows of 16, then the row ends broadcast to the rows after them).
+__device__ __forceinline__ void affine_scan_wave(double &P, double &Q) {
+  affine_step<kDppRowShr1>(P, Q);
+  affine_step<kDppRowShr2>(P, Q);
+  affine_step<kDppRowShr4>(P, Q);
+  affine_step<kDppRowShr8>(P, Q);
+  affine_step<kDppRowBcast15, 0xA>(P, Q);
+  affine_step<kDppRowBcast31, 0xC>(P, Q);
+}
+
+// Largest value over the 64 lanes of a wave (every lane gets it).
+__device__ __forceinline__ double wave_max_f64(double m) {
+  const double lo = -__builtin_inf();
+  double t;
+  t = dpp_f64<kDppRowShr1>(lo, m); m = t > m ? t : m;
+  t = dpp_f64<kDppRowShr2>(lo, m); m = t > m ? t : m;
+  t = dpp_f64<kDppRowShr4>(lo, m); m = t > m ? t : m;
+  t = dpp_f64<kDppRowShr8>(lo, m); m = t > m ? t : m;
+  t = dpp_f64<kDppRowBcast15, 0xA>(lo, m); m = t > m ? t : m;
+  t = dpp_f64<kDppRowBcast31, 0xC>(lo, m); m = t > m ? t : m;
+  const uint64_t b = (uint64_t)__double_as_longlong(m);
+  const uint32_t lo32 = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, 63);
+  const uint32_t hi32 = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), 63);
+  return __longlong_as_double((long long)(((uint64_t)hi32 << 32) | lo32));
+}
+
 // Scan of affine maps y -> p + q y across the work-group in thread order:
 // returns, for thread t, the composition of the maps of threads 0..t-1
 // applied to y = 0 (0 for thread 0).  Within a wave by shuffles, across the
 // (at most 16) waves through LDS: two barriers.  sp, sq: >= 48 doubles each.
 __device__ inline double affine_scan_excl(double *sp, double *sq, double P, double Q) {
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6, nw = (int)(blockDim.x >> 6);
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const double pp = __shfl_up(P, o), qq = __shfl_up(Q, o);
-    if (lane >= o) {
-      P = P + Q * pp;
-      Q = Q * qq;
-    }
-  }
+  affine_scan_wave(P, Q);
   // In-wave exclusive map (identity for lane 0).
-  double pe = __shfl_up(P, 1), qe = __shfl_up(Q, 1);
-  if (lane == 0) {
-    pe = 0.0;
-    qe = 1.0;
-  }
+  const double pe = dpp_f64<kDppWaveShr1>(0.0, P), qe = dpp_f64<kDppWaveShr1>(1.0, Q);
   if (lane == 63) {
     sp[wv] = P;
     sq[wv] = Q;
   }
   __syncthreads();
   if (wv == 0) {
+    // At most 16 waves: one row of lanes.
     double p = lane < nw ? sp[lane] : 0.0, q = lane < nw ? sq[lane] : 1.0;
-#pragma unroll
-    for (int o = 1; o < 16; o <<= 1) {
-      const double pp = __shfl_up(p, o), qq = __shfl_up(q, o);
-      if (lane >= o) {
-        p = p + q * pp;
-        q = q * qq;
-      }
-    }
+    affine_step<kDppRowShr1>(p, q);
+    affine_step<kDppRowShr2>(p, q);
+    affine_step<kDppRowShr4>(p, q);
+    affine_step<kDppRowShr8>(p, q);
     if (lane < nw) {
       sp[32 + lane] = p;
       sq[32 + lane] = q;
