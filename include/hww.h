@@ -311,20 +311,26 @@ int hww_init_batch(const hww_problem *problems, int32_t n, void *dev_workspace, 
  * the others return HWW_E_STATE. */
 int hww_batch_replica(hww_handle *batch, int32_t r, hww_handle **view);
 
-/* Launch shape of the sweep picked by hww_autotune. */
+/* Launch shape of the sweep picked by hww_autotune.  A batch sweeps its
+ * replicas in up to three persistent launches per chunk, one per LDS class
+ * (replicas whose sweep histogram needs at most a quarter of a compute
+ * unit's LDS, at most half, more), each tuned on its own; the shape reported
+ * is that of the class with the most source particles. */
 typedef struct hww_tune_result {
   int32_t block;   /* threads per work-group: 256, 512 or 1024                  */
   int32_t tile;    /* particles a wavefront claims per refill: 64 .. 512        */
   int32_t grid;    /* work-groups of a launch (batches: compute units x 1..4)   */
-  int32_t trials;  /* shapes measured                                            */
-  double ms;       /* best measured sweep time of the trial chunk              */
+  int32_t trials;  /* shapes measured (over all classes of a batch)             */
+  double ms;       /* best measured sweep time of the trial chunk (batches: the
+                      sum of the classes' best)                                 */
 } hww_tune_result;
 
 /* Measure the sweep of chunk 0 of step 1 under every launch shape (block
- * size, tile size and, for batches, the persistent grid) twice, keep the
- * fastest for every later sweep, and restore the state of step 0.  Must run
- * before the first hww_sweep_step (windows may already be set).  The shape
- * changes no result beyond the summation order of the tallies.
+ * size, tile size and, for batches, the persistent grid of each LDS class)
+ * twice, keep the fastest for every later sweep, and restore the state of
+ * step 0.  Must run before the first hww_sweep_step (windows may already be
+ * set).  The shape changes no result beyond the summation order of the
+ * tallies.
  * Errors: HWW_E_STATE after the first sweep, HWW_E_CAPACITY if a trial
  * overflows.  Synchronises. */
 int hww_autotune(hww_handle *h, hww_tune_result *best);

@@ -25,6 +25,17 @@ constexpr int kBlock = 512;         // threads per sweep work-group (default; se
 constexpr int kTile = 256;          // particles a wave claims per tile (default)
 constexpr int64_t kUnitParticles = 8192;  // start particles per batched work unit and launch
 constexpr int kGridMax = 1024;      // work-groups of a batched launch at most
+// Replicas of a batch fall in LDS classes by what one sweep unit's histogram
+// needs: at most a quarter of a compute unit's LDS (class 0, four work-groups
+// of 256 threads per compute unit by default), at most half (class 1, two of
+// 512), more (class 2, one of 1024, which may also keep the cell records in
+// LDS).  Each class is a persistent launch of its own, so small replicas are
+// not held to one work-group per compute unit by the largest one.
+constexpr int kBatchClasses = 3;
+
+int batch_class(size_t hist_lds) {
+  return hist_lds <= kLdsBytes / 4 ? 0 : (hist_lds <= kLdsBytes / 2 ? 1 : 2);
+}
 
 struct Layout {
   int64_t total = 0;
@@ -288,9 +299,8 @@ struct hww_handle {
   int ic_buf = -1;
   uint64_t ic_epoch = 0;
   size_t lds = 0;
-  int block = kBlock, tile = kTile, grid = 0;  // sweep launch shape (grid: batched launches)
+  int block = kBlock, tile = kTile;  // sweep launch shape of a single problem (batches: per LDS class)
   bool cells_lds = false;      // the sweep keeps the per-cell records in LDS
-  int cells_mode = 0;          // batches: 0 no replica, 1 every replica, 2 some keep cell records in LDS
   int is_view = 0;             // a replica of a batch, for reads only
   int static_dev = -1;        // device whose static workspace the handle uses (-1: caller's)
   // Batch of replicas (is_batch): the replicas are handles of their own
@@ -299,6 +309,14 @@ struct hww_handle {
   std::vector<hww_handle *> rep;
   int max_I = 0, max_K = 0, cus = 256;
   uint32_t n_units = 0;
+  // LDS classes of a batch: unit range, launch LDS, cell placement and shape.
+  struct BatchClass {
+    uint32_t u0 = 0, u1 = 0;
+    size_t lds = 0;
+    int cells_mode = 0, block = 1024, tile = kTile, grid = 0;
+    int64_t starts = 0;  // start particles of its replicas
+  };
+  BatchClass bcls[kBatchClasses];
   void *desc = nullptr;              // ReplicaDesc<Real>[n]
   uint32_t *units = nullptr, *work = nullptr;
   LosmReplica *losm_tab = nullptr;
@@ -458,25 +476,37 @@ SweepArgs<Real> base_args(hww_handle *h) {
   return a;
 }
 
+// The persistent launch of LDS class ci of a batch for one chunk.
+template <typename Real>
+int launch_class(hww_handle *h, int ci, int chunk, int k) {
+  const hww_handle::BatchClass &c = h->bcls[ci];
+  if (c.u1 == c.u0) return HWW_OK;
+  BatchSweepArgs<Real> a{};
+  a.desc = reinterpret_cast<const ReplicaDesc<Real> *>(h->desc);
+  a.units = h->units + c.u0;
+  a.n_units = c.u1 - c.u0;
+  a.work = h->work + 2 * ci;
+  a.par = k & 1;
+  a.start_bank = h->start_bank;
+  a.chunk = chunk;
+  a.ww_on = h->ww_on;
+  a.tile = c.tile;
+  if constexpr (sizeof(Real) == 8) a.dq = h->bq;
+  else a.dq = h->bq32;
+  a.dcap = h->bdcap;
+  a.err = h->err;
+  HIPCHK(h, launch_sweep_batch<Real>(a, c.cells_mode, c.grid, c.block, c.lds, h->stream));
+  return HWW_OK;
+}
+
 template <typename Real>
 int launch_chunk(hww_handle *h, int chunk, int k) {
   if (h->is_batch) {
-    BatchSweepArgs<Real> a{};
-    a.desc = reinterpret_cast<const ReplicaDesc<Real> *>(h->desc);
-    a.units = h->units;
-    a.n_units = h->n_units;
-    a.work = h->work;
-    a.par = k & 1;
-    a.start_bank = h->start_bank;
-    a.chunk = chunk;
-    a.ww_on = h->ww_on;
-    a.tile = h->tile;
-    if constexpr (sizeof(Real) == 8) a.dq = h->bq;
-    else a.dq = h->bq32;
-    a.dcap = h->bdcap;
-    a.err = h->err;
     ++h->tal_epoch[h->cur_tal];
-    HIPCHK(h, launch_sweep_batch<Real>(a, h->cells_mode, h->grid, h->block, h->lds, h->stream));
+    for (int ci = 0; ci < kBatchClasses; ++ci) {
+      const int rc = launch_class<Real>(h, ci, chunk, k);
+      if (rc != HWW_OK) return rc;
+    }
     return HWW_OK;
   }
   SweepArgs<Real> a = base_args<Real>(h);
@@ -631,6 +661,8 @@ struct BatchLayout {
       off_losm, off_bs, off_q;
   int64_t n_seg = 0, n_ovf = 0, n_phi = 0, n_J = 0, dcap = 0;
   int max_I = 0, max_K = 0;
+  std::vector<int> cls;                // LDS class of each replica
+  uint32_t cls_u0[kBatchClasses] = {}, cls_u1[kBatchClasses] = {};  // unit range of each class
 };
 
 int make_batch_layout(const hww_problem *probs, int n, BatchLayout *BL, std::string *why) {
@@ -667,18 +699,29 @@ int make_batch_layout(const hww_problem *probs, int n, BatchLayout *BL, std::str
   }
   BL->dcap = std::max<int64_t>(BL->dcap, 4096);
   if (sweep_lds_bytes(BL->max_I, nc, BL->max_K) > 160 * 1024) { *why = "too many cells for the LDS histogram"; return HWW_E_INVALID_ARG; }
-  // Units: biggest replicas first; the units of one batch next to each other.
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return probs[a].n_src > probs[b].n_src; });
+  // Units: by LDS class, in a class the biggest replicas first; the units of
+  // one batch next to each other.
+  BL->cls.resize(n);
+  for (int r = 0; r < n; ++r) BL->cls[r] = batch_class(sweep_lds_bytes(probs[r].n_cells, nc, BL->L[r].geom.K));
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    if (BL->cls[a] != BL->cls[b]) return BL->cls[a] < BL->cls[b];
+    return probs[a].n_src > probs[b].n_src;
+  });
   BL->units.clear();
-  for (int r : order)
-    for (int b = 0; b < probs[r].n_batches; ++b)
-      for (int j = 0; j < BL->L[r].geom.K; ++j) BL->units.push_back(((uint32_t)r << 16) | ((uint32_t)b << 8) | (uint32_t)j);
+  for (int ci = 0; ci < kBatchClasses; ++ci) {
+    BL->cls_u0[ci] = (uint32_t)BL->units.size();
+    for (int r : order)
+      if (BL->cls[r] == ci)
+        for (int b = 0; b < probs[r].n_batches; ++b)
+          for (int j = 0; j < BL->L[r].geom.K; ++j) BL->units.push_back(((uint32_t)r << 16) | ((uint32_t)b << 8) | (uint32_t)j);
+    BL->cls_u1[ci] = (uint32_t)BL->units.size();
+  }
   int64_t rb = 8;
   real_bytes(probs[0].precision, &rb);
   Carver c;
   BL->off_desc = c.take((int64_t)n * (int64_t)std::max(sizeof(ReplicaDesc<double>), sizeof(ReplicaDesc<float>)));
   BL->off_units = c.take(4 * (int64_t)BL->units.size());
-  BL->off_work = c.take(8);
+  BL->off_work = c.take(8 * kBatchClasses);
   BL->off_err = c.take(4);
   BL->off_counters = c.take(8 * 2 * C_NCOUNTERS * (int64_t)n);
   for (int k = 0; k < 2; ++k) {
@@ -865,9 +908,9 @@ void fill_stats(hww_handle *h, const unsigned long long *cnt, hww_step_stats *st
 
 // Default launch shape of a batch: as many work-groups per compute unit as
 // the LDS histogram and the thread limit allow, up to four.
-int default_grid(hww_handle *h, int block) {
+int default_grid(hww_handle *h, size_t lds, int block) {
   int wpc = 4;
-  while (wpc > 1 && ((size_t)wpc * h->lds > 160 * 1024 || wpc * block > 2048)) --wpc;
+  while (wpc > 1 && ((size_t)wpc * lds > 160 * 1024 || wpc * block > 2048)) --wpc;
   return std::min(kGridMax, h->cus * wpc);
 }
 
@@ -1541,21 +1584,27 @@ int hww_init_batch(const hww_problem *problems, int32_t n, void *dev_workspace, 
   h->max_I = BL.max_I;
   h->max_K = BL.max_K;
   {
-    // Each replica keeps its cell records in LDS when they fit beside its
-    // histogram; the launch's LDS holds the largest need.
-    h->lds = 0;
-    int fit = 0;
+    // Per LDS class: the launch's LDS holds the largest need of its
+    // replicas.  In class 2 (one work-group per compute unit) a replica
+    // keeps its cell records in LDS when they fit beside its histogram.
+    int fit[kBatchClasses] = {}, cnt[kBatchClasses] = {};
     const size_t cb = h->fp32 ? lds_cell_bytes<float>() : lds_cell_bytes<double>();
     for (int r = 0; r < n; ++r) {
-      const int I = problems[r].n_cells, K = BL.L[r].geom.K;
-      const bool f = sweep_lds_bytes(I, h->nc, K, cb) <= kLdsBytes;
-      fit += f ? 1 : 0;
-      h->lds = std::max(h->lds, sweep_lds_bytes(I, h->nc, K, f ? cb : 0));
+      const int I = problems[r].n_cells, K = BL.L[r].geom.K, ci = BL.cls[r];
+      const bool f = ci == 2 && sweep_lds_bytes(I, h->nc, K, cb) <= kLdsBytes;
+      fit[ci] += f ? 1 : 0;
+      ++cnt[ci];
+      h->bcls[ci].lds = std::max(h->bcls[ci].lds, sweep_lds_bytes(I, h->nc, K, f ? cb : 0));
+      h->bcls[ci].starts += problems[r].n_src;
     }
-    h->cells_mode = fit == 0 ? 0 : (fit == n ? 1 : 2);
-    h->cells_lds = fit > 0;
-    // One work-group per compute unit when the LDS allows no more: make it wide.
-    h->block = h->lds > kLdsBytes / 2 ? 1024 : kBlock;
+    for (int ci = 0; ci < kBatchClasses; ++ci) {
+      hww_handle::BatchClass &c = h->bcls[ci];
+      c.u0 = BL.cls_u0[ci];
+      c.u1 = BL.cls_u1[ci];
+      c.cells_mode = fit[ci] == 0 ? 0 : (fit[ci] == cnt[ci] ? 1 : 2);
+      c.block = ci == 0 ? 256 : (ci == 1 ? 512 : 1024);
+      c.tile = kTile;
+    }
   }
   h->n_units = (uint32_t)BL.units.size();
   h->desc = ws + BL.off_desc;
@@ -1579,7 +1628,7 @@ int hww_init_batch(const hww_problem *problems, int32_t n, void *dev_workspace, 
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
     h->cus = cus;
-  h->grid = default_grid(h, h->block);
+  for (int ci = 0; ci < kBatchClasses; ++ci) h->bcls[ci].grid = default_grid(h, h->bcls[ci].lds, h->bcls[ci].block);
   (void)losm_batch_lds(h->max_I, &h->losm_wil);
 
   auto bail = [&](int code) {
@@ -1614,7 +1663,7 @@ int hww_init_batch(const hww_problem *problems, int32_t n, void *dev_workspace, 
       return bail(rc);
     }
   }
-  HIPCHK(h, launch_fill_u32(h->work, 0u, 2, h->stream));
+  HIPCHK(h, launch_fill_u32(h->work, 0u, 2 * kBatchClasses, h->stream));
   // Device tables.
   std::vector<ReplicaDesc<double>> d64(n);
   std::vector<ReplicaDesc<float>> d32(n);
@@ -1681,19 +1730,29 @@ int hww_autotune(hww_handle *h, hww_tune_result *best) {
   HIPCHK(h, hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
   HIPCHK(h, hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
   auto clear_work = [&]() -> int {
-    if (h->is_batch) HIPCHK(h, launch_fill_u32(h->work, 0u, 2, h->stream));
+    if (h->is_batch) HIPCHK(h, launch_fill_u32(h->work, 0u, 2 * kBatchClasses, h->stream));
     return HWW_OK;
   };
-  auto trial = [&](int block, int tile, int grid, float *ms) -> int {
-    h->block = block;
-    h->tile = tile;
-    h->grid = grid;
+  // One trial: chunk 0 of step 1 under the shape (of a batch: LDS class ci
+  // only), timed by events on the stream.
+  auto trial = [&](int ci, int block, int tile, int grid, float *ms) -> int {
+    if (h->is_batch) {
+      h->bcls[ci].block = block;
+      h->bcls[ci].tile = tile;
+      h->bcls[ci].grid = grid;
+    } else {
+      h->block = block;
+      h->tile = tile;
+    }
     int rc = clear_work();
     if (rc != HWW_OK) return rc;
     flip_banks(h);
     rc = begin_step(h);
     if (rc == HWW_OK) rc = check_hip(h, hipEventRecord(e0, h->stream), "event");
-    if (rc == HWW_OK) rc = h->fp32 ? launch_chunk<float>(h, 0, 0) : launch_chunk<double>(h, 0, 0);
+    if (rc == HWW_OK) {
+      if (h->is_batch) rc = h->fp32 ? launch_class<float>(h, ci, 0, 0) : launch_class<double>(h, ci, 0, 0);
+      else rc = h->fp32 ? launch_chunk<float>(h, 0, 0) : launch_chunk<double>(h, 0, 0);
+    }
     if (rc == HWW_OK) rc = check_hip(h, hipEventRecord(e1, h->stream), "event");
     if (rc == HWW_OK) rc = check_hip(h, hipStreamSynchronize(h->stream), "sync");
     if (rc == HWW_OK) rc = check_hip(h, hipEventElapsedTime(ms, e0, e1), "event");
@@ -1702,34 +1761,55 @@ int hww_autotune(hww_handle *h, hww_tune_result *best) {
   };
   const int blocks[3] = {256, 512, 1024};
   const int tiles[4] = {64, 128, 256, 512};
-  float best_ms = 0.0f;
-  int bb = h->block, bt = h->tile, bg = h->grid, trials = 0;
-  float ms = 0.0f;
-  int rc = trial(kBlock, kTile, h->is_batch ? default_grid(h, kBlock) : 0, &ms);  // warm-up
-  for (int bi = 0; rc == HWW_OK && bi < 3; ++bi) {
-    std::vector<int> grids;
-    if (h->is_batch) {
-      for (int wpc = 1; wpc <= 4; ++wpc)
-        if ((size_t)wpc * h->lds <= 160 * 1024 && wpc * blocks[bi] <= 2048 && h->cus * wpc <= kGridMax)
-          grids.push_back(h->cus * wpc);
-    } else {
-      grids.push_back(0);
-    }
-    for (int g : grids)
-      for (int ti = 0; rc == HWW_OK && ti < 4; ++ti) {
-        float m = 0.0f, mbest = 1e30f;
-        for (int rep = 0; rc == HWW_OK && rep < 2; ++rep) {
-          rc = trial(blocks[bi], tiles[ti], g, &m);
-          mbest = std::min(mbest, m);
-        }
-        ++trials;
-        if (rc == HWW_OK && (trials == 1 || mbest < best_ms)) {
-          best_ms = mbest;
-          bb = blocks[bi];
-          bt = tiles[ti];
-          bg = g;
-        }
+  int trials = 0, report = 0;
+  float total_ms = 0.0f;
+  int rc = HWW_OK;
+  const int ncls = h->is_batch ? kBatchClasses : 1;
+  for (int ci = 0; rc == HWW_OK && ci < ncls; ++ci) {
+    if (h->is_batch && h->bcls[ci].u1 == h->bcls[ci].u0) continue;
+    if (h->is_batch && h->bcls[ci].starts > h->bcls[report].starts) report = ci;
+    const size_t lds = h->is_batch ? h->bcls[ci].lds : h->lds;
+    int bb = h->is_batch ? h->bcls[ci].block : h->block;
+    int bt = h->is_batch ? h->bcls[ci].tile : h->tile;
+    int bg = h->is_batch ? h->bcls[ci].grid : 0;
+    float ms = 0.0f, best_ms = 0.0f;
+    bool have = false;
+    rc = trial(ci, bb, bt, bg, &ms);  // warm-up
+    for (int bi = 0; rc == HWW_OK && bi < 3; ++bi) {
+      std::vector<int> grids;
+      if (h->is_batch) {
+        for (int wpc = 1; wpc <= 4; ++wpc)
+          if ((size_t)wpc * lds <= 160 * 1024 && wpc * blocks[bi] <= 2048 && h->cus * wpc <= kGridMax)
+            grids.push_back(h->cus * wpc);
+      } else {
+        grids.push_back(0);
       }
+      for (int g : grids)
+        for (int ti = 0; rc == HWW_OK && ti < 4; ++ti) {
+          float m = 0.0f, mbest = 1e30f;
+          for (int rep = 0; rc == HWW_OK && rep < 2; ++rep) {
+            rc = trial(ci, blocks[bi], tiles[ti], g, &m);
+            mbest = std::min(mbest, m);
+          }
+          ++trials;
+          if (rc == HWW_OK && (!have || mbest < best_ms)) {
+            have = true;
+            best_ms = mbest;
+            bb = blocks[bi];
+            bt = tiles[ti];
+            bg = g;
+          }
+        }
+    }
+    if (h->is_batch) {
+      h->bcls[ci].block = bb;
+      h->bcls[ci].tile = bt;
+      h->bcls[ci].grid = bg;
+    } else {
+      h->block = bb;
+      h->tile = bt;
+    }
+    total_ms += best_ms;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -1747,16 +1827,19 @@ int hww_autotune(hww_handle *h, hww_tune_result *best) {
   rc = clear_work();
   if (rc != HWW_OK) return rc;
   HIPCHK(h, hipStreamSynchronize(h->stream));
-  h->block = bb;
-  h->tile = bt;
-  h->grid = bg;
   rc = poll_errors(h);
   if (rc != HWW_OK) return rc;
-  best->block = bb;
-  best->tile = bt;
-  best->grid = h->is_batch ? bg : h->B * h->K;
+  if (h->is_batch) {
+    best->block = h->bcls[report].block;
+    best->tile = h->bcls[report].tile;
+    best->grid = h->bcls[report].grid;
+  } else {
+    best->block = h->block;
+    best->tile = h->tile;
+    best->grid = h->B * h->K;
+  }
   best->trials = trials;
-  best->ms = best_ms;
+  best->ms = total_ms;
   return HWW_OK;
 }
 
