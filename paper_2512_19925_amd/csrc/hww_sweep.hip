@@ -190,37 +190,24 @@ __device__ inline void store_record(const Bank<Real> &bk, int64_t k, Real x, Rea
 }
 
 // Append the census particles of the wave to the regions (b, c) of their
-// next-step chunks c: each lane's slot comes from ballots on the bits of c
-// and one LDS atomic per chunk present (issued by lane c), into the work-
-// group's own segment; what does not fit goes to the shared overflow.
+// next-step chunks c: each census lane takes the next slot of its chunk's
+// count in the work-group (one LDS atomic), in the work-group's own segment
+// j; what does not fit goes to the shared overflow segment.  The order of
+// the records within a segment is free (the bank is a multiset).
 template <typename Real>
 __device__ inline void census_append(const Bank<Real> &bk, const BankGeom &G, uint32_t *ccnt, uint32_t *ovfcnt_b,
                                      int64_t region_b0, int nc, int j, bool mine, int c, Real x, Real mu,
                                      double w, uint64_t lin, uint32_t src, uint32_t e, int32_t cell,
                                      uint32_t *err) {
   const int lane = (int)__lane_id();
-  const uint64_t M = __ballot(mine);
-  if (M == 0) return;
-  const uint64_t b0 = __ballot(mine && (c & 1));
-  const uint64_t b1 = __ballot(mine && (c & 2));
-  const uint64_t b2 = __ballot(mine && (c & 4));
-  auto mask_of = [&](int cc) {
-    uint64_t m = M;
-    m &= (cc & 1) ? b0 : ~b0;
-    m &= (cc & 2) ? b1 : ~b1;
-    m &= (cc & 4) ? b2 : ~b2;
-    return m;
-  };
-  uint32_t base = 0;
-  if (lane < nc) {
-    const uint32_t nl = (uint32_t)__popcll(mask_of(lane));
-    if (nl != 0) base = atomicAdd(&ccnt[lane], nl);
-  }
-  base = __shfl(base, mine ? c : 0);
-  const uint64_t slot = (uint64_t)base + rank_below(mask_of(c));
-  const bool in_seg = mine && slot < (uint64_t)G.seg_cap;
+  if (__ballot(mine) == 0) return;
+  uint32_t slot = 0;
+  if (mine) slot = atomicAdd(&ccnt[c], 1u);
+  const bool in_seg = mine && slot < (uint32_t)G.seg_cap;
+  // Region (b, c) starts c strides after the batch's first region; segment
+  // j of a region j seg_cap slots in.
   int64_t k = -1;
-  if (in_seg) k = region_b0 + (int64_t)c * G.stride + (int64_t)j * G.seg_cap + (int64_t)slot;
+  if (in_seg) k = region_b0 + (int64_t)j * G.seg_cap + (int64_t)c * G.stride + (int64_t)slot;
   if (__ballot(mine && !in_seg) != 0) {
     for (int cc = 0; cc < nc; ++cc) {
       const bool over = mine && !in_seg && c == cc;
