@@ -33,10 +33,15 @@ sys.path.insert(0, ROOT)
 
 METRIC = "particle segments/s and FOM per time step vs plain FP64 sweep, 1 MI355X"
 HBM_PEAK_GBS = 8000.0
-# HBM traffic of the sweep kernel measured by rocprofv3 on this same command
-# (FETCH_SIZE and WRITE_SIZE, scaled by a plain-copy calibration); valid only
-# for the kernel sources it was measured on.
+# Timed runs of the throughput and roofline passes (after one warm-up run):
+# the median is reported.
+REPEATS = 5
+# HBM traffic of the sweep kernel measured by rocprofv3 on the bench's own
+# passes (FETCH_SIZE and WRITE_SIZE, scaled by a plain-copy calibration), as
+# a ratio to the algorithmic bytes of the same launches; and its VALU issue
+# and lane counters.  Valid only for the kernel sources they were measured on.
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "sweep_full-1000c-c0.9-rho5_hbm_traffic.md")
+VALU_PROFILE = os.path.join(ROOT, "profiles", "sweep_full-1000c-c0.9-rho5_valu.md")
 # The sweep kernel's sources and the compiler flags it is built with.
 SWEEP_SOURCES = [os.path.join(ROOT, "paper_2512_19925_amd", "csrc", f) for f in ("hww_sweep.hip", "hww_internal.h")] + \
     [os.path.join(ROOT, "paper_2512_19925_amd", "build.py")]
@@ -163,18 +168,36 @@ def sweep_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per sweep launch from the committed rocprofv3 summary, or
-    None when the kernel sources differ from the measured ones."""
+def profile_figures(path, keys):
+    """Figures of a committed rocprofv3 summary (lines 'key: value'), or None
+    when the kernel sources differ from the measured ones."""
     try:
-        text = open(TRAFFIC_PROFILE).read()
+        text = open(path).read()
     except OSError:
         return None
     m_hash = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", text)
-    m_val = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    if not m_hash or not m_val or m_hash.group(1) != sweep_source_hash():
+    if not m_hash or m_hash.group(1) != sweep_source_hash():
         return None
-    return float(m_val.group(1))
+    out = {}
+    for k in keys:
+        m = re.search(k + r":\s*([0-9.eE+-]+)", text)
+        if not m:
+            return None
+        out[k] = float(m.group(1))
+    return out
+
+
+def host_cpu():
+    """CPU model and logical CPU count of the host the oracle runs on."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count()}
 
 
 def _batch_steps(bt, steps, kw, first=1):
@@ -265,6 +288,54 @@ def run_fp32_pair(steps=20, n_src=10_000_000):
         out[f"{name}_segments_per_s"] = st["segments"] / wall
         out[f"{name}_kernel_segments_per_s"] = st["segments"] / (st["kernel_ms"] * 1e-3)
     out["fp32_over_fp64_kernel"] = out["fp32_kernel_segments_per_s"] / out["fp64_kernel_segments_per_s"]
+    # Error of the FP32 tallies, every cell and step, against the FP64 path
+    # of the same seed (which equals the FP64 oracle within 1e-12 by the
+    # parity tests; the oracle at 1e7 particles is run by the test suite).
+    steps_t = {}
+    for prec in (H.HWW_FP32, H.HWW_FP64):
+        h = H.Handle(H.spec_from_workload(w, precision=prec))
+        steps_t[prec] = []
+        H.run(h, w, steps=steps, stats=False, on_step=lambda n, hh, _: steps_t[prec].append(hh.read_tallies(H.TALLY_CELLS)))
+        h.close()
+    out["error_vs_fp64"] = precision_error(steps_t[H.HWW_FP32], steps_t[H.HWW_FP64])
+    out["error_vs_fp64"]["definition"] = (
+        "per tally kind over every cell and step: z = (T32 - T64) / sigma64 with sigma64 the batch standard "
+        "deviation of the FP64 sum (cells with sigma64 = 0 left out); relative error |T32 - T64| / |T64| (J: "
+        "over phi of the same cell and estimator) over cells above 1e-3 of the step's largest")
+    return out
+
+
+KIND_NAMES = ("track phi", "track J", "track K", "census phi", "census J", "census K")
+
+
+def precision_error(steps_g, steps_o, floor=1e-3):
+    """Reduced-precision tallies against FP64 ones of the same seed: max |z|,
+    the fraction within 3 sigma and the median and largest relative error
+    per tally kind ([B][I][6] raw per-batch sums per step)."""
+    zs = [[] for _ in range(6)]
+    rel = [[] for _ in range(6)]
+    for g, o in zip(steps_g, steps_o):
+        B = o.shape[0]
+        To, Tg = o.sum(0), g.sum(0)
+        sig = np.sqrt(B / (B - 1.0) * ((o - To / B) ** 2).sum(0))
+        scale = np.abs(To)
+        scale[:, 1] = scale[:, 0]
+        scale[:, 4] = scale[:, 3]
+        for k in range(6):
+            m = sig[:, k] > 0
+            zs[k].append((Tg[m, k] - To[m, k]) / sig[m, k])
+            top = scale[:, k].max()
+            mr = scale[:, k] > floor * top if top > 0 else np.zeros(len(To), bool)
+            rel[k].append(np.abs(Tg[mr, k] - To[mr, k]) / scale[mr, k])
+    out = {}
+    for k in range(6):
+        z = np.concatenate(zs[k])
+        r = np.concatenate(rel[k])
+        out[KIND_NAMES[k]] = {"cell_steps": int(z.size),
+                              "max_abs_z": float(np.abs(z).max()) if z.size else 0.0,
+                              "frac_within_3sigma": float(np.mean(np.abs(z) <= 3.0)) if z.size else 1.0,
+                              "median_rel_err": float(np.median(r)) if r.size else 0.0,
+                              "max_rel_err": float(r.max()) if r.size else 0.0}
     return out
 
 
@@ -441,17 +512,23 @@ def _oracle_replica(args):
     return seg, time.perf_counter() - t0
 
 
+# CPU cores a one-GPU run may use on its host (whatever the host shows).
+HOST_CORES_PER_GPU = 16
+
+
 def cpu_aggregate(w, budget_s, procs=None):
     """The oracle in P independent processes at once, each the bounded
     sample of cpu_baseline under its own replica key, P = the host's CPU
-    count (at most 16): summed segments/s."""
+    count, at most the 16 cores a one-GPU run may use: summed segments/s."""
     import multiprocessing as mp
-    P = procs or min(os.cpu_count() or 1, 16)
+    P = procs or min(os.cpu_count() or 1, HOST_CORES_PER_GPU)
     n = max(w.n_src // 4, 1000)
     with mp.get_context("spawn").Pool(P) as pool:
         res = pool.map(_oracle_replica, [(w, n, k, budget_s) for k in range(P)])
     return {"value": sum(s / t for s, t in res), "unit": "segments/s", "processes": P,
-            "sample": f"{P} processes at once, each the single-core sample under replica key k = 0..{P - 1}, "
+            "cores": P, "host": host_cpu(),
+            "sample": f"{P} processes at once (the host's CPU count, at most the {HOST_CORES_PER_GPU} cores "
+                      f"of a one-GPU share), each the single-core sample under replica key k = 0..{P - 1}, "
                       f"about {budget_s:.0f} s each"}
 
 
@@ -479,7 +556,7 @@ def cpu_baseline(w, budget_s):
         if time.perf_counter() - t0 > budget_s:
             break
     dt = time.perf_counter() - t0
-    return {"value": seg / dt, "unit": "segments/s", "cores": 1, "kind": "oracle",
+    return {"value": seg / dt, "unit": "segments/s", "cores": 1, "kind": "oracle", "host": host_cpu(),
             "sample": f"{ws.name} with {n} source particles (1/{frac} of the workload), steps 1-{steps}, "
                       f"{seg} segments in {dt:.1f} s, serial FP64 C oracle"}
 
@@ -509,14 +586,25 @@ def main():
         print(f"warmup + steps must be <= {w.n_steps} time steps of the workload", file=sys.stderr)
         sys.exit(2)
     torch.cuda.init()
-    # Throughput pass: no timing events between the launches.
-    hww = run_gpu(w, total, args.warmup, analog=False, timing=False)
+    # Throughput pass: no timing events between the launches; one warm-up
+    # run, then the median of REPEATS runs (each W untimed steps and K timed
+    # ones on a fresh problem).
+    run_gpu(w, total, args.warmup, analog=False, timing=False)
+    runs = sorted((run_gpu(w, total, args.warmup, analog=False, timing=False) for _ in range(REPEATS)),
+                  key=lambda d: d["segments"] / d["wall_s"])
+    hww = runs[REPEATS // 2]
     value = hww["segments"] / hww["wall_s"]
     ms_per_step = hww["wall_s"] * 1e3 / args.steps
     # Roofline pass: the same steps with HIP events around every sweep launch
-    # on the library's stream.
-    tim = run_gpu(w, total, args.warmup, analog=False, timing=True)
+    # on the library's stream; the median run by average launch time.
+    tims = sorted((run_gpu(w, total, args.warmup, analog=False, timing=True) for _ in range(REPEATS)),
+                  key=lambda d: d["kernel_ms"] / max(d["launches"], 1))
+    tim = tims[REPEATS // 2]
     achieved = tim["bytes_moved"] / (tim["kernel_ms"] * 1e-3) / 1e9 if tim["kernel_ms"] > 0 else 0.0
+    bytes_per_launch = tim["bytes_moved"] / max(tim["launches"], 1)
+    avg_launch_s = tim["kernel_ms"] * 1e-3 / max(tim["launches"], 1)
+    traf = profile_figures(TRAFFIC_PROFILE, ["traffic_over_algorithmic"])
+    valu = profile_figures(VALU_PROFILE, ["valu_issue_frac", "active_lanes_per_valu", "valu_insts_per_launch"])
     line = {
         "metric": METRIC, "value": value, "unit": "segments/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
@@ -529,10 +617,22 @@ def main():
                    "n_src": w.n_src, "n_cells": w.n_cells, "time_steps": args.steps},
         "kernel_segments_per_s": tim["segments"] / (tim["kernel_ms"] * 1e-3) if tim["kernel_ms"] else None,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traf["traffic_over_algorithmic"] * bytes_per_launch if traf else None,
+                     "traffic_over_algorithmic": traf["traffic_over_algorithmic"] if traf else None,
                      "kernel": "sweep_kernel<double, true, false>",
-                     "launches": tim["launches"], "avg_launch_ms": tim["kernel_ms"] / max(tim["launches"], 1),
-                     "bytes_per_launch": tim["bytes_moved"] / max(tim["launches"], 1)},
+                     "launches": tim["launches"], "avg_launch_ms": avg_launch_s * 1e3,
+                     "bytes_per_launch": bytes_per_launch,
+                     "runs": REPEATS, "avg_launch_ms_runs": [d["kernel_ms"] / max(d["launches"], 1) for d in tims],
+                     # VALU side: wave-instruction issue cycles (4 per wave64
+                     # instruction) over the 1024 SIMDs' cycles of the launch,
+                     # and active lanes per VALU instruction, from committed
+                     # counters of the same command.
+                     "valu": ({"issue_frac": valu["valu_issue_frac"],
+                               "active_lanes_per_instruction": valu["active_lanes_per_valu"],
+                               "lane_frac": valu["active_lanes_per_valu"] / 64.0,
+                               "source": os.path.relpath(VALU_PROFILE, ROOT)} if valu else None)},
+        "value_runs": [d["segments"] / d["wall_s"] for d in runs],
     }
     if not args.no_analog:
         from paper_2512_19925_amd import pulse_reference as P
