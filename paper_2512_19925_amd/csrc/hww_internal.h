@@ -29,8 +29,10 @@ constexpr int kMaxGenerations = 4096;
 // Batch-summed tallies: every sweep work-group adds its histogram into copy
 // (work-group index mod kSumCopies) of [copy][6][I] (column-major), besides
 // its batch's row of [B][I][6]; an LOSM solve adds the copies up.  More copies
-// spread the atomics of the flush over more addresses.
-constexpr int kSumCopies = 4;
+// would spread the atomics of the flush over more addresses, but the flushes
+// of a launch are spread in time enough that one copy does not slow the
+// sweep, and each further copy costs the solve loads.
+constexpr int kSumCopies = 1;
 
 // Position and direction of a particle (one 16-byte load in FP64).
 template <typename Real>
