@@ -409,7 +409,7 @@ def run_sweep(total, warmup, n_src):
     return out
 
 
-def run_paper_problem(seeds=5, window_scale=1):
+def run_paper_problem(seeds=5, window_scale=1, comb_by_index=True):
     """The paper's own supercritical problem (Sec. 5.1: c_eff = 1.1 with
     fission, 201 cells, 20 steps of dt = 1, 1e4 histories per step kept by
     uniform combing, rho = 1.25, eps_min = 1e-3) for the paper's methods:
@@ -422,7 +422,7 @@ def run_paper_problem(seeds=5, window_scale=1):
     from paper_2512_19925_amd import hww as H
     from paper_2512_19925_amd import pulse_reference as P
     from paper_2512_19925_amd import workloads as W
-    w0 = W.paper_fission().with_(window_scale=window_scale)
+    w0 = W.paper_fission().with_(window_scale=window_scale, comb_by_index=comb_by_index)
     ref = P.cell_step_averages(w0.edges, w0.dt, w0.n_steps, 1.1)
     dx = np.diff(w0.edges)
     methods = (("analog", w0.with_(analog=True)), ("HWW", w0.with_(filter=0)), ("HWW-MA", w0),
@@ -464,7 +464,9 @@ def run_paper_problem(seeds=5, window_scale=1):
                      "ms_per_step": wall * 1e3 / (seeds * w.n_steps), "fissions_per_step": fis / (seeds * w.n_steps)}
     out = {"workload": f"{w0.name}: {w0.n_cells} cells on [{w0.x_lo},{w0.x_hi}], sigma_t=1, sigma_s=sigma_f=1/3, "
                        f"nu_f={w0.nu_f} (c_eff=1.1), v=1, dt={w0.dt}, {w0.n_steps} steps, H={w0.comb} histories "
-                       f"per step (uniform comb), rho={w0.rho}, eps_min={w0.eps_min}, CN, 3 window updates per "
+                       f"per step (uniform comb, teeth spaced in "
+                       f"{'particle index' if comb_by_index else 'cumulative weight'}), rho={w0.rho}, "
+                       f"eps_min={w0.eps_min}, CN, 3 window updates per "
                        f"step, window centres {'as printed (largest 1)' if window_scale else 'times s^n'}, "
                        f"{seeds} seeds",
            "fom": "per step, tau = step wall time (work_fom: tau = segments of the step); FOM averaged over "
@@ -659,7 +661,8 @@ def main():
         line["fp32"] = run_fp32_pair()
     if not args.no_paper:
         line["paper_problem"] = {"windows_times_s": run_paper_problem(window_scale=0),
-                                 "windows_as_printed": run_paper_problem(window_scale=1)}
+                                 "windows_as_printed": run_paper_problem(window_scale=1),
+                                 "comb_by_weight": run_paper_problem(window_scale=0, comb_by_index=False)}
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
         line["cpu_baseline"]["aggregate"] = cpu_aggregate(w, args.cpu_seconds)

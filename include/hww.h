@@ -69,7 +69,12 @@ typedef struct hww_problem {
   const double *sigma_f;  /* I fission cross sections (host), or NULL: no fission;
                              0 <= sigma_f, sigma_s + sigma_f <= sigma_t (Eq. HO_transport) */
   double nu_f;            /* mean neutrons per fission, 0 <= nu_f < 1e6 (with sigma_f) */
-  int32_t comb;           /* 1: reserve the workspace hww_comb needs, 0: none    */
+  int32_t comb;           /* reserve the workspace hww_comb needs and pick its reading of
+                             uniform combing (Sec. 5.1): 0 no combing; 1 teeth spaced in
+                             cumulative weight, every copy of weight W / n_target; 2 teeth
+                             spaced in particle index, each copy keeping its particle's
+                             weight times n / n_target (Sec. 5: the comb thins the many
+                             particles of weight near 1 at the source)           */
   int32_t track_moments;  /* track-length moments scored per segment (Eq. phi-mc and its mu, mu^2
                              moments): 0 or 3 phi, J and K; 2 phi and K (enough for track-length
                              closures); 1 phi only (census closures need no more); the
@@ -185,7 +190,12 @@ int hww_sweep_step(hww_handle *h, int32_t step, int32_t chunk, hww_step_stats *s
  * position, direction and cell of the particle it hits; the copy becomes
  * history k (lineage = step, event index 0) of batch k mod B and next-step
  * chunk (k / B) mod n_chunks.  Census tallies are unchanged; the per-chunk
- * census weights become count * W / n_target.  Call after the last chunk of
+ * census weights become count * W / n_target.  With comb = 2 in the problem
+ * the teeth are spaced in particle index instead: tooth k copies the
+ * particle at position floor((k + xi) n / n_target) of the n census
+ * particles in that order, with that particle's weight times n / n_target,
+ * and the per-chunk census weights are the sums of the copies' weights.
+ * Call after the last chunk of
  * a step and before the next step's semi-implicit solve.  n_before and
  * w_total (nullable host pointers) receive the census size and W; an empty
  * census stays empty (both 0).  With either pointer given the call
@@ -193,7 +203,7 @@ int hww_sweep_step(hww_handle *h, int32_t step, int32_t chunk, hww_step_stats *s
  * returns: an empty census then leaves an empty combed bank, and a weight
  * that is not positive and finite leaves an empty bank and an error that
  * the next synchronising call reports (HWW_E_NUMERIC, fatal).  Single
- * problems initialised with comb = 1 only.
+ * problems initialised with comb = 1 or 2 only.
  * Errors: HWW_E_INVALID_ARG (n_target outside 1..bank_capacity or > 2^32-1),
  * HWW_E_STATE (step not finished, no comb workspace, a batch or a view),
  * HWW_E_CAPACITY (a region of the new bank overflows), HWW_E_NUMERIC (a

@@ -204,6 +204,7 @@ struct orc_sim {
   nsum *w_chunk_start;               /* [n_chunks] weight of the start bank per chunk */
   nsum *w_chunk_next;                /* [n_chunks] same, for the next step (filled at census) */
   int32_t step, next_chunk;
+  int comb_mode;  /* 0: teeth spaced in cumulative weight, 1: spaced in particle index */
 };
 
 static int tally_alloc(tally_set *t, int B, int I) {
@@ -651,6 +652,52 @@ static int canon_cmp(const void *a, const void *b) {
  * and as a double, and so is each comparison with a tooth.  Copy k becomes
  * history k of lineage `step` (event index 0) in batch k mod B and chunk
  * (k / B) mod n_chunks. */
+int orc_set_comb_mode(orc_sim *s, int32_t mode) {
+  if (!s || mode < 0 || mode > 1) return -1;
+  s->comb_mode = mode;
+  return 0;
+}
+
+/* Comb with the teeth spaced in particle index (the other reading of Sec.
+ * 5.1's uniform combing, Sec. 5's remark that it thins the particles of
+ * weight near 1 at the source): tooth k = 0..n_target-1 takes the particle at
+ * canonical position floor((k + xi) n / n_target), with its weight times
+ * n / n_target, so every census particle is kept with the same expected
+ * number of copies and its expected weight is unchanged.  The weight is
+ * taken in the comb's integer unit 2^eu (q: inclusive prefix sums of the
+ * integer weights), and the chunk weights from exact integer sums, so that
+ * a change of a weight far below the unit changes nothing after the comb. */
+static int comb_by_index(orc_sim *s, int64_t n_target, const uint64_t *q, int eu, double *w_total) {
+  const int64_t n = s->n_census;
+  double xi;
+  draw(s->seed, s->replica, SLOT_COMB, (uint32_t)s->step, 0, 0, &xi, NULL, NULL);
+  const double delta = (double)n / (double)n_target;
+  uint64_t chunk_sum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  particle *dst = s->start;
+  for (int64_t k = 0; k < n_target; ++k) {
+    int64_t j = (int64_t)(((double)k + xi) * delta);
+    if (j >= n) j = n - 1;
+    const uint64_t wi = q[j] - (j > 0 ? q[j - 1] : 0);
+    particle c = s->census[j];
+    c.w = ldexp((double)wi, eu) * delta;
+    c.src = (uint32_t)k;
+    c.lin = (uint64_t)s->step;
+    c.e = 0;
+    c.chunk = (int32_t)((k / s->B) % s->n_chunks);
+    chunk_sum[c.chunk] += wi;
+    dst[k] = c;
+  }
+  for (int c = 0; c < s->n_chunks; ++c) {
+    s->w_chunk_next[c].s = ldexp((double)chunk_sum[c], eu) * delta;
+    s->w_chunk_next[c].c = 0.0;
+  }
+  s->start = s->census;
+  s->census = dst;
+  s->n_census = n_target;
+  if (w_total) *w_total = ldexp((double)q[n - 1], eu);
+  return 0;
+}
+
 int orc_comb(orc_sim *s, int64_t n_target, int64_t *n_before, double *w_total) {
   if (!s || n_target < 1 || n_target > s->cap || n_target > 0xFFFFFFFFll) return -1;
   if (s->next_chunk != s->n_chunks || s->step < 1) return -2;
@@ -678,6 +725,11 @@ int orc_comb(orc_sim *s, int64_t n_target, int64_t *n_before, double *w_total) {
     q[j] = acc; /* inclusive prefix sum */
   }
   const double W = (double)acc;
+  if (s->comb_mode == 1) {
+    const int rc = comb_by_index(s, n_target, q, eu, w_total);
+    free(q);
+    return rc;
+  }
   double xi;
   draw(s->seed, s->replica, SLOT_COMB, (uint32_t)s->step, 0, 0, &xi, NULL, NULL);
   const double delta = W / (double)n_target;

@@ -83,6 +83,10 @@ int orc_sweep_chunk(orc_sim *s, int32_t step, int32_t chunk);
  * problem, Sec. 5.1).  n_before and w_total (nullable) return the census
  * size and the total weight that the comb distributes. */
 int orc_comb(orc_sim *s, int64_t n_target, int64_t *n_before, double *w_total);
+/* Reading of the comb: 0 (default) teeth spaced in cumulative weight, every
+ * copy of weight W / n_target; 1 teeth spaced in particle index, every copy
+ * keeping its particle's weight times n / n_target. */
+int orc_set_comb_mode(orc_sim *s, int32_t mode);
 int orc_solve_losm(orc_sim *s, const orc_losm_opts *o, double *phi_out, double *J_out);
 /* Initial condition phi_o (I+2), J_o (I+1), F_o (I+2) and closures F_n
  * (I+2), P (2: P_L, P_R) of an HLOSM solve, before any filter:

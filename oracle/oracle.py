@@ -62,6 +62,7 @@ def lib():
         L.orc_set_windows.argtypes = [C.c_void_p, dp, C.c_double]
         L.orc_sweep_chunk.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
         L.orc_comb.argtypes = [C.c_void_p, C.c_int64, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
+        L.orc_set_comb_mode.argtypes = [C.c_void_p, C.c_int32]
         L.orc_solve_losm.argtypes = [C.c_void_p, C.c_void_p, dp, dp]
         L.orc_get_closures.argtypes = [C.c_void_p, dp, dp, dp, dp]
         L.orc_losm_inputs.argtypes = [C.c_void_p, C.c_int32, C.c_int32, dp, dp, dp, dp, dp]
@@ -291,6 +292,11 @@ class OracleSim:
         nb, wt = C.c_int64(), C.c_double()
         _check("comb", lib().orc_comb(self._h, int(n_target), C.byref(nb), C.byref(wt)))
         return int(nb.value), float(wt.value)
+
+    def set_comb_mode(self, mode):
+        """0: comb teeth spaced in cumulative weight (equal weights after);
+        1: spaced in particle index (weights scaled by n / n_target)."""
+        _check("set_comb_mode", lib().orc_set_comb_mode(self._h, int(mode)))
 
     def solve_losm(self, opts: LosmOpts, implicit: bool, apply_windows=True):
         o = _Opts(float(opts.theta), int(implicit), int(opts.filter), int(opts.ma_k),

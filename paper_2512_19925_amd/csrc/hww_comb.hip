@@ -1,8 +1,16 @@
 // Uniform combing of a census bank (the population control of the paper's
-// supercritical test problem, Sec. 5.1): the census particles are laid end
-// to end in canonical order (src, lineage, event), each as long as its
-// weight, and n_target equally spaced teeth with one random offset pick the
-// particles that are copied, at weight W / n_target.
+// supercritical test problem, Sec. 5.1), in two readings.  By weight: the
+// census particles are laid end to end in canonical order (src, lineage,
+// event), each as long as its weight, and n_target equally spaced teeth with
+// one random offset pick the particles that are copied, at weight
+// W / n_target.  By index: the teeth are spaced n / n_target apart over the
+// n particles in canonical order, every particle has the same chance, and
+// each copy keeps its particle's weight times n / n_target (the reading under
+// which the comb thins the many particles of weight near 1 at the source, as
+// Sec. 5 remarks of the paper's), the weight taken in the integer unit below
+// and the chunk weights from exact integer sums, so that rounding far below
+// the unit (the summation order of the window solve) changes nothing after
+// the comb.
 //
 // Order on the device: a counting sort by src (histogram, exclusive scan,
 // scatter), then each history's particles ranked by (lineage, event): one
@@ -50,6 +58,7 @@ __device__ inline void for_each_census_slot(const CombArgs<Real> &A, F &&f) {
 template <typename Real>
 __global__ void comb_clear_kernel(CombArgs<Real> A) {
   if (blockIdx.x == 0 && threadIdx.x < 8) A.misc[threadIdx.x] = 0ull;
+
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= A.n_hist; i += (int64_t)gridDim.x * blockDim.x) {
     A.cnt[i] = 0ull;
     if (i < A.n_hist) A.cur[i] = 0u;
@@ -307,6 +316,9 @@ __global__ void __launch_bounds__(1024) comb_sort_big_kernel(CombArgs<Real> A) {
 // weights in units of 2^eu, in canonical order.
 template <typename Real>
 __global__ void comb_weights_kernel(CombArgs<Real> A) {
+  // The history counts are done with; their first cells take the integer
+  // chunk sums of a comb by index.
+  if (blockIdx.x == 0 && threadIdx.x < 8) A.cnt[threadIdx.x] = 0ull;
   const CombScale c = comb_scale(A.misc);
   if (!c.ok) return;
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < c.n; j += (int64_t)gridDim.x * blockDim.x) {
@@ -348,7 +360,9 @@ __device__ inline CombPlace comb_place(int64_t k, int64_t H, int B, int nc, cons
   return p;
 }
 
-// Tooth k: the first particle whose inclusive prefix exceeds (k + xi) delta.
+// Tooth k: by weight, the first particle whose inclusive prefix exceeds
+// (k + xi) delta; by index, the particle at canonical position
+// floor((k + xi) n / n_target).
 template <typename Real>
 __global__ void comb_teeth_kernel(CombArgs<Real> A) {
   const CombScale c = comb_scale(A.misc);
@@ -359,17 +373,24 @@ __global__ void comb_teeth_kernel(CombArgs<Real> A) {
   draw(A.seed, A.key1, SLOT_COMB, A.step, 0ull, 0u, r);
   const double xi = u53(r[0], r[1]);
   const double W = (double)A.wq[n - 1];
-  const double delta = W / (double)A.n_target;
+  const double delta = A.by_index ? (double)n / (double)A.n_target : W / (double)A.n_target;
   const double w_out = ldexp(W, eu) / (double)A.n_target;
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < A.n_target;
        k += (int64_t)gridDim.x * blockDim.x) {
-    double t = ((double)k + xi) * delta;
-    if (t >= W) t = W - 1.0;
-    int64_t lo = 0, hi = n - 1;
-    while (lo < hi) {
-      const int64_t mid = lo + (hi - lo) / 2;
-      if ((double)A.wq[mid] > t) hi = mid;
-      else lo = mid + 1;
+    int64_t lo;
+    if (A.by_index) {
+      lo = (int64_t)(((double)k + xi) * delta);
+      if (lo >= n) lo = n - 1;
+    } else {
+      double t = ((double)k + xi) * delta;
+      if (t >= W) t = W - 1.0;
+      lo = 0;
+      int64_t hi = n - 1;
+      while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if ((double)A.wq[mid] > t) hi = mid;
+        else lo = mid + 1;
+      }
     }
     const unsigned long long q = A.order[lo];
     const CombPlace pl = comb_place(k, A.n_target, A.B, A.nc, A.G);
@@ -377,8 +398,14 @@ __global__ void comb_teeth_kernel(CombArgs<Real> A) {
       atomicOr(A.err, ERR_CAPACITY);
       continue;
     }
+    double wc = w_out;
+    if (A.by_index) {
+      const unsigned long long wi = A.wq[lo] - (lo > 0 ? A.wq[lo - 1] : 0ull);
+      wc = ldexp((double)wi, eu) * delta;
+      atomicAdd(&A.cnt[(int)((k / A.B) % A.nc)], wi);
+    }
     A.dst_bank.xm[pl.slot] = A.src_bank.xm[q];
-    A.dst_bank.w[pl.slot] = w_out;
+    A.dst_bank.w[pl.slot] = wc;
     A.dst_bank.lin[pl.slot] = (uint64_t)A.step;
     Tag tg;
     tg.src = (uint32_t)k;
@@ -427,7 +454,9 @@ __global__ void __launch_bounds__(1024) comb_finish_kernel(CombArgs<Real> A) {
   __syncthreads();
   const double W = (double)A.wq[cs.n - 1];
   const double w_out = ldexp(W, cs.eu) / (double)A.n_target;
-  if (threadIdx.x < (unsigned)A.nc) A.wnext[threadIdx.x] = (double)chunk[threadIdx.x] * w_out;
+  if (threadIdx.x < (unsigned)A.nc)
+    A.wnext[threadIdx.x] = A.by_index ? ldexp((double)A.cnt[threadIdx.x], cs.eu) * ((double)cs.n / (double)A.n_target)
+                                      : (double)chunk[threadIdx.x] * w_out;
   if (threadIdx.x == 0) A.misc[2] = (unsigned long long)__double_as_longlong(ldexp(W, cs.eu));
 }
 

@@ -163,6 +163,9 @@ struct CombArgs {
   int64_t n_hist;              // bound on src values + 1 of the census
   int64_t cap;                 // bound on census particles
   int64_t n_target;
+  int32_t by_index;            // 1: teeth spaced in particle index, each copy keeping its
+                               // particle's weight times n / n_target; 0: spaced in
+                               // cumulative weight, every copy of weight W / n_target
   int32_t no_wait;             // 1: the host will not read the census size, so an empty or
                                // invalid census leaves an empty combed bank (and, if
                                // invalid, ERR_COMB_WEIGHT) for it to take as the census

@@ -382,7 +382,7 @@ int validate(const hww_problem *p, std::string *why) {
     }
   }
   if (p->sigma_f && (!(p->nu_f >= 0.0) || !(p->nu_f < 1.0e6))) { *why = "nu_f must be in [0, 1e6)"; return HWW_E_INVALID_ARG; }
-  if (p->comb != 0 && p->comb != 1) { *why = "comb must be 0 or 1"; return HWW_E_INVALID_ARG; }
+  if (p->comb < 0 || p->comb > 2) { *why = "comb must be 0, 1 or 2"; return HWW_E_INVALID_ARG; }
   if (p->track_moments < 0 || p->track_moments > 3) { *why = "track_moments must be 0..3"; return HWW_E_INVALID_ARG; }
   if (!(p->src_x >= p->edges[0] && p->src_x <= p->edges[p->n_cells])) { *why = "src_x outside the mesh"; return HWW_E_INVALID_ARG; }
   if (sweep_lds_bytes(p->n_cells, p->n_chunks, 64) > 160 * 1024) { *why = "too many cells for the LDS histogram (I <= 3136 with 2..8 chunks, 3137 with 1)"; return HWW_E_INVALID_ARG; }
@@ -1114,6 +1114,7 @@ int hww_comb(hww_handle *h, int64_t n_target, int64_t *n_before, double *w_total
     a.cap = L.comb_slots;
     a.n_target = n_target;
     a.no_wait = (!n_before && !w_total) ? 1 : 0;
+    a.by_index = h->p.comb == 2 ? 1 : 0;
     a.seed = h->p.seed; a.key1 = h->p.replica << 4; a.step = (uint32_t)h->step;
     a.cnt = reinterpret_cast<unsigned long long *>(h->ws + L.off_c_cnt);
     a.cur = reinterpret_cast<uint32_t *>(h->ws + L.off_c_cur);
@@ -1133,7 +1134,7 @@ int hww_comb(hww_handle *h, int64_t n_target, int64_t *n_before, double *w_total
     a32.src_bank = h->bank32[1 - h->start_bank];
     a32.dst_bank = h->bank32[h->start_bank];
     a32.G = a.G; a32.B = a.B; a32.nc = a.nc; a32.R = a.R; a32.n_hist = a.n_hist; a32.cap = a.cap;
-    a32.n_target = a.n_target; a32.no_wait = a.no_wait; a32.seed = a.seed; a32.key1 = a.key1; a32.step = a.step;
+    a32.n_target = a.n_target; a32.no_wait = a.no_wait; a32.by_index = a.by_index; a32.seed = a.seed; a32.key1 = a.key1; a32.step = a.step;
     a32.cnt = a.cnt; a32.cur = a.cur; a32.order = a.order; a32.wq = a.wq; a32.blk = a.blk; a32.misc = a.misc;
     a32.wnext = a.wnext; a32.err = a.err;
   }

@@ -454,7 +454,8 @@ def spec_from_workload(w, precision=HWW_FP64) -> ProblemSpec:
     return ProblemSpec(edges=w.edges, sigma_t=w.sigma_t, sigma_s=w.sigma_s, speed=w.speed, dt=w.dt,
                        n_steps=w.n_steps, src_x=w.src_x, n_src=w.n_src, bank_capacity=w.capacity(),
                        seed=w.seed, replica=w.replica, n_batches=w.n_batches, precision=precision,
-                       n_chunks=w.n_chunks, sigma_f=w.sigma_f, nu_f=w.nu_f, comb=int(w.comb > 0),
+                       n_chunks=w.n_chunks, sigma_f=w.sigma_f, nu_f=w.nu_f,
+                       comb=(2 if w.comb_by_index else 1) if w.comb > 0 else 0,
                        track_moments=w.track_moments)
 
 

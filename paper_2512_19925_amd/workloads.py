@@ -48,6 +48,7 @@ class Workload:
     sigma_f: np.ndarray | None = None  # fission cross sections (None: no fission)
     nu_f: float = 0.0                  # mean neutrons per fission
     comb: int = 0                      # comb every census to this many particles (0: never)
+    comb_by_index: bool = False        # comb teeth spaced in particle index (else in cumulative weight)
     window_scale: int = 0              # 1: window centres as printed (largest 1), 0: times s^n
     track_moments: int = 0             # track moments per segment: 0/3 phi, J, K; 2 phi, K; 1 phi
 
@@ -99,7 +100,7 @@ def paper_fission(n_src: int = 10_000) -> Workload:
     st = np.ones(I)
     return Workload(name="paper-fission-201c", x_lo=-20.5, x_hi=20.5, n_cells=I, sigma_t=st,
                     sigma_s=st / 3.0, sigma_f=st / 3.0, nu_f=2.3, speed=1.0, dt=1.0, n_steps=20,
-                    n_src=n_src, comb=n_src, rho=1.25, eps_min=1e-3, filter=1, ma_k=3,
+                    n_src=n_src, comb=n_src, comb_by_index=True, rho=1.25, eps_min=1e-3, filter=1, ma_k=3,
                     bank_capacity=max(400 * n_src, 4096), seed=1)
 
 

@@ -16,9 +16,11 @@ def need_gpu():
 
 
 def oracle_sim(w):
-    return O.OracleSim(w.edges, w.sigma_t, w.sigma_s, w.speed, w.dt, w.n_steps, w.src_x, w.n_src,
-                       w.capacity(), w.seed, w.replica, w.n_batches, w.n_chunks, sigma_f=w.sigma_f,
-                       nu_f=w.nu_f, track_moments=w.track_moments)
+    sim = O.OracleSim(w.edges, w.sigma_t, w.sigma_s, w.speed, w.dt, w.n_steps, w.src_x, w.n_src,
+                      w.capacity(), w.seed, w.replica, w.n_batches, w.n_chunks, sigma_f=w.sigma_f,
+                      nu_f=w.nu_f, track_moments=w.track_moments)
+    sim.set_comb_mode(1 if w.comb_by_index else 0)
+    return sim
 
 
 def oracle_opts(w):

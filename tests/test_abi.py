@@ -97,7 +97,7 @@ def test_fission_comb_and_tally_options_validation():
         dict(sigma_f=w.sigma_t * 0.9),                 # sigma_s + sigma_f > sigma_t
         dict(sigma_f=-w.sigma_f),                      # negative fission cross section
         dict(nu_f=-1.0), dict(nu_f=float("nan")),
-        dict(comb=2), dict(track_moments=4), dict(track_moments=-1),
+        dict(comb=3), dict(comb=-1), dict(track_moments=4), dict(track_moments=-1),
     ]
     for kw in bad:
         spec = H.spec_from_workload(w)

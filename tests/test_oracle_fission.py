@@ -251,6 +251,77 @@ def test_comb_offsets_are_uniform():
     assert abs(hits - exp) < 4.0 * math.sqrt(var)
 
 
+def test_comb_by_index_is_systematic_sampling_over_particles():
+    # Teeth spaced in particle index: every particle of the laid-out census
+    # (canonical order) is one unit long, so every run of consecutive
+    # particles gets the floor or the ceiling of (run length) H / n copies,
+    # in order, and every copy keeps its particle's weight times n / H (its
+    # expected weight is its particle's), the weight taken in the comb's
+    # integer unit 2^eu (count * largest weight < 2^(53 + eu)).  Fewer and
+    # more copies than particles; each copy becomes history k of step 1 as
+    # in the other reading.
+    w = _fission("combi", -6.0, 6.0, 60, 1 / 3, 1 / 3, 2.3, dt=0.5, n_steps=3, n_src=3000, rho=1.25,
+                 bank_capacity=200000, n_batches=8, n_chunks=4)
+    for H in (1000, 9000):
+        sim = oracle_sim(w)
+        sim.set_comb_mode(1)
+        opts = O.LosmOpts(theta=0.5, rho=1.25, filter=1)
+        sim.solve_losm(opts, implicit=False)
+        for p in range(w.n_chunks):
+            sim.sweep(1, p)
+            if p < w.n_chunks - 1:
+                sim.solve_losm(opts, implicit=True)
+        before = _canonical(sim.bank(1))
+        n = len(before["w"])
+        assert len(np.unique(before["w"])) > 3
+        n_before, W_tot = sim.comb(H)
+        assert n_before == n and abs(W_tot / before["w"].sum() - 1.0) < 1e-12
+        after = sim.bank(1)
+        assert len(after["w"]) == H
+        assert np.array_equal(after["src"], np.arange(H, dtype=np.uint32))
+        assert np.all(after["lin"] == 1) and np.all(after["e"] == 0)
+        assert np.array_equal(after["chunk"], (np.arange(H) // w.n_batches) % w.n_chunks)
+        # Match the copies, in order, to runs of equal state and weight.
+        eu = int(np.frexp(before["w"].max())[1]) + int(np.ceil(np.log2(n))) - 53
+        w_unit = np.ldexp(np.rint(np.ldexp(before["w"], -eu)), eu)
+        assert np.all(np.abs(w_unit / before["w"] - 1.0) < 1e-9)
+        key_b = np.stack([before["x"], before["mu"], before["cell"].astype(float), w_unit * (n / H)], 1)
+        key_a = np.stack([after["x"], after["mu"], after["cell"].astype(float), after["w"]], 1)
+        groups = _groups(key_b)
+        pos = 0
+        for start, ln in groups:
+            share = ln * H / n
+            cnt = 0
+            while pos < H and np.array_equal(key_a[pos], key_b[start]):
+                pos += 1
+                cnt += 1
+            assert math.floor(share) <= cnt <= math.ceil(share), (start, ln, cnt, share)
+        assert pos == H
+
+
+def test_comb_by_index_keeps_the_weight_on_average():
+    # Over many combs (seeds) the total weight after a comb by index equals
+    # the census weight before it on average (each particle's expected
+    # number of copies is H / n, each copy of weight w n / H).
+    ratios = []
+    for seed in range(1, 61):
+        w = _fission("combw", -3.0, 3.0, 30, 1 / 3, 1 / 3, 2.3, dt=0.5, n_steps=2, n_src=400, rho=1.25,
+                     bank_capacity=40000, n_batches=4, n_chunks=2, seed=seed)
+        sim = oracle_sim(w)
+        sim.set_comb_mode(1)
+        opts = O.LosmOpts(theta=0.5, rho=1.25, filter=1)
+        sim.solve_losm(opts, implicit=False)
+        for p in range(w.n_chunks):
+            sim.sweep(1, p)
+            if p < w.n_chunks - 1:
+                sim.solve_losm(opts, implicit=True)
+        _, W_tot = sim.comb(150)
+        ratios.append(sim.bank(1)["w"].sum() / W_tot)
+    r = np.array(ratios)
+    assert r.std() > 0  # the windows made the weights differ, so the total varies
+    assert abs(r.mean() - 1.0) < 4.0 * r.std(ddof=1) / math.sqrt(len(r))
+
+
 def test_comb_keeps_the_paper_problem_bounded():
     # The paper's problem at a tenth of its population: with combing every
     # census holds exactly H particles while the total weight grows.
