@@ -49,15 +49,33 @@ __global__ void losm_factor_kernel(LosmArgs A) {
   losm_factor_body(A);
 }
 
-__device__ void ma_filter_dev(const double *in, double *out, int M, int k) {
-  for (int m = 1 + (int)threadIdx.x; m <= M; m += blockDim.x) {
-    int km = k;
-    if (m - 1 < km) km = m - 1;
-    if (M - m < km) km = M - m;
-    double acc = 0.0;
-    for (int l = -km; l <= km; ++l) acc += in[m - l - 1];
-    out[m - 1] = acc / (double)(2 * km + 1);
+// Moving average (Sec. 4 Eq. moving_average) of value m of in[0..M) into
+// out[m]: the mean over the 2k+1 values centred on it, the window shrunk
+// symmetrically where it would leave the range; terms added in the order
+// l = -k..k.
+template <int K>
+__device__ __forceinline__ double ma_full(const double *in, int m) {
+  double x[2 * K + 1];
+#pragma unroll
+  for (int l = -K; l <= K; ++l) x[l + K] = in[m - l];
+  double acc = 0.0;
+#pragma unroll
+  for (int l = 0; l <= 2 * K; ++l) acc += x[l];
+  return acc / (double)(2 * K + 1);
+}
+
+__device__ inline void ma_point(const double *in, double *out, int M, int m, int k) {
+  int km = k;
+  if (m < km) km = m;
+  if (M - 1 - m < km) km = M - 1 - m;
+  // Full windows of the usual widths: the window's loads issued together.
+  if (km == k && k >= 1 && k <= 4) {
+    out[m] = k == 1 ? ma_full<1>(in, m) : k == 2 ? ma_full<2>(in, m) : k == 3 ? ma_full<3>(in, m) : ma_full<4>(in, m);
+    return;
   }
+  double acc = 0.0;
+  for (int l = -km; l <= km; ++l) acc += in[m - l];
+  out[m] = acc / (double)(2 * km + 1);
 }
 
 // Fourier low pass (Sec. 4, Eqs. fft and ifft) of in[0..M) into out: of the
@@ -125,29 +143,23 @@ __device__ __forceinline__ void fourier_cells_swap(double *&f, double *&spare, i
   spare = t;
 }
 
-// Scale of the closure set: start weight / swept start weight (implicit),
-// 1 (semi-implicit); zero means no start weight has been swept yet.
-__device__ inline double closure_scale(const LosmArgs &A) {
-  if (!A.implicit) return 1.0;
-  double wtot = 0.0, done = 0.0;
-  for (int q = 0; q < A.nc; ++q) {
-    wtot += A.wstart[q];
-    if (q < A.next_chunk) done += A.wstart[q];
-  }
-  return done > 0.0 ? wtot / done : 0.0;
-}
-
-// Layout of a solve's working arrays (M = I + 2 doubles each): six grid
+// Layout of a solve's working arrays (M = I + 2 doubles each): eight grid
 // functions, in LDS when they fit (work_in_lds) else at the start of the
-// global scratch; the normalised batch sums after them (those of the
-// initial condition are kept for the later solves of the step); the Fourier
-// coefficients after those.
-__device__ inline double *losm_sums(const LosmArgs &A) { return A.scratch + 6 * (A.I + 2); }
+// global scratch; the initial condition's normalised batch sums after them
+// in the global scratch (kept there for the later solves of the step); the
+// Fourier coefficients after those.
+__device__ inline double *losm_sums(const LosmArgs &A) { return A.scratch + 8 * (A.I + 2); }
 __device__ inline double *losm_fourier_scratch(const LosmArgs &A) { return A.scratch + 12 * (A.I + 2) + 16; }
 
 // kWil: where the working arrays live (0 global scratch, 1 LDS, 2 LDS with
 // the Fourier coefficients too), fixed at compile time so that every access
 // is a plain LDS or global one.
+//
+// The solve is a chain of dependent phases on one work-group, so its time
+// is the latency of that chain.  All global reads of the inputs are issued
+// at once at the start (the closure scale and the early-exit checks are
+// wave-uniform values every wave computes for itself), and the phases meet
+// at seven barriers.
 template <int kWil>
 __device__ __forceinline__ void losm_body(const LosmArgs &A, double *dyn) {
   const int I = A.I;
@@ -163,118 +175,138 @@ __device__ __forceinline__ void losm_body(const LosmArgs &A, double *dyn) {
   const bool rows_in_regs = (n + T - 1) / T <= kScanRows;
   ScanRows<kScanRows> R;
   if (rows_in_regs) losm_scan_prefetch(A.factor, n, R);
-  // Grid functions and two spare buffers; filters write into a spare and
-  // the pointers swap (faces copied along).
-  double *phi_o = S, *J_o = S + M, *F_o = S + 2 * M, *F_n = S + 3 * M, *T1 = S + 4 * M, *T2 = S + 5 * M;
+  // Grid functions and four spare buffers; filters write into the spares and
+  // the pointers swap.
+  double *phi_o = S, *J_o = S + M, *F_o = S + 2 * M, *F_n = S + 3 * M;
+  double *T1 = S + 4 * M, *T2 = S + 5 * M, *T3 = S + 6 * M, *T4 = S + 7 * M;
   double *gi_phi = losm_sums(A);
   double *gi_J = gi_phi + I;
   double *gi_K = gi_J + I;
-  double *gc_phi = gi_K + I;
-  double *gc_K = gc_phi + I;
   __shared__ double sp[64], sq[64];
   __shared__ double face[12];  // ic: phi L/R, P L/R, F L/R; cl: same
-  __shared__ double sc[4];     // scale, s, max
   __shared__ int bad;
-  __shared__ int skip;
   __shared__ double red[LOSM_THREADS / 64];
 
-  if (tid == 0) {
-    bad = (*A.status != 0) ? 1 : 0;  // a failed factorization stays failed
-    skip = 0;
-    double wtot = 0.0, wn = 0.0;
-    for (int q = 0; q < A.nc; ++q) {
-      wtot += A.wstart[q];
-      wn += A.wnext[q];
+  // Wave-uniform set-up: a failed factorization stays failed; the closure
+  // scale W_start / W_done (1 when semi-implicit; zero when no start weight
+  // has been swept yet, so that no closures exist and the update is
+  // skipped); the start weight of the step per source particle.
+  const bool failed = *A.status != 0;
+  double wtot = 0.0, wn = 0.0, wdone = 0.0;
+  for (int q = 0; q < A.nc; ++q) {
+    wtot += A.wstart[q];
+    wn += A.wnext[q];
+    if (q < A.next_chunk) wdone += A.wstart[q];
+  }
+  const double scale = A.implicit ? (wdone > 0.0 ? wtot / wdone : 0.0) : 1.0;
+  const double s_w = (A.implicit ? wtot : wn) / A.n_src;
+  const bool skip = A.implicit && !(scale > 0.0);
+  if (tid == 0) bad = 0;
+
+  // 1.-2. Batch sums of the tallies (the copies the sweep flushed),
+  // normalised per source particle and cell width (and step for
+  // track-length closures; the closure set scaled by W_start / W_done), and
+  // the grid functions of the initial condition and the closures made from
+  // them at once: the thread of cell c reads what grid point c + 1 needs,
+  // the current of cell c + 1 included.
+  if (tid < 12 * 64) {
+    // Face values, one wave each (lane = batch, B <= 64): t = (phi L,
+    // phi R, P L, P R, F L, F R) of the initial-condition set (t < 6) and
+    // of the closure set (t >= 6).  The waves write the boundary entries of
+    // the grid functions themselves; the waves of P L and P R also add up
+    // phi L and phi R for the boundary currents.
+    const int t = tid >> 6, bl = tid & 63;
+    const int set = t / 6, q = t % 6;
+    const int f = q & 1, kind = q >> 1;
+    const double *bs = set == 0 ? A.bnd_ic : A.bnd_cl;
+    double acc = bl < A.B ? bs[(bl * 2 + f) * 3 + kind] : 0.0;
+    double acc0 = (t == 2 || t == 3) && bl < A.B ? A.bnd_ic[(bl * 2 + f) * 3] : 0.0;
+    acc = wave_sum_f64(acc);
+    if (t == 2 || t == 3) acc0 = wave_sum_f64(acc0);
+    if (bl == 0) {
+      const double v = (set == 0 ? 1.0 : scale) * acc / (A.n_src * A.dt);
+      face[t] = v;
+      const int e = f ? I + 1 : 0;
+      if (t == 0 || t == 1) phi_o[e] = v;
+      if (t == 2) J_o[0] = -0.5 * (acc0 / (A.n_src * A.dt)) + v;
+      if (t == 3) J_o[I] = 0.5 * (acc0 / (A.n_src * A.dt)) - v;
+      if (t == 4 || t == 5) {
+        F_o[e] = v;
+        if (!A.implicit) F_n[e] = v;
+      }
+      if ((t == 10 || t == 11) && A.implicit) F_n[e] = v;
     }
-    sc[0] = closure_scale(A);
-    sc[1] = (A.implicit ? wtot : wn) / A.n_src;
-    // No start weight swept yet: no closures exist, the update is skipped.
-    if (A.implicit && !(sc[0] > 0.0)) skip = 1;
+  }
+  {
+    const int kc = A.closure_track ? 0 : 3;
+    for (int c = tid; c < I; c += T) {
+      const int i = c + 1;
+      const bool right = c + 1 < I;  // an interior edge to the right
+      const double xl = A.edges[c], xr = A.edges[c + 1];
+      const double xrr = right ? A.edges[c + 2] : xr;
+      double p = 0.0, j = 0.0, k = 0.0, jn = 0.0;
+      if (A.ic_cached) {
+        p = gi_phi[c];
+        j = gi_J[c];
+        k = gi_K[c];
+        if (right) jn = gi_J[c + 1];
+      } else {
+#pragma unroll
+        for (int s = 0; s < kSumCopies; ++s) {
+          const double *t = A.tsum_ic + (size_t)s * 6 * I;
+          p += t[3 * I + c];
+          j += t[4 * I + c];
+          k += t[5 * I + c];
+          if (right) jn += t[4 * I + c + 1];
+        }
+      }
+      double cp = 0.0, ck = 0.0;
+#pragma unroll
+      for (int s = 0; s < kSumCopies; ++s) {
+        const double *t = A.tsum_cl + (size_t)s * 6 * I;
+        cp += t[kc * I + c];
+        ck += t[(kc + 2) * I + c];
+      }
+      const double dl = xr - xl, dr = xrr - xr;
+      const double norm = A.n_src * dl;
+      if (!A.ic_cached) {
+        p = p / norm;
+        j = j / norm;
+        k = k / norm;
+        if (right) jn = jn / (A.n_src * dr);
+        gi_phi[c] = p;
+        gi_J[c] = j;
+        gi_K[c] = k;
+      }
+      const double normc = A.closure_track ? norm * A.dt : norm;
+      const double gcp = scale * cp / normc, gck = scale * ck / normc;
+      phi_o[i] = p;
+      const double fo = p / 3.0 - k;
+      F_o[i] = fo;
+      F_n[i] = A.implicit ? gcp / 3.0 - gck : fo;
+      if (right) J_o[i] = (dr * j + dl * jn) / (dl + dr);
+      if (A.lagged) {
+        // Lagged windows: the shape is the previous step's Monte Carlo
+        // track-length flux (the closure set read as track tallies).
+        u[2 * i] = gcp;
+        u[2 * i - 1] = 0.0;
+      }
+    }
+    if (A.lagged && tid == 0) {
+      u[0] = 0.0;
+      u[2 * I + 1] = 0.0;
+      u[2 * I + 2] = 0.0;
+    }
   }
   __syncthreads();
-  if (bad) return;
+  if (failed) return;
   if (skip) {
     for (int i = tid; i <= I + 1; i += T) A.phi_out[i] = 0.0;
     for (int i = tid; i <= I; i += T) A.J_out[i] = 0.0;
     return;
   }
-
-  // 1. batch sums of the cell tallies, normalised per source particle and
-  // cell width (and step for track-length closures; the closure set scaled
-  // by W_start / W_done), and of the face tallies.
-  {
-    const double scale = sc[0];
-    if (tid < 12 * 64) {
-      // Face values, one wave each (lane = batch, B <= 64): t = (phi L,
-      // phi R, P L, P R, F L, F R) of the initial-condition set (t < 6) and
-      // of the closure set (t >= 6).
-      const int t = tid >> 6, bl = tid & 63;
-      const int set = t / 6, q = t % 6;
-      const int f = q & 1, kind = q >> 1;
-      const double *bs = set == 0 ? A.bnd_ic : A.bnd_cl;
-      double acc = bl < A.B ? bs[(bl * 2 + f) * 3 + kind] : 0.0;
-      for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
-      if (bl == 0) face[t] = (set == 0 ? 1.0 : scale) * acc / (A.n_src * A.dt);
-    }
-    const int kc = A.closure_track ? 0 : 3;
-    for (int i = tid; i < I; i += T) {
-      const double dxi = A.edges[i + 1] - A.edges[i];
-      const double norm = A.n_src * dxi;
-      if (!A.ic_cached) {
-        double p = 0.0, j = 0.0, k = 0.0;
-#pragma unroll
-        for (int c = 0; c < kSumCopies; ++c) {
-          const double *t = A.tsum_ic + (size_t)c * 6 * I;
-          p += t[3 * I + i];
-          j += t[4 * I + i];
-          k += t[5 * I + i];
-        }
-        gi_phi[i] = p / norm;
-        gi_J[i] = j / norm;
-        gi_K[i] = k / norm;
-      }
-      double cp = 0.0, ck = 0.0;
-#pragma unroll
-      for (int c = 0; c < kSumCopies; ++c) {
-        const double *t = A.tsum_cl + (size_t)c * 6 * I;
-        cp += t[kc * I + i];
-        ck += t[(kc + 2) * I + i];
-      }
-      const double normc = A.closure_track ? norm * A.dt : norm;
-      gc_phi[i] = scale * cp / normc;
-      gc_K[i] = scale * ck / normc;
-    }
-    __syncthreads();
-  }
-
-  // 2. grid functions of the initial condition and the closures.
-  for (int i = tid; i <= I + 1; i += T) {
-    double fo;
-    if (i == 0) {
-      phi_o[0] = face[0];
-      fo = face[4];
-      J_o[0] = -0.5 * face[0] + face[2];
-    } else if (i == I + 1) {
-      phi_o[I + 1] = face[1];
-      fo = face[5];
-      J_o[I] = 0.5 * face[1] - face[3];
-    } else {
-      phi_o[i] = gi_phi[i - 1];
-      fo = gi_phi[i - 1] / 3.0 - gi_K[i - 1];
-      if (i <= I - 1) {
-        const double dl = A.edges[i] - A.edges[i - 1], dr = A.edges[i + 1] - A.edges[i];
-        J_o[i] = (dr * gi_J[i - 1] + dl * gi_J[i]) / (dl + dr);
-      }
-    }
-    F_o[i] = fo;
-    if (!A.implicit) F_n[i] = fo;
-    else if (i == 0) F_n[0] = face[10];
-    else if (i == I + 1) F_n[I + 1] = face[11];
-    else F_n[i] = gc_phi[i - 1] / 3.0 - gc_K[i - 1];
-  }
   const double PL = A.implicit ? face[8] : face[2];
   const double PR = A.implicit ? face[9] : face[3];
-  __syncthreads();
 
   if (A.export_only) {
     // Closures and initial condition of the finished step, unfiltered.
@@ -290,35 +322,29 @@ __device__ __forceinline__ void losm_body(const LosmArgs &A, double *dyn) {
     return;
   }
 
-  // Lagged weight windows: the shape is the previous step's Monte Carlo
-  // track-length flux (the closure set read as track tallies), no solve.
-  if (A.lagged) {
-    for (int i = tid; i <= I + 1; i += T) u[2 * i] = (i == 0 || i == I + 1) ? 0.0 : gc_phi[i - 1];
-    for (int i = tid; i <= I; i += T) u[2 * i + 1] = 0.0;
-    __syncthreads();
-  } else {
+  if (!A.lagged) {
   // 3. filters of F^n, F^{n-1}, phi^{n-1} (cell values) and J^{n-1} (edges).
   if (A.filter == 1) {
-    // Moving average, two grid functions per pass.
-    ma_filter_dev(F_n + 1, T1 + 1, I, A.ma_k);
-    ma_filter_dev(F_o + 1, T2 + 1, I, A.ma_k);
-    if (tid == 0) {
-      T1[0] = F_n[0]; T1[I + 1] = F_n[I + 1];
-      T2[0] = F_o[0]; T2[I + 1] = F_o[I + 1];
+    // Moving average of the cell values of phi (g = 0), F^{n-1} (2), F^n
+    // (3) and of the edge values of J (1), grid function g at S + g M into
+    // S + (4 + g) M, as one loop over all of their values (one copy of the
+    // loop's code runs for all four); faces copied along.
+    const int L = I + 1;
+    for (int q = tid; q < 4 * L; q += T) {
+      const int g = q / L, m = q - g * L;
+      const int off = g == 1 ? 0 : 1, len = g == 1 ? I + 1 : I;
+      if (m < len) ma_point(S + g * M + off, S + (4 + g) * M + off, len, m, A.ma_k);
     }
-    __syncthreads();
-    double *a = F_n, *b = F_o;
-    F_n = T1; F_o = T2; T1 = a; T2 = b;
-    ma_filter_dev(phi_o + 1, T1 + 1, I, A.ma_k);
-    ma_filter_dev(J_o, T2, I + 1, A.ma_k);
     if (tid == 0) {
       T1[0] = phi_o[0]; T1[I + 1] = phi_o[I + 1];
+      T3[0] = F_o[0]; T3[I + 1] = F_o[I + 1];
+      T4[0] = F_n[0]; T4[I + 1] = F_n[I + 1];
     }
     __syncthreads();
-    phi_o = T1; J_o = T2;
+    phi_o = T1; J_o = T2; F_o = T3; F_n = T4;
   } else if (A.filter == 2) {
     // Fourier low pass, one grid function at a time.
-    double *xc = kWil == 2 ? S + 6 * M : losm_fourier_scratch(A);
+    double *xc = kWil == 2 ? S + 8 * M : losm_fourier_scratch(A);
     fourier_cells_swap(F_n, T1, I, A.kappa, xc);
     fourier_cells_swap(F_o, T1, I, A.kappa, xc);
     fourier_cells_swap(phi_o, T1, I, A.kappa, xc);
@@ -345,11 +371,11 @@ __device__ __forceinline__ void losm_body(const LosmArgs &A, double *dyn) {
     losm_solve_scans(u, n, A.factor, sp, sq);
   }
   }
-  for (int i = tid; i <= I + 1; i += T) A.phi_out[i] = u[2 * i];
-  for (int i = tid; i <= I; i += T) A.J_out[i] = u[2 * i + 1];
 
   // 6. window centres (an empty bank has nothing to window: unchanged).
-  if (A.apply_windows && sc[1] > 0.0) {
+  // The largest flux by a wave maximum and one barrier; every thread then
+  // reads the waves' maxima.
+  if (A.apply_windows && s_w > 0.0) {
     double mx = -__builtin_inf();
     int nonfinite = 0;
     for (int i = tid; i < I; i += T) {
@@ -361,36 +387,34 @@ __device__ __forceinline__ void losm_body(const LosmArgs &A, double *dyn) {
     if ((tid & 63) == 0) red[tid >> 6] = mx;
     if (nonfinite) atomicOr(&bad, 1);
     __syncthreads();
-    if (tid == 0) {
-      double mm = red[0];
-      for (int q = 1; q < (T >> 6); ++q) mm = red[q] > mm ? red[q] : mm;
-      sc[2] = mm;
-      // A lagged shape without any track flux (the first step) leaves the
-      // windows as they are.
-      if (!(mm > 0.0)) {
-        if (A.lagged && !bad) skip = 1;
-        else bad = 1;
+    const int lane = tid & 63;
+    const double mm = wave_max_f64(lane < (T >> 6) ? red[lane] : -__builtin_inf());
+    bool numeric = bad != 0, keep = false;
+    // A lagged shape without any track flux (the first step) leaves the
+    // windows as they are.
+    if (!(mm > 0.0)) {
+      if (A.lagged && !numeric) keep = true;
+      else numeric = true;
+    }
+    if (numeric) {
+      if (tid == 0) atomicOr(A.err, ERR_NUMERIC);
+    } else if (!keep) {
+      const double s = A.window_scale ? 1.0 : s_w;
+      for (int i = tid; i < I; i += T) {
+        const double p = u[2 * (i + 1)];
+        const double rr = p > 0.0 ? p / mm : 0.0;
+        const double ww = s * (rr * (1.0 - A.eps_min) + A.eps_min);
+        Window wd;
+        wd.ww = ww;
+        wd.ceil = ww * A.rho;
+        wd.floor = ww / A.rho;
+        wd.pad = 0.0;
+        A.win[i] = wd;
       }
     }
-    __syncthreads();
-    if (skip && !bad) return;
-    if (bad) {
-      if (tid == 0) atomicOr(A.err, ERR_NUMERIC);
-      return;
-    }
-    const double mm = sc[2], s = A.window_scale ? 1.0 : sc[1];
-    for (int i = tid; i < I; i += T) {
-      const double p = u[2 * (i + 1)];
-      const double rr = p > 0.0 ? p / mm : 0.0;
-      const double ww = s * (rr * (1.0 - A.eps_min) + A.eps_min);
-      Window wd;
-      wd.ww = ww;
-      wd.ceil = ww * A.rho;
-      wd.floor = ww / A.rho;
-      wd.pad = 0.0;
-      A.win[i] = wd;
-    }
   }
+  for (int i = tid; i <= I + 1; i += T) A.phi_out[i] = u[2 * i];
+  for (int i = tid; i <= I; i += T) A.J_out[i] = u[2 * i + 1];
 }
 
 template <int kWil>
@@ -438,7 +462,7 @@ __global__ void __launch_bounds__(LOSM_THREADS) losm_batch_kernel(const LosmRepl
 // 1) and also the Fourier filter's coefficients (2).
 static size_t losm_lds(int I, int *work_in_lds) {
   const size_t lds_min = (size_t)(2 * I + 3) * sizeof(double);
-  const size_t lds_full = lds_min + (size_t)6 * (I + 2) * sizeof(double);
+  const size_t lds_full = lds_min + (size_t)8 * (I + 2) * sizeof(double);
   const size_t lds_four = lds_full + (size_t)((I + 2) + 4) * sizeof(double);
   const size_t budget = 160 * 1024 - 2 * 1024;  // static LDS of the solve: about 1.3 KB
   *work_in_lds = lds_four <= budget ? 2 : (lds_full <= budget ? 1 : 0);

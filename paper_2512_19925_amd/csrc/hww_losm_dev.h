@@ -190,10 +190,27 @@ __device__ __forceinline__ double wave_max_f64(double m) {
   return __longlong_as_double((long long)(((uint64_t)hi32 << 32) | lo32));
 }
 
+// Sum over the 64 lanes of a wave (every lane gets it): an inclusive scan
+// by DPP lane moves, then lane 63.
+__device__ __forceinline__ double wave_sum_f64(double x) {
+  x += dpp_f64<kDppRowShr1>(0.0, x);
+  x += dpp_f64<kDppRowShr2>(0.0, x);
+  x += dpp_f64<kDppRowShr4>(0.0, x);
+  x += dpp_f64<kDppRowShr8>(0.0, x);
+  x += dpp_f64<kDppRowBcast15, 0xA>(0.0, x);
+  x += dpp_f64<kDppRowBcast31, 0xC>(0.0, x);
+  const uint64_t b = (uint64_t)__double_as_longlong(x);
+  const uint32_t lo32 = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, 63);
+  const uint32_t hi32 = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), 63);
+  return __longlong_as_double((long long)(((uint64_t)hi32 << 32) | lo32));
+}
+
 // Scan of affine maps y -> p + q y across the work-group in thread order:
 // returns, for thread t, the composition of the maps of threads 0..t-1
-// applied to y = 0 (0 for thread 0).  Within a wave by shuffles, across the
-// (at most 16) waves through LDS: two barriers.  sp, sq: >= 48 doubles each.
+// applied to y = 0 (0 for thread 0).  Within a wave by DPP lane moves;
+// across the (at most 16) waves through LDS with one barrier, after which
+// every wave scans the wave totals itself.  sp, sq: >= 16 doubles each.
+// Two calls need a barrier between them (the second one rewrites sp, sq).
 __device__ inline double affine_scan_excl(double *sp, double *sq, double P, double Q) {
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6, nw = (int)(blockDim.x >> 6);
   affine_scan_wave(P, Q);
@@ -204,21 +221,18 @@ __device__ inline double affine_scan_excl(double *sp, double *sq, double P, doub
     sq[wv] = Q;
   }
   __syncthreads();
-  if (wv == 0) {
-    // At most 16 waves: one row of lanes.
-    double p = lane < nw ? sp[lane] : 0.0, q = lane < nw ? sq[lane] : 1.0;
-    affine_step<kDppRowShr1>(p, q);
-    affine_step<kDppRowShr2>(p, q);
-    affine_step<kDppRowShr4>(p, q);
-    affine_step<kDppRowShr8>(p, q);
-    if (lane < nw) {
-      sp[32 + lane] = p;
-      sq[32 + lane] = q;
-    }
-  }
-  __syncthreads();
-  // Maps of the earlier waves, applied to 0, then this wave's lanes before t.
-  const double pw = wv > 0 ? sp[32 + wv - 1] : 0.0;
+  if (wv == 0) return pe + qe * 0.0;
+  // Inclusive scan of the wave totals in lanes 0..nw-1 (one row of 16); the
+  // maps of waves 0..wv-1 are lane wv-1's.
+  double p = lane < nw ? sp[lane] : 0.0, q = lane < nw ? sq[lane] : 1.0;
+  affine_step<kDppRowShr1>(p, q);
+  affine_step<kDppRowShr2>(p, q);
+  affine_step<kDppRowShr4>(p, q);
+  affine_step<kDppRowShr8>(p, q);
+  const uint64_t b = (uint64_t)__double_as_longlong(p);
+  const uint32_t lo32 = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, wv - 1);
+  const uint32_t hi32 = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), wv - 1);
+  const double pw = __longlong_as_double((long long)(((uint64_t)hi32 << 32) | lo32));
   return pe + qe * pw;
 }
 
