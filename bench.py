@@ -96,14 +96,19 @@ def _step(h, w, n, analog, kw, stats):
     return st
 
 
-def run_gpu(w, steps_total, warmup, analog, timing=True):
+def run_gpu(w, steps_total, warmup, analog, timing=True, tune=False):
     """Timed run: the host queues every step without waiting; one
     synchronisation at each end of the timed region.  Counters and the sweep
     kernels' HIP-event times (timing on) come from the library's run
-    totals."""
+    totals.  tune: the sweep's launch shape from the library's tuner instead
+    of the default one (the tuner times chunk 0 of step 1, where every
+    particle still sits at the pulse; on the full-scale problem it picks
+    512-particle tiles, which make steps 6-25 8 % slower than the default
+    256, so the benchmark keeps the default)."""
     import torch
     from paper_2512_19925_amd import hww as H
     h = H.Handle(H.spec_from_workload(w))
+    shape = h.autotune() if tune else None
     h.set_timing(timing)
     kw = H.losm_kwargs(w)
     for n in range(1, warmup + 1):
@@ -121,6 +126,7 @@ def run_gpu(w, steps_total, warmup, analog, timing=True):
                                        "launches", "kernel_ms")}
     d["wall_s"] = wall
     d["generations"] = tot["generations"]
+    d["shape"] = shape
     return d
 
 

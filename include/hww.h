@@ -338,9 +338,16 @@ typedef struct hww_tune_result {
 /* Measure the sweep of chunk 0 of step 1 under every launch shape (block
  * size, tile size and, for batches, the persistent grid of each LDS class)
  * twice, keep the fastest for every later sweep, and restore the state of
- * step 0.  Must run before the first hww_sweep_step (windows may already be
- * set).  The shape changes no result beyond the summation order of the
- * tallies.
+ * step 0.  The shapes found are kept for the life of the process: a later
+ * problem of the same kind on the same device (same precision, fission,
+ * chunk and batch counts, work-groups per batch and cell-record placement,
+ * and the same power-of-two buckets of cell count and source particles; for
+ * a batch, per LDS class: replica count, largest cell count and start
+ * particles of the class) takes the stored shape without measuring, and
+ * trials counts only the shapes measured by this call (0 when every shape
+ * came from the store).  Must run before the first hww_sweep_step (windows
+ * may already be set).  The shape changes no result beyond the summation
+ * order of the tallies.
  * Errors: HWW_E_STATE after the first sweep, HWW_E_CAPACITY if a trial
  * overflows.  Synchronises. */
 int hww_autotune(hww_handle *h, hww_tune_result *best);

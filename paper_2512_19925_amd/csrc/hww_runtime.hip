@@ -258,6 +258,49 @@ int static_workspace(int dev, char **ptr, std::string *why) {
   return HWW_OK;
 }
 
+// Launch shapes the tuner measured, kept for the life of the process: a
+// later problem of the same kind takes its shape without measuring.  The
+// key is the device, the flight precision, fission, the chunk and batch
+// counts, work-groups per batch and the LDS placement of the cell records
+// (single problems), or the LDS class and the replica count (batches), and
+// the power-of-two buckets of the cell count and the start particles.
+struct TuneKey {
+  int dev, fp32, fission, batch, cls, nc, B, K, cells, cells_bucket, particles_bucket, replicas;
+  bool operator==(const TuneKey &o) const { return std::memcmp(this, &o, sizeof(TuneKey)) == 0; }
+};
+struct TuneShape {
+  int block, tile, grid;
+  float ms;
+};
+std::mutex g_tune_mu;
+std::vector<std::pair<TuneKey, TuneShape>> g_tune_cache;
+
+int log2_bucket(int64_t v) {
+  int b = 0;
+  while (b < 62 && ((int64_t)1 << b) < v) ++b;
+  return b;
+}
+
+bool tune_lookup(const TuneKey &k, TuneShape *out) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  for (const auto &e : g_tune_cache)
+    if (e.first == k) {
+      *out = e.second;
+      return true;
+    }
+  return false;
+}
+
+void tune_store(const TuneKey &k, const TuneShape &v) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  for (auto &e : g_tune_cache)
+    if (e.first == k) {
+      e.second = v;
+      return;
+    }
+  g_tune_cache.emplace_back(k, v);
+}
+
 }  // namespace
 
 struct hww_handle {
@@ -315,6 +358,7 @@ struct hww_handle {
     size_t lds = 0;
     int cells_mode = 0, block = 1024, tile = kTile, grid = 0;
     int64_t starts = 0;  // start particles of its replicas
+    int n_rep = 0, max_cells = 0;
   };
   BatchClass bcls[kBatchClasses];
   void *desc = nullptr;              // ReplicaDesc<Real>[n]
@@ -1597,6 +1641,8 @@ int hww_init_batch(const hww_problem *problems, int32_t n, void *dev_workspace, 
       ++cnt[ci];
       h->bcls[ci].lds = std::max(h->bcls[ci].lds, sweep_lds_bytes(I, h->nc, K, f ? cb : 0));
       h->bcls[ci].starts += problems[r].n_src;
+      h->bcls[ci].n_rep += 1;
+      h->bcls[ci].max_cells = std::max(h->bcls[ci].max_cells, I);
     }
     for (int ci = 0; ci < kBatchClasses; ++ci) {
       hww_handle::BatchClass &c = h->bcls[ci];
@@ -1766,9 +1812,44 @@ int hww_autotune(hww_handle *h, hww_tune_result *best) {
   float total_ms = 0.0f;
   int rc = HWW_OK;
   const int ncls = h->is_batch ? kBatchClasses : 1;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
   for (int ci = 0; rc == HWW_OK && ci < ncls; ++ci) {
     if (h->is_batch && h->bcls[ci].u1 == h->bcls[ci].u0) continue;
     if (h->is_batch && h->bcls[ci].starts > h->bcls[report].starts) report = ci;
+    TuneKey key;
+    std::memset(&key, 0, sizeof key);
+    key.dev = dev;
+    key.fp32 = h->fp32;
+    key.nc = h->nc;
+    key.batch = h->is_batch;
+    if (h->is_batch) {
+      key.cls = ci;
+      key.cells = h->bcls[ci].cells_mode;
+      key.cells_bucket = log2_bucket(h->bcls[ci].max_cells);
+      key.particles_bucket = log2_bucket(h->bcls[ci].starts);
+      key.replicas = log2_bucket(h->bcls[ci].n_rep);
+    } else {
+      key.fission = h->cfis != nullptr;
+      key.B = h->B;
+      key.K = h->K;
+      key.cells = h->cells_lds;
+      key.cells_bucket = log2_bucket(h->I);
+      key.particles_bucket = log2_bucket(h->p.n_src);
+    }
+    TuneShape hit;
+    if (tune_lookup(key, &hit)) {
+      if (h->is_batch) {
+        h->bcls[ci].block = hit.block;
+        h->bcls[ci].tile = hit.tile;
+        h->bcls[ci].grid = hit.grid;
+      } else {
+        h->block = hit.block;
+        h->tile = hit.tile;
+      }
+      total_ms += hit.ms;
+      continue;
+    }
     const size_t lds = h->is_batch ? h->bcls[ci].lds : h->lds;
     int bb = h->is_batch ? h->bcls[ci].block : h->block;
     int bt = h->is_batch ? h->bcls[ci].tile : h->tile;
@@ -1810,6 +1891,7 @@ int hww_autotune(hww_handle *h, hww_tune_result *best) {
       h->block = bb;
       h->tile = bt;
     }
+    if (rc == HWW_OK && have) tune_store(key, TuneShape{bb, bt, bg, best_ms});
     total_ms += best_ms;
   }
   (void)hipEventDestroy(e0);

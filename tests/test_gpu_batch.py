@@ -92,6 +92,28 @@ def test_autotuned_batch_matches_oracles():
     _run_batch_vs_oracle(ws, steps=3, tune=True)
 
 
+def test_autotune_reuses_the_shape_of_a_problem_of_the_same_kind():
+    # A second problem of the same kind takes the stored shape without
+    # measuring; the shape changes only the summation order of the tallies.
+    need_gpu()
+    w = W.plain_small().with_(n_src=30_000, n_steps=3)
+    h1 = H.Handle(H.spec_from_workload(w))
+    r1 = h1.autotune()
+    h2 = H.Handle(H.spec_from_workload(w))
+    r2 = h2.autotune()
+    say(f"  first {r1}, second {r2}")
+    assert r2["trials"] == 0
+    assert (r2["block"], r2["tile"], r2["grid"]) == (r1["block"], r1["tile"], r1["grid"])
+    h3 = H.Handle(H.spec_from_workload(w))  # default shape, not tuned
+    out = []
+    for h in (h2, h3):
+        H.run(h, w, stats=False)
+        out.append(h.read_tallies(H.TALLY_CELLS))
+        h.close()
+    h1.close()
+    assert_tallies_match(out[0], out[1], what="tuned against default shape")
+
+
 def test_batch_fourier_filter_matches_oracles():
     ws = [w.with_(filter=2, kappa=12) for w in uneven_replicas(n_steps=3)]
     _run_batch_vs_oracle(ws, steps=3)
