@@ -215,6 +215,30 @@ def _batch_steps(bt, steps, kw, first=1):
                 bt.solve_losm(implicit=True, **kw)
 
 
+def device_check():
+    """The device as the runtime reports it, and the bandwidth of a plain
+    device copy (1 GiB read + 1 GiB written, ten copies timed by events on
+    the current stream): the measured ceiling beside the published peak."""
+    import torch
+    pr = torch.cuda.get_device_properties(0)
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 10 * 2 * src.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"name": pr.name, "arch": pr.gcnArchName, "compute_units": pr.multi_processor_count,
+            "hbm_bytes": pr.total_memory, "lds_bytes_per_block": pr.shared_memory_per_block,
+            "l2_bytes": pr.L2_cache_size, "copy_GBs": gbs}
+
+
 def run_batched(steps, compare_steps=10):
     """The batched form: 256 uneven replicas, one persistent sweep launch per
     chunk and one batched LOSM launch per solve, launch shape autotuned.
@@ -266,6 +290,8 @@ def run_batched(steps, compare_steps=10):
             "segments_per_s": st["segments"] / wall, "ms_per_step": wall * 1e3 / steps,
             "kernel_segments_per_s": st["segments"] / (st["kernel_ms"] * 1e-3) if st["kernel_ms"] else None,
             "kernel_achieved_GBs": st["bytes_moved"] / (st["kernel_ms"] * 1e-3) / 1e9 if st["kernel_ms"] else None,
+            "kernel_frac_of_hbm_peak": (st["bytes_moved"] / (st["kernel_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS
+                                        if st["kernel_ms"] else None),
             "autotune": tune,
             "steps_1_to_%d" % compare_steps: {
                 "batched_segments_per_s": seg_cmp / wall_cmp,
@@ -611,6 +637,7 @@ def main():
     achieved = tim["bytes_moved"] / (tim["kernel_ms"] * 1e-3) / 1e9 if tim["kernel_ms"] > 0 else 0.0
     bytes_per_launch = tim["bytes_moved"] / max(tim["launches"], 1)
     avg_launch_s = tim["kernel_ms"] * 1e-3 / max(tim["launches"], 1)
+    dev = device_check()
     traf = profile_figures(TRAFFIC_PROFILE, ["traffic_over_algorithmic"])
     valu = profile_figures(VALU_PROFILE, ["valu_issue_frac", "active_lanes_per_valu", "valu_insts_per_launch"])
     line = {
@@ -626,6 +653,9 @@ def main():
         "kernel_segments_per_s": tim["segments"] / (tim["kernel_ms"] * 1e-3) if tim["kernel_ms"] else None,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
+                     # Beside the published peak: the measured bandwidth of a
+                     # plain device copy on this GPU.
+                     "measured_copy_GBs": dev["copy_GBs"], "frac_of_copy": achieved / dev["copy_GBs"],
                      "traffic": traf["traffic_over_algorithmic"] * bytes_per_launch if traf else None,
                      "traffic_over_algorithmic": traf["traffic_over_algorithmic"] if traf else None,
                      "kernel": "sweep_kernel<double, true, false>",
@@ -641,6 +671,7 @@ def main():
                                "lane_frac": valu["active_lanes_per_valu"] / 64.0,
                                "source": os.path.relpath(VALU_PROFILE, ROOT)} if valu else None)},
         "value_runs": [d["segments"] / d["wall_s"] for d in runs],
+        "device": dev,
     }
     if not args.no_analog:
         from paper_2512_19925_amd import pulse_reference as P

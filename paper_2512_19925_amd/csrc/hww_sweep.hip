@@ -24,6 +24,9 @@ namespace hww {
 // Daughters of a generation that waves out of their own tiles take early
 // even when no wave has tiles of its own left.
 constexpr uint32_t kDrainSmall = 256;
+// A wave whose lanes each have at most this many daughters to write lets
+// every lane write its own; above it the wave writes them 64 at a time.
+constexpr uint32_t kLaneDaughters = 4;
 
 // Window and event actions of a lane (bit flags).
 enum : uint32_t { WW_ROULETTE = 1u, WW_SPLIT = 2u, EV_DRAW = 4u, EV_SCATTER = 8u, EV_FISSION = 16u,
@@ -386,30 +389,58 @@ __device__ __forceinline__ void sweep_unit(const SweepArgs<Real> &A, int b, int 
       base = __shfl(base, 0);
       if ((uint64_t)base + total > (uint64_t)A.dcap && lane == 0) atomicOr(A.err, ERR_DAUGHTERS);
       const int64_t qb = ((int64_t)out_buf * nq + qslot) * dstride;
-      const uint32_t start = base + incl - cntd;
-      for (uint32_t q = 1; q <= cntd; ++q) {
-        const uint64_t slot = (uint64_t)start + (q - 1);
-        if (slot >= (uint64_t)A.dcap) break;
+      // Daughter q = 1..n of a lane goes to slot base + (its lane's offset
+      // in the wave) + q - 1, with lineage base + q.
+      auto write_daughter = [&](uint32_t g, uint32_t q, Real dx, Real dmu, double dw, Real dtau, uint32_t dsrc,
+                                uint64_t dlin, uint32_t de, int32_t dcell, bool dfis) {
+        const uint64_t slot = (uint64_t)base + g;
+        if (slot >= (uint64_t)A.dcap) return;
         const int64_t k = qb + (int64_t)slot;
         XMu<Real> xm;
-        xm.x = x;
-        xm.mu = mu;
-        if (kFission && fis) {
+        xm.x = dx;
+        xm.mu = dmu;
+        if (kFission && dfis) {
           uint32_t rd[4];
-          draw(A.seed, A.key1, SLOT_FISSION_DIR, src, lin_base + q, e_d, rd);
+          draw(A.seed, A.key1, SLOT_FISSION_DIR, dsrc, dlin + q, de, rd);
           xm.mu = (Real)2 * uflight<Real>(rd[0], rd[1]) - (Real)1;
         }
         A.dq.xm[k] = xm;
         WTau wt;
-        wt.w = w;
-        wt.tau = (double)tau;
+        wt.w = dw;
+        wt.tau = (double)dtau;
         A.dq.wt[k] = wt;
-        A.dq.lin[k] = lin_base + q;
+        A.dq.lin[k] = dlin + q;
         Tag tg;
-        tg.src = src;
-        tg.e = e_d;
-        tg.cell = cell;
+        tg.src = dsrc;
+        tg.e = de;
+        tg.cell = dcell;
         A.dq.tag[k] = tg;
+      };
+      const uint32_t excl = incl - cntd;
+      if (__ballot(cntd > kLaneDaughters) == 0) {
+        // Few per lane: each lane writes its own.
+        for (uint32_t q = 1; q <= cntd; ++q)
+          write_daughter(excl + q - 1, q, x, mu, w, tau, src, lin_base, e_d, cell, kFission && fis);
+      } else {
+        // Many in some lane (a heavy split): the wave writes 64 daughters
+        // per pass, lane l the (64 j + l)-th of the wave, reading its
+        // parent's state from the parent's lane.
+        for (uint32_t j0 = 0; j0 < total; j0 += 64) {
+          const uint32_t g = j0 + lane;
+          // Parent: the first lane whose inclusive count exceeds g.
+          int sl = 0;
+#pragma unroll
+          for (int step = 32; step >= 1; step >>= 1)
+            if (__shfl(incl, sl + step - 1) <= g) sl += step;
+          if (sl > 63) sl = 63;
+          const Real px = __shfl(x, sl), pmu = __shfl(mu, sl), ptau = __shfl(tau, sl);
+          const double pw = __shfl(w, sl);
+          const uint32_t psrc = __shfl(src, sl), pe = __shfl(e_d, sl), pexcl = __shfl(excl, sl);
+          const int32_t pcell = __shfl(cell, sl);
+          const uint64_t plin = __shfl(lin_base, sl);
+          const bool pfis = kFission && __shfl((int)fis, sl) != 0;
+          if (g < total) write_daughter(g, g - pexcl + 1, px, pmu, pw, ptau, psrc, plin, pe, pcell, pfis);
+        }
       }
       pub += total;
       publish();
