@@ -24,6 +24,7 @@
 namespace hww {
 
 static constexpr int LOSM_THREADS = 1024;
+static constexpr double kThird = 1.0 / 3.0;
 
 // Thomas factors of the solve matrix for A.theta, then the old-time
 // diagonal of every row: factor = [alpha | 1/den | gamma | bb], each 2I+3
@@ -61,7 +62,7 @@ __device__ __forceinline__ double ma_full(const double *in, int m) {
   double acc = 0.0;
 #pragma unroll
   for (int l = 0; l <= 2 * K; ++l) acc += x[l];
-  return acc / (double)(2 * K + 1);
+  return acc * (1.0 / (double)(2 * K + 1));
 }
 
 __device__ inline void ma_point(const double *in, double *out, int M, int m, int k) {
@@ -269,21 +270,25 @@ __device__ __forceinline__ void losm_body(const LosmArgs &A, double *dyn) {
       }
       const double dl = xr - xl, dr = xrr - xr;
       const double norm = A.n_src * dl;
+      // The solve runs on one compute unit, so its FP64 divisions are a
+      // large share of its issue time: each divisor is inverted once.
       if (!A.ic_cached) {
-        p = p / norm;
-        j = j / norm;
-        k = k / norm;
-        if (right) jn = jn / (A.n_src * dr);
+        const double inv = 1.0 / norm;
+        p = p * inv;
+        j = j * inv;
+        k = k * inv;
+        if (right) jn = jn * (1.0 / (A.n_src * dr));  // as the next cell's thread scales its own
         gi_phi[c] = p;
         gi_J[c] = j;
         gi_K[c] = k;
       }
       const double normc = A.closure_track ? norm * A.dt : norm;
-      const double gcp = scale * cp / normc, gck = scale * ck / normc;
+      const double sn = scale / normc;
+      const double gcp = cp * sn, gck = ck * sn;
       phi_o[i] = p;
-      const double fo = p / 3.0 - k;
+      const double fo = p * kThird - k;
       F_o[i] = fo;
-      F_n[i] = A.implicit ? gcp / 3.0 - gck : fo;
+      F_n[i] = A.implicit ? gcp * kThird - gck : fo;
       if (right) J_o[i] = (dr * j + dl * jn) / (dl + dr);
       if (A.lagged) {
         // Lagged windows: the shape is the previous step's Monte Carlo
@@ -329,11 +334,9 @@ __device__ __forceinline__ void losm_body(const LosmArgs &A, double *dyn) {
     // (3) and of the edge values of J (1), grid function g at S + g M into
     // S + (4 + g) M, as one loop over all of their values (one copy of the
     // loop's code runs for all four); faces copied along.
-    const int L = I + 1;
-    for (int q = tid; q < 4 * L; q += T) {
-      const int g = q / L, m = q - g * L;
+    for (int g = 0; g < 4; ++g) {
       const int off = g == 1 ? 0 : 1, len = g == 1 ? I + 1 : I;
-      if (m < len) ma_point(S + g * M + off, S + (4 + g) * M + off, len, m, A.ma_k);
+      for (int m = tid; m < len; m += T) ma_point(S + g * M + off, S + (4 + g) * M + off, len, m, A.ma_k);
     }
     if (tid == 0) {
       T1[0] = phi_o[0]; T1[I + 1] = phi_o[I + 1];
@@ -389,6 +392,7 @@ __device__ __forceinline__ void losm_body(const LosmArgs &A, double *dyn) {
     __syncthreads();
     const int lane = tid & 63;
     const double mm = wave_max_f64(lane < (T >> 6) ? red[lane] : -__builtin_inf());
+    const double inv_mm = 1.0 / mm, inv_rho = 1.0 / A.rho;
     bool numeric = bad != 0, keep = false;
     // A lagged shape without any track flux (the first step) leaves the
     // windows as they are.
@@ -402,12 +406,12 @@ __device__ __forceinline__ void losm_body(const LosmArgs &A, double *dyn) {
       const double s = A.window_scale ? 1.0 : s_w;
       for (int i = tid; i < I; i += T) {
         const double p = u[2 * (i + 1)];
-        const double rr = p > 0.0 ? p / mm : 0.0;
+        const double rr = p > 0.0 ? p * inv_mm : 0.0;
         const double ww = s * (rr * (1.0 - A.eps_min) + A.eps_min);
         Window wd;
         wd.ww = ww;
         wd.ceil = ww * A.rho;
-        wd.floor = ww / A.rho;
+        wd.floor = ww * inv_rho;
         wd.pad = 0.0;
         A.win[i] = wd;
       }

@@ -106,7 +106,7 @@ __device__ inline double losm_rhs_bb(int I, double th, int r, double bb, const d
   }
   const int j = (r - 1) / 2;
   return bb * J_o[j] + th * (F_n[j + 1] - F_n[j])
-       + (th - 1.0) * ((phi_o[j + 1] - phi_o[j]) / 3.0 - (F_o[j + 1] - F_o[j]));
+       + (th - 1.0) * ((phi_o[j + 1] - phi_o[j]) * (1.0 / 3.0) - (F_o[j + 1] - F_o[j]));
 }
 
 // Thomas factors of the matrix (or of its transpose) for the forward
