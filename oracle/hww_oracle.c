@@ -44,6 +44,9 @@
  *   sweep (streaming)   exact geometric track lengths, single particles
  *   sweep (scattering)  exact weight/track conservation at c = 1 (analog),
  *                       closed-form moment solutions for 0 < c < 1
+ *   sweep (one short    track length and census weight per cell against
+ *    step)              the expectations over histories with at most one
+ *                       collision (first order in the collisions)
  *   split / roulette    exact daughter count and weight sum, unbiased
  *                       roulette, HWW vs analog tallies agree statistically
  *   fission             nu_f = 1 fission identical to scattering (tallies,
@@ -54,7 +57,10 @@
  *   orc_comb            systematic-sampling property (floor/ceil copies of
  *                       every run, canonical order kept), equal weights
  *                       summing to the census weight, identities and
- *                       chunks, uniform offset over seeds
+ *                       chunks, uniform offset over seeds; with teeth in
+ *                       particle index: systematic sampling over the
+ *                       particles, each copy's weight its particle's times
+ *                       n / n_target, the census weight kept on average
  * Parity unpinned: the variance/FOM benefit of a particular window schedule
  * (the paper shows it only in figures).
  */
