@@ -427,8 +427,8 @@ __global__ void __launch_bounds__(LOSM_THREADS) losm_kernel(LosmArgs A) {
   losm_body<kWil>(A, dyn);
 }
 
-// Batched solves: replica r of the table takes block r (factor, solve) or
-// row r of the grid (reduce); the call options are shared.
+// Batched solves: replica r of the table takes block r (factor, solve); the
+// call options are shared.
 __device__ inline LosmArgs losm_batch_args(const LosmReplica &R, const LosmCall &c) {
   LosmArgs A = R.a;
   if (!c.implicit) {
