@@ -210,13 +210,13 @@ __device__ __forceinline__ void losm_body(const LosmArgs &A, double *dyn) {
   // the grid functions of the initial condition and the closures made from
   // them at once: the thread of cell c reads what grid point c + 1 needs,
   // the current of cell c + 1 included.
-  if (tid < 12 * 64) {
+  for (int t = tid >> 6; t < 12; t += T >> 6) {
     // Face values, one wave each (lane = batch, B <= 64): t = (phi L,
     // phi R, P L, P R, F L, F R) of the initial-condition set (t < 6) and
     // of the closure set (t >= 6).  The waves write the boundary entries of
     // the grid functions themselves; the waves of P L and P R also add up
     // phi L and phi R for the boundary currents.
-    const int t = tid >> 6, bl = tid & 63;
+    const int bl = tid & 63;
     const int set = t / 6, q = t % 6;
     const int f = q & 1, kind = q >> 1;
     const double *bs = set == 0 ? A.bnd_ic : A.bnd_cl;
